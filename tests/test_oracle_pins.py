@@ -1,0 +1,278 @@
+"""Pins for the CPU oracle: everything here checks the oracle against facts
+fixed by the paper or by mathematics, never against itself or the GPU."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2301_05726_amd import synth
+from dense_jw import DenseJW
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_counts.json")
+
+
+def small_problem(n_orb, n_occ, sigma, seed):
+    h1, h2 = synth.make_hamiltonian(n_orb, seed)
+    exc = synth.ordered_excitations(h1, h2, n_occ)
+    theta = synth.make_theta(exc.shape[0], sigma, seed + 1)
+    return h1, h2, exc, theta, synth.hf_det(n_occ)
+
+
+# ---------------------------------------------------------------- counts
+
+
+def test_paper_counts():
+    g = json.load(open(GOLDEN))
+    for row in g["uccsd_factor_counts"]:
+        o, v = row["o"], row["v"]
+        assert synth.uccsd_count(o + v, o) == row["value"], row["cite"]
+        s, d = synth.canonical_excitations(o + v, o)
+        assert len(s) + len(d) == row["value"], row["cite"]
+    for row in g["hilbert_sizes"]:
+        val = math.comb(row["n_spatial"], row["n_alpha"]) * math.comb(row["n_spatial"], row["n_beta"])
+        assert abs(val - row["value"]) <= row["rel_tol"] * row["value"], row["cite"]
+
+
+def test_excitation_generator_properties():
+    s, d = synth.canonical_excitations(10, 5)
+    assert len(s) == 50 and len(d) == 825
+    for (i, j, a, b) in d:
+        assert i < j < 10 <= a < b
+        assert (i & 1) + (j & 1) == (a & 1) + (b & 1)
+    h1, h2 = synth.make_hamiltonian(10, 1002)
+    ex = synth.ordered_excitations(h1, h2, 5)
+    assert ex.shape == (875, 4)
+    assert (ex[-50:, 1] == -1).all() and (ex[:825, 1] >= 0).all()
+    h1b, h2b = synth.make_hamiltonian(10, 1002)
+    assert np.array_equal(h1, h1b) and np.array_equal(h2, h2b)
+    # 8-fold symmetry of the generated integrals
+    assert np.allclose(h2, h2.transpose(1, 0, 2, 3)) and np.allclose(h2, h2.transpose(2, 3, 0, 1))
+    assert np.allclose(h1, h1.T)
+
+
+# ---------------------------------------------------------------- sign rule
+
+
+def test_tau_sign_matches_dense_operator(orc):
+    """tau|D> from the oracle's sequential operators equals the Kronecker
+    Jordan-Wigner matrix element, exhaustively for 8 spin-orbitals."""
+    nq = 8
+    jw = DenseJW(nq)
+    rows = [(0, -1, 5, -1), (3, -1, 1, -1), (0, 2, 4, 6), (1, 3, 5, 7), (0, 3, 2, 7), (4, 6, 0, 1), (2, 5, 1, 7)]
+    for row in rows:
+        T = jw.tau(row).tocoo()
+        ref = {int(c): (int(r), int(v)) for r, c, v in zip(T.row, T.col, T.data)}
+        for D in range(1 << nq):
+            s, P = orc.tau(row, D)
+            if D in ref:
+                assert (P, s) == ref[D]
+            else:
+                assert s == 0
+
+
+# ---------------------------------------------------------------- factor action
+
+
+@pytest.mark.parametrize("n_orb,n_occ,sigma,seed", [(4, 2, 0.3, 11), (6, 3, 0.2, 12), (6, 2, 0.25, 13)])
+def test_forward_matches_dense_statevector(orc, n_orb, n_occ, sigma, seed):
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed)
+    nq = 2 * n_orb
+    d, a, _, _ = orc.apply_ucc(nq, [hf], [1.0], exc, theta, 0.0)
+    jw = DenseJW(nq)
+    psi = jw.apply_factors(jw.basis([hf]), exc, theta)
+    dense = np.zeros(1 << nq)
+    dense[d.astype(np.int64)] = a
+    assert np.max(np.abs(dense - psi)) < 1e-12
+    # energies: literal and Slater-Condon vs dense E_pq route and literal dense H
+    e_lit = orc.energy(n_orb, h1, h2, d, a, mode=0)
+    e_sc = orc.energy(n_orb, h1, h2, d, a, mode=1)
+    e_dense = jw.energy_epq(h1, h2, psi)
+    assert abs(e_lit - e_dense) < 1e-11
+    assert abs(e_sc - e_dense) < 1e-11
+    if nq <= 8:
+        H = jw.h_literal(h1, h2)
+        assert abs(psi @ (H @ psi) - e_dense) < 1e-11
+
+
+@pytest.mark.slow
+def test_forward_matches_dense_16_qubits(orc):
+    h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 14)
+    d, a, _, _ = orc.apply_ucc(16, [hf], [1.0], exc, theta, 0.0)
+    jw = DenseJW(16)
+    psi = jw.apply_factors(jw.basis([hf]), exc, theta)
+    dense = np.zeros(1 << 16)
+    dense[d.astype(np.int64)] = a
+    assert np.max(np.abs(dense - psi)) < 1e-12
+    assert abs(orc.energy(8, h1, h2, d, a, mode=1) - jw.energy_epq(h1, h2, psi)) < 1e-10
+
+
+def test_theta_half_pi_is_signed_swap(orc):
+    nq = 8
+    hf = synth.hf_det(2)
+    jw = DenseJW(nq)
+    for row in [(0, 2, 4, 6), (1, 2, 5, 6), (0, -1, 6, -1), (0, 3, 4, 7)]:
+        s, P = orc.tau(row, hf)
+        assert s != 0
+        d, a, _, _ = orc.apply_ucc(nq, [hf], [1.0], np.array([row], np.int8), [math.pi / 2], 0.0)
+        got = dict(zip(d.tolist(), a.tolist()))
+        assert abs(got[P] - s) < 1e-15 and abs(got[hf]) < 1e-15
+        psi = jw.apply_factors(jw.basis([hf]), [row], [math.pi / 2])
+        assert abs(psi[P] - s) < 1e-12
+
+
+def test_norm_preservation_and_reversibility(orc):
+    h1, h2, exc, theta, hf = small_problem(6, 3, 0.3, 21)
+    d, a, _, _ = orc.apply_ucc(12, [hf], [1.0], exc, theta, 0.0)
+    assert abs(np.sum(a * a) - 1.0) < 1e-13
+    d0, a0 = orc.apply_inverse(12, d, a, exc, theta)
+    back = dict(zip(d0.tolist(), a0.tolist()))
+    assert abs(back[hf] - 1.0) < 1e-12
+    assert max(abs(v) for k, v in back.items() if k != hf) < 1e-12
+
+
+# ---------------------------------------------------------------- energy
+
+
+def hf_energy_closed_form(h1, h2, o):
+    e = 2.0 * sum(h1[i, i] for i in range(o))
+    e += sum(2.0 * h2[i, i, j, j] - h2[i, j, j, i] for i in range(o) for j in range(o))
+    return e
+
+
+@pytest.mark.parametrize("n_orb,n_occ", [(4, 2), (6, 3), (10, 5)])
+def test_hf_energy_closed_form(orc, n_orb, n_occ):
+    h1, h2 = synth.make_hamiltonian(n_orb, 77 + n_orb)
+    hf = synth.hf_det(n_occ)
+    ref = hf_energy_closed_form(h1, h2, n_occ)
+    assert abs(orc.energy(n_orb, h1, h2, [hf], [1.0], mode=1) - ref) < 1e-12
+    assert abs(orc.energy(n_orb, h1, h2, [hf], [1.0], mode=0) - ref) < 1e-12
+
+
+def test_slater_condon_vs_literal_random_states(orc):
+    rng = np.random.default_rng(5)
+    n_orb, n_occ = 5, 2
+    h1, h2 = synth.make_hamiltonian(n_orb, 99)
+    jw = DenseJW(10)
+    sec = jw.sector(n_occ, n_occ)
+    for trial in range(3):
+        dets = rng.choice(sec, size=40, replace=False).astype(np.uint64)
+        amps = rng.normal(size=40)
+        e0 = orc.energy(n_orb, h1, h2, dets, amps, mode=0)
+        e1 = orc.energy(n_orb, h1, h2, dets, amps, mode=1)
+        assert abs(e0 - e1) < 1e-12
+        v0 = orc.h_apply(n_orb, h1, h2, dets, amps, mode=0)
+        v1 = orc.h_apply(n_orb, h1, h2, dets, amps, mode=1)
+        assert np.max(np.abs(v0 - v1)) < 1e-12
+        # and vs the dense literal Hamiltonian restricted to the support
+        H = jw.h_literal(h1, h2)
+        full = np.zeros(1 << 10)
+        full[dets.astype(np.int64)] = amps
+        hv = H @ full
+        assert np.max(np.abs(hv[dets.astype(np.int64)] - v0)) < 1e-12
+
+
+@pytest.mark.parametrize("thr", [0.0, 1e-3, 1e-2])
+def test_variational_bound(orc, thr):
+    n_orb, n_occ = 5, 2
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, 0.4, 31)
+    jw = DenseJW(10)
+    efci = jw.fci(jw.h_literal(h1, h2), n_occ, n_occ)
+    for b in range(3):
+        th = synth.make_theta(exc.shape[0], 0.4, 400 + b)
+        e = orc.energy_theta(10, [hf], [1.0], exc, th, thr, h1, h2)
+        assert e >= efci - 1e-12
+
+
+# ---------------------------------------------------------------- gradient
+
+
+def test_gradient_theta0_closed_form(orc):
+    n_orb, n_occ = 5, 2
+    h1, h2, exc, _, hf = small_problem(n_orb, n_occ, 0.1, 41)
+    M = exc.shape[0]
+    E, g, _ = orc.energy_and_grad(10, [hf], [1.0], exc, np.zeros(M), 0.0, h1, h2)
+    assert abs(E - hf_energy_closed_form(h1, h2, n_occ)) < 1e-12
+    occ = list(range(2 * n_occ))
+    for k, (i, j, a, b) in enumerate(exc.tolist()):
+        if j < 0:
+            f = h1[i >> 1, a >> 1] + sum(synth._antisym(h2, i, kk, a, kk) for kk in occ)
+            ref = 2.0 * f
+        else:
+            ref = 2.0 * synth._antisym(h2, i, j, a, b)
+        assert abs(g[k] - ref) < 1e-12, (k, g[k], ref)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_gradient_vs_central_fd_threshold0(orc, mode):
+    n_orb, n_occ = 5, 2
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, 0.3, 51)
+    E, g, _ = orc.energy_and_grad(10, [hf], [1.0], exc, theta, 0.0, h1, h2, mode=mode)
+    idx = synth.fd_subset(exc.shape[0], 24, 3051)
+    fd = orc.fd_grad(10, [hf], [1.0], exc, theta, 0.0, h1, h2, idx, h=1e-5, mode=mode)
+    assert np.max(np.abs(fd - g[idx])) < 2e-9
+
+
+def test_gradient_vs_fd_with_truncation(orc):
+    """Pruned instance: FD with a step far smaller than any amplitude's
+    distance to the cut equals the frozen-support gradient."""
+    n_orb, n_occ = 5, 2
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, 0.3, 61)
+    thr = 2e-3
+    E, g, nc = orc.energy_and_grad(10, [hf], [1.0], exc, theta, thr, h1, h2)
+    assert nc == 0  # no amplitude within 1e-3*thr of the cut at any step
+    d0, _, _, _ = orc.apply_ucc(10, [hf], [1.0], exc, theta, thr)
+    idx = synth.fd_subset(exc.shape[0], 20, 3061)
+    h = 1e-7
+    for p in idx:
+        for sgn in (1, -1):
+            t = theta.copy()
+            t[p] += sgn * h
+            d1, _, _, _ = orc.apply_ucc(10, [hf], [1.0], exc, t, thr)
+            assert np.array_equal(d0, d1)  # same truncation decisions at theta +- h
+    fd = orc.fd_grad(10, [hf], [1.0], exc, theta, thr, h1, h2, idx, h=h)
+    assert np.max(np.abs(fd - g[idx])) < 5e-7
+    # the truncated gradient differs from the untruncated one (pruning matters)
+    _, g0, _ = orc.energy_and_grad(10, [hf], [1.0], exc, theta, 0.0, h1, h2)
+    assert np.max(np.abs(g0 - g)) > 1e-6
+
+
+# ---------------------------------------------------------------- truncation semantics
+
+
+def test_truncation_semantics(orc):
+    n_orb, n_occ = 5, 2
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, 0.3, 71)
+    thr = 5e-3
+    d, a, _, _ = orc.apply_ucc(10, [hf], [1.0], exc, theta, thr)
+    assert np.all(np.abs(a) >= thr)
+    assert abs(np.sum(a * a) - 1.0) < 1e-13
+    assert np.all(np.diff(d.astype(np.float64)) > 0)
+    d0, a0, _, _ = orc.apply_ucc(10, [hf], [1.0], exc, theta, 0.0)
+    assert len(d) < len(d0)
+    # threshold 0 keeps exact zeros produced by theta = 0
+    dz, az, _, _ = orc.apply_ucc(10, [hf], [1.0], exc, np.zeros(exc.shape[0]), 0.0)
+    # (zero-amplitude entries also spawn zero partners in later factors)
+    assert len(dz) >= 1 + exc.shape[0] and np.count_nonzero(az) == 1
+
+
+def test_error_classification(orc):
+    hf = synth.hf_det(2)
+    ok = np.array([[0, 2, 4, 6]], np.int8)
+    with pytest.raises(orc.OracleError) as e:
+        orc.apply_ucc(8, [hf], [1.0], np.array([[0, 2, 2, 6]], np.int8), [0.1])
+    assert e.value.code == orc.EINVAL
+    for bad in ([[0, 2, 4, 8]], [[2, 0, 4, 6]], [[0, 2, 6, 4]], [[0, 0, 4, 6]], [[0, -1, 4, 6]]):
+        with pytest.raises(orc.OracleError) as e:
+            orc.apply_ucc(8, [hf], [1.0], np.array(bad, np.int8), [0.1])
+        assert e.value.code == orc.EINVAL
+    with pytest.raises(orc.OracleError) as e:
+        orc.apply_ucc(8, [hf], [1.0], ok, [float("nan")])
+    assert e.value.code == orc.EINVAL
+    with pytest.raises(orc.OracleError) as e:
+        orc.apply_ucc(8, [hf], [1.0], ok, [0.1], thr=-1.0)
+    assert e.value.code == orc.EINVAL
+    with pytest.raises(orc.OracleError) as e:
+        orc.apply_ucc(8, [hf], [1.0], ok, [0.1], thr=2.0)
+    assert e.value.code == orc.EEMPTY
