@@ -1,0 +1,179 @@
+/*
+ * swc.h -- C ABI of the MI355X sparse wavefunction circuit (swc) library.
+ *
+ * The library simulates the factorized unitary coupled cluster circuit of
+ * Mullinax & Tubman (arXiv:2301.05726) on one AMD Instinct MI355X (gfx950):
+ *
+ *   |Psi> = U_M ... U_2 U_1 |Psi_0>,   U_k = exp(theta_k (tau_k - tau_k^dag))
+ *                                          (Results section, Eqs. 1-5)
+ *
+ * on a sparse state (determinant bitstring -> amplitude), discarding small
+ * amplitudes after every factor (Methods section), and evaluates the energy
+ * E = <Psi|H|Psi> / <Psi|Psi> of a second-quantized molecular Hamiltonian
+ * and its exact gradient dE/dtheta by an adjoint (reverse) sweep.
+ *
+ * Conventions (fixed by this library; the paper states none):
+ *  - spin-orbital q = 2p + s (p spatial orbital, s = 0 alpha, 1 beta);
+ *    bit q of a determinant is set when q is occupied; n_qubits <= 64 (the
+ *    paper's 32-spatial-orbital cap, Methods section);
+ *  - |D> = a+_{q1} ... a+_{qN}|vac> with q1 < ... < qN (Jordan-Wigner order);
+ *  - excitation row {i, j, a, b}: double tau = a+_a a+_b a_j a_i with i<j,
+ *    a<b and {i,j}, {a,b} disjoint; single tau = a+_a a_i, encoded j=b=-1;
+ *  - H = sum h_pq a+_{ps} a_{qs} + 1/2 sum (pq|rs) a+_{ps} a+_{rt} a_{st} a_{qs}
+ *    with real h1[p][q] (n x n, row major) and chemist-notation
+ *    h2[p][q][r][s] (n^4, row major), n = n_qubits / 2, no nuclear term;
+ *  - truncation: after every factor, every determinant with
+ *    |amplitude| < threshold (strict, on the unit-norm state) is removed
+ *    and the state is renormalised if anything was removed; threshold 0
+ *    keeps everything (the circuit is then exactly unitary);
+ *  - gradient: exact derivative with the truncation decisions of the
+ *    forward sweep held fixed (equal to the true gradient at threshold 0).
+ *
+ * Precision: SWC_FP64 stores amplitudes in double; SWC_FP32 stores
+ * amplitudes and the adjoint vector in float and rotates in float.  In both
+ * modes the renormalisation, energy, sigma = H psi and gradient reductions
+ * are done in double; all reductions are exact fixed-point sums, so every
+ * result is bit-reproducible run to run.
+ *
+ * Memory and ownership: the caller allocates one device workspace of
+ * swc_workspace_bytes(...) bytes (e.g. a torch tensor) and passes it to
+ * swc_create; the library allocates no device memory itself, keeps that
+ * pointer until swc_destroy, and never frees it.  Every other pointer is
+ * used only during the call.  Pointers marked "device" must be device
+ * memory of the current HIP device; "host" pointers are ordinary host
+ * memory.  All device work is ordered on the stream given to swc_create;
+ * calls return after their results are complete (they synchronize that
+ * stream once at the end to read status flags).
+ *
+ * Errors: every int-returning call returns SWC_OK (0) or a negative code;
+ * nothing throws across the ABI.  After SWC_ECAPACITY, SWC_EEMPTY or
+ * SWC_EDEVICE the state held by the context is undefined until the next
+ * swc_build_state; the context can always be destroyed.
+ */
+#ifndef SWC_H
+#define SWC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SWC_OK = 0,
+  SWC_EINVAL = -1,    /* bad argument: sizes, indices, overlapping excitation
+                         index sets, non-finite theta, threshold < 0, bad
+                         determinant, workspace too small, batch index */
+  SWC_ECAPACITY = -2, /* hash table or truncation log full */
+  SWC_EEMPTY = -3,    /* truncation removed every determinant */
+  SWC_EDEVICE = -4,   /* a HIP runtime error (text via swc_last_error) */
+  SWC_ESTATE = -5     /* call order: no state built yet */
+};
+
+enum { SWC_FP64 = 0, SWC_FP32 = 1 };
+
+typedef struct swc_ctx swc_ctx;
+
+/* One UCC factor's excitation (Eq. 2): {i, j, a, b}, single: j = b = -1. */
+typedef struct {
+  int8_t i, j, a, b;
+} swc_exc;
+
+/* Counters of the last sweep(s), summed over the batch. */
+typedef struct {
+  int64_t n_live;        /* live determinants now (batch member 0) */
+  int64_t det_updates;   /* sum over factors of live determinants visited (last forward sweep) */
+  int64_t pair_updates;  /* rotated determinant pairs (last forward sweep) */
+  int64_t inserts;       /* determinants created (last forward sweep) */
+  int64_t pruned;        /* amplitudes removed by truncation (last forward sweep) */
+  int64_t log_records;   /* truncation-log records of the last gradient sweep */
+  int64_t table_slots;   /* hash slots per batch member */
+  int64_t slots_used;    /* occupied slots incl. tombstones (batch member 0) */
+  double fwd_ms;         /* device time of the last forward sweep */
+  double energy_ms;      /* device time of the last energy evaluation */
+  double rev_ms;         /* device time of the last reverse (adjoint) sweep */
+} swc_stats;
+
+/*
+ * Bytes of device workspace needed for a context with `capacity` hash slots
+ * per state (a power of two, >= 64; live determinants must stay below
+ * 0.9 * capacity), `batch` independent states, circuits of up to
+ * `max_factors` factors, and `log_capacity` truncation-log records per state
+ * (0 selects capacity / 4).  Returns 0 for invalid arguments.
+ */
+size_t swc_workspace_bytes(int n_qubits, uint64_t capacity, int prec, int batch, int64_t max_factors,
+                           uint64_t log_capacity);
+
+/*
+ * Create a context.  n_alpha/n_beta electrons define the default reference
+ * (Hartree-Fock determinant, bits 2p and 2p+1 occupied for p < n_alpha and
+ * p < n_beta).  `workspace` (device, >= swc_workspace_bytes) stays owned by
+ * the caller and must outlive the context; `stream` is a hipStream_t (NULL
+ * for the default stream).  On success *out receives the context.
+ */
+int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t capacity, int prec, int batch,
+               int64_t max_factors, uint64_t log_capacity, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Set the initial state |Psi_0> (Eq. 1) of every batch member: `n` host
+ * determinants and amplitudes (host arrays; duplicates or bits at or above
+ * n_qubits -> SWC_EINVAL).  The state is normalised.  n = 0 selects the
+ * Hartree-Fock reference.  Resets the current state to |Psi_0>.
+ */
+int swc_build_state(swc_ctx* ctx, const uint64_t* dets, const double* amps, int64_t n);
+
+/*
+ * Apply U_M ... U_1 (Eq. 3; factor k in the closed form of Eqs. 4-5) to the
+ * current state of every batch member, truncating after each factor.
+ * theta: device double [batch][M]; exc: host swc_exc[M]; 0 <= M <= max_factors.
+ */
+int swc_apply_ucc(swc_ctx* ctx, const double* theta, const swc_exc* exc, int64_t M, double threshold);
+
+/*
+ * E[b] = <psi_b|H|psi_b> / <psi_b|psi_b> of the current states.
+ * h1: device double [n][n]; h2: device double [n][n][n][n]; E: device double [batch].
+ */
+int swc_energy(swc_ctx* ctx, const double* h1, const double* h2, double* E);
+
+/*
+ * E(theta) and dE/dtheta for every batch member, starting from |Psi_0>
+ * (forward sweep with truncation, energy, adjoint sweep).  Arguments as in
+ * swc_apply_ucc and swc_energy; grad: device double [batch][M].  On return
+ * the current state is |Psi_0> again.
+ */
+int swc_energy_and_grad(swc_ctx* ctx, const double* theta, const swc_exc* exc, int64_t M, double threshold,
+                        const double* h1, const double* h2, double* E, double* grad);
+
+/*
+ * Copy the current state of batch member b to host arrays sorted by
+ * determinant (amplitudes normalised, in double).  *n_out receives the
+ * number of determinants; SWC_ECAPACITY if it exceeds `cap` (nothing copied).
+ */
+int swc_get_state(swc_ctx* ctx, int b, uint64_t* dets, double* amps, int64_t cap, int64_t* n_out);
+
+int swc_get_stats(swc_ctx* ctx, swc_stats* out);
+
+/* Static text for an error code; swc_last_error gives the last HIP/argument message. */
+const char* swc_strerror(int code);
+const char* swc_last_error(void);
+
+void swc_destroy(swc_ctx* ctx);
+
+/*
+ * Host-only helpers (no device work; usable on machines without a GPU).
+ * swc_validate_excitations: SWC_OK or SWC_EINVAL for an excitation list.
+ * swc_factor_masks: per factor k writes masks[3k..3k+2] =
+ *   {occupied-side mask, virtual-side mask, sign mask}; a determinant D is
+ *   the lower member of a pair when (D & occ) == occ and (D & vir) == 0,
+ *   the upper member when the roles swap, and the fermionic sign of
+ *   tau|lower> is (-1)^popcount(D & sign) for either member.
+ */
+int swc_validate_excitations(int n_qubits, const swc_exc* exc, int64_t M);
+int swc_factor_masks(int n_qubits, const swc_exc* exc, int64_t M, uint64_t* masks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWC_H */

@@ -44,6 +44,8 @@ def lib():
         L.orc_energy_theta.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, D, P, P, ctypes.c_int, P]
         L.orc_energy_and_grad.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, D, P, P, ctypes.c_int, P, P, P]
         L.orc_fd_grad.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, D, P, P, ctypes.c_int, D, P, I64, P]
+        L.orc_set_nearcut_window.argtypes = [D]
+        L.orc_set_nearcut_window.restype = None
         L.orc_apply_inverse.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, P, P, I64, P]
         _lib = L
     return _lib
@@ -68,6 +70,11 @@ def _init(dets0, amps0):
     d = np.ascontiguousarray(np.atleast_1d(np.asarray(dets0, dtype=np.uint64)))
     a = np.ascontiguousarray(np.atleast_1d(np.asarray(amps0, dtype=np.float64)))
     return d, a
+
+
+def set_nearcut_window(rel: float):
+    """Relative width of the near-cut window (default 1e-3)."""
+    lib().orc_set_nearcut_window(float(rel))
 
 
 def tau(exc4, D):

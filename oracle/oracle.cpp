@@ -44,6 +44,11 @@ constexpr int EEMPTY_ = -3;
 
 using State = std::map<uint64_t, double>;
 
+// Relative half-width of the "near the cut" window: an amplitude with
+// ||c| - thr| <= window * thr after some factor is reported, because a
+// different rounding order could flip its truncation decision.
+double g_nearcut_window = 1e-3;
+
 // ---------------------------------------------------------------------------
 // single fermionic operators (Jordan-Wigner sign by explicit counting)
 // ---------------------------------------------------------------------------
@@ -175,7 +180,7 @@ int prune_renorm(State& phi, double thr, double* nu, int64_t* nearcut) {
   *nu = 1.0;
   if (thr > 0.0 && nearcut) {
     for (const auto& kv : phi)
-      if (std::fabs(std::fabs(kv.second) - thr) <= 1e-3 * thr) ++*nearcut;
+      if (std::fabs(std::fabs(kv.second) - thr) <= g_nearcut_window * thr) ++*nearcut;
   }
   int64_t removed = 0;
   for (auto it = phi.begin(); it != phi.end();) {
@@ -390,6 +395,8 @@ int write_state(const State& psi, uint64_t* dets, double* amps, int64_t cap, int
 }  // namespace
 
 extern "C" {
+
+void orc_set_nearcut_window(double rel) { g_nearcut_window = rel; }
 
 // tau|D> for one excitation row (i, j, a, b): sign in {-1, 0, +1}.
 int orc_tau(const int8_t* exc4, uint64_t D, uint64_t* out) {

@@ -1,0 +1,610 @@
+// Host side of the C ABI declared in include/swc.h: argument checks,
+// workspace carving, and the orchestration of the forward sweep, the energy
+// and the adjoint sweep on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <unordered_set>
+#include <utility>
+#include <vector>
+
+#include "swc.h"
+#include "swc_internal.h"
+
+using namespace swc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define SWC_HIP(call)                                                                                    \
+  do {                                                                                                   \
+    hipError_t e_ = (call);                                                                              \
+    if (e_ != hipSuccess) return fail(SWC_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Byte offsets of every workspace region.
+struct Layout {
+  size_t keys, amp, meta, born, lam;
+  size_t lslot, lmeta, lborn, lamp;
+  size_t scale, pw, pcnt, gacc, logn, logoff;
+  size_t ckey, camp, cslot, csig;
+  size_t cnt, fac, trig, init_d, init_a;
+  size_t total;
+};
+
+bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
+  Layout l{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const size_t BH = static_cast<size_t>(B) * H;
+  const size_t BL = static_cast<size_t>(B) * L;
+  const size_t BS = static_cast<size_t>(B) * static_cast<size_t>(Mmax + 1);
+  l.keys = take(BH * 8);
+  l.amp = take(BH * tsz);
+  l.meta = take(BH * 4);
+  l.born = take(BH * 4);
+  l.lam = take(BH * tsz);
+  l.lslot = take(BL * 4);
+  l.lmeta = take(BL * 4);
+  l.lborn = take(BL * 4);
+  l.lamp = take(BL * tsz);
+  l.scale = take(BS * 8);
+  l.pw = take(BS * SH * sizeof(Fx));
+  l.pcnt = take(BS * SH * 4);
+  l.gacc = take(BS * SH * sizeof(Fx));
+  l.logn = take(BS * 4);
+  l.logoff = take(BS * 4);
+  l.ckey = take(BH * 8);
+  l.camp = take(BH * 8);
+  l.cslot = take(BH * 4);
+  l.csig = take(BH * sizeof(Fx));
+  l.cnt = take(static_cast<size_t>(B) * sizeof(Counters));
+  l.fac = take(static_cast<size_t>(Mmax + 1) * sizeof(FacMask));
+  l.trig = take(static_cast<size_t>(B) * static_cast<size_t>(Mmax + 1) * sizeof(Trig));
+  l.init_d = take(H / 2 * 8);
+  l.init_a = take(H / 2 * 8);
+  l.total = off;
+  return l;
+}
+
+uint64_t btw(int lo, int hi) {  // bits strictly between lo and hi (lo < hi)
+  uint64_t upto_hi = (hi >= 64) ? ~0ull : ((1ull << hi) - 1ull);
+  uint64_t thru_lo = (lo >= 63) ? ~0ull : ((2ull << lo) - 1ull);
+  return upto_hi & ~thru_lo;
+}
+
+int check_exc(int nq, const swc_exc* exc, int64_t M) {
+  if (M < 0) return fail(SWC_EINVAL, "negative factor count");
+  if (M > 0 && !exc) return fail(SWC_EINVAL, "null excitation list");
+  for (int64_t k = 0; k < M; ++k) {
+    const swc_exc& e = exc[k];
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "invalid excitation %lld = (%d,%d,%d,%d)", static_cast<long long>(k), e.i, e.j,
+                  e.a, e.b);
+    if (e.j == -1 && e.b == -1) {
+      if (e.i < 0 || e.a < 0 || e.i >= nq || e.a >= nq || e.i == e.a) return fail(SWC_EINVAL, buf);
+      continue;
+    }
+    if (e.i < 0 || e.j < 0 || e.a < 0 || e.b < 0) return fail(SWC_EINVAL, buf);
+    if (e.i >= nq || e.j >= nq || e.a >= nq || e.b >= nq) return fail(SWC_EINVAL, buf);
+    if (!(e.i < e.j) || !(e.a < e.b)) return fail(SWC_EINVAL, buf);
+    if (e.i == e.a || e.i == e.b || e.j == e.a || e.j == e.b) return fail(SWC_EINVAL, buf);
+  }
+  return SWC_OK;
+}
+
+// Occupied-side, virtual-side and sign masks of one factor.  Sign rule: for
+// tau = a+_a a+_b a_j a_i on the lower determinant L the Jordan-Wigner phase
+// is the parity of the occupied orbitals strictly between i and j plus those
+// strictly between a and b after i, j are emptied; bits of the four moved
+// orbitals are removed so the same mask serves the upper member.  A single
+// a+_a a_i counts the occupied orbitals strictly between i and a.
+FacMask factor_mask(const swc_exc& e) {
+  FacMask f;
+  if (e.j == -1 && e.b == -1) {
+    f.occ = 1ull << e.i;
+    f.vir = 1ull << e.a;
+    const int lo = std::min<int>(e.i, e.a), hi = std::max<int>(e.i, e.a);
+    f.sgn = btw(lo, hi) & ~(f.occ | f.vir);
+  } else {
+    f.occ = (1ull << e.i) | (1ull << e.j);
+    f.vir = (1ull << e.a) | (1ull << e.b);
+    f.sgn = (btw(e.i, e.j) ^ (btw(e.a, e.b) & ~f.occ)) & ~(f.occ | f.vir);
+  }
+  return f;
+}
+
+}  // namespace
+
+struct swc_ctx {
+  int nq = 0, na = 0, nb = 0, prec = 0, B = 1;
+  uint64_t H = 0, L = 0;
+  int64_t Mmax = 0;
+  hipStream_t st = nullptr;
+  char* ws = nullptr;
+  Layout lay{};
+  Tab tab{};
+  LogArr lg{};
+  StepArr sa{};
+  Compact cp{};
+  Counters* cnt = nullptr;
+  FacMask* fac = nullptr;
+  Trig* trig = nullptr;
+  uint64_t* init_d = nullptr;
+  double* init_a = nullptr;
+  std::vector<uint64_t> h_init_d;
+  std::vector<double> h_init_a;
+  double S0 = 1.0;
+  bool built = false;
+  std::vector<swc_exc> exc_cache;
+  hipEvent_t ev[6] = {};
+  double fwd_ms = 0, energy_ms = 0, rev_ms = 0;
+  int64_t log_records = 0;
+  int grid = 1;
+  std::vector<Counters> hcnt;
+};
+
+namespace {
+
+template <class F>
+int dispatch(swc_ctx* c, F&& f) {
+  if (c->prec == SWC_FP32) return f(static_cast<float*>(nullptr));
+  return f(static_cast<double*>(nullptr));
+}
+
+int read_counters(swc_ctx* c) {
+  SWC_HIP(hipMemcpyAsync(c->hcnt.data(), c->cnt, sizeof(Counters) * c->B, hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipStreamSynchronize(c->st));
+  return SWC_OK;
+}
+
+int upload_masks(swc_ctx* c, const swc_exc* exc, int64_t M) {
+  if (M == 0) return SWC_OK;
+  if (static_cast<int64_t>(c->exc_cache.size()) == M &&
+      std::memcmp(c->exc_cache.data(), exc, sizeof(swc_exc) * M) == 0)
+    return SWC_OK;
+  std::vector<FacMask> f(static_cast<size_t>(M));
+  for (int64_t k = 0; k < M; ++k) f[k] = factor_mask(exc[k]);
+  SWC_HIP(hipMemcpyAsync(c->fac, f.data(), sizeof(FacMask) * M, hipMemcpyHostToDevice, c->st));
+  SWC_HIP(hipStreamSynchronize(c->st));
+  c->exc_cache.assign(exc, exc + M);
+  return SWC_OK;
+}
+
+// Reset every batch member to |Psi_0>.
+int reset_state(swc_ctx* c) {
+  launch_fill(c->tab, c->B, c->st);
+  for (int b = 0; b < c->B; ++b) {
+    Counters z{};
+    z.S = c->S0;
+    c->hcnt[b] = z;
+  }
+  SWC_HIP(hipMemcpyAsync(c->cnt, c->hcnt.data(), sizeof(Counters) * c->B, hipMemcpyHostToDevice, c->st));
+  const int64_t n = static_cast<int64_t>(c->h_init_d.size());
+  SWC_HIP(hipMemcpyAsync(c->init_d, c->h_init_d.data(), 8 * n, hipMemcpyHostToDevice, c->st));
+  SWC_HIP(hipMemcpyAsync(c->init_a, c->h_init_a.data(), 8 * n, hipMemcpyHostToDevice, c->st));
+  int r = dispatch(c, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    launch_insert_init<T>(c->tab, c->cnt, c->init_d, c->init_a, n, c->B, c->st);
+    return SWC_OK;
+  });
+  if (r) return r;
+  SWC_HIP(hipGetLastError());
+  return SWC_OK;
+}
+
+int check_theta(swc_ctx* c, const double* theta, int64_t M) {
+  if (M == 0) return SWC_OK;
+  if (!theta) return fail(SWC_EINVAL, "null theta");
+  launch_trig(theta, c->trig, M, c->Mmax + 1, c->B, c->cnt, c->st);
+  SWC_HIP(hipGetLastError());
+  int r = read_counters(c);
+  if (r) return r;
+  if (c->hcnt[0].flags & F_BAD_THETA) {
+    unsigned int z = c->hcnt[0].flags & ~F_BAD_THETA;
+    SWC_HIP(hipMemcpyAsync(&c->cnt[0].flags, &z, sizeof z, hipMemcpyHostToDevice, c->st));
+    SWC_HIP(hipStreamSynchronize(c->st));
+    return fail(SWC_EINVAL, "theta contains a non-finite value");
+  }
+  return SWC_OK;
+}
+
+int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
+  launch_sweep_begin(c->tab, c->sa, c->cnt, M, c->B, c->st);
+  SWC_HIP(hipEventRecord(c->ev[0], c->st));
+  int r = dispatch(c, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    for (int64_t k = 1; k <= M; ++k)
+      launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
+                    log_on, c->B, c->grid, c->st);
+    return SWC_OK;
+  });
+  if (r) return r;
+  launch_sweep_end(c->sa, c->cnt, M, c->B, c->st);
+  SWC_HIP(hipEventRecord(c->ev[1], c->st));
+  SWC_HIP(hipGetLastError());
+  return SWC_OK;
+}
+
+int sweep_status(swc_ctx* c) {
+  for (int b = 0; b < c->B; ++b) {
+    const Counters& k = c->hcnt[b];
+    if (k.flags & F_TABLE_FULL) return fail(SWC_ECAPACITY, "hash table full");
+    if (k.occ > c->H - c->H / 10) return fail(SWC_ECAPACITY, "hash table above 90% occupancy");
+    if (k.live == 0) return fail(SWC_EEMPTY, "truncation removed every determinant");
+    if (k.flags & F_INCONSISTENT) return fail(SWC_EDEVICE, "inconsistent pair state in the reverse sweep");
+  }
+  return SWC_OK;
+}
+
+// compact + sigma + E (+ lambda); leaves counters read back
+int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool want_lambda) {
+  if (!h1 || !h2) return fail(SWC_EINVAL, "null integrals");
+  launch_energy_begin(c->cnt, c->B, c->st);
+  SWC_HIP(hipEventRecord(c->ev[2], c->st));
+  int r = dispatch(c, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    launch_compact<T>(c->tab, c->cp, c->cnt, c->B, c->grid, c->st);
+    return SWC_OK;
+  });
+  if (r) return r;
+  SWC_HIP(hipGetLastError());
+  if ((r = read_counters(c))) return r;
+  int64_t nmax = 0;
+  for (int b = 0; b < c->B; ++b) nmax = std::max<int64_t>(nmax, static_cast<int64_t>(c->hcnt[b].ncompact));
+  if (nmax == 0) return fail(SWC_EEMPTY, "empty state");
+  const int n = c->nq / 2;
+  launch_sigma(c->cp, c->cnt, c->H, h1, h2, n, nmax, c->B, c->st);
+  launch_energy_reduce(c->cp, c->cnt, c->H, h1, h2, n, nmax, c->B, c->st);
+  launch_energy_final(c->cnt, E, c->B, c->st);
+  if (want_lambda) {
+    r = dispatch(c, [&](auto* tp) {
+      using T = std::remove_pointer_t<decltype(tp)>;
+      launch_lambda<T>(c->tab, c->cp, c->cnt, nmax, c->B, c->st);
+      return SWC_OK;
+    });
+    if (r) return r;
+  }
+  SWC_HIP(hipEventRecord(c->ev[3], c->st));
+  SWC_HIP(hipGetLastError());
+  return read_counters(c);
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t swc_workspace_bytes(int n_qubits, uint64_t capacity, int prec, int batch, int64_t max_factors,
+                           uint64_t log_capacity) {
+  if (n_qubits < 2 || n_qubits > 64 || !pow2(capacity) || capacity < 64 || capacity > (1ull << 31)) return 0;
+  if ((prec != SWC_FP32 && prec != SWC_FP64) || batch < 1 || batch > 1024 || max_factors < 0 ||
+      max_factors > (1ll << 30))
+    return 0;
+  const uint64_t L = log_capacity ? log_capacity : capacity / 4;
+  if (L > (1ull << 32)) return 0;
+  return make_layout(capacity, prec == SWC_FP32 ? 4 : 8, batch, max_factors, L).total;
+}
+
+int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t capacity, int prec, int batch,
+               int64_t max_factors, uint64_t log_capacity, void* workspace, size_t ws_bytes, void* stream) {
+  if (!out) return fail(SWC_EINVAL, "null output pointer");
+  *out = nullptr;
+  const size_t need = swc_workspace_bytes(n_qubits, capacity, prec, batch, max_factors, log_capacity);
+  if (!need) return fail(SWC_EINVAL, "invalid sizes");
+  if (n_alpha < 0 || n_beta < 0 || n_alpha > n_qubits / 2 || n_beta > n_qubits / 2 ||
+      n_alpha + n_beta >= n_qubits || n_alpha + n_beta == 0)
+    return fail(SWC_EINVAL, "invalid electron counts");
+  if (!workspace || ws_bytes < need) return fail(SWC_EINVAL, "workspace missing or too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return fail(SWC_EINVAL, "workspace not 256-byte aligned");
+  swc_ctx* c = new swc_ctx();
+  c->nq = n_qubits;
+  c->na = n_alpha;
+  c->nb = n_beta;
+  c->prec = prec;
+  c->B = batch;
+  c->H = capacity;
+  c->Mmax = max_factors;
+  c->L = log_capacity ? log_capacity : capacity / 4;
+  c->st = static_cast<hipStream_t>(stream);
+  c->ws = static_cast<char*>(workspace);
+  const int tsz = prec == SWC_FP32 ? 4 : 8;
+  c->lay = make_layout(c->H, tsz, c->B, c->Mmax, c->L);
+  const Layout& l = c->lay;
+  char* w = c->ws;
+  c->tab = Tab{reinterpret_cast<uint64_t*>(w + l.keys), w + l.amp, reinterpret_cast<uint32_t*>(w + l.meta),
+               reinterpret_cast<uint32_t*>(w + l.born), w + l.lam, c->H};
+  c->lg = LogArr{reinterpret_cast<uint32_t*>(w + l.lslot), reinterpret_cast<uint32_t*>(w + l.lmeta),
+                 reinterpret_cast<uint32_t*>(w + l.lborn), w + l.lamp, c->L};
+  c->sa = StepArr{reinterpret_cast<double*>(w + l.scale),   reinterpret_cast<Fx*>(w + l.pw),
+                  reinterpret_cast<uint32_t*>(w + l.pcnt),  reinterpret_cast<Fx*>(w + l.gacc),
+                  reinterpret_cast<uint32_t*>(w + l.logn),  reinterpret_cast<uint32_t*>(w + l.logoff),
+                  c->Mmax + 1};
+  c->cp = Compact{reinterpret_cast<uint64_t*>(w + l.ckey), reinterpret_cast<double*>(w + l.camp),
+                  reinterpret_cast<uint32_t*>(w + l.cslot), reinterpret_cast<Fx*>(w + l.csig)};
+  c->cnt = reinterpret_cast<Counters*>(w + l.cnt);
+  c->fac = reinterpret_cast<FacMask*>(w + l.fac);
+  c->trig = reinterpret_cast<Trig*>(w + l.trig);
+  c->init_d = reinterpret_cast<uint64_t*>(w + l.init_d);
+  c->init_a = reinterpret_cast<double*>(w + l.init_a);
+  c->hcnt.assign(static_cast<size_t>(batch), Counters{});
+  int g = grid_for(c->H, 256, 2048);
+  if (const char* e = std::getenv("SWC_GRID")) {
+    int v = std::atoi(e);
+    if (v > 0) g = std::min(v, grid_for(c->H, 256, 1 << 20));
+  }
+  c->grid = g;
+  for (auto& e : c->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      swc_destroy(c);
+      return fail(SWC_EDEVICE, "hipEventCreate failed");
+    }
+  }
+  if (hipMemsetAsync(c->cnt, 0, sizeof(Counters) * batch, c->st) != hipSuccess ||
+      hipStreamSynchronize(c->st) != hipSuccess) {
+    swc_destroy(c);
+    return fail(SWC_EDEVICE, "initialisation failed");
+  }
+  *out = c;
+  return SWC_OK;
+}
+
+int swc_build_state(swc_ctx* c, const uint64_t* dets, const double* amps, int64_t n) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  std::vector<uint64_t> d;
+  std::vector<double> a;
+  if (n == 0) {
+    uint64_t hf = 0;
+    for (int p = 0; p < c->na; ++p) hf |= 1ull << (2 * p);
+    for (int p = 0; p < c->nb; ++p) hf |= 1ull << (2 * p + 1);
+    d.push_back(hf);
+    a.push_back(1.0);
+  } else {
+    if (n < 0 || !dets || !amps) return fail(SWC_EINVAL, "invalid initial state arrays");
+    if (static_cast<uint64_t>(n) > c->H / 2) return fail(SWC_EINVAL, "initial state larger than half the table");
+    std::unordered_set<uint64_t> seen;
+    for (int64_t i = 0; i < n; ++i) {
+      if (dets[i] == EMPTY_KEY || (c->nq < 64 && (dets[i] >> c->nq)))
+        return fail(SWC_EINVAL, "determinant uses bits at or above n_qubits");
+      if (!std::isfinite(amps[i])) return fail(SWC_EINVAL, "non-finite amplitude");
+      if (!seen.insert(dets[i]).second) return fail(SWC_EINVAL, "duplicate determinant");
+    }
+    d.assign(dets, dets + n);
+    a.assign(amps, amps + n);
+  }
+  double n2 = 0.0;
+  for (double v : a) n2 += v * v;
+  if (!(n2 > 0.0)) return fail(SWC_EINVAL, "initial state has zero norm");
+  c->h_init_d = std::move(d);
+  c->h_init_a = std::move(a);
+  c->S0 = 1.0 / std::sqrt(n2);
+  int r = reset_state(c);
+  if (r) return r;
+  if ((r = read_counters(c))) return r;
+  for (int b = 0; b < c->B; ++b)
+    if (c->hcnt[b].flags & F_TABLE_FULL) return fail(SWC_ECAPACITY, "hash table full");
+  c->built = true;
+  return SWC_OK;
+}
+
+int swc_apply_ucc(swc_ctx* c, const double* theta, const swc_exc* exc, int64_t M, double threshold) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  if (!c->built) return fail(SWC_ESTATE, "no state built");
+  if (M < 0 || M > c->Mmax) return fail(SWC_EINVAL, "factor count above max_factors");
+  if (!(threshold >= 0.0) || !std::isfinite(threshold)) return fail(SWC_EINVAL, "threshold must be finite and >= 0");
+  int r = check_exc(c->nq, exc, M);
+  if (r) return r;
+  if ((r = upload_masks(c, exc, M))) return r;
+  if ((r = check_theta(c, theta, M))) return r;
+  if ((r = forward_sweep(c, M, threshold, 0))) return r;
+  if ((r = read_counters(c))) return r;
+  c->fwd_ms = elapsed(c->ev[0], c->ev[1]);
+  r = sweep_status(c);
+  if (r) c->built = false;
+  return r;
+}
+
+int swc_energy(swc_ctx* c, const double* h1, const double* h2, double* E) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  if (!c->built) return fail(SWC_ESTATE, "no state built");
+  if (!E) return fail(SWC_EINVAL, "null output");
+  int r = energy_impl(c, h1, h2, E, false);
+  if (r) return r;
+  c->energy_ms = elapsed(c->ev[2], c->ev[3]);
+  return SWC_OK;
+}
+
+int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int64_t M, double threshold,
+                        const double* h1, const double* h2, double* E, double* grad) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  if (!c->built) return fail(SWC_ESTATE, "no state built");
+  if (M < 0 || M > c->Mmax) return fail(SWC_EINVAL, "factor count above max_factors");
+  if (!(threshold >= 0.0) || !std::isfinite(threshold)) return fail(SWC_EINVAL, "threshold must be finite and >= 0");
+  if (!E || (M > 0 && !grad)) return fail(SWC_EINVAL, "null output");
+  int r = check_exc(c->nq, exc, M);
+  if (r) return r;
+  if ((r = upload_masks(c, exc, M))) return r;
+  if ((r = check_theta(c, theta, M))) return r;
+  if ((r = reset_state(c))) return r;
+  if ((r = forward_sweep(c, M, threshold, 1))) return r;
+  if ((r = read_counters(c))) return r;
+  if ((r = sweep_status(c))) {
+    reset_state(c);
+    return r;
+  }
+  for (int b = 0; b < c->B; ++b)
+    if (c->hcnt[b].flags & F_LOG_FULL) {
+      reset_state(c);
+      return fail(SWC_ECAPACITY, "truncation log full");
+    }
+  c->fwd_ms = elapsed(c->ev[0], c->ev[1]);
+  if ((r = energy_impl(c, h1, h2, E, true))) {
+    reset_state(c);
+    return r;
+  }
+  c->energy_ms = elapsed(c->ev[2], c->ev[3]);
+  // offsets of the per-step truncation-log records
+  const int64_t S = c->Mmax + 1;
+  std::vector<uint32_t> logn(static_cast<size_t>(c->B * S)), logoff(static_cast<size_t>(c->B * S), 0u);
+  SWC_HIP(hipMemcpyAsync(logn.data(), c->sa.logn, 4 * c->B * S, hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipStreamSynchronize(c->st));
+  std::vector<uint32_t> maxn(static_cast<size_t>(M + 1), 0u);
+  c->log_records = 0;
+  for (int b = 0; b < c->B; ++b) {
+    uint32_t off = 0;
+    for (int64_t k = 0; k <= M; ++k) {
+      logoff[b * S + k] = off;
+      off += logn[b * S + k];
+      maxn[k] = std::max(maxn[k], logn[b * S + k]);
+    }
+    c->log_records += off;
+  }
+  if (c->log_records) {
+    SWC_HIP(hipMemcpyAsync(c->sa.logoff, logoff.data(), 4 * c->B * S, hipMemcpyHostToDevice, c->st));
+  }
+  SWC_HIP(hipEventRecord(c->ev[4], c->st));
+  r = dispatch(c, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    for (int64_t k = M; k >= 1; --k) {
+      launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid, c->st);
+      if (maxn[k]) launch_log_restore<T>(c->tab, c->lg, c->sa, static_cast<int>(k), c->B, maxn[k], c->st);
+    }
+    return SWC_OK;
+  });
+  if (r) return r;
+  launch_grad_final(c->sa, c->cnt, grad, M, c->B, c->st);
+  SWC_HIP(hipEventRecord(c->ev[5], c->st));
+  SWC_HIP(hipGetLastError());
+  if ((r = read_counters(c))) return r;
+  c->rev_ms = elapsed(c->ev[4], c->ev[5]);
+  for (int b = 0; b < c->B; ++b)
+    if (c->hcnt[b].flags & F_INCONSISTENT) {
+      reset_state(c);
+      return fail(SWC_EDEVICE, "inconsistent pair state in the reverse sweep");
+    }
+  if ((r = reset_state(c))) return r;
+  return read_counters(c);
+}
+
+int swc_get_state(swc_ctx* c, int b, uint64_t* dets, double* amps, int64_t cap, int64_t* n_out) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  if (!c->built) return fail(SWC_ESTATE, "no state built");
+  if (b < 0 || b >= c->B || !n_out) return fail(SWC_EINVAL, "bad batch index or output");
+  launch_energy_begin(c->cnt, c->B, c->st);
+  int r = dispatch(c, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    launch_compact<T>(c->tab, c->cp, c->cnt, c->B, c->grid, c->st);
+    return SWC_OK;
+  });
+  if (r) return r;
+  SWC_HIP(hipGetLastError());
+  if ((r = read_counters(c))) return r;
+  const int64_t n = static_cast<int64_t>(c->hcnt[b].ncompact);
+  *n_out = n;
+  if (n > cap) return fail(SWC_ECAPACITY, "output arrays too small");
+  std::vector<uint64_t> k(static_cast<size_t>(n));
+  std::vector<double> a(static_cast<size_t>(n));
+  SWC_HIP(hipMemcpyAsync(k.data(), c->cp.key + b * c->H, 8 * n, hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipMemcpyAsync(a.data(), c->cp.amp + b * c->H, 8 * n, hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipStreamSynchronize(c->st));
+  std::vector<int64_t> idx(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return k[x] < k[y]; });
+  double n2 = 0.0;
+  for (int64_t i = 0; i < n; ++i) n2 += a[idx[i]] * a[idx[i]];
+  const double inv = n2 > 0.0 ? 1.0 / std::sqrt(n2) : 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    dets[i] = k[idx[i]];
+    amps[i] = a[idx[i]] * inv;
+  }
+  return SWC_OK;
+}
+
+int swc_get_stats(swc_ctx* c, swc_stats* out) {
+  if (!c || !out) return fail(SWC_EINVAL, "null argument");
+  int r = read_counters(c);
+  if (r) return r;
+  swc_stats s{};
+  for (int b = 0; b < c->B; ++b) {
+    const Counters& k = c->hcnt[b];
+    s.det_updates += static_cast<int64_t>(k.du);
+    s.pair_updates += static_cast<int64_t>(k.pairs);
+    s.inserts += static_cast<int64_t>(k.inserts);
+    s.pruned += static_cast<int64_t>(k.pruned);
+  }
+  s.n_live = static_cast<int64_t>(c->hcnt[0].live);
+  s.slots_used = static_cast<int64_t>(c->hcnt[0].occ);
+  s.log_records = c->log_records;
+  s.table_slots = static_cast<int64_t>(c->H);
+  s.fwd_ms = c->fwd_ms;
+  s.energy_ms = c->energy_ms;
+  s.rev_ms = c->rev_ms;
+  *out = s;
+  return SWC_OK;
+}
+
+const char* swc_strerror(int code) {
+  switch (code) {
+    case SWC_OK: return "ok";
+    case SWC_EINVAL: return "invalid argument";
+    case SWC_ECAPACITY: return "capacity exceeded";
+    case SWC_EEMPTY: return "state became empty";
+    case SWC_EDEVICE: return "HIP device error";
+    case SWC_ESTATE: return "no state built";
+    default: return "unknown error";
+  }
+}
+
+const char* swc_last_error(void) { return g_err.c_str(); }
+
+void swc_destroy(swc_ctx* c) {
+  if (!c) return;
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int swc_validate_excitations(int n_qubits, const swc_exc* exc, int64_t M) {
+  if (n_qubits < 2 || n_qubits > 64) return fail(SWC_EINVAL, "n_qubits out of range");
+  return check_exc(n_qubits, exc, M);
+}
+
+int swc_factor_masks(int n_qubits, const swc_exc* exc, int64_t M, uint64_t* masks) {
+  int r = swc_validate_excitations(n_qubits, exc, M);
+  if (r) return r;
+  for (int64_t k = 0; k < M; ++k) {
+    const FacMask f = factor_mask(exc[k]);
+    masks[3 * k] = f.occ;
+    masks[3 * k + 1] = f.vir;
+    masks[3 * k + 2] = f.sgn;
+  }
+  return SWC_OK;
+}
+
+}  // extern "C"

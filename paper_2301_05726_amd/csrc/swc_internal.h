@@ -1,0 +1,141 @@
+// Internal definitions shared by the kernels (swc_kernels.hip) and the host
+// side of the C ABI (swc_api.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace swc {
+
+// ---------------------------------------------------------------------------
+// hash-table slot encoding
+// ---------------------------------------------------------------------------
+// keys[s] == EMPTY_KEY: never used.  Otherwise meta[s] holds a state bit and
+// a step tag (1-based factor index within the current sweep, 0 = before it):
+//   alive:  meta = born tag          (step that created the entry)
+//   dead:   meta = DEAD | death tag   (step whose truncation removed it)
+// born[s] keeps the creation tag of dead entries (needed when the reverse
+// sweep resurrects them).  A dead entry keeps its key (tombstone) and, for a
+// death during the current sweep, the pre-truncation amplitude.
+constexpr uint64_t EMPTY_KEY = ~0ull;
+constexpr int SH = 16;  // shards of each per-step accumulator
+constexpr uint32_t DEAD = 0x80000000u;
+constexpr uint32_t TAG = 0x7fffffffu;
+
+// status flags (Counters::flags)
+enum : uint32_t {
+  F_TABLE_FULL = 1u,
+  F_LOG_FULL = 2u,
+  F_BAD_THETA = 4u,
+  F_INCONSISTENT = 8u,
+};
+
+// 128-bit two's complement fixed point, value = (hi:lo) * 2^-96.  Every
+// reduction of floating-point terms is done by converting each term to this
+// format and adding integers, so sums are exact and order independent.
+struct Fx {
+  unsigned long long lo;
+  unsigned long long hi;
+};
+
+// per-state device counters
+struct Counters {
+  unsigned long long live;      // alive entries
+  unsigned long long occ;       // slots holding a key (alive + tombstones)
+  unsigned long long logcnt;    // truncation-log records this sweep
+  unsigned long long du;        // det visits (forward)
+  unsigned long long pairs;     // rotated pairs (forward)
+  unsigned long long inserts;   // created entries (forward)
+  unsigned long long pruned;    // truncated amplitudes (forward)
+  unsigned long long ncompact;  // entries in the compact arrays
+  unsigned int flags;
+  unsigned int pad;
+  double S;                     // current renormalisation scale: psi = S * raw
+  Fx num;                       // sum c sigma
+  Fx den;                       // sum c^2
+  double E;
+  double pad2;
+};
+
+struct FacMask {
+  uint64_t occ, vir, sgn;
+};
+
+struct Trig {
+  double c, s, cm1;  // cos, sin, cos - 1 (= -2 sin^2(theta/2))
+};
+
+// per-state arrays; member b lives at offset b*H
+struct Tab {
+  uint64_t* keys;
+  void* amp;
+  uint32_t* meta;
+  uint32_t* born;
+  void* lam;
+  uint64_t H;  // slots, power of two
+};
+
+// truncation log: states of tombstones overwritten by a resurrection
+// during the forward sweep; member b at offset b*cap
+struct LogArr {
+  uint32_t* slot;
+  uint32_t* meta;
+  uint32_t* born;
+  void* amp;
+  uint64_t cap;
+};
+
+// per-step arrays, member b at offset b*stride (stride = max_factors + 1)
+struct StepArr {
+  double* scale;   // scale[j] = S after step j
+  Fx* pw;          // removed raw weight at step k
+  uint32_t* pcnt;  // removed count at step k
+  Fx* gacc;        // gradient dot product of step k
+  uint32_t* logn;  // log records pushed at step k
+  uint32_t* logoff;
+  int64_t stride;
+};
+
+// compact copies of the live entries (energy / state export), member b at b*H
+struct Compact {
+  uint64_t* key;
+  double* amp;
+  uint32_t* slot;
+  Fx* sig;
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (swc_kernels.hip); all asynchronous on `st`
+// ---------------------------------------------------------------------------
+void launch_fill(const Tab& t, int B, hipStream_t st);
+template <class T>
+void launch_insert_init(const Tab& t, Counters* cnt, const uint64_t* dets, const double* amps, int64_t n, int B,
+                        hipStream_t st);
+void launch_trig(const double* theta, Trig* trig, int64_t M, int64_t ld, int B, Counters* cnt, hipStream_t st);
+void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st);
+void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st);
+template <class T>
+void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
+                const LogArr& lg, int k, double thr, int prune_all, int log_on, int B, int grid, hipStream_t st);
+template <class T>
+void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
+                int k, int B, int grid, hipStream_t st);
+template <class T>
+void launch_log_restore(const Tab& t, const LogArr& lg, const StepArr& sa, int k, int B, uint32_t maxcnt,
+                        hipStream_t st);
+template <class T>
+void launch_compact(const Tab& t, const Compact& cp, Counters* cnt, int B, int grid, hipStream_t st);
+void launch_sigma(const Compact& cp, const Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
+                  int64_t nmax, int B, hipStream_t st);
+void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
+                          int64_t nmax, int B, hipStream_t st);
+void launch_energy_final(Counters* cnt, double* E, int B, hipStream_t st);
+template <class T>
+void launch_lambda(const Tab& t, const Compact& cp, const Counters* cnt, int64_t nmax, int B, hipStream_t st);
+void launch_energy_begin(Counters* cnt, int B, hipStream_t st);
+void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int64_t M, int B, hipStream_t st);
+
+int grid_for(uint64_t work, int block, int cap);
+
+}  // namespace swc

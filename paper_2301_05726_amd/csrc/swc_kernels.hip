@@ -1,0 +1,890 @@
+// HIP kernels of the sparse wavefunction circuit (gfx950).
+//
+// State layout (per batch member): an open-addressed hash table in HBM with
+// structure-of-arrays slots {key u64, amplitude T, meta u32, born u32,
+// adjoint T}, linear probing on a 64-bit mixer of the determinant.  One lane
+// owns one slot per sweep step; a determinant pair touched by a factor is
+// updated by exactly one lane (the lower member if it is present, else the
+// upper one), so no amplitude is ever written by two lanes.
+//
+// Cross-lane rules inside one step kernel:
+//  * new entries are placed with atomicCAS on an EMPTY key, so two inserts
+//    never share a slot; lookups of entries that existed before the step
+//    are unaffected by concurrent inserts;
+//  * "present at the start of step k" is read from meta as
+//    alive-and-not-born-in-k, or dead-with-tag-k (killed in this step); every
+//    write a lane makes during step k keeps that predicate unchanged, so a
+//    partner's presence test gives the same answer whenever it runs;
+//  * floating-point reductions are exact 128-bit fixed-point integer sums,
+//    spread over a few shards to avoid a single hot atomic address.
+#include <hip/hip_runtime.h>
+
+#include "swc_internal.h"
+
+namespace swc {
+
+constexpr int BLK = 256;
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+
+__device__ __forceinline__ Fx fx_zero() { return Fx{0ull, 0ull}; }
+
+__device__ __forceinline__ Fx fx_add(Fx a, Fx b) {
+  Fx r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1ull : 0ull);
+  return r;
+}
+
+// floor(v * 2^96) as 128-bit two's complement; |v| < 2^31.
+__device__ __forceinline__ Fx fx_from(double v) {
+  const double t = v * 0x1p32;
+  const double h = floor(t);
+  const double f = t - h;  // exact, in [0, 1)
+  Fx r;
+  r.hi = static_cast<unsigned long long>(static_cast<long long>(h));
+  r.lo = static_cast<unsigned long long>(f * 0x1p64);
+  return r;
+}
+
+__device__ __forceinline__ double fx_to_d(Fx a) {
+  return static_cast<double>(static_cast<long long>(a.hi)) * 0x1p-32 + static_cast<double>(a.lo) * 0x1p-96;
+}
+
+__device__ __forceinline__ bool fx_nonzero(Fx a) { return (a.lo | a.hi) != 0ull; }
+
+__device__ __forceinline__ void fx_atomic_add(Fx* dst, Fx v) {
+  const unsigned long long old = atomicAdd(&dst->lo, v.lo);
+  const unsigned long long carry = (old + v.lo < old) ? 1ull : 0ull;
+  atomicAdd(&dst->hi, v.hi + carry);
+}
+
+__device__ __forceinline__ Fx wave_fx(Fx v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    Fx t;
+    t.lo = __shfl_xor(v.lo, o, 64);
+    t.hi = __shfl_xor(v.hi, o, 64);
+    v = fx_add(v, t);
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sums of one Fx and up to 6 counters; result valid in thread 0
+struct Red {
+  Fx f;
+  unsigned long long c[6];
+};
+
+__device__ __forceinline__ Red block_reduce(Red r) {
+  __shared__ Red part[BLK / 64];
+  r.f = wave_fx(r.f);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) r.c[i] = wave_u64(r.c[i]);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) part[w] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < static_cast<int>(blockDim.x >> 6); ++i) {
+      r.f = fx_add(r.f, part[i].f);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) r.c[j] += part[i].c[j];
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ int64_t find_slot(const uint64_t* __restrict__ keys, uint64_t H, uint64_t key,
+                                             uint64_t* first_free) {
+  const uint64_t mask = H - 1;
+  uint64_t s = mix64(key) & mask;
+  for (uint64_t i = 0; i < H; ++i, s = (s + 1) & mask) {
+    const uint64_t kk = keys[s];
+    if (kk == key) return static_cast<int64_t>(s);
+    if (kk == EMPTY_KEY) {
+      *first_free = s;
+      return -1;
+    }
+  }
+  *first_free = H;
+  return -1;
+}
+
+// Claim an EMPTY slot for `key` (known to be absent), starting the linear
+// probe at `start`.  Returns the slot or -1 when the table is full.
+__device__ __forceinline__ int64_t claim_slot(uint64_t* keys, uint64_t H, uint64_t key, uint64_t start) {
+  if (start >= H) return -1;
+  const uint64_t mask = H - 1;
+  uint64_t s = start;
+  for (uint64_t i = 0; i < H; ++i, s = (s + 1) & mask) {
+    if (keys[s] != EMPTY_KEY) continue;
+    const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&keys[s]),
+                                             static_cast<unsigned long long>(EMPTY_KEY),
+                                             static_cast<unsigned long long>(key));
+    if (old == EMPTY_KEY) return static_cast<int64_t>(s);
+  }
+  return -1;
+}
+
+__device__ __forceinline__ uint32_t shard() { return blockIdx.x & (SH - 1); }
+
+template <class T>
+__device__ __forceinline__ T fmaT(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fmaT<float>(float a, float b, float c) {
+  return fmaf(a, b, c);
+}
+template <>
+__device__ __forceinline__ double fmaT<double>(double a, double b, double c) {
+  return fma(a, b, c);
+}
+
+// Renormalisation scale before step k (1-based): S_{k-1}.  Computed by the
+// first wave from S_{k-2} and the removed weight of step k-1; broadcast via LDS.
+__device__ double scale_before(const StepArr& sa, int b, int k) {
+  __shared__ double sS;
+  if (threadIdx.x < 64) {
+    const int64_t base = static_cast<int64_t>(b) * sa.stride;
+    double S = sa.scale[base + (k >= 2 ? k - 2 : 0)];
+    if (k >= 2) {
+      const int lane = threadIdx.x;
+      Fx w = fx_zero();
+      unsigned long long c = 0;
+      if (lane < SH) {
+        w = sa.pw[(base + k - 1) * SH + lane];
+        c = sa.pcnt[(base + k - 1) * SH + lane];
+      }
+      w = wave_fx(w);
+      c = wave_u64(c);
+      if (c) {
+        const double R = fx_to_d(w);
+        const double nu2 = 1.0 - S * S * R;
+        if (nu2 > 0.0) S = S / sqrt(nu2);
+      }
+    }
+    if (threadIdx.x == 0) sS = S;
+  }
+  __syncthreads();
+  return sS;
+}
+
+// ---------------------------------------------------------------------------
+// table set-up
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill(Tab t) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += gridDim.x * blockDim.x) {
+    t.keys[b * H + s] = EMPTY_KEY;
+    t.meta[b * H + s] = DEAD;
+    t.born[b * H + s] = 0u;
+  }
+}
+
+template <class T>
+__global__ void k_insert_init(Tab t, Counters* cnt, const uint64_t* __restrict__ dets,
+                              const double* __restrict__ amps, int64_t n) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  uint64_t* keys = t.keys + b * H;
+  T* amp = static_cast<T*>(t.amp) + b * H;
+  unsigned long long ok = 0;
+  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint64_t key = dets[i];
+    const uint64_t h = mix64(key) & (H - 1);
+    const int64_t s = claim_slot(keys, H, key, h);
+    if (s < 0) {
+      atomicOr(&cnt[b].flags, F_TABLE_FULL);
+      continue;
+    }
+    amp[s] = static_cast<T>(amps[i]);
+    t.meta[b * H + s] = 0u;
+    t.born[b * H + s] = 0u;
+    static_cast<T*>(t.lam)[b * H + s] = T(0);
+    ++ok;
+  }
+  ok = wave_u64(ok);
+  if ((threadIdx.x & 63) == 0 && ok) {
+    atomicAdd(&cnt[b].live, ok);
+    atomicAdd(&cnt[b].occ, ok);
+  }
+}
+
+__global__ void k_trig(const double* __restrict__ theta, Trig* __restrict__ trig, int64_t M, int64_t ld,
+                       Counters* cnt) {
+  const int b = blockIdx.y;
+  for (int64_t k = blockIdx.x * blockDim.x + threadIdx.x; k < M; k += gridDim.x * blockDim.x) {
+    const double th = theta[b * M + k];
+    if (!isfinite(th)) atomicOr(&cnt[0].flags, F_BAD_THETA);
+    const double sh = sin(0.5 * th);
+    Trig r;
+    r.c = cos(th);
+    r.s = sin(th);
+    r.cm1 = -2.0 * sh * sh;
+    trig[b * ld + k] = r;
+  }
+}
+
+// Start of a sweep: every live entry becomes "born before the sweep"
+// (tag 0), tombstones get tag 0, per-step accumulators are cleared.
+__global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  const uint64_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t gsz = gridDim.x * blockDim.x;
+  for (uint64_t s = gtid; s < H; s += gsz) {
+    const uint32_t m = t.meta[b * H + s];
+    t.meta[b * H + s] = (m & DEAD) ? DEAD : 0u;
+    t.born[b * H + s] = 0u;
+  }
+  const int64_t base = static_cast<int64_t>(b) * sa.stride;
+  for (uint64_t i = gtid; i < static_cast<uint64_t>((M + 1) * SH); i += gsz) {
+    sa.pw[base * SH + i] = fx_zero();
+    sa.pcnt[base * SH + i] = 0u;
+    sa.gacc[base * SH + i] = fx_zero();
+  }
+  for (uint64_t i = gtid; i < static_cast<uint64_t>(M + 1); i += gsz) sa.logn[base + i] = 0u;
+  if (gtid == 0) {
+    sa.scale[base] = cnt[b].S;
+    cnt[b].logcnt = 0;
+    cnt[b].du = 0;
+    cnt[b].pairs = 0;
+    cnt[b].inserts = 0;
+    cnt[b].pruned = 0;
+  }
+}
+
+__global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M) {
+  const int b = blockIdx.x;
+  if (M == 0) return;
+  const double S = scale_before(sa, b, static_cast<int>(M) + 1);
+  if (threadIdx.x == 0) {
+    sa.scale[static_cast<int64_t>(b) * sa.stride + M] = S;
+    cnt[b].S = S;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward step k: pair rotation exp(theta_k A_k) + truncation
+// ---------------------------------------------------------------------------
+// For a pair (L, U) with tau|L> = s|U> and amplitudes (x, y):
+//   x' = x cos - s sin y,  y' = y cos + s sin x       (closed form, Eqs. 4-5)
+// written as x' = x + (x (cos-1) - s sin y) for accuracy at small theta.
+// Truncation (Methods section): a member whose |S x'| < thr is removed; its
+// tombstone keeps x' for the reverse sweep.  The removed weight feeds the
+// renormalisation scale of the next step.
+template <class T>
+__global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
+                                             int64_t ld, StepArr sa, Counters* cnt, LogArr lg, int k, double thr,
+                                             int prune_all, int log_on) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  uint64_t* keys = t.keys + b * H;
+  T* amp = static_cast<T*>(t.amp) + b * H;
+  uint32_t* meta = t.meta + b * H;
+  uint32_t* born = t.born + b * H;
+  const int64_t base = static_cast<int64_t>(b) * sa.stride;
+
+  const double S = scale_before(sa, b, k);
+  if (k >= 2 && blockIdx.x == 0 && threadIdx.x == 0) sa.scale[base + k - 1] = S;
+
+  const FacMask f = fac[k - 1];
+  const Trig tr = trig[b * ld + k - 1];
+  const T sn = static_cast<T>(tr.s), cm1 = static_cast<T>(tr.cm1);
+  const uint64_t pm = f.occ | f.vir;
+  const uint32_t K = static_cast<uint32_t>(k);
+
+  Red r;
+  r.f = fx_zero();
+  for (int i = 0; i < 6; ++i) r.c[i] = 0;
+  // c[0] removed count, c[1] visits, c[2] pairs, c[3] creates, c[4] kills, c[5] new slots
+  unsigned int flags = 0;
+
+  auto kill = [&](uint64_t s, T v) {
+    amp[s] = v;
+    meta[s] = DEAD | K;
+    const double dv = static_cast<double>(v);
+    r.f = fx_add(r.f, fx_from(dv * dv));
+    r.c[0] += 1;
+    r.c[4] += 1;
+  };
+  auto drop_new = [&](T v) {  // created and truncated in the same step
+    const double dv = static_cast<double>(v);
+    r.f = fx_add(r.f, fx_from(dv * dv));
+    r.c[0] += 1;
+  };
+  // create `key` with value v: revive the tombstone at `hint` or claim a slot
+  auto create = [&](uint64_t key, T v, int64_t hint, uint64_t free_start) {
+    int64_t s = hint;
+    if (s >= 0) {
+      const uint32_t old = meta[s];
+      if ((old & TAG) != 0u && log_on) {  // tombstone from this sweep: remember it
+        const unsigned long long pos = atomicAdd(&cnt[b].logcnt, 1ull);
+        if (pos < lg.cap) {
+          const uint64_t li = b * lg.cap + pos;
+          lg.slot[li] = static_cast<uint32_t>(s);
+          lg.meta[li] = old;
+          lg.born[li] = born[s];
+          static_cast<T*>(lg.amp)[li] = amp[s];
+          atomicAdd(&sa.logn[base + k], 1u);
+        } else {
+          flags |= F_LOG_FULL;
+        }
+      }
+    } else {
+      s = claim_slot(keys, H, key, free_start);
+      if (s < 0) {
+        flags |= F_TABLE_FULL;
+        return;
+      }
+      r.c[5] += 1;
+    }
+    amp[s] = v;
+    born[s] = K;
+    meta[s] = K;
+    r.c[3] += 1;
+  };
+
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
+    const uint64_t key = keys[s];
+    if (key == EMPTY_KEY) continue;
+    const uint32_t m = meta[s];
+    if ((m & DEAD) || (m & TAG) == K) continue;  // dead, or created in this step
+    r.c[1] += 1;
+    const bool lower = ((key & f.occ) == f.occ) && !(key & f.vir);
+    const bool upper = ((key & f.vir) == f.vir) && !(key & f.occ);
+    if (!lower && !upper) {
+      if (prune_all) {
+        const T x = amp[s];
+        if (!(fabs(S * static_cast<double>(x)) >= thr)) kill(s, x);
+      }
+      continue;
+    }
+    const uint64_t pk = key ^ pm;
+    uint64_t free_start = H;
+    const int64_t ps = find_slot(keys, H, pk, &free_start);
+    bool p_alive = false, p_start = false;
+    if (ps >= 0) {
+      const uint32_t q = meta[ps];
+      p_alive = !(q & DEAD);
+      p_start = p_alive || ((q & TAG) == K);
+    }
+    if (upper && p_start) continue;  // the lower member owns the pair
+    r.c[2] += 1;
+    const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
+    T x, y;
+    if (lower) {
+      x = amp[s];
+      y = p_alive ? amp[ps] : T(0);
+    } else {
+      x = T(0);
+      y = amp[s];
+    }
+    const T xn = x + fmaT<T>(x, cm1, -ss * y);
+    const T yn = y + fmaT<T>(y, cm1, ss * x);
+    const bool keepx = fabs(S * static_cast<double>(xn)) >= thr;
+    const bool keepy = fabs(S * static_cast<double>(yn)) >= thr;
+    if (lower) {
+      if (keepx) amp[s] = xn; else kill(s, xn);
+      if (p_alive) {
+        if (keepy) amp[ps] = yn; else kill(static_cast<uint64_t>(ps), yn);
+      } else if (keepy) {
+        create(pk, yn, ps, free_start);
+      } else {
+        drop_new(yn);
+      }
+    } else {
+      if (keepy) amp[s] = yn; else kill(s, yn);
+      if (keepx) create(pk, xn, ps, free_start); else drop_new(xn);
+    }
+  }
+
+  if (flags) atomicOr(&cnt[b].flags, flags);
+  r = block_reduce(r);
+  if (threadIdx.x == 0) {
+    const uint32_t sh = shard();
+    if (r.c[0]) {
+      fx_atomic_add(&sa.pw[(base + k) * SH + sh], r.f);
+      atomicAdd(&sa.pcnt[(base + k) * SH + sh], static_cast<uint32_t>(r.c[0]));
+      atomicAdd(&cnt[b].pruned, r.c[0]);
+    }
+    if (r.c[1]) atomicAdd(&cnt[b].du, r.c[1]);
+    if (r.c[2]) atomicAdd(&cnt[b].pairs, r.c[2]);
+    if (r.c[3]) atomicAdd(&cnt[b].inserts, r.c[3]);
+    if (r.c[3] != r.c[4]) atomicAdd(&cnt[b].live, r.c[3] - r.c[4]);
+    if (r.c[5]) atomicAdd(&cnt[b].occ, r.c[5]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reverse step k: exact inverse of the truncated forward step on psi, and
+// the adjoint update  w = U_k^T lambda_k,  g_k = <w|A_k psi_{k-1}>,
+// lambda_{k-1} = P_{k-1} w  (raw, unnormalised amplitudes; the
+// renormalisation constants cancel in the Rayleigh quotient).
+// ---------------------------------------------------------------------------
+// "Present after step k": alive, or dead with tag k (removed by the
+// truncation of step k; its tombstone holds the pre-truncation value and its
+// adjoint component is 0).  Pair inversion:
+//   both present            (x, y) = U^T (x', y')
+//   only one present        the other was created and truncated in step k:
+//                           x = x' / cos (or y = y' / cos)
+// Members born in step k are removed; tombstones of step k are revived.
+template <class T>
+__global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
+                                             int64_t ld, StepArr sa, Counters* cnt, int k) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  uint64_t* keys = t.keys + b * H;
+  T* amp = static_cast<T*>(t.amp) + b * H;
+  T* lam = static_cast<T*>(t.lam) + b * H;
+  uint32_t* meta = t.meta + b * H;
+  uint32_t* born = t.born + b * H;
+  const int64_t base = static_cast<int64_t>(b) * sa.stride;
+
+  const FacMask f = fac[k - 1];
+  const Trig tr = trig[b * ld + k - 1];
+  const T c = static_cast<T>(tr.c), sn = static_cast<T>(tr.s), cm1 = static_cast<T>(tr.cm1);
+  const uint64_t pm = f.occ | f.vir;
+  const uint32_t K = static_cast<uint32_t>(k);
+
+  Red r;
+  r.f = fx_zero();
+  for (int i = 0; i < 6; ++i) r.c[i] = 0;
+  unsigned int flags = 0;
+
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
+    const uint64_t key = keys[s];
+    if (key == EMPTY_KEY) continue;
+    const uint32_t m = meta[s];
+    const bool dead = (m & DEAD) != 0u;
+    if (dead && (m & TAG) != K) continue;
+    const bool lower = ((key & f.occ) == f.occ) && !(key & f.vir);
+    const bool upper = ((key & f.vir) == f.vir) && !(key & f.occ);
+    if (!lower && !upper) {
+      if (dead) {  // truncated at step k without being rotated (first step of a sweep)
+        meta[s] = born[s];
+        lam[s] = T(0);
+      }
+      continue;
+    }
+    const uint64_t pk = key ^ pm;
+    uint64_t free_start = H;
+    const int64_t ps = find_slot(keys, H, pk, &free_start);
+    uint32_t q = 0;
+    bool p_pres = false;
+    if (ps >= 0) {
+      q = meta[ps];
+      p_pres = !(q & DEAD) || ((q & TAG) == K);
+    }
+    if (upper && p_pres) continue;  // the lower member owns the pair
+    const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
+
+    int64_t sL, sU;
+    uint32_t mL, mU;
+    bool hL, hU;
+    if (lower) {
+      sL = static_cast<int64_t>(s); mL = m; hL = true;
+      sU = ps; mU = q; hU = p_pres;
+    } else {
+      sU = static_cast<int64_t>(s); mU = m; hU = true;
+      sL = ps; mL = q; hL = false;
+    }
+    const T xp = hL ? amp[sL] : T(0);
+    const T yp = hU ? amp[sU] : T(0);
+    const T lL = (hL && !(mL & DEAD)) ? lam[sL] : T(0);
+    const T lU = (hU && !(mU & DEAD)) ? lam[sU] : T(0);
+    const T wL = lL + fmaT<T>(lL, cm1, ss * lU);
+    const T wU = lU + fmaT<T>(lU, cm1, -ss * lL);
+    T x, y;
+    if (hL && hU) {
+      x = xp + fmaT<T>(xp, cm1, ss * yp);
+      y = yp + fmaT<T>(yp, cm1, -ss * xp);
+    } else if (hL) {
+      x = xp / c;
+      y = T(0);
+    } else {
+      x = T(0);
+      y = yp / c;
+    }
+    const double sgn = (__popcll(key & f.sgn) & 1) ? -1.0 : 1.0;
+    const double term = sgn * (static_cast<double>(wU) * static_cast<double>(x) -
+                               static_cast<double>(wL) * static_cast<double>(y));
+    r.f = fx_add(r.f, fx_from(term));
+    r.c[2] += 1;
+    if (hL) {
+      const uint32_t bL = (mL & DEAD) ? born[sL] : (mL & TAG);
+      if (bL == K) {
+        if (!hU) flags |= F_INCONSISTENT;
+        meta[sL] = DEAD | K;
+        r.c[4] += 1;
+      } else {
+        amp[sL] = x;
+        lam[sL] = wL;
+        meta[sL] = bL;
+      }
+    }
+    if (hU) {
+      const uint32_t bU = (mU & DEAD) ? born[sU] : (mU & TAG);
+      if (bU == K) {
+        if (!hL) flags |= F_INCONSISTENT;
+        meta[sU] = DEAD | K;
+        r.c[4] += 1;
+      } else {
+        amp[sU] = y;
+        lam[sU] = wU;
+        meta[sU] = bU;
+      }
+    }
+  }
+  if (flags) atomicOr(&cnt[b].flags, flags);
+  r = block_reduce(r);
+  if (threadIdx.x == 0 && fx_nonzero(r.f)) fx_atomic_add(&sa.gacc[(base + k) * SH + shard()], r.f);
+}
+
+// Tombstones overwritten by a resurrection in forward step k get their old
+// state back once the reverse sweep has undone step k.
+template <class T>
+__global__ void k_log_restore(Tab t, LogArr lg, StepArr sa, int k) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  const int64_t base = static_cast<int64_t>(b) * sa.stride;
+  const uint32_t n = sa.logn[base + k];
+  const uint32_t off = sa.logoff[base + k];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint64_t li = b * lg.cap + off + i;
+    const uint64_t s = lg.slot[li];
+    t.meta[b * H + s] = lg.meta[li];
+    t.born[b * H + s] = lg.born[li];
+    static_cast<T*>(t.amp)[b * H + s] = static_cast<const T*>(lg.amp)[li];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// energy: compact live entries, sigma = H psi on the support, E
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cnt) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  for (uint64_t s0 = blockIdx.x * blockDim.x; s0 < H; s0 += stride) {
+    const uint64_t s = s0 + threadIdx.x;
+    bool live = false;
+    uint64_t key = 0;
+    if (s < H) {
+      key = t.keys[b * H + s];
+      live = key != EMPTY_KEY && !(t.meta[b * H + s] & DEAD);
+    }
+    const unsigned long long mask = __ballot(live);
+    if (!mask) continue;
+    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+    unsigned long long basep = 0;
+    if (lane == leader) basep = atomicAdd(&cnt[b].ncompact, static_cast<unsigned long long>(__popcll(mask)));
+    basep = __shfl(basep, leader, 64);
+    if (live) {
+      const unsigned long long below = lane ? (mask & ((1ull << lane) - 1ull)) : 0ull;
+      const uint64_t pos = basep + __popcll(below);
+      cp.key[b * H + pos] = key;
+      cp.amp[b * H + pos] = static_cast<double>(static_cast<const T*>(t.amp)[b * H + s]);
+      cp.slot[b * H + pos] = static_cast<uint32_t>(s);
+      cp.sig[b * H + pos] = fx_zero();
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t between(int lo, int hi) {  // bits lo+1 .. hi-1
+  return ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
+}
+
+__device__ __forceinline__ double eri(const double* __restrict__ h2, int n, int p, int q, int r, int s) {
+  return h2[((static_cast<int64_t>(p) * n + q) * n + r) * n + s];
+}
+
+// <I|H|J> for determinants differing in pc = 2 (single) or 4 (double) bits
+// (Slater-Condon rules; sign from the occupied orbitals common to I and J
+// strictly between the moved ones).
+__device__ double h_offdiag(uint64_t I, uint64_t J, int pc, const double* __restrict__ h1,
+                            const double* __restrict__ h2, int n) {
+  const uint64_t d = I ^ J, C = I & J;
+  if (pc == 2) {
+    const int p = __ffsll(static_cast<long long>(I & d)) - 1;
+    const int q = __ffsll(static_cast<long long>(J & d)) - 1;
+    if ((p ^ q) & 1) return 0.0;
+    const int lo = p < q ? p : q, hi = p < q ? q : p;
+    const int P = p >> 1, Q = q >> 1, sp = p & 1;
+    double v = h1[P * n + Q];
+    for (uint64_t mm = C; mm; mm &= mm - 1ull) {
+      const int kk = __ffsll(static_cast<long long>(mm)) - 1;
+      const int Kk = kk >> 1;
+      v += eri(h2, n, P, Q, Kk, Kk);
+      if ((kk & 1) == sp) v -= eri(h2, n, P, Kk, Kk, Q);
+    }
+    return (__popcll(C & between(lo, hi)) & 1) ? -v : v;
+  }
+  const uint64_t dI = I & d, dJ = J & d;
+  const int p1 = __ffsll(static_cast<long long>(dI)) - 1, p2 = 63 - __clzll(static_cast<long long>(dI));
+  const int q1 = __ffsll(static_cast<long long>(dJ)) - 1, q2 = 63 - __clzll(static_cast<long long>(dJ));
+  double v = 0.0;
+  if (((p1 ^ q1) & 1) == 0 && ((p2 ^ q2) & 1) == 0) v += eri(h2, n, p1 >> 1, q1 >> 1, p2 >> 1, q2 >> 1);
+  if (((p1 ^ q2) & 1) == 0 && ((p2 ^ q1) & 1) == 0) v -= eri(h2, n, p1 >> 1, q2 >> 1, p2 >> 1, q1 >> 1);
+  const int par = __popcll(C & between(q1, q2)) + __popcll(C & between(p1, p2));
+  return (par & 1) ? -v : v;
+}
+
+__device__ double h_diag(uint64_t I, const double* __restrict__ h1, const double* __restrict__ h2, int n) {
+  double v = 0.0;
+  for (uint64_t a = I; a; a &= a - 1ull) {
+    const int p = __ffsll(static_cast<long long>(a)) - 1;
+    const int P = p >> 1;
+    v += h1[P * n + P];
+    for (uint64_t bb = a & (a - 1ull); bb; bb &= bb - 1ull) {
+      const int q = __ffsll(static_cast<long long>(bb)) - 1;
+      const int Q = q >> 1;
+      v += eri(h2, n, P, P, Q, Q);
+      if (((p ^ q) & 1) == 0) v -= eri(h2, n, P, Q, Q, P);
+    }
+  }
+  return v;
+}
+
+constexpr int TJ = 256;
+
+// sigma_I += sum_J <I|H|J> c_J over J in a chunk of the compact list; one
+// lane per I, J tiles staged in LDS.  Exact fixed-point accumulation.
+__global__ __launch_bounds__(BLK) void k_sigma(Compact cp, const Counters* cnt, uint64_t H,
+                                               const double* __restrict__ h1, const double* __restrict__ h2, int n) {
+  const int b = blockIdx.z;
+  const int64_t N = static_cast<int64_t>(cnt[b].ncompact);
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * BLK;
+  const int64_t chunks = gridDim.y;
+  int64_t per = (N + chunks - 1) / chunks;
+  per = (per + TJ - 1) / TJ * TJ;
+  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * per;
+  const int64_t j1 = (j0 + per < N) ? j0 + per : N;
+  if (i0 >= N || j0 >= N) return;
+  const uint64_t* ck = cp.key + b * H;
+  const double* ca = cp.amp + b * H;
+  __shared__ uint64_t sk[TJ];
+  __shared__ double sa[TJ];
+  const int64_t i = i0 + threadIdx.x;
+  const bool act = i < N;
+  const uint64_t I = act ? ck[i] : 0ull;
+  Fx acc = fx_zero();
+  for (int64_t jt = j0; jt < j1; jt += TJ) {
+    __syncthreads();
+    const int64_t j = jt + threadIdx.x;
+    if (j < j1) {
+      sk[threadIdx.x] = ck[j];
+      sa[threadIdx.x] = ca[j];
+    }
+    __syncthreads();
+    const int cntj = static_cast<int>((j1 - jt) < TJ ? (j1 - jt) : TJ);
+    if (act) {
+      for (int tt = 0; tt < cntj; ++tt) {
+        const uint64_t J = sk[tt];
+        const int pc = __popcll(I ^ J);
+        if (pc == 2 || pc == 4) acc = fx_add(acc, fx_from(h_offdiag(I, J, pc, h1, h2, n) * sa[tt]));
+      }
+    }
+  }
+  if (act && fx_nonzero(acc)) fx_atomic_add(&cp.sig[b * H + i], acc);
+}
+
+// adds the diagonal, then sum c*sigma and sum c^2 (exact) per state
+__global__ __launch_bounds__(BLK) void k_energy_reduce(Compact cp, Counters* cnt, uint64_t H,
+                                                       const double* __restrict__ h1, const double* __restrict__ h2,
+                                                       int n) {
+  const int b = blockIdx.y;
+  const int64_t N = static_cast<int64_t>(cnt[b].ncompact);
+  Fx num = fx_zero(), den = fx_zero();
+  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const double c = cp.amp[b * H + i];
+    const Fx sg = fx_add(cp.sig[b * H + i], fx_from(h_diag(cp.key[b * H + i], h1, h2, n) * c));
+    cp.sig[b * H + i] = sg;
+    const double sig = fx_to_d(sg);
+    num = fx_add(num, fx_from(c * sig));
+    den = fx_add(den, fx_from(c * c));
+  }
+  Red r;
+  r.f = num;
+  for (int q = 0; q < 6; ++q) r.c[q] = 0;
+  r = block_reduce(r);
+  if (threadIdx.x == 0 && fx_nonzero(r.f)) fx_atomic_add(&cnt[b].num, r.f);
+  __syncthreads();
+  r.f = den;
+  r = block_reduce(r);
+  if (threadIdx.x == 0 && fx_nonzero(r.f)) fx_atomic_add(&cnt[b].den, r.f);
+}
+
+__global__ void k_energy_begin(Counters* cnt, int B) {
+  const int b = threadIdx.x;
+  if (b >= B) return;
+  cnt[b].ncompact = 0;
+  cnt[b].num = fx_zero();
+  cnt[b].den = fx_zero();
+}
+
+__global__ void k_energy_final(Counters* cnt, double* E, int B) {
+  const int b = threadIdx.x;
+  if (b >= B) return;
+  const double e = fx_to_d(cnt[b].num) / fx_to_d(cnt[b].den);
+  cnt[b].E = e;
+  if (E) E[b] = e;
+}
+
+// lambda_M = P_M (H - E) psi_M on the support (raw amplitudes)
+template <class T>
+__global__ void k_lambda(Tab t, Compact cp, const Counters* cnt) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  const int64_t N = static_cast<int64_t>(cnt[b].ncompact);
+  const double E = cnt[b].E;
+  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const double v = fx_to_d(cp.sig[b * H + i]) - E * cp.amp[b * H + i];
+    static_cast<T*>(t.lam)[b * H + cp.slot[b * H + i]] = static_cast<T>(v);
+  }
+}
+
+__global__ void k_grad_final(StepArr sa, const Counters* cnt, double* grad, int64_t M) {
+  const int b = blockIdx.y;
+  const int64_t base = static_cast<int64_t>(b) * sa.stride;
+  const double den = fx_to_d(cnt[b].den);
+  for (int64_t k = blockIdx.x * blockDim.x + threadIdx.x; k < M; k += gridDim.x * blockDim.x) {
+    Fx g = fx_zero();
+    for (int q = 0; q < SH; ++q) g = fx_add(g, sa.gacc[(base + k + 1) * SH + q]);
+    grad[b * M + k] = 2.0 * fx_to_d(g) / den;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+int grid_for(uint64_t work, int block, int cap) {
+  uint64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > static_cast<uint64_t>(cap)) g = cap;
+  return static_cast<int>(g);
+}
+
+void launch_fill(const Tab& t, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t);
+}
+
+template <class T>
+void launch_insert_init(const Tab& t, Counters* cnt, const uint64_t* dets, const double* amps, int64_t n, int B,
+                        hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_insert_init<T>, dim3(grid_for(n, BLK, 4096), B), dim3(BLK), 0, st, t, cnt, dets, amps, n);
+}
+
+void launch_trig(const double* theta, Trig* trig, int64_t M, int64_t ld, int B, Counters* cnt, hipStream_t st) {
+  if (M <= 0) return;
+  hipLaunchKernelGGL(k_trig, dim3(grid_for(M, BLK, 1024), B), dim3(BLK), 0, st, theta, trig, M, ld, cnt);
+}
+
+void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_sweep_begin, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t, sa, cnt, M);
+}
+
+void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_sweep_end, dim3(B), dim3(64), 0, st, sa, cnt, M);
+}
+
+template <class T>
+void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
+                const LogArr& lg, int k, double thr, int prune_all, int log_on, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_fwd<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all,
+                     log_on);
+}
+
+template <class T>
+void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
+                int k, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_rev<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
+}
+
+template <class T>
+void launch_log_restore(const Tab& t, const LogArr& lg, const StepArr& sa, int k, int B, uint32_t maxcnt,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_log_restore<T>, dim3(grid_for(maxcnt, BLK, 1024), B), dim3(BLK), 0, st, t, lg, sa, k);
+}
+
+template <class T>
+void launch_compact(const Tab& t, const Compact& cp, Counters* cnt, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_compact<T>, dim3(grid, B), dim3(BLK), 0, st, t, cp, cnt);
+}
+
+void launch_sigma(const Compact& cp, const Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
+                  int64_t nmax, int B, hipStream_t st) {
+  if (nmax <= 0) return;
+  const int gi = grid_for(nmax, BLK, 1 << 30);
+  // enough J chunks to give the chip a few thousand blocks, each chunk >= 1 tile
+  int64_t chunks = (4096 + gi - 1) / gi;
+  const int64_t maxch = (nmax + TJ - 1) / TJ;
+  if (chunks > maxch) chunks = maxch;
+  if (chunks < 1) chunks = 1;
+  hipLaunchKernelGGL(k_sigma, dim3(gi, static_cast<unsigned>(chunks), B), dim3(BLK), 0, st, cp, cnt, H, h1, h2, n);
+}
+
+void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
+                          int64_t nmax, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_reduce, dim3(grid_for(nmax, BLK, 2048), B), dim3(BLK), 0, st, cp, cnt, H, h1, h2, n);
+}
+
+void launch_energy_begin(Counters* cnt, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_begin, dim3(1), dim3(64 * ((B + 63) / 64)), 0, st, cnt, B);
+}
+
+void launch_energy_final(Counters* cnt, double* E, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64 * ((B + 63) / 64)), 0, st, cnt, E, B);
+}
+
+template <class T>
+void launch_lambda(const Tab& t, const Compact& cp, const Counters* cnt, int64_t nmax, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_lambda<T>, dim3(grid_for(nmax, BLK, 4096), B), dim3(BLK), 0, st, t, cp, cnt);
+}
+
+void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int64_t M, int B, hipStream_t st) {
+  if (M <= 0) return;
+  hipLaunchKernelGGL(k_grad_final, dim3(grid_for(M, BLK, 1024), B), dim3(BLK), 0, st, sa, cnt, grad, M);
+}
+
+#define SWC_INST(T)                                                                                                \
+  template void launch_insert_init<T>(const Tab&, Counters*, const uint64_t*, const double*, int64_t, int,         \
+                                      hipStream_t);                                                                \
+  template void launch_fwd<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*,        \
+                              const LogArr&, int, double, int, int, int, int, hipStream_t);                        \
+  template void launch_rev<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,   \
+                              int, int, hipStream_t);                                                              \
+  template void launch_log_restore<T>(const Tab&, const LogArr&, const StepArr&, int, int, uint32_t,              \
+                                      hipStream_t);                                                                \
+  template void launch_compact<T>(const Tab&, const Compact&, Counters*, int, int, hipStream_t);                  \
+  template void launch_lambda<T>(const Tab&, const Compact&, const Counters*, int64_t, int, hipStream_t);
+
+SWC_INST(float)
+SWC_INST(double)
+
+}  // namespace swc

@@ -1,0 +1,243 @@
+"""Python binding of libswc.so (C ABI in include/swc.h).
+
+Argument marshalling only: every step of the circuit, energy and gradient
+runs in the HIP library.  PyTorch provides the device workspace and the
+stream.  There is no fallback: if the library is not built, or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswc.so")
+
+OK, EINVAL, ECAPACITY, EEMPTY, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
+FP64, FP32 = 0, 1
+
+EXPORTS = [
+    "swc_workspace_bytes", "swc_create", "swc_build_state", "swc_apply_ucc", "swc_energy",
+    "swc_energy_and_grad", "swc_get_state", "swc_get_stats", "swc_strerror", "swc_last_error",
+    "swc_destroy", "swc_validate_excitations", "swc_factor_masks",
+]
+
+
+class SwcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"swc error {code}: {msg}")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_live", ctypes.c_int64), ("det_updates", ctypes.c_int64), ("pair_updates", ctypes.c_int64),
+        ("inserts", ctypes.c_int64), ("pruned", ctypes.c_int64), ("log_records", ctypes.c_int64),
+        ("table_slots", ctypes.c_int64), ("slots_used", ctypes.c_int64),
+        ("fwd_ms", ctypes.c_double), ("energy_ms", ctypes.c_double), ("rev_ms", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libswc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2301_05726_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, I64, U64, D, SZ = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
+                                 ctypes.c_double, ctypes.c_size_t)
+        L.swc_workspace_bytes.argtypes = [I, U64, I, I, I64, U64]
+        L.swc_workspace_bytes.restype = SZ
+        L.swc_create.argtypes = [ctypes.POINTER(P), I, I, I, U64, I, I, I64, U64, P, SZ, P]
+        L.swc_build_state.argtypes = [P, P, P, I64]
+        L.swc_apply_ucc.argtypes = [P, P, P, I64, D]
+        L.swc_energy.argtypes = [P, P, P, P]
+        L.swc_energy_and_grad.argtypes = [P, P, P, I64, D, P, P, P, P]
+        L.swc_get_state.argtypes = [P, I, P, P, I64, ctypes.POINTER(I64)]
+        L.swc_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+        L.swc_strerror.argtypes = [I]
+        L.swc_strerror.restype = ctypes.c_char_p
+        L.swc_last_error.argtypes = []
+        L.swc_last_error.restype = ctypes.c_char_p
+        L.swc_destroy.argtypes = [P]
+        L.swc_destroy.restype = None
+        L.swc_validate_excitations.argtypes = [I, P, I64]
+        L.swc_factor_masks.argtypes = [I, P, I64, P]
+        _lib = L
+    return _lib
+
+
+def _chk(code: int):
+    if code != 0:
+        raise SwcError(code, lib().swc_last_error().decode())
+
+
+def _exc_array(exc) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(exc, dtype=np.int8).reshape(-1, 4))
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def validate_excitations(n_qubits: int, exc) -> int:
+    """Host-only check (no GPU): 0 or the negative error code."""
+    e = _exc_array(exc)
+    return lib().swc_validate_excitations(n_qubits, _ptr(e), e.shape[0])
+
+
+def factor_masks(n_qubits: int, exc) -> np.ndarray:
+    """Host-only: per factor (occupied mask, virtual mask, sign mask)."""
+    e = _exc_array(exc)
+    out = np.zeros((e.shape[0], 3), dtype=np.uint64)
+    _chk(lib().swc_factor_masks(n_qubits, _ptr(e), e.shape[0], _ptr(out)))
+    return out
+
+
+def workspace_bytes(n_qubits, capacity, prec, batch, max_factors, log_capacity=0) -> int:
+    return int(lib().swc_workspace_bytes(n_qubits, capacity, prec, batch, max_factors, log_capacity))
+
+
+class Solver:
+    """One context of the library: `batch` sparse states of `n_qubits`
+    spin-orbitals in hash tables of `capacity` slots on one GPU."""
+
+    def __init__(self, n_qubits: int, n_alpha: int, n_beta: int, capacity: int, prec: int = FP32,
+                 batch: int = 1, max_factors: int = 1, log_capacity: int = 0, device="cuda:0",
+                 stream: torch.cuda.Stream | None = None):
+        L = lib()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the swc library runs on an MI355X only")
+        self.device = torch.device(device)
+        self.n_qubits, self.batch, self.prec, self.max_factors = n_qubits, batch, prec, max_factors
+        nbytes = workspace_bytes(n_qubits, capacity, prec, batch, max_factors, log_capacity)
+        if nbytes == 0:
+            raise SwcError(EINVAL, "invalid sizes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ctx = ctypes.c_void_p()
+        _chk(L.swc_create(ctypes.byref(self._ctx), n_qubits, n_alpha, n_beta, capacity, prec, batch, max_factors,
+                          log_capacity, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                          ctypes.c_void_p(self.stream.cuda_stream)))
+
+    # -- helpers ----------------------------------------------------------
+    def _dev(self, t, shape=None) -> torch.Tensor:
+        t = torch.as_tensor(t, dtype=torch.float64, device=self.device).contiguous()
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            t = t.reshape(shape).contiguous()
+        return t
+
+    def _theta(self, theta, M) -> torch.Tensor:
+        t = self._dev(theta)
+        if t.dim() == 1:
+            t = t.unsqueeze(0).expand(self.batch, M).contiguous()
+        if tuple(t.shape) != (self.batch, M):
+            raise SwcError(EINVAL, f"theta must be [{self.batch}, {M}]")
+        return t
+
+    def _sync_inputs(self):
+        # inputs written on torch's current stream must be ready on ours
+        if self.stream != torch.cuda.current_stream(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    # -- API ----------------------------------------------------------------
+    def build_state(self, dets=None, amps=None):
+        if dets is None:
+            _chk(lib().swc_build_state(self._ctx, None, None, 0))
+            return
+        d = np.ascontiguousarray(np.asarray(dets, dtype=np.uint64).reshape(-1))
+        a = np.ascontiguousarray(np.asarray(amps, dtype=np.float64).reshape(-1))
+        if d.shape != a.shape:
+            raise SwcError(EINVAL, "dets and amps differ in length")
+        _chk(lib().swc_build_state(self._ctx, _ptr(d), _ptr(a), d.shape[0]))
+
+    def apply_ucc(self, theta, exc, threshold: float = 0.0):
+        e = _exc_array(exc)
+        M = e.shape[0]
+        t = self._theta(theta, M)
+        self._sync_inputs()
+        _chk(lib().swc_apply_ucc(self._ctx, ctypes.c_void_p(t.data_ptr()), _ptr(e), M, float(threshold)))
+
+    def energy(self, h1, h2) -> torch.Tensor:
+        h1d, h2d = self._dev(h1), self._dev(h2)
+        E = torch.empty(self.batch, dtype=torch.float64, device=self.device)
+        self._sync_inputs()
+        _chk(lib().swc_energy(self._ctx, ctypes.c_void_p(h1d.data_ptr()), ctypes.c_void_p(h2d.data_ptr()),
+                              ctypes.c_void_p(E.data_ptr())))
+        return E
+
+    def energy_and_grad(self, theta, exc, threshold, h1, h2):
+        e = _exc_array(exc)
+        M = e.shape[0]
+        t = self._theta(theta, M)
+        h1d, h2d = self._dev(h1), self._dev(h2)
+        E = torch.empty(self.batch, dtype=torch.float64, device=self.device)
+        g = torch.empty((self.batch, M), dtype=torch.float64, device=self.device)
+        self._sync_inputs()
+        _chk(lib().swc_energy_and_grad(self._ctx, ctypes.c_void_p(t.data_ptr()), _ptr(e), M, float(threshold),
+                                       ctypes.c_void_p(h1d.data_ptr()), ctypes.c_void_p(h2d.data_ptr()),
+                                       ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(g.data_ptr())))
+        return E, g
+
+    def get_state(self, b: int = 0, cap: int | None = None):
+        n = ctypes.c_int64(0)
+        cap = cap if cap is not None else 1 << 16
+        while True:
+            d = np.empty(cap, np.uint64)
+            a = np.empty(cap, np.float64)
+            r = lib().swc_get_state(self._ctx, b, _ptr(d), _ptr(a), cap, ctypes.byref(n))
+            if r == ECAPACITY and n.value > cap:
+                cap = n.value
+                continue
+            _chk(r)
+            return d[: n.value].copy(), a[: n.value].copy()
+
+    def stats(self) -> dict:
+        s = Stats()
+        _chk(lib().swc_get_stats(self._ctx, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib().swc_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class UCCEnergy(torch.autograd.Function):
+    """E(theta) with the adjoint gradient of the library as backward.
+
+    forward(theta[B, M], solver, exc, threshold, h1, h2) -> E[B]
+    """
+
+    @staticmethod
+    def forward(ctx, theta, solver: Solver, exc, threshold, h1, h2):
+        E, g = solver.energy_and_grad(theta.detach(), exc, threshold, h1, h2)
+        ctx.save_for_backward(g)
+        ctx.theta_dim = theta.dim()
+        return E.to(theta.dtype)
+
+    @staticmethod
+    def backward(ctx, gE):
+        (g,) = ctx.saved_tensors
+        grad = gE.to(g.dtype)[:, None] * g
+        if ctx.theta_dim == 1:
+            grad = grad.sum(0)
+        return grad, None, None, None, None, None
+
+
+def ucc_energy(theta, solver: Solver, exc, threshold, h1, h2):
+    return UCCEnergy.apply(theta, solver, exc, threshold, h1, h2)

@@ -1,0 +1,167 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on
+the same seeded inputs, element by element."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import TOL, capacity_for, compare_states, say, small_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def swc():
+    from paper_2301_05726_amd import swc as s
+    s.lib()
+    assert torch.cuda.is_available()
+    return s
+
+
+CASES = [
+    # (name, n_orb, n_occ, sigma, seed, n_factors, threshold)
+    ("q8", 4, 2, 0.3, 101, None, 0.0),
+    ("q12", 6, 3, 0.2, 102, None, 0.0),
+    ("q12_thr", 6, 3, 0.25, 103, None, 2e-3),
+    ("q16", 8, 4, 0.1, 104, None, 0.0),
+    ("q16_thr", 8, 4, 0.1, 105, None, 1e-4),
+    ("q20_pre", 10, 5, 0.05, 106, 160, 0.0),
+    ("q20_pre_thr", 10, 5, 0.05, 107, 300, 1e-5),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_forward_energy_grad_vs_oracle(swc, orc, case, prec):
+    name, n_orb, n_occ, sigma, seed, nf, thr = case
+    say(f"[case] {name} prec={prec} thr={thr}")
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed, nf)
+    nq = 2 * n_orb
+    tol = TOL[prec]
+    orc.set_nearcut_window(1e-5)
+    d_ref, a_ref, nc, _ = orc.apply_ucc(nq, [hf], [1.0], exc, theta[0], thr)
+    E_ref, g_ref, nc2 = orc.energy_and_grad(nq, [hf], [1.0], exc, theta[0], thr, h1, h2)
+    say(f"  oracle N={len(d_ref)} nearcut={nc} E={E_ref:.12f}")
+    assert nc == 0, "test instance must have no amplitude near the cut"
+    cap = capacity_for(n_orb, n_occ)
+    s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=1, max_factors=exc.shape[0])
+    s.build_state()
+    s.apply_ucc(theta, exc, thr)
+    d, a = s.get_state(0)
+    err = compare_states(d, a, d_ref, a_ref, tol["amp"])
+    E = s.energy(h1, h2).cpu().numpy()[0]
+    say(f"  gpu N={len(d)} amp_err={err:.3e} dE={abs(E - E_ref):.3e}")
+    assert abs(E - E_ref) <= tol["E"]
+    E2, g = s.energy_and_grad(theta, exc, thr, h1, h2)
+    E2 = E2.cpu().numpy()[0]
+    g = g.cpu().numpy()[0]
+    say(f"  grad: dE={abs(E2 - E_ref):.3e} max|dg|={np.max(np.abs(g - g_ref)):.3e}")
+    assert abs(E2 - E_ref) <= tol["E"]
+    assert np.max(np.abs(g - g_ref)) <= tol["g"]
+    # energy_and_grad leaves |Psi_0>
+    d0, a0 = s.get_state(0)
+    assert list(d0) == [hf] and abs(a0[0] - 1.0) < 1e-15
+    s.close()
+
+
+def test_batch_members_independent(swc, orc):
+    say("[case] batch3 q12")
+    h1, h2, exc, theta, hf = small_problem(6, 3, 0.2, 111, batch=3)
+    s = swc.Solver(12, 3, 3, 1024, prec=0, batch=3, max_factors=exc.shape[0])
+    s.build_state()
+    E, g = s.energy_and_grad(theta, exc, 0.0, h1, h2)
+    E = E.cpu().numpy()
+    g = g.cpu().numpy()
+    for b in range(3):
+        E_ref, g_ref, _ = orc.energy_and_grad(12, [hf], [1.0], exc, theta[b], 0.0, h1, h2)
+        assert abs(E[b] - E_ref) < 1e-10
+        assert np.max(np.abs(g[b] - g_ref)) < 1e-8
+    s.apply_ucc(theta, exc, 0.0)
+    for b in range(3):
+        d, a = s.get_state(b)
+        d_ref, a_ref, _, _ = orc.apply_ucc(12, [hf], [1.0], exc, theta[b], 0.0)
+        compare_states(d, a, d_ref, a_ref, 1e-12)
+
+
+def test_bitwise_reproducible(swc):
+    say("[case] determinism q16 thr")
+    h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 121)
+    out = []
+    for prec in (0, 1):
+        for rep in range(2):
+            s = swc.Solver(16, 4, 4, 16384, prec=prec, batch=1, max_factors=exc.shape[0])
+            s.build_state()
+            E, g = s.energy_and_grad(theta, exc, 1e-4, h1, h2)
+            out.append((prec, E.cpu().numpy().tobytes(), g.cpu().numpy().tobytes()))
+            s.close()
+    assert out[0] == out[1] and out[2] == out[3]
+
+
+def test_custom_initial_state_and_sequential_calls(swc, orc):
+    say("[case] initial state + two apply calls")
+    h1, h2, exc, theta, hf = small_problem(6, 3, 0.3, 131)
+    rng = np.random.default_rng(7)
+    _, d0, a0 = None, None, None
+    d_ref0, a_ref0, _, _ = orc.apply_ucc(12, [hf], [1.0], exc[:40], theta[0, :40], 0.0)
+    dets = d_ref0[:25]
+    amps = rng.normal(size=25)
+    s = swc.Solver(12, 3, 3, 2048, prec=0, batch=1, max_factors=exc.shape[0])
+    s.build_state(dets, amps)
+    s.apply_ucc(theta[:, :50], exc[:50], 1e-3)
+    s.apply_ucc(theta[:, 50:], exc[50:], 1e-3)
+    d, a = s.get_state(0)
+    d1, a1, nc1, _ = orc.apply_ucc(12, dets, amps, exc[:50], theta[0, :50], 1e-3)
+    d2, a2, nc2, _ = orc.apply_ucc(12, d1, a1, exc[50:], theta[0, 50:], 1e-3)
+    assert nc1 == 0 and nc2 == 0
+    compare_states(d, a, d2, a2, 1e-12)
+    E = s.energy(h1, h2).cpu().numpy()[0]
+    assert abs(E - orc.energy(6, h1, h2, d2, a2)) < 1e-10
+
+
+def test_error_paths(swc):
+    say("[case] error paths")
+    h1, h2, exc, theta, hf = small_problem(4, 2, 0.3, 141)
+    s = swc.Solver(8, 2, 2, 256, prec=0, batch=1, max_factors=exc.shape[0])
+    with pytest.raises(swc.SwcError) as e:
+        s.apply_ucc(theta, exc, 0.0)
+    assert e.value.code == swc.ESTATE
+    s.build_state()
+    bad = exc.copy()
+    bad[0] = (0, 2, 0, 6)
+    with pytest.raises(swc.SwcError) as e:
+        s.apply_ucc(theta, bad, 0.0)
+    assert e.value.code == swc.EINVAL
+    t = theta.copy()
+    t[0, 3] = np.nan
+    with pytest.raises(swc.SwcError) as e:
+        s.apply_ucc(t, exc, 0.0)
+    assert e.value.code == swc.EINVAL
+    with pytest.raises(swc.SwcError) as e:
+        s.apply_ucc(theta, exc, -1.0)
+    assert e.value.code == swc.EINVAL
+    with pytest.raises(swc.SwcError) as e:
+        s.apply_ucc(theta, exc, 2.0)
+    assert e.value.code == swc.EEMPTY
+    s.build_state()
+    with pytest.raises(swc.SwcError) as e:
+        s.build_state([1 << 8], [1.0])
+    assert e.value.code == swc.EINVAL
+    # a table too small for the state
+    s2 = swc.Solver(12, 3, 3, 64, prec=0, batch=1, max_factors=200)
+    s2.build_state()
+    h1b, h2b, excb, thetab, _ = small_problem(6, 3, 0.3, 142)
+    with pytest.raises(swc.SwcError) as e:
+        s2.apply_ucc(thetab, excb, 0.0)
+    assert e.value.code == swc.ECAPACITY
+
+
+def test_autograd_function(swc, orc):
+    say("[case] autograd")
+    h1, h2, exc, theta, hf = small_problem(6, 3, 0.2, 151)
+    s = swc.Solver(12, 3, 3, 1024, prec=1, batch=1, max_factors=exc.shape[0])
+    s.build_state()
+    th = torch.tensor(theta[0], dtype=torch.float64, device="cuda", requires_grad=True)
+    E = swc.ucc_energy(th, s, exc, 0.0, h1, h2)
+    (2.0 * E.sum()).backward()
+    E_ref, g_ref, _ = orc.energy_and_grad(12, [hf], [1.0], exc, theta[0], 0.0, h1, h2)
+    assert abs(E.item() - E_ref) < 1e-6
+    assert np.max(np.abs(th.grad.cpu().numpy() - 2.0 * g_ref)) < 2e-5

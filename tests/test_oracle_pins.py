@@ -220,6 +220,7 @@ def test_gradient_vs_fd_with_truncation(orc):
     n_orb, n_occ = 5, 2
     h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, 0.3, 61)
     thr = 2e-3
+    orc.set_nearcut_window(1e-3)
     E, g, nc = orc.energy_and_grad(10, [hf], [1.0], exc, theta, thr, h1, h2)
     assert nc == 0  # no amplitude within 1e-3*thr of the cut at any step
     d0, _, _, _ = orc.apply_ucc(10, [hf], [1.0], exc, theta, thr)
