@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of the sparse wavefunction UCC circuit on one MI355X.
+
+One step = one energy_and_grad call: forward sweep of all UCC factors with
+truncation, sigma = H psi and E, and the adjoint sweep giving dE/dtheta,
+for one theta vector of the workload, inputs already resident in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--workload q20] [--prec fp32]
+
+Prints one JSON line.  Besides the step rate it reports the forward
+det-update rate, the same-GPU FP64 forward + central finite-difference
+gradient rate (extrapolated from sampled parameters), the roofline figures
+of the dominant kernel from HIP events, and the CPU oracle timed on the
+host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("det-updates/s (UCC forward); E+∇E evals/s adjoint vs FD, 1 MI355X, ΔE≤1e-6")
+HBM_PEAK_GBS = 8000.0
+
+
+def rotate_bytes(st: dict, tsz: int) -> float:
+    """Algorithmic bytes of one forward sweep's rotate kernels: 8 B key per
+    visited determinant; per rotated pair the own amplitude read+write and
+    an 8 B partner-key probe; partner amplitude read+write when it exists;
+    key + amplitude per inserted determinant."""
+    return (8.0 * st["det_updates"] + st["pair_updates"] * (2 * tsz + 8) + st["partner_hits"] * 2 * tsz
+            + st["inserts"] * (8 + tsz))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="q20")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--fd-params", type=int, default=32)
+    ap.add_argument("--no-fd", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); run it with --gpus 1", file=sys.stderr)
+        return 2
+    # per-launch HIP events around the rotate / reverse / sigma kernels
+    os.environ.setdefault("SWC_KERNEL_TIMING", "1")
+
+    import numpy as np
+    import torch
+
+    from paper_2301_05726_amd import swc, synth
+
+    wl = synth.WORKLOADS[args.workload]
+    p = synth.make_problem(wl, batch=1)
+    nq, M = wl.n_qubits, p.M
+    prec = swc.FP32 if args.prec == "fp32" else swc.FP64
+    tsz = 4 if prec == swc.FP32 else 8
+    dev = torch.device("cuda:0")
+    theta = torch.tensor(p.theta, dtype=torch.float64, device=dev)
+    h1 = torch.tensor(p.h1, dtype=torch.float64, device=dev)
+    h2 = torch.tensor(p.h2, dtype=torch.float64, device=dev)
+
+    s = swc.Solver(nq, wl.n_occ, wl.n_occ, wl.capacity, prec=prec, batch=1, max_factors=M, device=dev)
+    s.build_state()
+    for _ in range(args.warmup):
+        s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
+    torch.cuda.synchronize()
+    rot_ms = rot_n = rev_ms = rev_n = sig_ms = fwd_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E, g = s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
+        st = s.stats()
+        rot_ms += st["rotate_kernel_ms"]
+        rot_n += st["rotate_launches"]
+        rev_ms += st["reverse_kernel_ms"]
+        rev_n += st["reverse_launches"]
+        sig_ms += st["sigma_kernel_ms"]
+        fwd_ms += st["fwd_ms"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+    E0 = float(E.item())
+    g0 = g.cpu().numpy()[0]
+
+    # forward sweep statistics of one step (identical every step)
+    s.apply_ucc(theta, p.exc, wl.threshold)
+    st = s.stats()
+    n_live = st["n_live"]
+    det_updates = st["det_updates"]
+    s.build_state()
+
+    # dominant kernel: the largest summed device time per step
+    per_step = {"rotate": rot_ms / args.steps, "reverse": rev_ms / args.steps, "sigma": sig_ms / args.steps}
+    bytes_sweep = rotate_bytes(st, tsz)
+    avg_rot_ms = rot_ms / max(rot_n, 1)
+    achieved = (bytes_sweep / M) / (avg_rot_ms * 1e-3) / 1e9 if avg_rot_ms > 0 else 0.0
+    roofline = {
+        "kernel": "k_fwd (rotate + truncate, one launch per factor)",
+        "bound": "hbm",
+        "achieved": round(achieved, 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": None,
+        "bytes_per_launch": bytes_sweep / M,
+        "avg_launch_us": avg_rot_ms * 1e3,
+        "kernel_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "E+grad evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == swc.FP32 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{wl.name}: {nq} qubits, {2 * wl.n_occ} electrons, full spin-conserving UCCSD "
+                         f"({M} factors), theta~N(0,{wl.theta_sigma}), threshold {wl.threshold}, "
+                         f"capacity 2^{int(np.log2(wl.capacity))}"),
+            "amplitudes": args.prec, "reductions": "f64 (exact fixed point)",
+            "n_det_final": n_live,
+        },
+        "det_updates_per_step": det_updates,
+        "det_updates_per_s_forward": round(det_updates / (fwd_ms / args.steps * 1e-3), 1) if fwd_ms else None,
+        "energy": E0,
+        "roofline": roofline,
+    }
+
+    if not args.no_fd:
+        # same-GPU FP64 forward + central finite differences (h = 1e-5)
+        sf = swc.Solver(nq, wl.n_occ, wl.n_occ, wl.capacity, prec=swc.FP64, batch=1, max_factors=M, device=dev)
+        sf.build_state()
+        idx = synth.fd_subset(M, args.fd_params, 3000 + wl.cfg)
+        h = 1e-5
+        tp = theta.clone()
+        sf.apply_ucc(tp, p.exc, wl.threshold)
+        sf.energy(h1, h2)
+        sf.build_state()
+        torch.cuda.synchronize()
+        fd = np.empty(len(idx))
+        f0 = time.perf_counter()
+        for q, k in enumerate(idx):
+            ev = []
+            for sgn in (1.0, -1.0):
+                tp.copy_(theta)
+                tp[0, k] += sgn * h
+                sf.build_state()
+                sf.apply_ucc(tp, p.exc, wl.threshold)
+                ev.append(sf.energy(h1, h2).item())
+            fd[q] = (ev[0] - ev[1]) / (2 * h)
+        torch.cuda.synchronize()
+        f1 = time.perf_counter()
+        t_full = (f1 - f0) / len(idx) * M
+        out["fd_baseline"] = {
+            "what": "same GPU, FP64 amplitudes: E(theta +- h e_p) by forward sweep + energy, h=1e-5",
+            "params_timed": int(len(idx)),
+            "extrapolated": True,
+            "seconds_per_full_gradient": round(t_full, 4),
+            "evals_per_s": round(1.0 / t_full, 6),
+            "adjoint_speedup": round(value * t_full, 2),
+            "max_abs_grad_diff_vs_adjoint": float(np.max(np.abs(fd - g0[idx]))),
+        }
+        sf.close()
+
+    if not args.no_cpu_baseline:
+        import oracle
+        c0 = time.perf_counter()
+        E_ref, g_ref, _ = oracle.energy_and_grad(nq, [p.hf], [1.0], p.exc, p.theta[0], wl.threshold, p.h1, p.h2)
+        c1 = time.perf_counter()
+        out["cpu_baseline"] = {
+            "value": round(1.0 / (c1 - c0), 6),
+            "unit": "E+grad evals/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"one full E+grad evaluation of {wl.name} ({M} factors), single-threaded std::map FP64",
+            "seconds": round(c1 - c0, 3),
+            "host_cpus": os.cpu_count(),
+        }
+        out["parity_vs_oracle"] = {"abs_dE": abs(E0 - E_ref), "max_abs_dg": float(np.max(np.abs(g0 - g_ref)))}
+
+    s.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

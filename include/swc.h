@@ -93,6 +93,15 @@ typedef struct {
   double fwd_ms;         /* device time of the last forward sweep */
   double energy_ms;      /* device time of the last energy evaluation */
   double rev_ms;         /* device time of the last reverse (adjoint) sweep */
+  /* Per-kernel timing, filled only when the environment variable
+     SWC_KERNEL_TIMING=1 was set at swc_create (an event pair is then
+     recorded around every launch of these kernels): */
+  double rotate_kernel_ms;   /* summed duration of the forward rotate kernels */
+  int64_t rotate_launches;
+  double reverse_kernel_ms;  /* summed duration of the reverse kernels */
+  int64_t reverse_launches;
+  double sigma_kernel_ms;    /* duration of the sigma kernel */
+  int64_t partner_hits;      /* pairs whose partner existed (last forward sweep) */
 } swc_stats;
 
 /*

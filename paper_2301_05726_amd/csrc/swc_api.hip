@@ -78,7 +78,7 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   l.ckey = take(BH * 8);
   l.camp = take(BH * 8);
   l.cslot = take(BH * 4);
-  l.csig = take(BH * sizeof(Fx));
+  l.csig = take(BH * 8);
   l.cnt = take(static_cast<size_t>(B) * sizeof(Counters));
   l.fac = take(static_cast<size_t>(Mmax + 1) * sizeof(FacMask));
   l.trig = take(static_cast<size_t>(B) * static_cast<size_t>(Mmax + 1) * sizeof(Trig));
@@ -158,11 +158,16 @@ struct swc_ctx {
   double S0 = 1.0;
   bool built = false;
   std::vector<swc_exc> exc_cache;
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[8] = {};
   double fwd_ms = 0, energy_ms = 0, rev_ms = 0;
   int64_t log_records = 0;
   int grid = 1;
   std::vector<Counters> hcnt;
+  // optional per-launch timing (SWC_KERNEL_TIMING=1)
+  bool ktiming = false;
+  std::vector<hipEvent_t> kev;
+  double rot_ms = 0, revk_ms = 0, sig_ms = 0;
+  int64_t rot_n = 0, revk_n = 0;
 };
 
 namespace {
@@ -230,14 +235,41 @@ int check_theta(swc_ctx* c, const double* theta, int64_t M) {
   return SWC_OK;
 }
 
+// Event pool for per-launch timing: 2 events per timed launch.
+int ensure_kev(swc_ctx* c, size_t n) {
+  while (c->kev.size() < n) {
+    hipEvent_t e;
+    SWC_HIP(hipEventCreate(&e));
+    c->kev.push_back(e);
+  }
+  return SWC_OK;
+}
+
+// Sum of the durations between event pairs [2i, 2i+1) for i < n.
+double sum_pairs(swc_ctx* c, int64_t n) {
+  double t = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->kev[2 * i], c->kev[2 * i + 1]) == hipSuccess) t += ms;
+  }
+  return t;
+}
+
 int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
+  if (c->ktiming) {
+    int r0 = ensure_kev(c, static_cast<size_t>(2 * M + 2));
+    if (r0) return r0;
+  }
   launch_sweep_begin(c->tab, c->sa, c->cnt, M, c->B, c->st);
   SWC_HIP(hipEventRecord(c->ev[0], c->st));
   int r = dispatch(c, [&](auto* tp) {
     using T = std::remove_pointer_t<decltype(tp)>;
-    for (int64_t k = 1; k <= M; ++k)
+    for (int64_t k = 1; k <= M; ++k) {
+      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
                     log_on, c->B, c->grid, c->st);
+      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
+    }
     return SWC_OK;
   });
   if (r) return r;
@@ -251,8 +283,8 @@ int sweep_status(swc_ctx* c) {
   for (int b = 0; b < c->B; ++b) {
     const Counters& k = c->hcnt[b];
     if (k.flags & F_TABLE_FULL) return fail(SWC_ECAPACITY, "hash table full");
-    if (k.occ > c->H - c->H / 10) return fail(SWC_ECAPACITY, "hash table above 90% occupancy");
-    if (k.live == 0) return fail(SWC_EEMPTY, "truncation removed every determinant");
+    if (counter_total(k, C_OCC) > c->H - c->H / 10) return fail(SWC_ECAPACITY, "hash table above 90% occupancy");
+    if (counter_total(k, C_LIVE) == 0) return fail(SWC_EEMPTY, "truncation removed every determinant");
     if (k.flags & F_INCONSISTENT) return fail(SWC_EDEVICE, "inconsistent pair state in the reverse sweep");
   }
   return SWC_OK;
@@ -275,7 +307,14 @@ int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool 
   for (int b = 0; b < c->B; ++b) nmax = std::max<int64_t>(nmax, static_cast<int64_t>(c->hcnt[b].ncompact));
   if (nmax == 0) return fail(SWC_EEMPTY, "empty state");
   const int n = c->nq / 2;
-  launch_sigma(c->cp, c->cnt, c->H, h1, h2, n, nmax, c->B, c->st);
+  SWC_HIP(hipEventRecord(c->ev[6], c->st));
+  r = dispatch(c, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    launch_sigma<T>(c->tab, c->cp, c->cnt, h1, h2, c->nq, nmax, c->B, c->st);
+    return SWC_OK;
+  });
+  if (r) return r;
+  SWC_HIP(hipEventRecord(c->ev[7], c->st));
   launch_energy_reduce(c->cp, c->cnt, c->H, h1, h2, n, nmax, c->B, c->st);
   launch_energy_final(c->cnt, E, c->B, c->st);
   if (want_lambda) {
@@ -347,7 +386,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
                   reinterpret_cast<uint32_t*>(w + l.logn),  reinterpret_cast<uint32_t*>(w + l.logoff),
                   c->Mmax + 1};
   c->cp = Compact{reinterpret_cast<uint64_t*>(w + l.ckey), reinterpret_cast<double*>(w + l.camp),
-                  reinterpret_cast<uint32_t*>(w + l.cslot), reinterpret_cast<Fx*>(w + l.csig)};
+                  reinterpret_cast<uint32_t*>(w + l.cslot), reinterpret_cast<double*>(w + l.csig)};
   c->cnt = reinterpret_cast<Counters*>(w + l.cnt);
   c->fac = reinterpret_cast<FacMask*>(w + l.fac);
   c->trig = reinterpret_cast<Trig*>(w + l.trig);
@@ -360,6 +399,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     if (v > 0) g = std::min(v, grid_for(c->H, 256, 1 << 20));
   }
   c->grid = g;
+  if (const char* e = std::getenv("SWC_KERNEL_TIMING")) c->ktiming = std::atoi(e) != 0;
   for (auto& e : c->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
       swc_destroy(c);
@@ -425,6 +465,10 @@ int swc_apply_ucc(swc_ctx* c, const double* theta, const swc_exc* exc, int64_t M
   if ((r = forward_sweep(c, M, threshold, 0))) return r;
   if ((r = read_counters(c))) return r;
   c->fwd_ms = elapsed(c->ev[0], c->ev[1]);
+  if (c->ktiming) {
+    c->rot_ms = sum_pairs(c, M);
+    c->rot_n = M;
+  }
   r = sweep_status(c);
   if (r) c->built = false;
   return r;
@@ -437,6 +481,7 @@ int swc_energy(swc_ctx* c, const double* h1, const double* h2, double* E) {
   int r = energy_impl(c, h1, h2, E, false);
   if (r) return r;
   c->energy_ms = elapsed(c->ev[2], c->ev[3]);
+  c->sig_ms = elapsed(c->ev[6], c->ev[7]);
   return SWC_OK;
 }
 
@@ -464,11 +509,16 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
       return fail(SWC_ECAPACITY, "truncation log full");
     }
   c->fwd_ms = elapsed(c->ev[0], c->ev[1]);
+  if (c->ktiming) {
+    c->rot_ms = sum_pairs(c, M);
+    c->rot_n = M;
+  }
   if ((r = energy_impl(c, h1, h2, E, true))) {
     reset_state(c);
     return r;
   }
   c->energy_ms = elapsed(c->ev[2], c->ev[3]);
+  c->sig_ms = elapsed(c->ev[6], c->ev[7]);
   // offsets of the per-step truncation-log records
   const int64_t S = c->Mmax + 1;
   std::vector<uint32_t> logn(static_cast<size_t>(c->B * S)), logoff(static_cast<size_t>(c->B * S), 0u);
@@ -492,7 +542,9 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   r = dispatch(c, [&](auto* tp) {
     using T = std::remove_pointer_t<decltype(tp)>;
     for (int64_t k = M; k >= 1; --k) {
+      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid, c->st);
+      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
       if (maxn[k]) launch_log_restore<T>(c->tab, c->lg, c->sa, static_cast<int>(k), c->B, maxn[k], c->st);
     }
     return SWC_OK;
@@ -503,6 +555,10 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   SWC_HIP(hipGetLastError());
   if ((r = read_counters(c))) return r;
   c->rev_ms = elapsed(c->ev[4], c->ev[5]);
+  if (c->ktiming) {
+    c->revk_ms = sum_pairs(c, M);
+    c->revk_n = M;
+  }
   for (int b = 0; b < c->B; ++b)
     if (c->hcnt[b].flags & F_INCONSISTENT) {
       reset_state(c);
@@ -553,18 +609,24 @@ int swc_get_stats(swc_ctx* c, swc_stats* out) {
   swc_stats s{};
   for (int b = 0; b < c->B; ++b) {
     const Counters& k = c->hcnt[b];
-    s.det_updates += static_cast<int64_t>(k.du);
-    s.pair_updates += static_cast<int64_t>(k.pairs);
-    s.inserts += static_cast<int64_t>(k.inserts);
-    s.pruned += static_cast<int64_t>(k.pruned);
+    s.det_updates += static_cast<int64_t>(counter_total(k, C_DU));
+    s.pair_updates += static_cast<int64_t>(counter_total(k, C_PAIRS));
+    s.inserts += static_cast<int64_t>(counter_total(k, C_INS));
+    s.pruned += static_cast<int64_t>(counter_total(k, C_PRUNED));
   }
-  s.n_live = static_cast<int64_t>(c->hcnt[0].live);
-  s.slots_used = static_cast<int64_t>(c->hcnt[0].occ);
+  s.n_live = static_cast<int64_t>(counter_total(c->hcnt[0], C_LIVE));
+  s.slots_used = static_cast<int64_t>(counter_total(c->hcnt[0], C_OCC));
   s.log_records = c->log_records;
   s.table_slots = static_cast<int64_t>(c->H);
   s.fwd_ms = c->fwd_ms;
   s.energy_ms = c->energy_ms;
   s.rev_ms = c->rev_ms;
+  s.rotate_kernel_ms = c->rot_ms;
+  s.rotate_launches = c->rot_n;
+  s.reverse_kernel_ms = c->revk_ms;
+  s.reverse_launches = c->revk_n;
+  s.sigma_kernel_ms = c->sig_ms;
+  for (int b = 0; b < c->B; ++b) s.partner_hits += static_cast<int64_t>(counter_total(c->hcnt[b], C_HITS));
   *out = s;
   return SWC_OK;
 }
@@ -587,6 +649,7 @@ void swc_destroy(swc_ctx* c) {
   if (!c) return;
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->kev) (void)hipEventDestroy(e);
   delete c;
 }
 

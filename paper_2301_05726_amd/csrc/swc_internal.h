@@ -39,15 +39,27 @@ struct Fx {
   unsigned long long hi;
 };
 
+// Event counters are sharded: a block adds to shard (blockIdx.x % CSH), each
+// shard in its own 128-byte line, so concurrent atomics rarely meet.
+constexpr int CSH = 32;
+enum : int {
+  C_LIVE = 0,  // alive entries
+  C_OCC,       // slots holding a key (alive + tombstones)
+  C_DU,        // det visits (forward)
+  C_PAIRS,     // rotated pairs (forward)
+  C_INS,       // created entries (forward)
+  C_PRUNED,    // truncated amplitudes (forward)
+  C_HITS,      // rotated pairs whose partner existed (forward)
+  C_NCNT
+};
+struct alignas(128) CShard {
+  unsigned long long v[16];
+};
+
 // per-state device counters
 struct Counters {
-  unsigned long long live;      // alive entries
-  unsigned long long occ;       // slots holding a key (alive + tombstones)
+  CShard sh[CSH];
   unsigned long long logcnt;    // truncation-log records this sweep
-  unsigned long long du;        // det visits (forward)
-  unsigned long long pairs;     // rotated pairs (forward)
-  unsigned long long inserts;   // created entries (forward)
-  unsigned long long pruned;    // truncated amplitudes (forward)
   unsigned long long ncompact;  // entries in the compact arrays
   unsigned int flags;
   unsigned int pad;
@@ -57,6 +69,12 @@ struct Counters {
   double E;
   double pad2;
 };
+
+inline unsigned long long counter_total(const Counters& c, int which) {
+  unsigned long long t = 0;
+  for (int s = 0; s < CSH; ++s) t += c.sh[s].v[which];
+  return t;
+}
 
 struct FacMask {
   uint64_t occ, vir, sgn;
@@ -86,7 +104,9 @@ struct LogArr {
   uint64_t cap;
 };
 
-// per-step arrays, member b at offset b*stride (stride = max_factors + 1)
+// per-step arrays (stride = max_factors + 1): scale/logn/logoff of member b
+// at b*stride + k; the sharded accumulators pw/pcnt/gacc at
+// (b*SH + shard)*stride + k, so different shards live in different lines.
 struct StepArr {
   double* scale;   // scale[j] = S after step j
   Fx* pw;          // removed raw weight at step k
@@ -102,7 +122,7 @@ struct Compact {
   uint64_t* key;
   double* amp;
   uint32_t* slot;
-  Fx* sig;
+  double* sig;
 };
 
 // ---------------------------------------------------------------------------
@@ -126,7 +146,8 @@ void launch_log_restore(const Tab& t, const LogArr& lg, const StepArr& sa, int k
                         hipStream_t st);
 template <class T>
 void launch_compact(const Tab& t, const Compact& cp, Counters* cnt, int B, int grid, hipStream_t st);
-void launch_sigma(const Compact& cp, const Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
+template <class T>
+void launch_sigma(const Tab& t, const Compact& cp, const Counters* cnt, const double* h1, const double* h2, int nq,
                   int64_t nmax, int B, hipStream_t st);
 void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
                           int64_t nmax, int B, hipStream_t st);

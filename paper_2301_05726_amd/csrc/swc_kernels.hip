@@ -87,17 +87,17 @@ __device__ __forceinline__ unsigned long long wave_u64(unsigned long long v) {
   return v;
 }
 
-// block-wide sums of one Fx and up to 6 counters; result valid in thread 0
+// block-wide sums of one Fx and up to 7 counters; result valid in thread 0
 struct Red {
   Fx f;
-  unsigned long long c[6];
+  unsigned long long c[7];
 };
 
 __device__ __forceinline__ Red block_reduce(Red r) {
   __shared__ Red part[BLK / 64];
   r.f = wave_fx(r.f);
 #pragma unroll
-  for (int i = 0; i < 6; ++i) r.c[i] = wave_u64(r.c[i]);
+  for (int i = 0; i < 7; ++i) r.c[i] = wave_u64(r.c[i]);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) part[w] = r;
   __syncthreads();
@@ -105,7 +105,7 @@ __device__ __forceinline__ Red block_reduce(Red r) {
     for (int i = 1; i < static_cast<int>(blockDim.x >> 6); ++i) {
       r.f = fx_add(r.f, part[i].f);
 #pragma unroll
-      for (int j = 0; j < 6; ++j) r.c[j] += part[i].c[j];
+      for (int j = 0; j < 7; ++j) r.c[j] += part[i].c[j];
     }
   }
   return r;
@@ -144,6 +144,16 @@ __device__ __forceinline__ int64_t claim_slot(uint64_t* keys, uint64_t H, uint64
 }
 
 __device__ __forceinline__ uint32_t shard() { return blockIdx.x & (SH - 1); }
+__device__ __forceinline__ uint32_t cshard() { return blockIdx.x & (CSH - 1); }
+
+// index of the sharded per-step accumulators
+__device__ __forceinline__ int64_t sidx(const StepArr& sa, int b, int sh, int64_t k) {
+  return (static_cast<int64_t>(b) * SH + sh) * sa.stride + k;
+}
+
+__device__ __forceinline__ void count(Counters* cnt, int b, int which, unsigned long long v) {
+  if (v) atomicAdd(&cnt[b].sh[cshard()].v[which], v);
+}
 
 template <class T>
 __device__ __forceinline__ T fmaT(T a, T b, T c);
@@ -168,8 +178,8 @@ __device__ double scale_before(const StepArr& sa, int b, int k) {
       Fx w = fx_zero();
       unsigned long long c = 0;
       if (lane < SH) {
-        w = sa.pw[(base + k - 1) * SH + lane];
-        c = sa.pcnt[(base + k - 1) * SH + lane];
+        w = sa.pw[sidx(sa, b, lane, k - 1)];
+        c = sa.pcnt[sidx(sa, b, lane, k - 1)];
       }
       w = wave_fx(w);
       c = wave_u64(c);
@@ -223,8 +233,8 @@ __global__ void k_insert_init(Tab t, Counters* cnt, const uint64_t* __restrict__
   }
   ok = wave_u64(ok);
   if ((threadIdx.x & 63) == 0 && ok) {
-    atomicAdd(&cnt[b].live, ok);
-    atomicAdd(&cnt[b].occ, ok);
+    count(cnt, b, C_LIVE, ok);
+    count(cnt, b, C_OCC, ok);
   }
 }
 
@@ -257,18 +267,23 @@ __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
   }
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
   for (uint64_t i = gtid; i < static_cast<uint64_t>((M + 1) * SH); i += gsz) {
-    sa.pw[base * SH + i] = fx_zero();
-    sa.pcnt[base * SH + i] = 0u;
-    sa.gacc[base * SH + i] = fx_zero();
+    const int sh = static_cast<int>(i / (M + 1));
+    const int64_t k = static_cast<int64_t>(i % (M + 1));
+    sa.pw[sidx(sa, b, sh, k)] = fx_zero();
+    sa.pcnt[sidx(sa, b, sh, k)] = 0u;
+    sa.gacc[sidx(sa, b, sh, k)] = fx_zero();
   }
   for (uint64_t i = gtid; i < static_cast<uint64_t>(M + 1); i += gsz) sa.logn[base + i] = 0u;
+  for (uint64_t i = gtid; i < static_cast<uint64_t>(CSH); i += gsz) {
+    cnt[b].sh[i].v[C_DU] = 0;
+    cnt[b].sh[i].v[C_PAIRS] = 0;
+    cnt[b].sh[i].v[C_INS] = 0;
+    cnt[b].sh[i].v[C_PRUNED] = 0;
+    cnt[b].sh[i].v[C_HITS] = 0;
+  }
   if (gtid == 0) {
     sa.scale[base] = cnt[b].S;
     cnt[b].logcnt = 0;
-    cnt[b].du = 0;
-    cnt[b].pairs = 0;
-    cnt[b].inserts = 0;
-    cnt[b].pruned = 0;
   }
 }
 
@@ -314,8 +329,9 @@ __global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ 
 
   Red r;
   r.f = fx_zero();
-  for (int i = 0; i < 6; ++i) r.c[i] = 0;
-  // c[0] removed count, c[1] visits, c[2] pairs, c[3] creates, c[4] kills, c[5] new slots
+  for (int i = 0; i < 7; ++i) r.c[i] = 0;
+  // c[0] removed count, c[1] visits, c[2] pairs, c[3] creates, c[4] kills, c[5] new slots,
+  // c[6] pairs whose partner existed
   unsigned int flags = 0;
 
   auto kill = [&](uint64_t s, T v) {
@@ -390,6 +406,7 @@ __global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ 
     }
     if (upper && p_start) continue;  // the lower member owns the pair
     r.c[2] += 1;
+    if (lower && p_alive) r.c[6] += 1;
     const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
     T x, y;
     if (lower) {
@@ -423,15 +440,16 @@ __global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ 
   if (threadIdx.x == 0) {
     const uint32_t sh = shard();
     if (r.c[0]) {
-      fx_atomic_add(&sa.pw[(base + k) * SH + sh], r.f);
-      atomicAdd(&sa.pcnt[(base + k) * SH + sh], static_cast<uint32_t>(r.c[0]));
-      atomicAdd(&cnt[b].pruned, r.c[0]);
+      fx_atomic_add(&sa.pw[sidx(sa, b, sh, k)], r.f);
+      atomicAdd(&sa.pcnt[sidx(sa, b, sh, k)], static_cast<uint32_t>(r.c[0]));
     }
-    if (r.c[1]) atomicAdd(&cnt[b].du, r.c[1]);
-    if (r.c[2]) atomicAdd(&cnt[b].pairs, r.c[2]);
-    if (r.c[3]) atomicAdd(&cnt[b].inserts, r.c[3]);
-    if (r.c[3] != r.c[4]) atomicAdd(&cnt[b].live, r.c[3] - r.c[4]);
-    if (r.c[5]) atomicAdd(&cnt[b].occ, r.c[5]);
+    count(cnt, b, C_PRUNED, r.c[0]);
+    count(cnt, b, C_DU, r.c[1]);
+    count(cnt, b, C_PAIRS, r.c[2]);
+    count(cnt, b, C_INS, r.c[3]);
+    count(cnt, b, C_LIVE, r.c[3] - r.c[4]);
+    count(cnt, b, C_OCC, r.c[5]);
+    count(cnt, b, C_HITS, r.c[6]);
   }
 }
 
@@ -458,7 +476,6 @@ __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ 
   T* lam = static_cast<T*>(t.lam) + b * H;
   uint32_t* meta = t.meta + b * H;
   uint32_t* born = t.born + b * H;
-  const int64_t base = static_cast<int64_t>(b) * sa.stride;
 
   const FacMask f = fac[k - 1];
   const Trig tr = trig[b * ld + k - 1];
@@ -468,7 +485,7 @@ __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ 
 
   Red r;
   r.f = fx_zero();
-  for (int i = 0; i < 6; ++i) r.c[i] = 0;
+  for (int i = 0; i < 7; ++i) r.c[i] = 0;
   unsigned int flags = 0;
 
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
@@ -558,7 +575,7 @@ __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ 
   }
   if (flags) atomicOr(&cnt[b].flags, flags);
   r = block_reduce(r);
-  if (threadIdx.x == 0 && fx_nonzero(r.f)) fx_atomic_add(&sa.gacc[(base + k) * SH + shard()], r.f);
+  if (threadIdx.x == 0 && fx_nonzero(r.f)) fx_atomic_add(&sa.gacc[sidx(sa, b, shard(), k)], r.f);
 }
 
 // Tombstones overwritten by a resurrection in forward step k get their old
@@ -609,7 +626,7 @@ __global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cn
       cp.key[b * H + pos] = key;
       cp.amp[b * H + pos] = static_cast<double>(static_cast<const T*>(t.amp)[b * H + s]);
       cp.slot[b * H + pos] = static_cast<uint32_t>(s);
-      cp.sig[b * H + pos] = fx_zero();
+      cp.sig[b * H + pos] = 0.0;
     }
   }
 }
@@ -669,47 +686,110 @@ __device__ double h_diag(uint64_t I, const double* __restrict__ h1, const double
   return v;
 }
 
-constexpr int TJ = 256;
+constexpr int SG = 16;               // lanes per determinant in the sigma kernel
+constexpr int TRI = 32 * 31 / 2;     // index pairs i1 < i2 < 32
+constexpr int LROW = 132;            // bytes per lane of orbital lists (padded: no LDS bank conflicts)
 
-// sigma_I += sum_J <I|H|J> c_J over J in a chunk of the compact list; one
-// lane per I, J tiles staged in LDS.  Exact fixed-point accumulation.
-__global__ __launch_bounds__(BLK) void k_sigma(Compact cp, const Counters* cnt, uint64_t H,
-                                               const double* __restrict__ h1, const double* __restrict__ h2, int n) {
-  const int b = blockIdx.z;
+// sigma_I = sum_J <I|H|J> c_J over the single and double excitations J of I
+// that are alive in the table (off-diagonal part; the diagonal is added in
+// k_energy_reduce).  SG lanes share one I.  Every excitation class
+// (alpha/beta singles, alpha-alpha, beta-beta, alpha-beta doubles) is a flat
+// index range; lane g takes indices g, g+SG, ... so all lanes of a wave probe
+// in lockstep.  Each lane keeps the orbital lists of I in its own LDS row
+// (occupied alpha, occupied beta, empty alpha, empty beta) and a block-shared
+// table maps a pair index to (i1 < i2).  The SG partial sums are combined by
+// a fixed shuffle tree, so sigma is bit-reproducible.
+template <class T>
+__global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters* cnt,
+                                               const double* __restrict__ h1, const double* __restrict__ h2,
+                                               int nq) {
+  __shared__ uint16_t tri[TRI];
+  __shared__ uint8_t lists[BLK * LROW];
+  for (int e = threadIdx.x; e < TRI; e += blockDim.x) {
+    int i2 = 1;
+    while ((i2 + 1) * i2 / 2 <= e) ++i2;
+    const int i1 = e - i2 * (i2 - 1) / 2;
+    tri[e] = static_cast<uint16_t>(i1 | (i2 << 8));
+  }
+  __syncthreads();
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
   const int64_t N = static_cast<int64_t>(cnt[b].ncompact);
-  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * BLK;
-  const int64_t chunks = gridDim.y;
-  int64_t per = (N + chunks - 1) / chunks;
-  per = (per + TJ - 1) / TJ * TJ;
-  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * per;
-  const int64_t j1 = (j0 + per < N) ? j0 + per : N;
-  if (i0 >= N || j0 >= N) return;
-  const uint64_t* ck = cp.key + b * H;
-  const double* ca = cp.amp + b * H;
-  __shared__ uint64_t sk[TJ];
-  __shared__ double sa[TJ];
-  const int64_t i = i0 + threadIdx.x;
-  const bool act = i < N;
-  const uint64_t I = act ? ck[i] : 0ull;
-  Fx acc = fx_zero();
-  for (int64_t jt = j0; jt < j1; jt += TJ) {
-    __syncthreads();
-    const int64_t j = jt + threadIdx.x;
-    if (j < j1) {
-      sk[threadIdx.x] = ck[j];
-      sa[threadIdx.x] = ca[j];
+  const uint64_t* keys = t.keys + b * H;
+  const T* amp = static_cast<const T*>(t.amp) + b * H;
+  const uint32_t* meta = t.meta + b * H;
+  const int n = nq / 2;
+  const int g = threadIdx.x & (SG - 1);
+  const uint64_t full = nq >= 64 ? ~0ull : ((1ull << nq) - 1ull);
+  const uint64_t ALPHA = 0x5555555555555555ull & full, BETA = 0xAAAAAAAAAAAAAAAAull & full;
+  const int64_t gstride = static_cast<int64_t>(gridDim.x) * (blockDim.x / SG);
+  uint8_t* occA = lists + threadIdx.x * LROW;
+  uint8_t* occB = occA + 32;
+  uint8_t* virA = occA + 64;
+  uint8_t* virB = occA + 96;
+  auto probe = [&](uint64_t J, double* a) -> bool {
+    uint64_t ff;
+    const int64_t s = find_slot(keys, H, J, &ff);
+    if (s < 0 || (meta[s] & DEAD)) return false;
+    *a = static_cast<double>(amp[s]);
+    return true;
+  };
+  auto fill = [](uint8_t* dst, uint64_t m) -> int {
+    int c = 0;
+    for (; m; m &= m - 1ull) dst[c++] = static_cast<uint8_t>(__ffsll(static_cast<long long>(m)) - 1);
+    return c;
+  };
+  for (int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / SG; i < N; i += gstride) {
+    const uint64_t I = cp.key[b * H + i];
+    const int oA = fill(occA, I & ALPHA), oB = fill(occB, I & BETA);
+    const int vA = fill(virA, ~I & ALPHA), vB = fill(virB, ~I & BETA);
+    double acc = 0.0;
+    double a;
+    // singles
+    for (int e = g; e < oA * vA; e += SG) {
+      const int x = e / vA;
+      const uint64_t J = I ^ (1ull << occA[x]) ^ (1ull << virA[e - x * vA]);
+      if (probe(J, &a)) acc += h_offdiag(I, J, 2, h1, h2, n) * a;
     }
-    __syncthreads();
-    const int cntj = static_cast<int>((j1 - jt) < TJ ? (j1 - jt) : TJ);
-    if (act) {
-      for (int tt = 0; tt < cntj; ++tt) {
-        const uint64_t J = sk[tt];
-        const int pc = __popcll(I ^ J);
-        if (pc == 2 || pc == 4) acc = fx_add(acc, fx_from(h_offdiag(I, J, pc, h1, h2, n) * sa[tt]));
+    for (int e = g; e < oB * vB; e += SG) {
+      const int x = e / vB;
+      const uint64_t J = I ^ (1ull << occB[x]) ^ (1ull << virB[e - x * vB]);
+      if (probe(J, &a)) acc += h_offdiag(I, J, 2, h1, h2, n) * a;
+    }
+    // same-spin doubles
+    for (int sp = 0; sp < 2; ++sp) {
+      const uint8_t* oc = sp ? occB : occA;
+      const uint8_t* vi = sp ? virB : virA;
+      const int no = sp ? oB : oA, nv = sp ? vB : vA;
+      const int npv = nv * (nv - 1) / 2;
+      const int tot = no * (no - 1) / 2 * npv;
+      for (int e = g; e < tot; e += SG) {
+        const int x = e / npv;
+        const uint16_t po = tri[x], pv = tri[e - x * npv];
+        const uint64_t J = I ^ (1ull << oc[po & 255]) ^ (1ull << oc[po >> 8]) ^ (1ull << vi[pv & 255]) ^
+                           (1ull << vi[pv >> 8]);
+        if (probe(J, &a)) acc += h_offdiag(I, J, 4, h1, h2, n) * a;
       }
     }
+    // opposite-spin doubles
+    {
+      const int tot = oA * oB * vA * vB;
+      for (int e = g; e < tot; e += SG) {
+        int r = e;
+        const int xa = r % vA;
+        r /= vA;
+        const int xb = r % vB;
+        r /= vB;
+        const int jb = r % oB;
+        const int ia = r / oB;
+        const uint64_t J = I ^ (1ull << occA[ia]) ^ (1ull << occB[jb]) ^ (1ull << virA[xa]) ^ (1ull << virB[xb]);
+        if (probe(J, &a)) acc += h_offdiag(I, J, 4, h1, h2, n) * a;
+      }
+    }
+#pragma unroll
+    for (int o = SG / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, SG);
+    if (g == 0) cp.sig[b * H + i] = acc;
   }
-  if (act && fx_nonzero(acc)) fx_atomic_add(&cp.sig[b * H + i], acc);
 }
 
 // adds the diagonal, then sum c*sigma and sum c^2 (exact) per state
@@ -721,15 +801,14 @@ __global__ __launch_bounds__(BLK) void k_energy_reduce(Compact cp, Counters* cnt
   Fx num = fx_zero(), den = fx_zero();
   for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     const double c = cp.amp[b * H + i];
-    const Fx sg = fx_add(cp.sig[b * H + i], fx_from(h_diag(cp.key[b * H + i], h1, h2, n) * c));
-    cp.sig[b * H + i] = sg;
-    const double sig = fx_to_d(sg);
+    const double sig = cp.sig[b * H + i] + h_diag(cp.key[b * H + i], h1, h2, n) * c;
+    cp.sig[b * H + i] = sig;
     num = fx_add(num, fx_from(c * sig));
     den = fx_add(den, fx_from(c * c));
   }
   Red r;
   r.f = num;
-  for (int q = 0; q < 6; ++q) r.c[q] = 0;
+  for (int q = 0; q < 7; ++q) r.c[q] = 0;
   r = block_reduce(r);
   if (threadIdx.x == 0 && fx_nonzero(r.f)) fx_atomic_add(&cnt[b].num, r.f);
   __syncthreads();
@@ -762,18 +841,17 @@ __global__ void k_lambda(Tab t, Compact cp, const Counters* cnt) {
   const int64_t N = static_cast<int64_t>(cnt[b].ncompact);
   const double E = cnt[b].E;
   for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
-    const double v = fx_to_d(cp.sig[b * H + i]) - E * cp.amp[b * H + i];
+    const double v = cp.sig[b * H + i] - E * cp.amp[b * H + i];
     static_cast<T*>(t.lam)[b * H + cp.slot[b * H + i]] = static_cast<T>(v);
   }
 }
 
 __global__ void k_grad_final(StepArr sa, const Counters* cnt, double* grad, int64_t M) {
   const int b = blockIdx.y;
-  const int64_t base = static_cast<int64_t>(b) * sa.stride;
   const double den = fx_to_d(cnt[b].den);
   for (int64_t k = blockIdx.x * blockDim.x + threadIdx.x; k < M; k += gridDim.x * blockDim.x) {
     Fx g = fx_zero();
-    for (int q = 0; q < SH; ++q) g = fx_add(g, sa.gacc[(base + k + 1) * SH + q]);
+    for (int q = 0; q < SH; ++q) g = fx_add(g, sa.gacc[sidx(sa, b, q, k + 1)]);
     grad[b * M + k] = 2.0 * fx_to_d(g) / den;
   }
 }
@@ -837,16 +915,12 @@ void launch_compact(const Tab& t, const Compact& cp, Counters* cnt, int B, int g
   hipLaunchKernelGGL(k_compact<T>, dim3(grid, B), dim3(BLK), 0, st, t, cp, cnt);
 }
 
-void launch_sigma(const Compact& cp, const Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
+template <class T>
+void launch_sigma(const Tab& t, const Compact& cp, const Counters* cnt, const double* h1, const double* h2, int nq,
                   int64_t nmax, int B, hipStream_t st) {
   if (nmax <= 0) return;
-  const int gi = grid_for(nmax, BLK, 1 << 30);
-  // enough J chunks to give the chip a few thousand blocks, each chunk >= 1 tile
-  int64_t chunks = (4096 + gi - 1) / gi;
-  const int64_t maxch = (nmax + TJ - 1) / TJ;
-  if (chunks > maxch) chunks = maxch;
-  if (chunks < 1) chunks = 1;
-  hipLaunchKernelGGL(k_sigma, dim3(gi, static_cast<unsigned>(chunks), B), dim3(BLK), 0, st, cp, cnt, H, h1, h2, n);
+  hipLaunchKernelGGL(k_sigma<T>, dim3(grid_for(static_cast<uint64_t>(nmax) * SG, BLK, 16384), B), dim3(BLK), 0, st,
+                     t, cp, cnt, h1, h2, nq);
 }
 
 void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
@@ -882,7 +956,9 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
   template void launch_log_restore<T>(const Tab&, const LogArr&, const StepArr&, int, int, uint32_t,              \
                                       hipStream_t);                                                                \
   template void launch_compact<T>(const Tab&, const Compact&, Counters*, int, int, hipStream_t);                  \
-  template void launch_lambda<T>(const Tab&, const Compact&, const Counters*, int64_t, int, hipStream_t);
+  template void launch_lambda<T>(const Tab&, const Compact&, const Counters*, int64_t, int, hipStream_t);        \
+  template void launch_sigma<T>(const Tab&, const Compact&, const Counters*, const double*, const double*, int,   \
+                                int64_t, int, hipStream_t);
 
 SWC_INST(float)
 SWC_INST(double)

@@ -38,6 +38,9 @@ class Stats(ctypes.Structure):
         ("inserts", ctypes.c_int64), ("pruned", ctypes.c_int64), ("log_records", ctypes.c_int64),
         ("table_slots", ctypes.c_int64), ("slots_used", ctypes.c_int64),
         ("fwd_ms", ctypes.c_double), ("energy_ms", ctypes.c_double), ("rev_ms", ctypes.c_double),
+        ("rotate_kernel_ms", ctypes.c_double), ("rotate_launches", ctypes.c_int64),
+        ("reverse_kernel_ms", ctypes.c_double), ("reverse_launches", ctypes.c_int64),
+        ("sigma_kernel_ms", ctypes.c_double), ("partner_hits", ctypes.c_int64),
     ]
 
 
