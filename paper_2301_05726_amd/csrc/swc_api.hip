@@ -39,15 +39,20 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of every workspace region.
 struct Layout {
-  size_t keys, amp, meta, born, lam;
+  size_t slots, aux;
   size_t lslot, lmeta, lborn, lamp;
-  size_t scale, pw, pcnt, gacc, logn, logoff;
+  size_t scale, pw, pcnt, gacc, logn, logoff, rmax, ws;
   size_t ckey, camp, cslot, csig;
-  size_t cnt, fac, trig, init_d, init_a;
+  size_t cnt, fac, trig, init_d, init_a, sync;
   size_t total;
 };
 
 bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+// Sweep kernels use at most this many 256-thread blocks per state; each of
+// their waves owns a statistics slot.
+constexpr int MAX_SWEEP_BLOCKS = 2048;
+size_t max_waves(uint64_t H) { return static_cast<size_t>(grid_for(H, 256, MAX_SWEEP_BLOCKS)) * 4; }
 
 Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   Layout l{};
@@ -60,11 +65,8 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   const size_t BH = static_cast<size_t>(B) * H;
   const size_t BL = static_cast<size_t>(B) * L;
   const size_t BS = static_cast<size_t>(B) * static_cast<size_t>(Mmax + 1);
-  l.keys = take(BH * 8);
-  l.amp = take(BH * tsz);
-  l.meta = take(BH * 4);
-  l.born = take(BH * 4);
-  l.lam = take(BH * tsz);
+  l.slots = take(BH * (tsz == 4 ? sizeof(Slot<float>) : sizeof(Slot<double>)));
+  l.aux = take(tsz == 4 ? BH * sizeof(AuxF) : 0);
   l.lslot = take(BL * 4);
   l.lmeta = take(BL * 4);
   l.lborn = take(BL * 4);
@@ -75,6 +77,8 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   l.gacc = take(BS * SH * sizeof(Fx));
   l.logn = take(BS * 4);
   l.logoff = take(BS * 4);
+  l.rmax = take(static_cast<size_t>(Mmax + 1) * 4);
+  l.ws = take(static_cast<size_t>(B) * max_waves(H) * WSTAT * 8);
   l.ckey = take(BH * 8);
   l.camp = take(BH * 8);
   l.cslot = take(BH * 4);
@@ -84,6 +88,7 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   l.trig = take(static_cast<size_t>(B) * static_cast<size_t>(Mmax + 1) * sizeof(Trig));
   l.init_d = take(H / 2 * 8);
   l.init_a = take(H / 2 * 8);
+  l.sync = take(sizeof(Sync));
   l.total = off;
   return l;
 }
@@ -135,6 +140,20 @@ FacMask factor_mask(const swc_exc& e) {
   return f;
 }
 
+// A captured run of per-step kernels: direction (0 forward, 1 reverse),
+// steps k0..k1, threshold and log flag are baked into the kernel arguments.
+struct GraphKey {
+  int dir;
+  int64_t k0, k1;
+  double thr;
+  int log_on;
+  uint64_t extra;
+  bool operator==(const GraphKey& o) const {
+    return dir == o.dir && k0 == o.k0 && k1 == o.k1 && thr == o.thr && log_on == o.log_on && extra == o.extra;
+  }
+};
+constexpr int64_t GRAPH_CHUNK = 2048;
+
 }  // namespace
 
 struct swc_ctx {
@@ -162,7 +181,17 @@ struct swc_ctx {
   double fwd_ms = 0, energy_ms = 0, rev_ms = 0;
   int64_t log_records = 0;
   int grid = 1;
+  // persistent (cooperative) sweeps, one launch per sweep: opt-in with
+  // SWC_SWEEP=persistent (per-step launches are faster on MI355X: a
+  // device-wide barrier needs agent-scope fences in every block)
+  bool persistent = false;
+  Sync* sy = nullptr;
+  int grid_fwd = 1, grid_rev = 1;
   std::vector<Counters> hcnt;
+  // per-step sweeps replayed from captured hipGraphs (SWC_GRAPH=0 disables)
+  bool use_graph = true;
+  hipStream_t cap_st = nullptr;
+  std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
   // optional per-launch timing (SWC_KERNEL_TIMING=1)
   bool ktiming = false;
   std::vector<hipEvent_t> kev;
@@ -199,7 +228,10 @@ int upload_masks(swc_ctx* c, const swc_exc* exc, int64_t M) {
 
 // Reset every batch member to |Psi_0>.
 int reset_state(swc_ctx* c) {
-  launch_fill(c->tab, c->B, c->st);
+  dispatch(c, [&](auto* tp) -> int {
+    launch_fill<std::remove_pointer_t<decltype(tp)>>(c->tab, c->B, c->st);
+    return SWC_OK;
+  });
   for (int b = 0; b < c->B; ++b) {
     Counters z{};
     z.S = c->S0;
@@ -209,7 +241,7 @@ int reset_state(swc_ctx* c) {
   const int64_t n = static_cast<int64_t>(c->h_init_d.size());
   SWC_HIP(hipMemcpyAsync(c->init_d, c->h_init_d.data(), 8 * n, hipMemcpyHostToDevice, c->st));
   SWC_HIP(hipMemcpyAsync(c->init_a, c->h_init_a.data(), 8 * n, hipMemcpyHostToDevice, c->st));
-  int r = dispatch(c, [&](auto* tp) {
+  int r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
     launch_insert_init<T>(c->tab, c->cnt, c->init_d, c->init_a, n, c->B, c->st);
     return SWC_OK;
@@ -255,15 +287,67 @@ double sum_pairs(swc_ctx* c, int64_t n) {
   return t;
 }
 
+// Executable graph for `key`, captured on first use: `record(stream)` issues
+// the kernel launches on a private capture stream (kernels only, no memset
+// or copy nodes); the graph is then replayed on the caller's stream.
+template <class F>
+int cached_graph(swc_ctx* c, const GraphKey& key, hipGraphExec_t* out, F&& record) {
+  for (auto& g : c->graphs)
+    if (g.first == key) {
+      *out = g.second;
+      return SWC_OK;
+    }
+  if (!c->cap_st) SWC_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+  SWC_HIP(hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal));
+  record(c->cap_st);
+  hipGraph_t g = nullptr;
+  SWC_HIP(hipStreamEndCapture(c->cap_st, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  SWC_HIP(e);
+  c->graphs.push_back({key, ex});
+  *out = ex;
+  return SWC_OK;
+}
+
 int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   if (c->ktiming) {
     int r0 = ensure_kev(c, static_cast<size_t>(2 * M + 2));
     if (r0) return r0;
   }
-  launch_sweep_begin(c->tab, c->sa, c->cnt, M, c->B, c->st);
+  dispatch(c, [&](auto* tp) -> int {
+    launch_sweep_begin<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, c->cnt, M, c->B, c->st);
+    return SWC_OK;
+  });
+  if (c->persistent) launch_sync_reset(c->sy, c->st);
   SWC_HIP(hipEventRecord(c->ev[0], c->st));
-  int r = dispatch(c, [&](auto* tp) {
+  int r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
+    if (M == 0) return SWC_OK;
+    if (c->persistent) {
+      if (c->ktiming) (void)hipEventRecord(c->kev[0], c->st);
+      SWC_HIP(launch_fwd_sweep<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, 1,
+                                  static_cast<int>(M), thr, 1, log_on, c->sy, c->B, c->grid_fwd, c->st));
+      if (c->ktiming) (void)hipEventRecord(c->kev[1], c->st);
+      return SWC_OK;
+    }
+    if (c->use_graph && !c->ktiming) {
+      // replay cached graphs of up to GRAPH_CHUNK steps each
+      for (int64_t k0 = 1; k0 <= M; k0 += GRAPH_CHUNK) {
+        const int64_t k1 = std::min<int64_t>(M, k0 + GRAPH_CHUNK - 1);
+        const GraphKey key{0, k0, k1, thr, log_on, 0};
+        hipGraphExec_t ex = nullptr;
+        const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) {
+          for (int64_t k = k0; k <= k1; ++k)
+            launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr,
+                          k == 1, log_on, c->B, c->grid, cs);
+        });
+        if (rr) return rr;
+        SWC_HIP(hipGraphLaunch(ex, c->st));
+      }
+      return SWC_OK;
+    }
     for (int64_t k = 1; k <= M; ++k) {
       if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
@@ -273,7 +357,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
     return SWC_OK;
   });
   if (r) return r;
-  launch_sweep_end(c->sa, c->cnt, M, c->B, c->st);
+  launch_sweep_end(c->sa, c->cnt, M, c->B, c->persistent ? c->sy : nullptr, c->st);
   SWC_HIP(hipEventRecord(c->ev[1], c->st));
   SWC_HIP(hipGetLastError());
   return SWC_OK;
@@ -286,6 +370,7 @@ int sweep_status(swc_ctx* c) {
     if (counter_total(k, C_OCC) > c->H - c->H / 10) return fail(SWC_ECAPACITY, "hash table above 90% occupancy");
     if (counter_total(k, C_LIVE) == 0) return fail(SWC_EEMPTY, "truncation removed every determinant");
     if (k.flags & F_INCONSISTENT) return fail(SWC_EDEVICE, "inconsistent pair state in the reverse sweep");
+    if (k.flags & F_TIMEOUT) return fail(SWC_EDEVICE, "grid barrier of a persistent sweep timed out");
   }
   return SWC_OK;
 }
@@ -295,7 +380,7 @@ int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool 
   if (!h1 || !h2) return fail(SWC_EINVAL, "null integrals");
   launch_energy_begin(c->cnt, c->B, c->st);
   SWC_HIP(hipEventRecord(c->ev[2], c->st));
-  int r = dispatch(c, [&](auto* tp) {
+  int r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
     launch_compact<T>(c->tab, c->cp, c->cnt, c->B, c->grid, c->st);
     return SWC_OK;
@@ -308,7 +393,7 @@ int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool 
   if (nmax == 0) return fail(SWC_EEMPTY, "empty state");
   const int n = c->nq / 2;
   SWC_HIP(hipEventRecord(c->ev[6], c->st));
-  r = dispatch(c, [&](auto* tp) {
+  r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
     launch_sigma<T>(c->tab, c->cp, c->cnt, h1, h2, c->nq, nmax, c->B, c->st);
     return SWC_OK;
@@ -318,7 +403,7 @@ int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool 
   launch_energy_reduce(c->cp, c->cnt, c->H, h1, h2, n, nmax, c->B, c->st);
   launch_energy_final(c->cnt, E, c->B, c->st);
   if (want_lambda) {
-    r = dispatch(c, [&](auto* tp) {
+    r = dispatch(c, [&](auto* tp) -> int {
       using T = std::remove_pointer_t<decltype(tp)>;
       launch_lambda<T>(c->tab, c->cp, c->cnt, nmax, c->B, c->st);
       return SWC_OK;
@@ -377,13 +462,15 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   c->lay = make_layout(c->H, tsz, c->B, c->Mmax, c->L);
   const Layout& l = c->lay;
   char* w = c->ws;
-  c->tab = Tab{reinterpret_cast<uint64_t*>(w + l.keys), w + l.amp, reinterpret_cast<uint32_t*>(w + l.meta),
-               reinterpret_cast<uint32_t*>(w + l.born), w + l.lam, c->H};
+  c->tab = Tab{w + l.slots, w + l.aux, c->H};
   c->lg = LogArr{reinterpret_cast<uint32_t*>(w + l.lslot), reinterpret_cast<uint32_t*>(w + l.lmeta),
                  reinterpret_cast<uint32_t*>(w + l.lborn), w + l.lamp, c->L};
   c->sa = StepArr{reinterpret_cast<double*>(w + l.scale),   reinterpret_cast<Fx*>(w + l.pw),
                   reinterpret_cast<uint32_t*>(w + l.pcnt),  reinterpret_cast<Fx*>(w + l.gacc),
                   reinterpret_cast<uint32_t*>(w + l.logn),  reinterpret_cast<uint32_t*>(w + l.logoff),
+                  reinterpret_cast<uint32_t*>(w + l.rmax),
+                  reinterpret_cast<unsigned long long*>(w + l.ws),
+                  static_cast<int64_t>(max_waves(c->H)),
                   c->Mmax + 1};
   c->cp = Compact{reinterpret_cast<uint64_t*>(w + l.ckey), reinterpret_cast<double*>(w + l.camp),
                   reinterpret_cast<uint32_t*>(w + l.cslot), reinterpret_cast<double*>(w + l.csig)};
@@ -393,13 +480,30 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   c->init_d = reinterpret_cast<uint64_t*>(w + l.init_d);
   c->init_a = reinterpret_cast<double*>(w + l.init_a);
   c->hcnt.assign(static_cast<size_t>(batch), Counters{});
-  int g = grid_for(c->H, 256, 2048);
-  if (const char* e = std::getenv("SWC_GRID")) {
+  int g = grid_for(c->H, 256, MAX_SWEEP_BLOCKS);
+  if (const char* e = std::getenv("SWC_GRID")) {  // tuning override, capped by the statistics slots
     int v = std::atoi(e);
-    if (v > 0) g = std::min(v, grid_for(c->H, 256, 1 << 20));
+    if (v > 0) g = std::min(v, grid_for(c->H, 256, MAX_SWEEP_BLOCKS));
   }
   c->grid = g;
+  c->sy = reinterpret_cast<Sync*>(w + l.sync);
+  if (const char* e = std::getenv("SWC_SWEEP")) c->persistent = std::strcmp(e, "persistent") == 0;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      delete c;
+      return fail(SWC_EDEVICE, "cannot query the device");
+    }
+    const int bf = prec == SWC_FP32 ? coop_blocks_per_cu<float>(0) : coop_blocks_per_cu<double>(0);
+    const int br = prec == SWC_FP32 ? coop_blocks_per_cu<float>(1) : coop_blocks_per_cu<double>(1);
+    // co-resident blocks shared by the batch members (grid.y = batch)
+    c->grid_fwd = std::min(g, bf * ncu / batch);
+    c->grid_rev = std::min(g, br * ncu / batch);
+    if (c->grid_fwd < 1 || c->grid_rev < 1) c->persistent = false;
+  }
   if (const char* e = std::getenv("SWC_KERNEL_TIMING")) c->ktiming = std::atoi(e) != 0;
+  if (const char* e = std::getenv("SWC_GRAPH")) c->use_graph = std::atoi(e) != 0;
   for (auto& e : c->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
       swc_destroy(c);
@@ -407,6 +511,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     }
   }
   if (hipMemsetAsync(c->cnt, 0, sizeof(Counters) * batch, c->st) != hipSuccess ||
+      hipMemsetAsync(c->sy, 0, sizeof(Sync), c->st) != hipSuccess ||
       hipStreamSynchronize(c->st) != hipSuccess) {
     swc_destroy(c);
     return fail(SWC_EDEVICE, "initialisation failed");
@@ -466,8 +571,9 @@ int swc_apply_ucc(swc_ctx* c, const double* theta, const swc_exc* exc, int64_t M
   if ((r = read_counters(c))) return r;
   c->fwd_ms = elapsed(c->ev[0], c->ev[1]);
   if (c->ktiming) {
-    c->rot_ms = sum_pairs(c, M);
-    c->rot_n = M;
+    const int64_t nl = c->persistent ? (M > 0 ? 1 : 0) : M;
+    c->rot_ms = sum_pairs(c, nl);
+    c->rot_n = nl;
   }
   r = sweep_status(c);
   if (r) c->built = false;
@@ -510,8 +616,9 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
     }
   c->fwd_ms = elapsed(c->ev[0], c->ev[1]);
   if (c->ktiming) {
-    c->rot_ms = sum_pairs(c, M);
-    c->rot_n = M;
+    const int64_t nl = c->persistent ? (M > 0 ? 1 : 0) : M;
+    c->rot_ms = sum_pairs(c, nl);
+    c->rot_n = nl;
   }
   if ((r = energy_impl(c, h1, h2, E, true))) {
     reset_state(c);
@@ -538,9 +645,37 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   if (c->log_records) {
     SWC_HIP(hipMemcpyAsync(c->sa.logoff, logoff.data(), 4 * c->B * S, hipMemcpyHostToDevice, c->st));
   }
+  if (c->persistent && M > 0) {
+    SWC_HIP(hipMemcpyAsync(c->sa.rmax, maxn.data(), 4 * (M + 1), hipMemcpyHostToDevice, c->st));
+    launch_sync_reset(c->sy, c->st);
+  }
   SWC_HIP(hipEventRecord(c->ev[4], c->st));
-  r = dispatch(c, [&](auto* tp) {
+  r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
+    if (c->persistent) {
+      if (M == 0) return SWC_OK;
+      if (c->ktiming) (void)hipEventRecord(c->kev[0], c->st);
+      SWC_HIP(launch_rev_sweep<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(M), 1,
+                                  c->sy, c->B, c->grid_rev, c->st));
+      if (c->ktiming) (void)hipEventRecord(c->kev[1], c->st);
+      return SWC_OK;
+    }
+    if (c->use_graph && !c->ktiming && c->log_records == 0) {
+      // no log restores interleaved: replay cached graphs, last chunk first
+      for (int64_t k1 = M; k1 >= 1; k1 -= GRAPH_CHUNK) {
+        const int64_t k0 = std::max<int64_t>(1, k1 - GRAPH_CHUNK + 1);
+        const GraphKey key{1, k0, k1, 0.0, 0, 0};
+        hipGraphExec_t ex = nullptr;
+        const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) {
+          for (int64_t k = k1; k >= k0; --k)
+            launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid,
+                          cs);
+        });
+        if (rr) return rr;
+        SWC_HIP(hipGraphLaunch(ex, c->st));
+      }
+      return SWC_OK;
+    }
     for (int64_t k = M; k >= 1; --k) {
       if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid, c->st);
@@ -552,17 +687,20 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   if (r) return r;
   launch_grad_final(c->sa, c->cnt, grad, M, c->B, c->st);
   SWC_HIP(hipEventRecord(c->ev[5], c->st));
+  if (c->persistent) launch_sweep_end(c->sa, c->cnt, 0, c->B, c->sy, c->st);  // barrier status only
   SWC_HIP(hipGetLastError());
   if ((r = read_counters(c))) return r;
   c->rev_ms = elapsed(c->ev[4], c->ev[5]);
   if (c->ktiming) {
-    c->revk_ms = sum_pairs(c, M);
-    c->revk_n = M;
+    const int64_t nl = c->persistent ? (M > 0 ? 1 : 0) : M;
+    c->revk_ms = sum_pairs(c, nl);
+    c->revk_n = nl;
   }
   for (int b = 0; b < c->B; ++b)
-    if (c->hcnt[b].flags & F_INCONSISTENT) {
+    if (c->hcnt[b].flags & (F_INCONSISTENT | F_TIMEOUT)) {
       reset_state(c);
-      return fail(SWC_EDEVICE, "inconsistent pair state in the reverse sweep");
+      return fail(SWC_EDEVICE, (c->hcnt[b].flags & F_TIMEOUT) ? "grid barrier of a persistent sweep timed out"
+                                                               : "inconsistent pair state in the reverse sweep");
     }
   if ((r = reset_state(c))) return r;
   return read_counters(c);
@@ -573,7 +711,7 @@ int swc_get_state(swc_ctx* c, int b, uint64_t* dets, double* amps, int64_t cap, 
   if (!c->built) return fail(SWC_ESTATE, "no state built");
   if (b < 0 || b >= c->B || !n_out) return fail(SWC_EINVAL, "bad batch index or output");
   launch_energy_begin(c->cnt, c->B, c->st);
-  int r = dispatch(c, [&](auto* tp) {
+  int r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
     launch_compact<T>(c->tab, c->cp, c->cnt, c->B, c->grid, c->st);
     return SWC_OK;
@@ -650,6 +788,8 @@ void swc_destroy(swc_ctx* c) {
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c->kev) (void)hipEventDestroy(e);
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+  if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
   delete c;
 }
 

@@ -19,7 +19,7 @@ namespace swc {
 // sweep resurrects them).  A dead entry keeps its key (tombstone) and, for a
 // death during the current sweep, the pre-truncation amplitude.
 constexpr uint64_t EMPTY_KEY = ~0ull;
-constexpr int SH = 16;  // shards of each per-step accumulator
+constexpr int SH = 64;  // shards of each per-step accumulator
 constexpr uint32_t DEAD = 0x80000000u;
 constexpr uint32_t TAG = 0x7fffffffu;
 
@@ -29,6 +29,13 @@ enum : uint32_t {
   F_LOG_FULL = 2u,
   F_BAD_THETA = 4u,
   F_INCONSISTENT = 8u,
+  F_TIMEOUT = 16u,  // a grid barrier of a persistent sweep gave up waiting
+};
+
+// grid-barrier state of the persistent sweeps (one 256-byte line)
+struct alignas(256) Sync {
+  unsigned int count;
+  unsigned int timeout;
 };
 
 // 128-bit two's complement fixed point, value = (hi:lo) * 2^-96.  Every
@@ -84,14 +91,35 @@ struct Trig {
   double c, s, cm1;  // cos, sin, cos - 1 (= -2 sin^2(theta/2))
 };
 
-// per-state arrays; member b lives at offset b*H
+// Hash-table slots.  float states: 16-byte {key, amp, meta} plus an 8-byte
+// side array {lam, born}; double states: one 32-byte slot.  lam is the
+// adjoint amplitude of the reverse sweep, born the creation tag.
+template <class T>
+struct Slot;
+template <>
+struct alignas(16) Slot<float> {
+  uint64_t key;
+  float amp;
+  uint32_t meta;
+};
+template <>
+struct alignas(32) Slot<double> {
+  uint64_t key;
+  double amp;
+  double lam;
+  uint32_t meta;
+  uint32_t born;
+};
+struct alignas(8) AuxF {
+  float lam;
+  uint32_t born;
+};
+
+// per-state tables; member b's slots start at b*H
 struct Tab {
-  uint64_t* keys;
-  void* amp;
-  uint32_t* meta;
-  uint32_t* born;
-  void* lam;
-  uint64_t H;  // slots, power of two
+  void* slots;  // Slot<T>[B*H]
+  void* aux;    // AuxF[B*H] for float states, unused for double
+  uint64_t H;   // slots per state, power of two
 };
 
 // truncation log: states of tombstones overwritten by a resurrection
@@ -114,8 +142,12 @@ struct StepArr {
   Fx* gacc;        // gradient dot product of step k
   uint32_t* logn;  // log records pushed at step k
   uint32_t* logoff;
+  uint32_t* rmax;  // max over the batch of logn at step k (index k only)
+  unsigned long long* ws;  // per-wave forward statistics, WSTAT per wave, nws waves per state
+  int64_t nws;
   int64_t stride;
 };
+constexpr int WSTAT = 8;
 
 // compact copies of the live entries (energy / state export), member b at b*H
 struct Compact {
@@ -128,13 +160,27 @@ struct Compact {
 // ---------------------------------------------------------------------------
 // kernel launchers (swc_kernels.hip); all asynchronous on `st`
 // ---------------------------------------------------------------------------
+template <class T>
 void launch_fill(const Tab& t, int B, hipStream_t st);
 template <class T>
 void launch_insert_init(const Tab& t, Counters* cnt, const uint64_t* dets, const double* amps, int64_t n, int B,
                         hipStream_t st);
 void launch_trig(const double* theta, Trig* trig, int64_t M, int64_t ld, int B, Counters* cnt, hipStream_t st);
+template <class T>
 void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st);
-void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st);
+void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, hipStream_t st);
+void launch_sync_reset(Sync* sy, hipStream_t st);
+// co-resident blocks per CU of the persistent forward (which=0) / reverse (1) sweep
+template <class T>
+int coop_blocks_per_cu(int which);
+template <class T>
+hipError_t launch_fwd_sweep(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa,
+                            Counters* cnt, const LogArr& lg, int k0, int k1, double thr, int prune_first, int log_on,
+                            Sync* sy, int B, int grid, hipStream_t st);
+template <class T>
+hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa,
+                            Counters* cnt, const LogArr& lg, int k_hi, int k_lo, Sync* sy, int B, int grid,
+                            hipStream_t st);
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, int B, int grid, hipStream_t st);

@@ -1,11 +1,13 @@
 // HIP kernels of the sparse wavefunction circuit (gfx950).
 //
-// State layout (per batch member): an open-addressed hash table in HBM with
-// structure-of-arrays slots {key u64, amplitude T, meta u32, born u32,
-// adjoint T}, linear probing on a 64-bit mixer of the determinant.  One lane
-// owns one slot per sweep step; a determinant pair touched by a factor is
-// updated by exactly one lane (the lower member if it is present, else the
-// upper one), so no amplitude is ever written by two lanes.
+// State layout (per batch member): an open-addressed hash table in HBM,
+// linear probing on a 64-bit mixer of the determinant, array-of-structs
+// slots so that one load returns key, state word and amplitude:
+//   float  states: 16-byte slot {key, amp, meta} + 8-byte side slot {lam, born}
+//   double states: 32-byte slot {key, amp, lam, meta, born}
+// One lane owns one slot per sweep step; a determinant pair touched by a
+// factor is updated by exactly one lane (the lower member if it is present,
+// else the upper one), so no amplitude is ever written by two lanes.
 //
 // Cross-lane rules inside one step kernel:
 //  * new entries are placed with atomicCAS on an EMPTY key, so two inserts
@@ -16,7 +18,7 @@
 //    write a lane makes during step k keeps that predicate unchanged, so a
 //    partner's presence test gives the same answer whenever it runs;
 //  * floating-point reductions are exact 128-bit fixed-point integer sums,
-//    spread over a few shards to avoid a single hot atomic address.
+//    spread over shards in separate cache lines.
 #include <hip/hip_runtime.h>
 
 #include "swc_internal.h"
@@ -24,6 +26,41 @@
 namespace swc {
 
 constexpr int BLK = 256;
+
+// ---------------------------------------------------------------------------
+// table views
+// ---------------------------------------------------------------------------
+
+template <class T>
+struct View;
+
+template <>
+struct View<float> {
+  Slot<float>* sl;
+  AuxF* aux;
+  __device__ float& lam(uint64_t s) const { return aux[s].lam; }
+  __device__ uint32_t& born(uint64_t s) const { return aux[s].born; }
+  __device__ float lam_of(const Slot<float>&, uint64_t s) const { return aux[s].lam; }
+};
+
+template <>
+struct View<double> {
+  Slot<double>* sl;
+  __device__ double& lam(uint64_t s) const { return sl[s].lam; }
+  __device__ uint32_t& born(uint64_t s) const { return sl[s].born; }
+  __device__ double lam_of(const Slot<double>& v, uint64_t) const { return v.lam; }
+};
+
+template <class T>
+__device__ __forceinline__ View<T> view(const Tab& t, int b);
+template <>
+__device__ __forceinline__ View<float> view<float>(const Tab& t, int b) {
+  return View<float>{static_cast<Slot<float>*>(t.slots) + b * t.H, static_cast<AuxF*>(t.aux) + b * t.H};
+}
+template <>
+__device__ __forceinline__ View<double> view<double>(const Tab& t, int b) {
+  return View<double>{static_cast<Slot<double>*>(t.slots) + b * t.H};
+}
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -111,14 +148,20 @@ __device__ __forceinline__ Red block_reduce(Red r) {
   return r;
 }
 
-__device__ __forceinline__ int64_t find_slot(const uint64_t* __restrict__ keys, uint64_t H, uint64_t key,
-                                             uint64_t* first_free) {
+// Linear probe for `key`; on a hit returns the slot and its contents (one
+// whole-slot load per probe step), else -1 and the first EMPTY slot seen.
+template <class T>
+__device__ __forceinline__ int64_t find_slot(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key,
+                                             uint64_t* first_free, Slot<T>* out) {
   const uint64_t mask = H - 1;
   uint64_t s = mix64(key) & mask;
   for (uint64_t i = 0; i < H; ++i, s = (s + 1) & mask) {
-    const uint64_t kk = keys[s];
-    if (kk == key) return static_cast<int64_t>(s);
-    if (kk == EMPTY_KEY) {
+    const Slot<T> v = sl[s];
+    if (v.key == key) {
+      *out = v;
+      return static_cast<int64_t>(s);
+    }
+    if (v.key == EMPTY_KEY) {
       *first_free = s;
       return -1;
     }
@@ -129,13 +172,14 @@ __device__ __forceinline__ int64_t find_slot(const uint64_t* __restrict__ keys, 
 
 // Claim an EMPTY slot for `key` (known to be absent), starting the linear
 // probe at `start`.  Returns the slot or -1 when the table is full.
-__device__ __forceinline__ int64_t claim_slot(uint64_t* keys, uint64_t H, uint64_t key, uint64_t start) {
+template <class T>
+__device__ __forceinline__ int64_t claim_slot(Slot<T>* sl, uint64_t H, uint64_t key, uint64_t start) {
   if (start >= H) return -1;
   const uint64_t mask = H - 1;
   uint64_t s = start;
   for (uint64_t i = 0; i < H; ++i, s = (s + 1) & mask) {
-    if (keys[s] != EMPTY_KEY) continue;
-    const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&keys[s]),
+    if (sl[s].key != EMPTY_KEY) continue;
+    const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&sl[s].key),
                                              static_cast<unsigned long long>(EMPTY_KEY),
                                              static_cast<unsigned long long>(key));
     if (old == EMPTY_KEY) return static_cast<int64_t>(s);
@@ -166,46 +210,53 @@ __device__ __forceinline__ double fmaT<double>(double a, double b, double c) {
   return fma(a, b, c);
 }
 
-// Renormalisation scale before step k (1-based): S_{k-1}.  Computed by the
-// first wave from S_{k-2} and the removed weight of step k-1; broadcast via LDS.
-__device__ double scale_before(const StepArr& sa, int b, int k) {
-  __shared__ double sS;
-  if (threadIdx.x < 64) {
-    const int64_t base = static_cast<int64_t>(b) * sa.stride;
-    double S = sa.scale[base + (k >= 2 ? k - 2 : 0)];
-    if (k >= 2) {
-      const int lane = threadIdx.x;
-      Fx w = fx_zero();
-      unsigned long long c = 0;
-      if (lane < SH) {
-        w = sa.pw[sidx(sa, b, lane, k - 1)];
-        c = sa.pcnt[sidx(sa, b, lane, k - 1)];
-      }
-      w = wave_fx(w);
-      c = wave_u64(c);
-      if (c) {
-        const double R = fx_to_d(w);
-        const double nu2 = 1.0 - S * S * R;
-        if (nu2 > 0.0) S = S / sqrt(nu2);
-      }
+// Renormalisation scale before step k (1-based): S_{k-1}, from S_{k-2} and the
+// removed weight of step k-1.  Every wave computes it (its first SH lanes read
+// the shards) with identical arithmetic: no LDS and no block barrier.
+__device__ __forceinline__ double wave_scale(const StepArr& sa, int b, int k) {
+  const int64_t base = static_cast<int64_t>(b) * sa.stride;
+  double S = sa.scale[base + (k >= 2 ? k - 2 : 0)];
+  if (k >= 2) {
+    const int lane = threadIdx.x & 63;
+    Fx w = fx_zero();
+    unsigned long long c = 0;
+    if (lane < SH) {
+      w = sa.pw[sidx(sa, b, lane, k - 1)];
+      c = sa.pcnt[sidx(sa, b, lane, k - 1)];
     }
-    if (threadIdx.x == 0) sS = S;
+    w = wave_fx(w);
+    c = wave_u64(c);
+    if (c) {
+      const double R = fx_to_d(w);
+      const double nu2 = 1.0 - S * S * R;
+      if (nu2 > 0.0) S = S / sqrt(nu2);
+    }
   }
-  __syncthreads();
-  return sS;
+  return S;
+}
+
+__device__ __forceinline__ unsigned int wave_u32(unsigned int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// global wave index within state b's launch (per-wave statistics slot)
+__device__ __forceinline__ int64_t wave_id() {
+  return (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * (BLK / 64) + (threadIdx.x >> 6);
 }
 
 // ---------------------------------------------------------------------------
 // table set-up
 // ---------------------------------------------------------------------------
 
+template <class T>
 __global__ void k_fill(Tab t) {
-  const int b = blockIdx.y;
-  const uint64_t H = t.H;
-  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += gridDim.x * blockDim.x) {
-    t.keys[b * H + s] = EMPTY_KEY;
-    t.meta[b * H + s] = DEAD;
-    t.born[b * H + s] = 0u;
+  const View<T> v = view<T>(t, blockIdx.y);
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
+    v.sl[s].key = EMPTY_KEY;
+    v.sl[s].meta = DEAD;
+    v.born(s) = 0u;
   }
 }
 
@@ -214,21 +265,19 @@ __global__ void k_insert_init(Tab t, Counters* cnt, const uint64_t* __restrict__
                               const double* __restrict__ amps, int64_t n) {
   const int b = blockIdx.y;
   const uint64_t H = t.H;
-  uint64_t* keys = t.keys + b * H;
-  T* amp = static_cast<T*>(t.amp) + b * H;
+  const View<T> v = view<T>(t, b);
   unsigned long long ok = 0;
   for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint64_t key = dets[i];
-    const uint64_t h = mix64(key) & (H - 1);
-    const int64_t s = claim_slot(keys, H, key, h);
+    const int64_t s = claim_slot(v.sl, H, key, mix64(key) & (H - 1));
     if (s < 0) {
       atomicOr(&cnt[b].flags, F_TABLE_FULL);
       continue;
     }
-    amp[s] = static_cast<T>(amps[i]);
-    t.meta[b * H + s] = 0u;
-    t.born[b * H + s] = 0u;
-    static_cast<T*>(t.lam)[b * H + s] = T(0);
+    v.sl[s].amp = static_cast<T>(amps[i]);
+    v.sl[s].meta = 0u;
+    v.born(s) = 0u;
+    v.lam(s) = T(0);
     ++ok;
   }
   ok = wave_u64(ok);
@@ -255,15 +304,16 @@ __global__ void k_trig(const double* __restrict__ theta, Trig* __restrict__ trig
 
 // Start of a sweep: every live entry becomes "born before the sweep"
 // (tag 0), tombstones get tag 0, per-step accumulators are cleared.
+template <class T>
 __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
   const int b = blockIdx.y;
-  const uint64_t H = t.H;
+  const View<T> v = view<T>(t, b);
   const uint64_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t gsz = gridDim.x * blockDim.x;
-  for (uint64_t s = gtid; s < H; s += gsz) {
-    const uint32_t m = t.meta[b * H + s];
-    t.meta[b * H + s] = (m & DEAD) ? DEAD : 0u;
-    t.born[b * H + s] = 0u;
+  for (uint64_t s = gtid; s < t.H; s += gsz) {
+    const uint32_t m = v.sl[s].meta;
+    v.sl[s].meta = (m & DEAD) ? DEAD : 0u;
+    v.born(s) = 0u;
   }
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
   for (uint64_t i = gtid; i < static_cast<uint64_t>((M + 1) * SH); i += gsz) {
@@ -274,6 +324,7 @@ __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
     sa.gacc[sidx(sa, b, sh, k)] = fx_zero();
   }
   for (uint64_t i = gtid; i < static_cast<uint64_t>(M + 1); i += gsz) sa.logn[base + i] = 0u;
+  for (uint64_t i = gtid; i < static_cast<uint64_t>(sa.nws * WSTAT); i += gsz) sa.ws[b * sa.nws * WSTAT + i] = 0ull;
   for (uint64_t i = gtid; i < static_cast<uint64_t>(CSH); i += gsz) {
     cnt[b].sh[i].v[C_DU] = 0;
     cnt[b].sh[i].v[C_PAIRS] = 0;
@@ -287,13 +338,29 @@ __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
   }
 }
 
-__global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M) {
+// End of a forward sweep (one wave per state): final scale S_M, and the
+// per-wave statistics folded into the state's counters.
+__global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy) {
   const int b = blockIdx.x;
+  if (threadIdx.x == 0 && sy && sy->timeout) atomicOr(&cnt[b].flags, F_TIMEOUT);
   if (M == 0) return;
-  const double S = scale_before(sa, b, static_cast<int>(M) + 1);
+  const double S = wave_scale(sa, b, static_cast<int>(M) + 1);
+  unsigned long long tot[WSTAT];
+  for (int i = 0; i < WSTAT; ++i) tot[i] = 0;
+  for (int64_t w = threadIdx.x; w < sa.nws; w += 64)
+    for (int i = 0; i < WSTAT; ++i) tot[i] += sa.ws[(b * sa.nws + w) * WSTAT + i];
+  for (int i = 0; i < WSTAT; ++i) tot[i] = wave_u64(tot[i]);
   if (threadIdx.x == 0) {
     sa.scale[static_cast<int64_t>(b) * sa.stride + M] = S;
     cnt[b].S = S;
+    CShard& c0 = cnt[b].sh[0];
+    c0.v[C_PRUNED] += tot[0];
+    c0.v[C_DU] += tot[1];
+    c0.v[C_PAIRS] += tot[2];
+    c0.v[C_INS] += tot[3];
+    c0.v[C_LIVE] += tot[3] - tot[4];
+    c0.v[C_OCC] += tot[5];
+    c0.v[C_HITS] += tot[6];
   }
 }
 
@@ -307,19 +374,22 @@ __global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M) {
 // tombstone keeps x' for the reverse sweep.  The removed weight feeds the
 // renormalisation scale of the next step.
 template <class T>
-__global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
-                                             int64_t ld, StepArr sa, Counters* cnt, LogArr lg, int k, double thr,
-                                             int prune_all, int log_on) {
+__device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict__ fac,
+                                         const Trig* __restrict__ trig, int64_t ld, const StepArr& sa, Counters* cnt,
+                                         const LogArr& lg, int k, double thr, int prune_all, int log_on) {
   const int b = blockIdx.y;
   const uint64_t H = t.H;
-  uint64_t* keys = t.keys + b * H;
-  T* amp = static_cast<T*>(t.amp) + b * H;
-  uint32_t* meta = t.meta + b * H;
-  uint32_t* born = t.born + b * H;
+  const View<T> v = view<T>(t, b);
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
+  const int lane = threadIdx.x & 63;
+  // this wave's statistics slot (read now, written back at the end)
+  unsigned long long* wst = sa.ws + (static_cast<int64_t>(b) * sa.nws + (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6))) * WSTAT;
+  const unsigned long long wold = lane < WSTAT ? wst[lane] : 0ull;
 
-  const double S = scale_before(sa, b, k);
-  if (k >= 2 && blockIdx.x == 0 && threadIdx.x == 0) sa.scale[base + k - 1] = S;
+  // threshold 0 never truncates, so the scale is not needed
+  const bool trunc = thr > 0.0;
+  const double S = trunc ? wave_scale(sa, b, k) : 1.0;
+  if (trunc && k >= 2 && blockIdx.x == 0 && threadIdx.x == 0) sa.scale[base + k - 1] = S;
 
   const FacMask f = fac[k - 1];
   const Trig tr = trig[b * ld + k - 1];
@@ -334,122 +404,118 @@ __global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ 
   // c[6] pairs whose partner existed
   unsigned int flags = 0;
 
-  auto kill = [&](uint64_t s, T v) {
-    amp[s] = v;
-    meta[s] = DEAD | K;
-    const double dv = static_cast<double>(v);
+  auto kill = [&](uint64_t s, T x) {
+    v.sl[s].amp = x;
+    v.sl[s].meta = DEAD | K;
+    const double dv = static_cast<double>(x);
     r.f = fx_add(r.f, fx_from(dv * dv));
     r.c[0] += 1;
     r.c[4] += 1;
   };
-  auto drop_new = [&](T v) {  // created and truncated in the same step
-    const double dv = static_cast<double>(v);
+  auto drop_new = [&](T x) {  // created and truncated in the same step
+    const double dv = static_cast<double>(x);
     r.f = fx_add(r.f, fx_from(dv * dv));
     r.c[0] += 1;
   };
-  // create `key` with value v: revive the tombstone at `hint` or claim a slot
-  auto create = [&](uint64_t key, T v, int64_t hint, uint64_t free_start) {
+  // create `key` with value x: revive the tombstone `old` at `hint`, or claim a slot
+  auto create = [&](uint64_t key, T x, int64_t hint, const Slot<T>& old, uint64_t free_start) {
     int64_t s = hint;
     if (s >= 0) {
-      const uint32_t old = meta[s];
-      if ((old & TAG) != 0u && log_on) {  // tombstone from this sweep: remember it
+      if ((old.meta & TAG) != 0u && log_on) {  // tombstone from this sweep: remember it
         const unsigned long long pos = atomicAdd(&cnt[b].logcnt, 1ull);
         if (pos < lg.cap) {
           const uint64_t li = b * lg.cap + pos;
           lg.slot[li] = static_cast<uint32_t>(s);
-          lg.meta[li] = old;
-          lg.born[li] = born[s];
-          static_cast<T*>(lg.amp)[li] = amp[s];
+          lg.meta[li] = old.meta;
+          lg.born[li] = v.born(s);
+          static_cast<T*>(lg.amp)[li] = old.amp;
           atomicAdd(&sa.logn[base + k], 1u);
         } else {
           flags |= F_LOG_FULL;
         }
       }
     } else {
-      s = claim_slot(keys, H, key, free_start);
+      s = claim_slot(v.sl, H, key, free_start);
       if (s < 0) {
         flags |= F_TABLE_FULL;
         return;
       }
       r.c[5] += 1;
     }
-    amp[s] = v;
-    born[s] = K;
-    meta[s] = K;
+    v.sl[s].amp = x;
+    v.born(s) = K;
+    v.sl[s].meta = K;
     r.c[3] += 1;
   };
 
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
-    const uint64_t key = keys[s];
-    if (key == EMPTY_KEY) continue;
-    const uint32_t m = meta[s];
+    const Slot<T> me = v.sl[s];
+    if (me.key == EMPTY_KEY) continue;
+    const uint32_t m = me.meta;
     if ((m & DEAD) || (m & TAG) == K) continue;  // dead, or created in this step
     r.c[1] += 1;
+    const uint64_t key = me.key;
     const bool lower = ((key & f.occ) == f.occ) && !(key & f.vir);
     const bool upper = ((key & f.vir) == f.vir) && !(key & f.occ);
     if (!lower && !upper) {
-      if (prune_all) {
-        const T x = amp[s];
-        if (!(fabs(S * static_cast<double>(x)) >= thr)) kill(s, x);
-      }
+      if (prune_all && !(fabs(S * static_cast<double>(me.amp)) >= thr)) kill(s, me.amp);
       continue;
     }
     const uint64_t pk = key ^ pm;
     uint64_t free_start = H;
-    const int64_t ps = find_slot(keys, H, pk, &free_start);
+    Slot<T> pv;
+    pv.meta = 0u;
+    pv.amp = T(0);
+    const int64_t ps = find_slot(v.sl, H, pk, &free_start, &pv);
     bool p_alive = false, p_start = false;
     if (ps >= 0) {
-      const uint32_t q = meta[ps];
-      p_alive = !(q & DEAD);
-      p_start = p_alive || ((q & TAG) == K);
+      p_alive = !(pv.meta & DEAD);
+      p_start = p_alive || ((pv.meta & TAG) == K);
     }
     if (upper && p_start) continue;  // the lower member owns the pair
     r.c[2] += 1;
     if (lower && p_alive) r.c[6] += 1;
     const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
-    T x, y;
-    if (lower) {
-      x = amp[s];
-      y = p_alive ? amp[ps] : T(0);
-    } else {
-      x = T(0);
-      y = amp[s];
-    }
+    const T x = lower ? me.amp : T(0);
+    const T y = lower ? (p_alive ? pv.amp : T(0)) : me.amp;
     const T xn = x + fmaT<T>(x, cm1, -ss * y);
     const T yn = y + fmaT<T>(y, cm1, ss * x);
     const bool keepx = fabs(S * static_cast<double>(xn)) >= thr;
     const bool keepy = fabs(S * static_cast<double>(yn)) >= thr;
     if (lower) {
-      if (keepx) amp[s] = xn; else kill(s, xn);
+      if (keepx) v.sl[s].amp = xn; else kill(s, xn);
       if (p_alive) {
-        if (keepy) amp[ps] = yn; else kill(static_cast<uint64_t>(ps), yn);
+        if (keepy) v.sl[ps].amp = yn; else kill(static_cast<uint64_t>(ps), yn);
       } else if (keepy) {
-        create(pk, yn, ps, free_start);
+        create(pk, yn, ps, pv, free_start);
       } else {
         drop_new(yn);
       }
     } else {
-      if (keepy) amp[s] = yn; else kill(s, yn);
-      if (keepx) create(pk, xn, ps, free_start); else drop_new(xn);
+      if (keepy) v.sl[s].amp = yn; else kill(s, yn);
+      if (keepx) create(pk, xn, ps, pv, free_start); else drop_new(xn);
     }
   }
 
   if (flags) atomicOr(&cnt[b].flags, flags);
-  r = block_reduce(r);
-  if (threadIdx.x == 0) {
-    const uint32_t sh = shard();
-    if (r.c[0]) {
-      fx_atomic_add(&sa.pw[sidx(sa, b, sh, k)], r.f);
-      atomicAdd(&sa.pcnt[sidx(sa, b, sh, k)], static_cast<uint32_t>(r.c[0]));
+  // wave totals: statistics go to the wave's private slot (plain stores, no
+  // block barrier); removed weight, when there is any, to a sharded atomic
+  unsigned int c[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) c[i] = wave_u32(static_cast<unsigned int>(r.c[i]));
+  const int wsh = (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6)) & (SH - 1);
+  if (c[0]) {
+    const Fx w = wave_fx(r.f);
+    if (lane == 0) {
+      fx_atomic_add(&sa.pw[sidx(sa, b, wsh, k)], w);
+      atomicAdd(&sa.pcnt[sidx(sa, b, wsh, k)], c[0]);
     }
-    count(cnt, b, C_PRUNED, r.c[0]);
-    count(cnt, b, C_DU, r.c[1]);
-    count(cnt, b, C_PAIRS, r.c[2]);
-    count(cnt, b, C_INS, r.c[3]);
-    count(cnt, b, C_LIVE, r.c[3] - r.c[4]);
-    count(cnt, b, C_OCC, r.c[5]);
-    count(cnt, b, C_HITS, r.c[6]);
+  }
+  if (lane < 7) {
+    const unsigned int mine = lane == 0 ? c[0] : lane == 1 ? c[1] : lane == 2 ? c[2] : lane == 3 ? c[3]
+                              : lane == 4 ? c[4] : lane == 5 ? c[5] : c[6];
+    wst[lane] = wold + mine;
   }
 }
 
@@ -467,15 +533,12 @@ __global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ 
 //                           x = x' / cos (or y = y' / cos)
 // Members born in step k are removed; tombstones of step k are revived.
 template <class T>
-__global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
-                                             int64_t ld, StepArr sa, Counters* cnt, int k) {
+__device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict__ fac,
+                                         const Trig* __restrict__ trig, int64_t ld, const StepArr& sa, Counters* cnt,
+                                         int k) {
   const int b = blockIdx.y;
   const uint64_t H = t.H;
-  uint64_t* keys = t.keys + b * H;
-  T* amp = static_cast<T*>(t.amp) + b * H;
-  T* lam = static_cast<T*>(t.lam) + b * H;
-  uint32_t* meta = t.meta + b * H;
-  uint32_t* born = t.born + b * H;
+  const View<T> v = view<T>(t, b);
 
   const FacMask f = fac[k - 1];
   const Trig tr = trig[b * ld + k - 1];
@@ -490,46 +553,51 @@ __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ 
 
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
-    const uint64_t key = keys[s];
-    if (key == EMPTY_KEY) continue;
-    const uint32_t m = meta[s];
+    const Slot<T> me = v.sl[s];
+    if (me.key == EMPTY_KEY) continue;
+    const uint32_t m = me.meta;
     const bool dead = (m & DEAD) != 0u;
     if (dead && (m & TAG) != K) continue;
+    const uint64_t key = me.key;
     const bool lower = ((key & f.occ) == f.occ) && !(key & f.vir);
     const bool upper = ((key & f.vir) == f.vir) && !(key & f.occ);
     if (!lower && !upper) {
       if (dead) {  // truncated at step k without being rotated (first step of a sweep)
-        meta[s] = born[s];
-        lam[s] = T(0);
+        v.sl[s].meta = v.born(s);
+        v.lam(s) = T(0);
       }
       continue;
     }
     const uint64_t pk = key ^ pm;
     uint64_t free_start = H;
-    const int64_t ps = find_slot(keys, H, pk, &free_start);
-    uint32_t q = 0;
+    Slot<T> pv;
+    pv.meta = 0u;
+    pv.amp = T(0);
+    const int64_t ps = find_slot(v.sl, H, pk, &free_start, &pv);
     bool p_pres = false;
-    if (ps >= 0) {
-      q = meta[ps];
-      p_pres = !(q & DEAD) || ((q & TAG) == K);
-    }
+    if (ps >= 0) p_pres = !(pv.meta & DEAD) || ((pv.meta & TAG) == K);
     if (upper && p_pres) continue;  // the lower member owns the pair
     const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
 
     int64_t sL, sU;
     uint32_t mL, mU;
     bool hL, hU;
+    T xp, yp, lL, lU;
     if (lower) {
       sL = static_cast<int64_t>(s); mL = m; hL = true;
-      sU = ps; mU = q; hU = p_pres;
+      sU = ps; mU = pv.meta; hU = p_pres;
+      xp = me.amp;
+      yp = hU ? pv.amp : T(0);
+      lL = dead ? T(0) : v.lam_of(me, s);
+      lU = (hU && !(mU & DEAD)) ? v.lam_of(pv, static_cast<uint64_t>(ps)) : T(0);
     } else {
       sU = static_cast<int64_t>(s); mU = m; hU = true;
-      sL = ps; mL = q; hL = false;
+      sL = ps; mL = pv.meta; hL = false;
+      xp = T(0);
+      yp = me.amp;
+      lL = T(0);
+      lU = dead ? T(0) : v.lam_of(me, s);
     }
-    const T xp = hL ? amp[sL] : T(0);
-    const T yp = hU ? amp[sU] : T(0);
-    const T lL = (hL && !(mL & DEAD)) ? lam[sL] : T(0);
-    const T lU = (hU && !(mU & DEAD)) ? lam[sU] : T(0);
     const T wL = lL + fmaT<T>(lL, cm1, ss * lU);
     const T wU = lU + fmaT<T>(lU, cm1, -ss * lL);
     T x, y;
@@ -549,50 +617,140 @@ __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ 
     r.f = fx_add(r.f, fx_from(term));
     r.c[2] += 1;
     if (hL) {
-      const uint32_t bL = (mL & DEAD) ? born[sL] : (mL & TAG);
+      const uint32_t bL = (mL & DEAD) ? v.born(sL) : (mL & TAG);
       if (bL == K) {
         if (!hU) flags |= F_INCONSISTENT;
-        meta[sL] = DEAD | K;
+        v.sl[sL].meta = DEAD | K;
         r.c[4] += 1;
       } else {
-        amp[sL] = x;
-        lam[sL] = wL;
-        meta[sL] = bL;
+        v.sl[sL].amp = x;
+        v.lam(sL) = wL;
+        v.sl[sL].meta = bL;
       }
     }
     if (hU) {
-      const uint32_t bU = (mU & DEAD) ? born[sU] : (mU & TAG);
+      const uint32_t bU = (mU & DEAD) ? v.born(sU) : (mU & TAG);
       if (bU == K) {
         if (!hL) flags |= F_INCONSISTENT;
-        meta[sU] = DEAD | K;
+        v.sl[sU].meta = DEAD | K;
         r.c[4] += 1;
       } else {
-        amp[sU] = y;
-        lam[sU] = wU;
-        meta[sU] = bU;
+        v.sl[sU].amp = y;
+        v.lam(sU) = wU;
+        v.sl[sU].meta = bU;
       }
     }
   }
   if (flags) atomicOr(&cnt[b].flags, flags);
-  r = block_reduce(r);
-  if (threadIdx.x == 0 && fx_nonzero(r.f)) fx_atomic_add(&sa.gacc[sidx(sa, b, shard(), k)], r.f);
+  // wave total of the gradient dot product -> sharded exact accumulator
+  const Fx g = wave_fx(r.f);
+  const int wsh = (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6)) & (SH - 1);
+  if ((threadIdx.x & 63) == 0 && fx_nonzero(g)) fx_atomic_add(&sa.gacc[sidx(sa, b, wsh, k)], g);
 }
 
 // Tombstones overwritten by a resurrection in forward step k get their old
 // state back once the reverse sweep has undone step k.
 template <class T>
-__global__ void k_log_restore(Tab t, LogArr lg, StepArr sa, int k) {
+__device__ __forceinline__ void restore_step(const Tab& t, const LogArr& lg, const StepArr& sa, int k) {
   const int b = blockIdx.y;
-  const uint64_t H = t.H;
+  const View<T> v = view<T>(t, b);
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
   const uint32_t n = sa.logn[base + k];
   const uint32_t off = sa.logoff[base + k];
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint64_t li = b * lg.cap + off + i;
     const uint64_t s = lg.slot[li];
-    t.meta[b * H + s] = lg.meta[li];
-    t.born[b * H + s] = lg.born[li];
-    static_cast<T*>(t.amp)[b * H + s] = static_cast<const T*>(lg.amp)[li];
+    v.sl[s].meta = lg.meta[li];
+    v.born(s) = lg.born[li];
+    v.sl[s].amp = static_cast<const T*>(lg.amp)[li];
+  }
+}
+
+// one launch per step
+template <class T>
+__global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
+                                             int64_t ld, StepArr sa, Counters* cnt, LogArr lg, int k, double thr,
+                                             int prune_all, int log_on) {
+  fwd_step<T>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
+                                             int64_t ld, StepArr sa, Counters* cnt, int k) {
+  rev_step<T>(t, fac, trig, ld, sa, cnt, k);
+}
+
+template <class T>
+__global__ void k_log_restore(Tab t, LogArr lg, StepArr sa, int k) {
+  restore_step<T>(t, lg, sa, k);
+}
+
+// ---------------------------------------------------------------------------
+// persistent sweeps: one cooperative launch runs many steps
+// ---------------------------------------------------------------------------
+// Grid-wide barrier of a cooperative (all blocks co-resident) launch.
+// Arrivals are counted monotonically: barrier e completes when the counter
+// reaches e * nblocks.  Agent-scope fences publish each step's writes to all
+// XCDs before the next step reads them.  Every wait is bounded; when the
+// bound is hit the sticky timeout flag is raised, later barriers return at
+// once and the host reports an error, so the launch always terminates.
+constexpr unsigned int SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ void grid_barrier(Sync* sy, unsigned int target) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(&sy->count, 1u);
+    for (unsigned int it = 0;; ++it) {
+      if (__hip_atomic_load(&sy->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (__hip_atomic_load(&sy->timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      if (it >= SPIN_LIMIT) {
+        atomicOr(&sy->timeout, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+__global__ void k_sync_reset(Sync* sy) {
+  if (threadIdx.x == 0) {
+    sy->count = 0u;
+    sy->timeout = 0u;
+  }
+}
+
+// forward steps k0..k1 (inclusive)
+template <class T>
+__global__ __launch_bounds__(BLK) void k_fwd_sweep(Tab t, const FacMask* __restrict__ fac,
+                                                   const Trig* __restrict__ trig, int64_t ld, StepArr sa,
+                                                   Counters* cnt, LogArr lg, int k0, int k1, double thr,
+                                                   int prune_first, int log_on, Sync* sy) {
+  const unsigned int nblk = gridDim.x * gridDim.y;
+  unsigned int epoch = 0;
+  for (int k = k0; k <= k1; ++k) {
+    fwd_step<T>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_first && k == k0, log_on);
+    grid_barrier(sy, ++epoch * nblk);
+  }
+}
+
+// reverse steps k_hi down to k_lo, with the log restores of the steps whose
+// forward pass overwrote tombstones (rmax[k] > 0)
+template <class T>
+__global__ __launch_bounds__(BLK) void k_rev_sweep(Tab t, const FacMask* __restrict__ fac,
+                                                   const Trig* __restrict__ trig, int64_t ld, StepArr sa,
+                                                   Counters* cnt, LogArr lg, int k_hi, int k_lo, Sync* sy) {
+  const unsigned int nblk = gridDim.x * gridDim.y;
+  unsigned int epoch = 0;
+  for (int k = k_hi; k >= k_lo; --k) {
+    rev_step<T>(t, fac, trig, ld, sa, cnt, k);
+    grid_barrier(sy, ++epoch * nblk);
+    if (sa.rmax[k]) {
+      restore_step<T>(t, lg, sa, k);
+      grid_barrier(sy, ++epoch * nblk);
+    }
   }
 }
 
@@ -604,15 +762,18 @@ template <class T>
 __global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cnt) {
   const int b = blockIdx.y;
   const uint64_t H = t.H;
+  const View<T> v = view<T>(t, b);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   const int lane = threadIdx.x & 63;
   for (uint64_t s0 = blockIdx.x * blockDim.x; s0 < H; s0 += stride) {
     const uint64_t s = s0 + threadIdx.x;
     bool live = false;
-    uint64_t key = 0;
+    Slot<T> me;
+    me.key = 0;
+    me.amp = T(0);
     if (s < H) {
-      key = t.keys[b * H + s];
-      live = key != EMPTY_KEY && !(t.meta[b * H + s] & DEAD);
+      me = v.sl[s];
+      live = me.key != EMPTY_KEY && !(me.meta & DEAD);
     }
     const unsigned long long mask = __ballot(live);
     if (!mask) continue;
@@ -623,8 +784,8 @@ __global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cn
     if (live) {
       const unsigned long long below = lane ? (mask & ((1ull << lane) - 1ull)) : 0ull;
       const uint64_t pos = basep + __popcll(below);
-      cp.key[b * H + pos] = key;
-      cp.amp[b * H + pos] = static_cast<double>(static_cast<const T*>(t.amp)[b * H + s]);
+      cp.key[b * H + pos] = me.key;
+      cp.amp[b * H + pos] = static_cast<double>(me.amp);
       cp.slot[b * H + pos] = static_cast<uint32_t>(s);
       cp.sig[b * H + pos] = 0.0;
     }
@@ -715,9 +876,7 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
   const int b = blockIdx.y;
   const uint64_t H = t.H;
   const int64_t N = static_cast<int64_t>(cnt[b].ncompact);
-  const uint64_t* keys = t.keys + b * H;
-  const T* amp = static_cast<const T*>(t.amp) + b * H;
-  const uint32_t* meta = t.meta + b * H;
+  const View<T> v = view<T>(t, b);
   const int n = nq / 2;
   const int g = threadIdx.x & (SG - 1);
   const uint64_t full = nq >= 64 ? ~0ull : ((1ull << nq) - 1ull);
@@ -729,9 +888,10 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
   uint8_t* virB = occA + 96;
   auto probe = [&](uint64_t J, double* a) -> bool {
     uint64_t ff;
-    const int64_t s = find_slot(keys, H, J, &ff);
-    if (s < 0 || (meta[s] & DEAD)) return false;
-    *a = static_cast<double>(amp[s]);
+    Slot<T> pv;
+    const int64_t s = find_slot(v.sl, H, J, &ff, &pv);
+    if (s < 0 || (pv.meta & DEAD)) return false;
+    *a = static_cast<double>(pv.amp);
     return true;
   };
   auto fill = [](uint8_t* dst, uint64_t m) -> int {
@@ -775,13 +935,13 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
     {
       const int tot = oA * oB * vA * vB;
       for (int e = g; e < tot; e += SG) {
-        int r = e;
-        const int xa = r % vA;
-        r /= vA;
-        const int xb = r % vB;
-        r /= vB;
-        const int jb = r % oB;
-        const int ia = r / oB;
+        int rr = e;
+        const int xa = rr % vA;
+        rr /= vA;
+        const int xb = rr % vB;
+        rr /= vB;
+        const int jb = rr % oB;
+        const int ia = rr / oB;
         const uint64_t J = I ^ (1ull << occA[ia]) ^ (1ull << occB[jb]) ^ (1ull << virA[xa]) ^ (1ull << virB[xb]);
         if (probe(J, &a)) acc += h_offdiag(I, J, 4, h1, h2, n) * a;
       }
@@ -838,11 +998,12 @@ template <class T>
 __global__ void k_lambda(Tab t, Compact cp, const Counters* cnt) {
   const int b = blockIdx.y;
   const uint64_t H = t.H;
+  const View<T> v = view<T>(t, b);
   const int64_t N = static_cast<int64_t>(cnt[b].ncompact);
   const double E = cnt[b].E;
   for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
-    const double v = cp.sig[b * H + i] - E * cp.amp[b * H + i];
-    static_cast<T*>(t.lam)[b * H + cp.slot[b * H + i]] = static_cast<T>(v);
+    const double x = cp.sig[b * H + i] - E * cp.amp[b * H + i];
+    v.lam(cp.slot[b * H + i]) = static_cast<T>(x);
   }
 }
 
@@ -867,8 +1028,9 @@ int grid_for(uint64_t work, int block, int cap) {
   return static_cast<int>(g);
 }
 
+template <class T>
 void launch_fill(const Tab& t, int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t);
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t);
 }
 
 template <class T>
@@ -883,12 +1045,61 @@ void launch_trig(const double* theta, Trig* trig, int64_t M, int64_t ld, int B, 
   hipLaunchKernelGGL(k_trig, dim3(grid_for(M, BLK, 1024), B), dim3(BLK), 0, st, theta, trig, M, ld, cnt);
 }
 
+template <class T>
 void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_sweep_begin, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t, sa, cnt, M);
+  hipLaunchKernelGGL(k_sweep_begin<T>, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t, sa, cnt, M);
 }
 
-void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_sweep_end, dim3(B), dim3(64), 0, st, sa, cnt, M);
+void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, hipStream_t st) {
+  hipLaunchKernelGGL(k_sweep_end, dim3(B), dim3(64), 0, st, sa, cnt, M, sy);
+}
+
+void launch_sync_reset(Sync* sy, hipStream_t st) { hipLaunchKernelGGL(k_sync_reset, dim3(1), dim3(64), 0, st, sy); }
+
+template <class T>
+int coop_blocks_per_cu(int which) {
+  int nb = 0;
+  const hipError_t e = which == 0
+                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_sweep<T>, BLK, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev_sweep<T>, BLK, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+template <class T>
+hipError_t launch_fwd_sweep(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa,
+                            Counters* cnt, const LogArr& lg, int k0, int k1, double thr, int prune_first, int log_on,
+                            Sync* sy, int B, int grid, hipStream_t st) {
+  Tab a_t = t;
+  const FacMask* a_fac = fac;
+  const Trig* a_trig = trig;
+  int64_t a_ld = ld;
+  StepArr a_sa = sa;
+  Counters* a_cnt = cnt;
+  LogArr a_lg = lg;
+  int a_k0 = k0, a_k1 = k1, a_pf = prune_first, a_log = log_on;
+  double a_thr = thr;
+  Sync* a_sy = sy;
+  void* args[] = {&a_t, &a_fac, &a_trig, &a_ld, &a_sa, &a_cnt, &a_lg, &a_k0, &a_k1, &a_thr, &a_pf, &a_log, &a_sy};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_fwd_sweep<T>), dim3(grid, B), dim3(BLK), args,
+                                    0, st);
+}
+
+template <class T>
+hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa,
+                            Counters* cnt, const LogArr& lg, int k_hi, int k_lo, Sync* sy, int B, int grid,
+                            hipStream_t st) {
+  Tab a_t = t;
+  const FacMask* a_fac = fac;
+  const Trig* a_trig = trig;
+  int64_t a_ld = ld;
+  StepArr a_sa = sa;
+  Counters* a_cnt = cnt;
+  LogArr a_lg = lg;
+  int a_hi = k_hi, a_lo = k_lo;
+  Sync* a_sy = sy;
+  void* args[] = {&a_t, &a_fac, &a_trig, &a_ld, &a_sa, &a_cnt, &a_lg, &a_hi, &a_lo, &a_sy};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_rev_sweep<T>), dim3(grid, B), dim3(BLK), args,
+                                    0, st);
 }
 
 template <class T>
@@ -947,8 +1158,10 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
 }
 
 #define SWC_INST(T)                                                                                                \
+  template void launch_fill<T>(const Tab&, int, hipStream_t);                                                      \
   template void launch_insert_init<T>(const Tab&, Counters*, const uint64_t*, const double*, int64_t, int,         \
                                       hipStream_t);                                                                \
+  template void launch_sweep_begin<T>(const Tab&, const StepArr&, Counters*, int64_t, int, hipStream_t);          \
   template void launch_fwd<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*,        \
                               const LogArr&, int, double, int, int, int, int, hipStream_t);                        \
   template void launch_rev<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,   \
@@ -958,7 +1171,13 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
   template void launch_compact<T>(const Tab&, const Compact&, Counters*, int, int, hipStream_t);                  \
   template void launch_lambda<T>(const Tab&, const Compact&, const Counters*, int64_t, int, hipStream_t);        \
   template void launch_sigma<T>(const Tab&, const Compact&, const Counters*, const double*, const double*, int,   \
-                                int64_t, int, hipStream_t);
+                                int64_t, int, hipStream_t);                                                        \
+  template int coop_blocks_per_cu<T>(int);                                                                         \
+  template hipError_t launch_fwd_sweep<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&,       \
+                                          Counters*, const LogArr&, int, int, double, int, int, Sync*, int, int,   \
+                                          hipStream_t);                                                            \
+  template hipError_t launch_rev_sweep<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&,       \
+                                          Counters*, const LogArr&, int, int, Sync*, int, int, hipStream_t);
 
 SWC_INST(float)
 SWC_INST(double)

@@ -165,3 +165,31 @@ def test_autograd_function(swc, orc):
     E_ref, g_ref, _ = orc.energy_and_grad(12, [hf], [1.0], exc, theta[0], 0.0, h1, h2)
     assert abs(E.item() - E_ref) < 1e-6
     assert np.max(np.abs(th.grad.cpu().numpy() - 2.0 * g_ref)) < 2e-5
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_sweep_modes_bitwise_identical(swc, monkeypatch, prec):
+    """Captured-graph replay, direct per-step launches and the persistent
+    cooperative sweep run the same step arithmetic: results agree to the
+    bit, and repeated graph replays (with eager work in between) agree too."""
+    say(f"[case] sweep modes prec={prec}")
+    h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 161)
+    results = {}
+    for mode, env in (("graph", {}), ("direct", {"SWC_GRAPH": "0"}), ("persistent", {"SWC_SWEEP": "persistent"})):
+        for k in ("SWC_GRAPH", "SWC_SWEEP"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        s = swc.Solver(16, 4, 4, 16384, prec=prec, batch=1, max_factors=exc.shape[0])
+        s.build_state()
+        reps = []
+        for rep in range(3):
+            E, g = s.energy_and_grad(theta, exc, 1e-4, h1, h2)
+            s.apply_ucc(theta, exc, 0.0)          # eager work between replays
+            d, a = s.get_state(0)
+            s.build_state()
+            reps.append((E.cpu().numpy().tobytes(), g.cpu().numpy().tobytes(), d.tobytes(), a.tobytes()))
+        assert reps[0] == reps[1] == reps[2], mode
+        results[mode] = reps[0]
+        s.close()
+    assert results["graph"] == results["direct"] == results["persistent"]
