@@ -37,6 +37,41 @@ def rotate_bytes(st: dict, tsz: int) -> float:
             + st["inserts"] * (8 + tsz))
 
 
+def sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("swc_kernels.hip", "swc_api.hip", "swc_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2301_05726_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, prec: str) -> dict:
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (calibrated against a copy kernel), only while the kernel sources
+    are the ones that were profiled; otherwise empty (traffic reported null)."""
+    path = os.path.join(ROOT, "profiles", f"k_fwd_k_rev_{workload}_traffic.txt")
+    if prec != "fp32" or not os.path.exists(path):
+        return {}
+    vals, sha = {}, None
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 3 and parts[0] == "traffic_kib":
+            vals[parts[1]] = float(parts[2]) * 1024.0
+        elif len(parts) == 2 and parts[0] == "sources_sha":
+            sha = parts[1]
+    return vals if sha == sources_sha() else {}
+
+
+def reverse_bytes(st: dict, tsz: int) -> float:
+    """Algorithmic bytes of one reverse sweep, counted on the forward's
+    pairs (the reverse visits the same pairs): 8 B key per visited
+    determinant; per pair the own amplitude and adjoint read+write and an
+    8 B partner-key probe; partner amplitude and adjoint read+write when it
+    exists; created entries are removed (one 4 B state write)."""
+    return (8.0 * st["det_updates"] + st["pair_updates"] * (4 * tsz + 8) + st["partner_hits"] * 4 * tsz
+            + st["inserts"] * 4)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,9 +87,6 @@ def main() -> int:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see the sharding notes in DESIGN.md); run it with --gpus 1", file=sys.stderr)
         return 2
-    # per-launch HIP events around the rotate / reverse / sigma kernels
-    os.environ.setdefault("SWC_KERNEL_TIMING", "1")
-
     import numpy as np
     import torch
 
@@ -75,17 +107,16 @@ def main() -> int:
     for _ in range(args.warmup):
         s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
     torch.cuda.synchronize()
-    rot_ms = rot_n = rev_ms = rev_n = sig_ms = fwd_ms = 0.0
+    # HIP events recorded by the library on its stream bracket each sweep
+    # (forward, reverse) and the sigma kernel inside every timed step
+    fwd_ms = rev_ms = sig_ms = 0.0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         E, g = s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
         st = s.stats()
-        rot_ms += st["rotate_kernel_ms"]
-        rot_n += st["rotate_launches"]
-        rev_ms += st["reverse_kernel_ms"]
-        rev_n += st["reverse_launches"]
-        sig_ms += st["sigma_kernel_ms"]
         fwd_ms += st["fwd_ms"]
+        rev_ms += st["rev_ms"]
+        sig_ms += st["sigma_kernel_ms"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -100,23 +131,28 @@ def main() -> int:
     det_updates = st["det_updates"]
     s.build_state()
 
-    # dominant kernel: the largest summed device time per step
-    per_step = {"rotate": rot_ms / args.steps, "reverse": rev_ms / args.steps, "sigma": sig_ms / args.steps}
-    bytes_sweep = rotate_bytes(st, tsz)
-    avg_rot_ms = rot_ms / max(rot_n, 1)
-    achieved = (bytes_sweep / M) / (avg_rot_ms * 1e-3) / 1e9 if avg_rot_ms > 0 else 0.0
-    roofline = {
-        "kernel": "k_fwd (rotate + truncate, one launch per factor)",
-        "bound": "hbm",
-        "achieved": round(achieved, 2),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 5),
-        "traffic": None,
-        "bytes_per_launch": bytes_sweep / M,
-        "avg_launch_us": avg_rot_ms * 1e3,
-        "kernel_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+    # per-step kernels: one launch per factor, back to back on the stream,
+    # so the mean launch duration is the bracketed sweep time / M
+    per_step = {"forward_sweep": fwd_ms / args.steps, "reverse_sweep": rev_ms / args.steps,
+                "sigma": sig_ms / args.steps}
+    kern = {
+        "k_fwd": (rotate_bytes(st, tsz) / M, fwd_ms / args.steps / M,
+                  "forward step: pair rotation + truncation, one launch per factor"),
+        "k_rev": (reverse_bytes(st, tsz) / M, rev_ms / args.steps / M,
+                  "reverse step: exact inverse + adjoint rotation + gradient dot, one launch per factor"),
     }
+    traffic = measured_traffic(args.workload, args.prec)
+    lines = {}
+    for name, (bpl, ms, what) in kern.items():
+        ach = bpl / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        lines[name] = {"kernel": name, "what": what, "bound": "hbm", "achieved": round(ach, 2),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
+                       "traffic": traffic.get(name), "bytes_per_launch": round(bpl, 1),
+                       "avg_launch_us": round(ms * 1e3, 3)}
+    dom = max(lines, key=lambda n: kern[n][1])
+    roofline = dict(lines[dom])
+    roofline["kernel_ms_per_step"] = {k: round(v, 4) for k, v in per_step.items()}
+    roofline["other"] = {n: l for n, l in lines.items() if n != dom}
 
     out = {
         "metric": METRIC,

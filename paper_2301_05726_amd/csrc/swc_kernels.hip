@@ -41,6 +41,9 @@ struct View<float> {
   __device__ float& lam(uint64_t s) const { return aux[s].lam; }
   __device__ uint32_t& born(uint64_t s) const { return aux[s].born; }
   __device__ float lam_of(const Slot<float>&, uint64_t s) const { return aux[s].lam; }
+  // split load: issue lam_pre(s) early, combine with the slot later
+  __device__ float lam_pre(uint64_t s) const { return aux[s].lam; }
+  __device__ float lam_fin(const Slot<float>&, float pre) const { return pre; }
 };
 
 template <>
@@ -49,6 +52,8 @@ struct View<double> {
   __device__ double& lam(uint64_t s) const { return sl[s].lam; }
   __device__ uint32_t& born(uint64_t s) const { return sl[s].born; }
   __device__ double lam_of(const Slot<double>& v, uint64_t) const { return v.lam; }
+  __device__ double lam_pre(uint64_t) const { return 0.0; }
+  __device__ double lam_fin(const Slot<double>& v, double) const { return v.lam; }
 };
 
 template <class T>
@@ -554,6 +559,7 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
     const Slot<T> me = v.sl[s];
+    const T lam_me = v.lam_pre(s);  // issued together with the slot load
     if (me.key == EMPTY_KEY) continue;
     const uint32_t m = me.meta;
     const bool dead = (m & DEAD) != 0u;
@@ -569,6 +575,10 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
       continue;
     }
     const uint64_t pk = key ^ pm;
+    // the partner usually sits in its home slot: fetch its adjoint value
+    // there while the probe runs
+    const uint64_t home = mix64(pk) & (H - 1);
+    const T lam_home = v.lam_pre(home);
     uint64_t free_start = H;
     Slot<T> pv;
     pv.meta = 0u;
@@ -588,15 +598,18 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
       sU = ps; mU = pv.meta; hU = p_pres;
       xp = me.amp;
       yp = hU ? pv.amp : T(0);
-      lL = dead ? T(0) : v.lam_of(me, s);
-      lU = (hU && !(mU & DEAD)) ? v.lam_of(pv, static_cast<uint64_t>(ps)) : T(0);
+      lL = dead ? T(0) : v.lam_fin(me, lam_me);
+      lU = (hU && !(mU & DEAD))
+               ? (static_cast<uint64_t>(ps) == home ? v.lam_fin(pv, lam_home)
+                                                    : v.lam_of(pv, static_cast<uint64_t>(ps)))
+               : T(0);
     } else {
       sU = static_cast<int64_t>(s); mU = m; hU = true;
       sL = ps; mL = pv.meta; hL = false;
       xp = T(0);
       yp = me.amp;
       lL = T(0);
-      lU = dead ? T(0) : v.lam_of(me, s);
+      lU = dead ? T(0) : v.lam_fin(me, lam_me);
     }
     const T wL = lL + fmaT<T>(lL, cm1, ss * lU);
     const T wU = lU + fmaT<T>(lU, cm1, -ss * lL);
