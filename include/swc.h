@@ -88,7 +88,7 @@ typedef struct {
   int64_t inserts;       /* determinants created (last forward sweep) */
   int64_t pruned;        /* amplitudes removed by truncation (last forward sweep) */
   int64_t log_records;   /* truncation-log records of the last gradient sweep */
-  int64_t table_slots;   /* hash slots per batch member */
+  int64_t table_slots;   /* current hash-table size per batch member (grows up to the capacity) */
   int64_t slots_used;    /* occupied slots incl. tombstones (batch member 0) */
   double fwd_ms;         /* device time of the last forward sweep */
   double energy_ms;      /* device time of the last energy evaluation */
@@ -102,14 +102,20 @@ typedef struct {
   int64_t reverse_launches;
   double sigma_kernel_ms;    /* duration of the sigma kernel */
   int64_t partner_hits;      /* pairs whose partner existed (last forward sweep) */
+  int64_t rehashes;          /* table growths during the last forward sweep */
 } swc_stats;
 
 /*
- * Bytes of device workspace needed for a context with `capacity` hash slots
- * per state (a power of two, >= 64; live determinants must stay below
- * 0.9 * capacity), `batch` independent states, circuits of up to
- * `max_factors` factors, and `log_capacity` truncation-log records per state
- * (0 selects capacity / 4).  Returns 0 for invalid arguments.
+ * Bytes of device workspace needed for a context whose hash table may grow
+ * to `capacity` slots per state (a power of two, >= 64; determinants plus
+ * tombstones of the current sweep must stay below 0.9 * capacity), `batch`
+ * independent states, circuits of up to `max_factors` factors, and
+ * `log_capacity` truncation-log records per state (0 selects capacity / 4).
+ * The table starts small after every reset to |Psi_0> and is rehashed into a
+ * larger one (x2 or more) during a forward sweep when its occupancy nears a
+ * growth limit, so the per-factor scan covers the current table, not the
+ * capacity; the workspace holds two capacity-sized table regions for this.
+ * Returns 0 for invalid arguments.
  */
 size_t swc_workspace_bytes(int n_qubits, uint64_t capacity, int prec, int batch, int64_t max_factors,
                            uint64_t log_capacity);

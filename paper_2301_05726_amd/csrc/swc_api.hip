@@ -39,8 +39,8 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of every workspace region.
 struct Layout {
-  size_t slots, aux;
-  size_t lslot, lmeta, lborn, lamp;
+  size_t slots[2], aux[2];
+  size_t lkey, lmeta, lborn, lamp;
   size_t scale, pw, pcnt, gacc, logn, logoff, rmax, ws;
   size_t ckey, camp, cslot, csig;
   size_t cnt, fac, trig, init_d, init_a, sync;
@@ -65,9 +65,12 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   const size_t BH = static_cast<size_t>(B) * H;
   const size_t BL = static_cast<size_t>(B) * L;
   const size_t BS = static_cast<size_t>(B) * static_cast<size_t>(Mmax + 1);
-  l.slots = take(BH * (tsz == 4 ? sizeof(Slot<float>) : sizeof(Slot<double>)));
-  l.aux = take(tsz == 4 ? BH * sizeof(AuxF) : 0);
-  l.lslot = take(BL * 4);
+  // two table regions: the table ping-pongs between them when it grows
+  for (int r = 0; r < 2; ++r) {
+    l.slots[r] = take(BH * (tsz == 4 ? sizeof(Slot<float>) : sizeof(Slot<double>)));
+    l.aux[r] = take(tsz == 4 ? BH * sizeof(AuxF) : 0);
+  }
+  l.lkey = take(BL * 8);
   l.lmeta = take(BL * 4);
   l.lborn = take(BL * 4);
   l.lamp = take(BL * tsz);
@@ -141,24 +144,49 @@ FacMask factor_mask(const swc_exc& e) {
 }
 
 // A captured run of per-step kernels: direction (0 forward, 1 reverse),
-// steps k0..k1, threshold and log flag are baked into the kernel arguments.
+// steps k0..k1, threshold, log flag, table and occupancy limit are baked
+// into the kernel arguments.
 struct GraphKey {
   int dir;
   int64_t k0, k1;
   double thr;
   int log_on;
-  uint64_t extra;
+  const void* slots;
+  uint64_t H, lim;
   bool operator==(const GraphKey& o) const {
-    return dir == o.dir && k0 == o.k0 && k1 == o.k1 && thr == o.thr && log_on == o.log_on && extra == o.extra;
+    return dir == o.dir && k0 == o.k0 && k1 == o.k1 && thr == o.thr && log_on == o.log_on && slots == o.slots &&
+           H == o.H && lim == o.lim;
   }
 };
 constexpr int64_t GRAPH_CHUNK = 2048;
+constexpr size_t GRAPH_CACHE_MAX = 512;  // executable graphs kept per context
+
+// Forward steps run in chunks [2^j, 2^(j+1) - 1] below GRAPH_CHUNK and in
+// GRAPH_CHUNK-aligned chunks above: the last step of the chunk holding k.
+int64_t chunk_end(int64_t k) {
+  if (k >= GRAPH_CHUNK) return (k / GRAPH_CHUNK + 1) * GRAPH_CHUNK - 1;
+  int64_t p = 1;
+  while (2 * p <= k) p *= 2;
+  return 2 * p - 1;
+}
+int64_t chunk_begin(int64_t k) {
+  if (k >= GRAPH_CHUNK) return k / GRAPH_CHUNK * GRAPH_CHUNK;
+  int64_t p = 1;
+  while (2 * p <= k) p *= 2;
+  return p;
+}
 
 }  // namespace
 
 struct swc_ctx {
   int nq = 0, na = 0, nb = 0, prec = 0, B = 1;
-  uint64_t H = 0, L = 0;
+  uint64_t H = 0, L = 0;  // H: capacity (largest table), L: log records per state
+  // The table starts small and grows by rehashing into the other of two
+  // workspace regions (each sized for the capacity) between chunks of steps.
+  int region = 0;              // region holding the current table (tab.H slots)
+  uint64_t table_min = 1024;   // smallest table after a reset (SWC_TABLE_MIN)
+  int grid_override = 0;       // SWC_GRID
+  int64_t rehashes = 0;        // table growths in the last call
   int64_t Mmax = 0;
   hipStream_t st = nullptr;
   char* ws = nullptr;
@@ -226,8 +254,48 @@ int upload_masks(swc_ctx* c, const swc_exc* exc, int64_t M) {
   return SWC_OK;
 }
 
-// Reset every batch member to |Psi_0>.
+// Make table `Hn` in workspace region `r` the current one.
+void set_table(swc_ctx* c, int r, uint64_t Hn) {
+  c->region = r;
+  c->tab = Tab{c->ws + c->lay.slots[r], c->ws + c->lay.aux[r], Hn};
+  int g = grid_for(Hn, 256, MAX_SWEEP_BLOCKS);
+  if (c->grid_override > 0) g = std::min(c->grid_override, g);
+  c->grid = g;
+}
+
+// Occupancy above which a forward step stops the sweep for a growth: with at
+// most a doubling per step and a stop that takes effect two steps later, the
+// table never passes 4 x 0.225 = 90% occupancy.
+uint64_t occ_limit(const swc_ctx* c) { return c->tab.H < c->H ? c->tab.H / 40 * 9 : NO_LIMIT; }
+
+// Smallest table, at least Hmin, that holds `need` occupied slots at <= 10% load.
+uint64_t table_size_for(const swc_ctx* c, uint64_t need, uint64_t Hmin) {
+  if (c->persistent) return c->H;  // a persistent sweep cannot stop for a growth
+  uint64_t h = std::min(Hmin, c->H);
+  while (h < c->H && need > h / 10) h <<= 1;
+  return h;
+}
+
+// Rehash the current table into the other region at a larger size.
+int grow_table(swc_ctx* c, uint64_t need) {
+  const uint64_t Hn = table_size_for(c, need, 2 * c->tab.H);
+  if (Hn <= c->tab.H) return SWC_OK;
+  const int r = 1 - c->region;
+  const Tab to{c->ws + c->lay.slots[r], c->ws + c->lay.aux[r], Hn};
+  const Tab from = c->tab;
+  dispatch(c, [&](auto* tp) -> int {
+    launch_rehash<std::remove_pointer_t<decltype(tp)>>(from, to, c->cnt, c->B, c->st);
+    return SWC_OK;
+  });
+  SWC_HIP(hipGetLastError());
+  set_table(c, r, Hn);
+  ++c->rehashes;
+  return SWC_OK;
+}
+
+// Reset every batch member to |Psi_0> in a table sized for it.
 int reset_state(swc_ctx* c) {
+  set_table(c, 0, table_size_for(c, c->h_init_d.size(), c->table_min));
   dispatch(c, [&](auto* tp) -> int {
     launch_fill<std::remove_pointer_t<decltype(tp)>>(c->tab, c->B, c->st);
     return SWC_OK;
@@ -235,6 +303,7 @@ int reset_state(swc_ctx* c) {
   for (int b = 0; b < c->B; ++b) {
     Counters z{};
     z.S = c->S0;
+    z.stop = ~0u;
     c->hcnt[b] = z;
   }
   SWC_HIP(hipMemcpyAsync(c->cnt, c->hcnt.data(), sizeof(Counters) * c->B, hipMemcpyHostToDevice, c->st));
@@ -297,6 +366,11 @@ int cached_graph(swc_ctx* c, const GraphKey& key, hipGraphExec_t* out, F&& recor
       *out = g.second;
       return SWC_OK;
     }
+  if (c->graphs.size() >= GRAPH_CACHE_MAX) {  // bounded cache: start over once full
+    SWC_HIP(hipStreamSynchronize(c->st));
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+  }
   if (!c->cap_st) SWC_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
   SWC_HIP(hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal));
   record(c->cap_st);
@@ -311,53 +385,106 @@ int cached_graph(swc_ctx* c, const GraphKey& key, hipGraphExec_t* out, F&& recor
   return SWC_OK;
 }
 
+// Forward steps k0..k1 (k1 the end of k0's chunk, or M) on the current
+// table: a cached graph from the start of a chunk, single launches for a
+// chunk resumed after a growth or when every launch is timed.
+int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint64_t lim) {
+  return dispatch(c, [&](auto* tp) -> int {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    if (c->use_graph && !c->ktiming && chunk_begin(k0) == k0) {
+      const GraphKey key{0, k0, k1, thr, log_on, c->tab.slots, c->tab.H, lim};
+      hipGraphExec_t ex = nullptr;
+      const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) {
+        for (int64_t k = k0; k <= k1; ++k)
+          launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
+                        log_on, lim, c->B, c->grid, cs);
+      });
+      if (rr) return rr;
+      SWC_HIP(hipGraphLaunch(ex, c->st));
+      return SWC_OK;
+    }
+    for (int64_t k = k0; k <= k1; ++k) {
+      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
+      launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
+                    log_on, lim, c->B, c->grid, c->st);
+      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
+    }
+    return SWC_OK;
+  });
+}
+
+uint64_t max_occupancy(const swc_ctx* c) {
+  uint64_t o = 0;
+  for (int b = 0; b < c->B; ++b) o = std::max<uint64_t>(o, counter_total(c->hcnt[b], C_OCC));
+  return o;
+}
+
+// The forward sweep (Eq. 3): steps 1..M in order.  While the table can still
+// grow, the host reads the counters after every chunk of steps and rehashes
+// into a larger table when the occupancy approaches the growth limit, or
+// when a step stopped the sweep at that limit (the stopped steps are run
+// again on the grown table).
 int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   if (c->ktiming) {
     int r0 = ensure_kev(c, static_cast<size_t>(2 * M + 2));
     if (r0) return r0;
   }
+  c->rehashes = 0;
   dispatch(c, [&](auto* tp) -> int {
     launch_sweep_begin<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, c->cnt, M, c->B, c->st);
     return SWC_OK;
   });
   if (c->persistent) launch_sync_reset(c->sy, c->st);
   SWC_HIP(hipEventRecord(c->ev[0], c->st));
-  int r = dispatch(c, [&](auto* tp) -> int {
-    using T = std::remove_pointer_t<decltype(tp)>;
-    if (M == 0) return SWC_OK;
-    if (c->persistent) {
+  if (c->persistent && M > 0) {
+    const int r = dispatch(c, [&](auto* tp) -> int {
+      using T = std::remove_pointer_t<decltype(tp)>;
       if (c->ktiming) (void)hipEventRecord(c->kev[0], c->st);
-      SWC_HIP(launch_fwd_sweep<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, 1,
-                                  static_cast<int>(M), thr, 1, log_on, c->sy, c->B, c->grid_fwd, c->st));
+      SWC_HIP(launch_fwd_sweep<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, 1, static_cast<int>(M),
+                                  thr, 1, log_on, c->sy, c->B, c->grid_fwd, c->st));
       if (c->ktiming) (void)hipEventRecord(c->kev[1], c->st);
       return SWC_OK;
-    }
-    if (c->use_graph && !c->ktiming) {
-      // replay cached graphs of up to GRAPH_CHUNK steps each
-      for (int64_t k0 = 1; k0 <= M; k0 += GRAPH_CHUNK) {
-        const int64_t k1 = std::min<int64_t>(M, k0 + GRAPH_CHUNK - 1);
-        const GraphKey key{0, k0, k1, thr, log_on, 0};
-        hipGraphExec_t ex = nullptr;
-        const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) {
-          for (int64_t k = k0; k <= k1; ++k)
-            launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr,
-                          k == 1, log_on, c->B, c->grid, cs);
-        });
-        if (rr) return rr;
-        SWC_HIP(hipGraphLaunch(ex, c->st));
+    });
+    if (r) return r;
+  } else {
+    int64_t k = 1;
+    double prev_occ = -1.0;
+    while (k <= M) {
+      const uint64_t lim = occ_limit(c);
+      const int64_t k1 = std::min(M, chunk_end(k));
+      int r = run_fwd_steps(c, k, k1, thr, log_on, lim);
+      if (r) return r;
+      if (lim == NO_LIMIT) {
+        k = k1 + 1;
+        continue;
       }
-      return SWC_OK;
+      launch_sweep_end(c->sa, c->cnt, k1, c->B, nullptr, 1, c->st);
+      if ((r = read_counters(c))) return r;
+      // a step that stopped the sweep (stop = first step not run) asks for a growth
+      const uint32_t stop = c->hcnt[0].stop;
+      const bool stopped = stop != ~0u;
+      const int64_t next = stopped ? std::min<int64_t>(static_cast<int64_t>(stop), k1 + 1) : k1 + 1;
+      bool full = false;
+      for (int b = 0; b < c->B; ++b) full = full || (c->hcnt[b].flags & F_TABLE_FULL);
+      if (full) break;  // reported by the caller's status check
+      const double occ = static_cast<double>(max_occupancy(c));
+      const int64_t done = next - k;
+      // occupancy expected at the end of the next chunk, extrapolating the
+      // per-step growth of the last one, with a margin
+      double pred = 1.5 * occ;
+      if (next <= M && prev_occ > 0.0 && done > 0) {
+        const int64_t nlen = std::min(M, chunk_end(next)) - next + 1;
+        const double rate = std::max(1.0, occ / prev_occ);
+        pred = 1.5 * occ * std::pow(rate, static_cast<double>(nlen) / static_cast<double>(done));
+      }
+      if (stopped || pred > static_cast<double>(lim)) {
+        if ((r = grow_table(c, static_cast<uint64_t>(std::min(pred, 1e18))))) return r;
+      }
+      prev_occ = occ;
+      k = next;
     }
-    for (int64_t k = 1; k <= M; ++k) {
-      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
-      launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, c->B, c->grid, c->st);
-      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
-    }
-    return SWC_OK;
-  });
-  if (r) return r;
-  launch_sweep_end(c->sa, c->cnt, M, c->B, c->persistent ? c->sy : nullptr, c->st);
+  }
+  launch_sweep_end(c->sa, c->cnt, M, c->B, c->persistent ? c->sy : nullptr, 0, c->st);
   SWC_HIP(hipEventRecord(c->ev[1], c->st));
   SWC_HIP(hipGetLastError());
   return SWC_OK;
@@ -367,7 +494,8 @@ int sweep_status(swc_ctx* c) {
   for (int b = 0; b < c->B; ++b) {
     const Counters& k = c->hcnt[b];
     if (k.flags & F_TABLE_FULL) return fail(SWC_ECAPACITY, "hash table full");
-    if (counter_total(k, C_OCC) > c->H - c->H / 10) return fail(SWC_ECAPACITY, "hash table above 90% occupancy");
+    if (counter_total(k, C_OCC) > c->tab.H - c->tab.H / 10)
+      return fail(SWC_ECAPACITY, "hash table above 90% occupancy");
     if (counter_total(k, C_LIVE) == 0) return fail(SWC_EEMPTY, "truncation removed every determinant");
     if (k.flags & F_INCONSISTENT) return fail(SWC_EDEVICE, "inconsistent pair state in the reverse sweep");
     if (k.flags & F_TIMEOUT) return fail(SWC_EDEVICE, "grid barrier of a persistent sweep timed out");
@@ -400,7 +528,7 @@ int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool 
   });
   if (r) return r;
   SWC_HIP(hipEventRecord(c->ev[7], c->st));
-  launch_energy_reduce(c->cp, c->cnt, c->H, h1, h2, n, nmax, c->B, c->st);
+  launch_energy_reduce(c->cp, c->cnt, c->tab.H, h1, h2, n, nmax, c->B, c->st);
   launch_energy_final(c->cnt, E, c->B, c->st);
   if (want_lambda) {
     r = dispatch(c, [&](auto* tp) -> int {
@@ -462,8 +590,8 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   c->lay = make_layout(c->H, tsz, c->B, c->Mmax, c->L);
   const Layout& l = c->lay;
   char* w = c->ws;
-  c->tab = Tab{w + l.slots, w + l.aux, c->H};
-  c->lg = LogArr{reinterpret_cast<uint32_t*>(w + l.lslot), reinterpret_cast<uint32_t*>(w + l.lmeta),
+  c->tab = Tab{w + l.slots[0], w + l.aux[0], c->H};
+  c->lg = LogArr{reinterpret_cast<uint64_t*>(w + l.lkey), reinterpret_cast<uint32_t*>(w + l.lmeta),
                  reinterpret_cast<uint32_t*>(w + l.lborn), w + l.lamp, c->L};
   c->sa = StepArr{reinterpret_cast<double*>(w + l.scale),   reinterpret_cast<Fx*>(w + l.pw),
                   reinterpret_cast<uint32_t*>(w + l.pcnt),  reinterpret_cast<Fx*>(w + l.gacc),
@@ -480,12 +608,13 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   c->init_d = reinterpret_cast<uint64_t*>(w + l.init_d);
   c->init_a = reinterpret_cast<double*>(w + l.init_a);
   c->hcnt.assign(static_cast<size_t>(batch), Counters{});
-  int g = grid_for(c->H, 256, MAX_SWEEP_BLOCKS);
-  if (const char* e = std::getenv("SWC_GRID")) {  // tuning override, capped by the statistics slots
-    int v = std::atoi(e);
-    if (v > 0) g = std::min(v, grid_for(c->H, 256, MAX_SWEEP_BLOCKS));
+  if (const char* e = std::getenv("SWC_GRID")) c->grid_override = std::max(0, std::atoi(e));  // tuning override
+  if (const char* e = std::getenv("SWC_TABLE_MIN")) {  // smallest table after a reset (testing and tuning)
+    const long long v = std::atoll(e);
+    if (v >= 64 && pow2(static_cast<uint64_t>(v))) c->table_min = static_cast<uint64_t>(v);
   }
-  c->grid = g;
+  set_table(c, 0, c->H);
+  const int g = c->grid;
   c->sy = reinterpret_cast<Sync*>(w + l.sync);
   if (const char* e = std::getenv("SWC_SWEEP")) c->persistent = std::strcmp(e, "persistent") == 0;
   {
@@ -664,7 +793,7 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
       // no log restores interleaved: replay cached graphs, last chunk first
       for (int64_t k1 = M; k1 >= 1; k1 -= GRAPH_CHUNK) {
         const int64_t k0 = std::max<int64_t>(1, k1 - GRAPH_CHUNK + 1);
-        const GraphKey key{1, k0, k1, 0.0, 0, 0};
+        const GraphKey key{1, k0, k1, 0.0, 0, c->tab.slots, c->tab.H, 0};
         hipGraphExec_t ex = nullptr;
         const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) {
           for (int64_t k = k1; k >= k0; --k)
@@ -687,7 +816,7 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   if (r) return r;
   launch_grad_final(c->sa, c->cnt, grad, M, c->B, c->st);
   SWC_HIP(hipEventRecord(c->ev[5], c->st));
-  if (c->persistent) launch_sweep_end(c->sa, c->cnt, 0, c->B, c->sy, c->st);  // barrier status only
+  if (c->persistent) launch_sweep_end(c->sa, c->cnt, 0, c->B, c->sy, 0, c->st);  // barrier status only
   SWC_HIP(hipGetLastError());
   if ((r = read_counters(c))) return r;
   c->rev_ms = elapsed(c->ev[4], c->ev[5]);
@@ -724,8 +853,8 @@ int swc_get_state(swc_ctx* c, int b, uint64_t* dets, double* amps, int64_t cap, 
   if (n > cap) return fail(SWC_ECAPACITY, "output arrays too small");
   std::vector<uint64_t> k(static_cast<size_t>(n));
   std::vector<double> a(static_cast<size_t>(n));
-  SWC_HIP(hipMemcpyAsync(k.data(), c->cp.key + b * c->H, 8 * n, hipMemcpyDeviceToHost, c->st));
-  SWC_HIP(hipMemcpyAsync(a.data(), c->cp.amp + b * c->H, 8 * n, hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipMemcpyAsync(k.data(), c->cp.key + b * c->tab.H, 8 * n, hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipMemcpyAsync(a.data(), c->cp.amp + b * c->tab.H, 8 * n, hipMemcpyDeviceToHost, c->st));
   SWC_HIP(hipStreamSynchronize(c->st));
   std::vector<int64_t> idx(static_cast<size_t>(n));
   for (int64_t i = 0; i < n; ++i) idx[i] = i;
@@ -755,7 +884,8 @@ int swc_get_stats(swc_ctx* c, swc_stats* out) {
   s.n_live = static_cast<int64_t>(counter_total(c->hcnt[0], C_LIVE));
   s.slots_used = static_cast<int64_t>(counter_total(c->hcnt[0], C_OCC));
   s.log_records = c->log_records;
-  s.table_slots = static_cast<int64_t>(c->H);
+  s.table_slots = static_cast<int64_t>(c->tab.H);
+  s.rehashes = c->rehashes;
   s.fwd_ms = c->fwd_ms;
   s.energy_ms = c->energy_ms;
   s.rev_ms = c->rev_ms;

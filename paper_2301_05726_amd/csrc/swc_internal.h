@@ -19,6 +19,7 @@ namespace swc {
 // sweep resurrects them).  A dead entry keeps its key (tombstone) and, for a
 // death during the current sweep, the pre-truncation amplitude.
 constexpr uint64_t EMPTY_KEY = ~0ull;
+constexpr uint64_t NO_LIMIT = ~0ull;  // occupancy limit of a table that cannot grow
 constexpr int SH = 64;  // shards of each per-step accumulator
 constexpr uint32_t DEAD = 0x80000000u;
 constexpr uint32_t TAG = 0x7fffffffu;
@@ -57,6 +58,7 @@ enum : int {
   C_INS,       // created entries (forward)
   C_PRUNED,    // truncated amplitudes (forward)
   C_HITS,      // rotated pairs whose partner existed (forward)
+  C_COPY,      // slots copied by the last rehash
   C_NCNT
 };
 struct alignas(128) CShard {
@@ -69,7 +71,7 @@ struct Counters {
   unsigned long long logcnt;    // truncation-log records this sweep
   unsigned long long ncompact;  // entries in the compact arrays
   unsigned int flags;
-  unsigned int pad;
+  unsigned int stop;            // (member 0 only) first forward step that must not run; ~0u = none
   double S;                     // current renormalisation scale: psi = S * raw
   Fx num;                       // sum c sigma
   Fx den;                       // sum c^2
@@ -125,7 +127,7 @@ struct Tab {
 // truncation log: states of tombstones overwritten by a resurrection
 // during the forward sweep; member b at offset b*cap
 struct LogArr {
-  uint32_t* slot;
+  uint64_t* key;  // determinant of the overwritten tombstone (slots move on a rehash)
   uint32_t* meta;
   uint32_t* born;
   void* amp;
@@ -168,7 +170,10 @@ void launch_insert_init(const Tab& t, Counters* cnt, const uint64_t* dets, const
 void launch_trig(const double* theta, Trig* trig, int64_t M, int64_t ld, int B, Counters* cnt, hipStream_t st);
 template <class T>
 void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st);
-void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, hipStream_t st);
+// fold the per-wave statistics into the counters; unless fold_only, also the
+// final scale S_M
+void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, int fold_only,
+                      hipStream_t st);
 void launch_sync_reset(Sync* sy, hipStream_t st);
 // co-resident blocks per CU of the persistent forward (which=0) / reverse (1) sweep
 template <class T>
@@ -181,9 +186,13 @@ template <class T>
 hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa,
                             Counters* cnt, const LogArr& lg, int k_hi, int k_lo, Sync* sy, int B, int grid,
                             hipStream_t st);
+// occ_lim: a step that sees a member's occupancy above it stops the steps
+// after the next one (Counters::stop) so the host can grow the table;
+// NO_LIMIT for a table at full capacity
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                const LogArr& lg, int k, double thr, int prune_all, int log_on, int B, int grid, hipStream_t st);
+                const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
+                hipStream_t st);
 template <class T>
 void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 int k, int B, int grid, hipStream_t st);
@@ -201,6 +210,11 @@ void launch_energy_final(Counters* cnt, double* E, int B, hipStream_t st);
 template <class T>
 void launch_lambda(const Tab& t, const Compact& cp, const Counters* cnt, int64_t nmax, int B, hipStream_t st);
 void launch_energy_begin(Counters* cnt, int B, hipStream_t st);
+// rehash every slot of `from` that is alive or a tombstone of the current
+// sweep into the empty table `to` (larger); the occupancy counter becomes the
+// number of slots copied
+template <class T>
+void launch_rehash(const Tab& from, const Tab& to, Counters* cnt, int B, hipStream_t st);
 void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int64_t M, int B, hipStream_t st);
 
 int grid_for(uint64_t work, int block, int cap);

@@ -328,7 +328,10 @@ __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
     sa.pcnt[sidx(sa, b, sh, k)] = 0u;
     sa.gacc[sidx(sa, b, sh, k)] = fx_zero();
   }
-  for (uint64_t i = gtid; i < static_cast<uint64_t>(M + 1); i += gsz) sa.logn[base + i] = 0u;
+  for (uint64_t i = gtid; i < static_cast<uint64_t>(M + 1); i += gsz) {
+    sa.logn[base + i] = 0u;
+    sa.scale[base + i] = cnt[b].S;  // steps that remove nothing keep the scale
+  }
   for (uint64_t i = gtid; i < static_cast<uint64_t>(sa.nws * WSTAT); i += gsz) sa.ws[b * sa.nws * WSTAT + i] = 0ull;
   for (uint64_t i = gtid; i < static_cast<uint64_t>(CSH); i += gsz) {
     cnt[b].sh[i].v[C_DU] = 0;
@@ -338,33 +341,38 @@ __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
     cnt[b].sh[i].v[C_HITS] = 0;
   }
   if (gtid == 0) {
-    sa.scale[base] = cnt[b].S;
     cnt[b].logcnt = 0;
+    if (b == 0) cnt[0].stop = ~0u;
   }
 }
 
-// End of a forward sweep (one wave per state): final scale S_M, and the
-// per-wave statistics folded into the state's counters.
-__global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy) {
+// End of a forward sweep, or of a run of its steps (one wave per state): the
+// per-wave statistics folded into the state's counters, and at the end of
+// the sweep the final scale S_M.
+__global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy, int fold_only) {
   const int b = blockIdx.x;
   if (threadIdx.x == 0 && sy && sy->timeout) atomicOr(&cnt[b].flags, F_TIMEOUT);
   if (M == 0) return;
-  const double S = wave_scale(sa, b, static_cast<int>(M) + 1);
+  const double S = fold_only ? 0.0 : wave_scale(sa, b, static_cast<int>(M) + 1);
   unsigned long long tot[WSTAT];
   for (int i = 0; i < WSTAT; ++i) tot[i] = 0;
   for (int64_t w = threadIdx.x; w < sa.nws; w += 64)
-    for (int i = 0; i < WSTAT; ++i) tot[i] += sa.ws[(b * sa.nws + w) * WSTAT + i];
+    for (int i = 0; i < WSTAT; ++i) {
+      tot[i] += sa.ws[(b * sa.nws + w) * WSTAT + i];
+      sa.ws[(b * sa.nws + w) * WSTAT + i] = 0ull;  // folded: a later chunk starts from zero
+    }
   for (int i = 0; i < WSTAT; ++i) tot[i] = wave_u64(tot[i]);
   if (threadIdx.x == 0) {
-    sa.scale[static_cast<int64_t>(b) * sa.stride + M] = S;
-    cnt[b].S = S;
+    if (!fold_only) {
+      sa.scale[static_cast<int64_t>(b) * sa.stride + M] = S;
+      cnt[b].S = S;
+    }
     CShard& c0 = cnt[b].sh[0];
     c0.v[C_PRUNED] += tot[0];
     c0.v[C_DU] += tot[1];
     c0.v[C_PAIRS] += tot[2];
     c0.v[C_INS] += tot[3];
     c0.v[C_LIVE] += tot[3] - tot[4];
-    c0.v[C_OCC] += tot[5];
     c0.v[C_HITS] += tot[6];
   }
 }
@@ -381,12 +389,27 @@ __global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy
 template <class T>
 __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict__ fac,
                                          const Trig* __restrict__ trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                                         const LogArr& lg, int k, double thr, int prune_all, int log_on) {
+                                         const LogArr& lg, int k, double thr, int prune_all, int log_on,
+                                         uint64_t occ_lim) {
   const int b = blockIdx.y;
   const uint64_t H = t.H;
   const View<T> v = view<T>(t, b);
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
   const int lane = threadIdx.x & 63;
+  const uint32_t K = static_cast<uint32_t>(k);
+  if (occ_lim != NO_LIMIT) {
+    // Growth guard.  A step adds at most one slot per live entry, so the
+    // occupancy at most doubles per step.  Wave 0 of block 0 compares the
+    // occupancy it sees (>= that after step k-1) with the limit and, above
+    // it, stops every step from k+1 on: a step that runs saw occupancy
+    // <= limit two steps earlier, so it ends at <= 4 x limit.
+    if (K >= cnt[0].stop) return;
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+      unsigned long long o = lane < CSH ? cnt[b].sh[lane].v[C_OCC] : 0ull;
+      o = wave_u64(o);
+      if (lane == 0 && o > occ_lim) atomicMin(&cnt[0].stop, K + 1u);
+    }
+  }
   // this wave's statistics slot (read now, written back at the end)
   unsigned long long* wst = sa.ws + (static_cast<int64_t>(b) * sa.nws + (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6))) * WSTAT;
   const unsigned long long wold = lane < WSTAT ? wst[lane] : 0ull;
@@ -400,7 +423,6 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   const Trig tr = trig[b * ld + k - 1];
   const T sn = static_cast<T>(tr.s), cm1 = static_cast<T>(tr.cm1);
   const uint64_t pm = f.occ | f.vir;
-  const uint32_t K = static_cast<uint32_t>(k);
 
   Red r;
   r.f = fx_zero();
@@ -430,7 +452,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
         const unsigned long long pos = atomicAdd(&cnt[b].logcnt, 1ull);
         if (pos < lg.cap) {
           const uint64_t li = b * lg.cap + pos;
-          lg.slot[li] = static_cast<uint32_t>(s);
+          lg.key[li] = key;
           lg.meta[li] = old.meta;
           lg.born[li] = v.born(s);
           static_cast<T*>(lg.amp)[li] = old.amp;
@@ -517,6 +539,8 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       atomicAdd(&sa.pcnt[sidx(sa, b, wsh, k)], c[0]);
     }
   }
+  // occupancy is live: the growth guard of later steps reads it
+  if (c[5] && lane == 0) atomicAdd(&cnt[b].sh[wsh & (CSH - 1)].v[C_OCC], static_cast<unsigned long long>(c[5]));
   if (lane < 7) {
     const unsigned int mine = lane == 0 ? c[0] : lane == 1 ? c[1] : lane == 2 ? c[2] : lane == 3 ? c[3]
                               : lane == 4 ? c[4] : lane == 5 ? c[5] : c[6];
@@ -672,7 +696,12 @@ __device__ __forceinline__ void restore_step(const Tab& t, const LogArr& lg, con
   const uint32_t off = sa.logoff[base + k];
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint64_t li = b * lg.cap + off + i;
-    const uint64_t s = lg.slot[li];
+    // the determinant is still in the table (removed by the reverse step, so
+    // a tombstone); locate its slot by key
+    uint64_t ff;
+    Slot<T> cur;
+    const int64_t s = find_slot(v.sl, t.H, lg.key[li], &ff, &cur);
+    if (s < 0) continue;
     v.sl[s].meta = lg.meta[li];
     v.born(s) = lg.born[li];
     v.sl[s].amp = static_cast<const T*>(lg.amp)[li];
@@ -683,8 +712,8 @@ __device__ __forceinline__ void restore_step(const Tab& t, const LogArr& lg, con
 template <class T>
 __global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
                                              int64_t ld, StepArr sa, Counters* cnt, LogArr lg, int k, double thr,
-                                             int prune_all, int log_on) {
-  fwd_step<T>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on);
+                                             int prune_all, int log_on, uint64_t occ_lim) {
+  fwd_step<T>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on, occ_lim);
 }
 
 template <class T>
@@ -744,7 +773,7 @@ __global__ __launch_bounds__(BLK) void k_fwd_sweep(Tab t, const FacMask* __restr
   const unsigned int nblk = gridDim.x * gridDim.y;
   unsigned int epoch = 0;
   for (int k = k0; k <= k1; ++k) {
-    fwd_step<T>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_first && k == k0, log_on);
+    fwd_step<T>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_first && k == k0, log_on, NO_LIMIT);
     grid_barrier(sy, ++epoch * nblk);
   }
 }
@@ -990,6 +1019,46 @@ __global__ __launch_bounds__(BLK) void k_energy_reduce(Compact cp, Counters* cnt
   if (threadIdx.x == 0 && fx_nonzero(r.f)) fx_atomic_add(&cnt[b].den, r.f);
 }
 
+// ---------------------------------------------------------------------------
+// table growth: rehash into a larger, empty table
+// ---------------------------------------------------------------------------
+__global__ void k_rehash_begin(Counters* cnt) {
+  for (int i = threadIdx.x; i < CSH; i += blockDim.x) cnt[blockIdx.x].sh[i].v[C_COPY] = 0ull;
+}
+
+// Alive entries and tombstones of the current sweep (tag != 0; the reverse
+// sweep still needs their values) move to the new table; older tombstones are
+// dropped.  Keys are unique, so every copy claims its own slot.
+template <class T>
+__global__ void k_rehash(Tab from, Tab to, Counters* cnt) {
+  const int b = blockIdx.y;
+  const View<T> vf = view<T>(from, b), vt = view<T>(to, b);
+  unsigned long long n = 0;
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < from.H; s += gridDim.x * blockDim.x) {
+    const Slot<T> x = vf.sl[s];
+    if (x.key == EMPTY_KEY) continue;
+    if ((x.meta & DEAD) && (x.meta & TAG) == 0u) continue;
+    const int64_t d = claim_slot(vt.sl, to.H, x.key, mix64(x.key) & (to.H - 1));
+    if (d < 0) {
+      atomicOr(&cnt[b].flags, F_TABLE_FULL);
+      continue;
+    }
+    vt.sl[d].amp = x.amp;
+    vt.sl[d].meta = x.meta;
+    vt.born(d) = vf.born(s);
+    vt.lam(d) = vf.lam(s);
+    ++n;
+  }
+  n = wave_u64(n);
+  if ((threadIdx.x & 63) == 0 && n) atomicAdd(&cnt[b].sh[cshard()].v[C_COPY], n);
+}
+
+// the occupancy of the new table is the number of slots copied
+__global__ void k_rehash_end(Counters* cnt) {
+  for (int i = threadIdx.x; i < CSH; i += blockDim.x) cnt[blockIdx.x].sh[i].v[C_OCC] = cnt[blockIdx.x].sh[i].v[C_COPY];
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[0].stop = ~0u;  // the grown table lets the stopped steps run
+}
+
 __global__ void k_energy_begin(Counters* cnt, int B) {
   const int b = threadIdx.x;
   if (b >= B) return;
@@ -1063,8 +1132,9 @@ void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t 
   hipLaunchKernelGGL(k_sweep_begin<T>, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t, sa, cnt, M);
 }
 
-void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, hipStream_t st) {
-  hipLaunchKernelGGL(k_sweep_end, dim3(B), dim3(64), 0, st, sa, cnt, M, sy);
+void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, int fold_only,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_sweep_end, dim3(B), dim3(64), 0, st, sa, cnt, M, sy, fold_only);
 }
 
 void launch_sync_reset(Sync* sy, hipStream_t st) { hipLaunchKernelGGL(k_sync_reset, dim3(1), dim3(64), 0, st, sy); }
@@ -1117,9 +1187,10 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
 
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                const LogArr& lg, int k, double thr, int prune_all, int log_on, int B, int grid, hipStream_t st) {
+                const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
+                hipStream_t st) {
   hipLaunchKernelGGL(k_fwd<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all,
-                     log_on);
+                     log_on, occ_lim);
 }
 
 template <class T>
@@ -1156,6 +1227,14 @@ void launch_energy_begin(Counters* cnt, int B, hipStream_t st) {
   hipLaunchKernelGGL(k_energy_begin, dim3(1), dim3(64 * ((B + 63) / 64)), 0, st, cnt, B);
 }
 
+template <class T>
+void launch_rehash(const Tab& from, const Tab& to, Counters* cnt, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(to.H, BLK, 8192), B), dim3(BLK), 0, st, to);
+  hipLaunchKernelGGL(k_rehash_begin, dim3(B), dim3(64), 0, st, cnt);
+  hipLaunchKernelGGL(k_rehash<T>, dim3(grid_for(from.H, BLK, 8192), B), dim3(BLK), 0, st, from, to, cnt);
+  hipLaunchKernelGGL(k_rehash_end, dim3(B), dim3(64), 0, st, cnt);
+}
+
 void launch_energy_final(Counters* cnt, double* E, int B, hipStream_t st) {
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64 * ((B + 63) / 64)), 0, st, cnt, E, B);
 }
@@ -1176,7 +1255,7 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
                                       hipStream_t);                                                                \
   template void launch_sweep_begin<T>(const Tab&, const StepArr&, Counters*, int64_t, int, hipStream_t);          \
   template void launch_fwd<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*,        \
-                              const LogArr&, int, double, int, int, int, int, hipStream_t);                        \
+                              const LogArr&, int, double, int, int, uint64_t, int, int, hipStream_t);              \
   template void launch_rev<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,   \
                               int, int, hipStream_t);                                                              \
   template void launch_log_restore<T>(const Tab&, const LogArr&, const StepArr&, int, int, uint32_t,              \
@@ -1190,7 +1269,8 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
                                           Counters*, const LogArr&, int, int, double, int, int, Sync*, int, int,   \
                                           hipStream_t);                                                            \
   template hipError_t launch_rev_sweep<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&,       \
-                                          Counters*, const LogArr&, int, int, Sync*, int, int, hipStream_t);
+                                          Counters*, const LogArr&, int, int, Sync*, int, int, hipStream_t);      \
+  template void launch_rehash<T>(const Tab&, const Tab&, Counters*, int, hipStream_t);
 
 SWC_INST(float)
 SWC_INST(double)

@@ -41,6 +41,7 @@ class Stats(ctypes.Structure):
         ("rotate_kernel_ms", ctypes.c_double), ("rotate_launches", ctypes.c_int64),
         ("reverse_kernel_ms", ctypes.c_double), ("reverse_launches", ctypes.c_int64),
         ("sigma_kernel_ms", ctypes.c_double), ("partner_hits", ctypes.c_int64),
+        ("rehashes", ctypes.c_int64),
     ]
 
 

@@ -193,3 +193,78 @@ def test_sweep_modes_bitwise_identical(swc, monkeypatch, prec):
         results[mode] = reps[0]
         s.close()
     assert results["graph"] == results["direct"] == results["persistent"]
+
+
+GROW_CASES = [
+    ("q16", 8, 4, 0.1, 104, None, 0.0),
+    ("q12_thr", 6, 3, 0.25, 103, None, 2e-3),
+    ("q16_thr", 8, 4, 0.1, 105, None, 1e-4),
+    ("q20_pre_thr", 10, 5, 0.05, 107, 300, 1e-5),
+]
+
+
+def _run_with_table_min(swc, monkeypatch, tmin, nq, n_occ, cap, prec, batch, exc, theta, thr, h1, h2):
+    monkeypatch.setenv("SWC_TABLE_MIN", str(tmin))
+    s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=batch, max_factors=exc.shape[0])
+    s.build_state()
+    s.apply_ucc(theta, exc, thr)
+    st = s.stats()
+    states = [s.get_state(b) for b in range(batch)]
+    E = s.energy(h1, h2).cpu().numpy()
+    E2, g = s.energy_and_grad(theta, exc, thr, h1, h2)
+    st2 = s.stats()
+    s.close()
+    return st, st2, states, E, E2.cpu().numpy(), g.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", GROW_CASES, ids=[c[0] for c in GROW_CASES])
+def test_table_growth_exact(swc, orc, monkeypatch, case, prec):
+    """A table that starts at 64 slots and is rehashed into larger ones during
+    the sweep gives the same bits as a table of full capacity from the start
+    (every reduction is an exact fixed-point sum and each pair rotation is
+    independent of slot placement), and matches the oracle."""
+    name, n_orb, n_occ, sigma, seed, nf, thr = case
+    say(f"[case] growth {name} prec={prec} thr={thr}")
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed, nf)
+    nq = 2 * n_orb
+    cap = capacity_for(n_orb, n_occ)
+    grown = _run_with_table_min(swc, monkeypatch, 64, nq, n_occ, cap, prec, 1, exc, theta, thr, h1, h2)
+    fixed = _run_with_table_min(swc, monkeypatch, cap, nq, n_occ, cap, prec, 1, exc, theta, thr, h1, h2)
+    say(f"  grown: rehashes={grown[0]['rehashes']}/{grown[1]['rehashes']} table={grown[0]['table_slots']} "
+        f"fixed: rehashes={fixed[0]['rehashes']} table={fixed[0]['table_slots']}")
+    assert grown[0]["rehashes"] >= 2 and grown[1]["rehashes"] >= 2
+    assert fixed[0]["rehashes"] == 0 and fixed[0]["table_slots"] == cap
+    assert grown[0]["n_live"] == fixed[0]["n_live"]
+    for x, y in zip(grown[2][0], fixed[2][0]):
+        assert x.tobytes() == y.tobytes()
+    for i in (3, 4, 5):
+        assert grown[i].tobytes() == fixed[i].tobytes()
+    tol = TOL[prec]
+    orc.set_nearcut_window(1e-5)
+    d_ref, a_ref, nc, _ = orc.apply_ucc(nq, [hf], [1.0], exc, theta[0], thr)
+    E_ref, g_ref, _ = orc.energy_and_grad(nq, [hf], [1.0], exc, theta[0], thr, h1, h2)
+    assert nc == 0
+    compare_states(grown[2][0][0], grown[2][0][1], d_ref, a_ref, tol["amp"])
+    assert abs(grown[3][0] - E_ref) <= tol["E"] and abs(grown[4][0] - E_ref) <= tol["E"]
+    assert np.max(np.abs(grown[5][0] - g_ref)) <= tol["g"]
+
+
+def test_table_growth_batch(swc, orc, monkeypatch):
+    """Batch members share one table size: a growth triggered by any member
+    rehashes all of them; each still matches its own oracle run."""
+    say("[case] growth batch3 q16_thr fp32")
+    h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 171, batch=3)
+    thr = 1e-4
+    cap = capacity_for(8, 4)
+    grown = _run_with_table_min(swc, monkeypatch, 64, 16, 4, cap, 1, 3, exc, theta, thr, h1, h2)
+    fixed = _run_with_table_min(swc, monkeypatch, cap, 16, 4, cap, 1, 3, exc, theta, thr, h1, h2)
+    assert grown[0]["rehashes"] >= 2
+    for i in (3, 4, 5):
+        assert grown[i].tobytes() == fixed[i].tobytes()
+    orc.set_nearcut_window(1e-5)
+    for b in range(3):
+        E_ref, g_ref, nc = orc.energy_and_grad(16, [hf], [1.0], exc, theta[b], thr, h1, h2)
+        assert nc == 0
+        assert abs(grown[4][b] - E_ref) <= TOL[1]["E"]
+        assert np.max(np.abs(grown[5][b] - g_ref)) <= TOL[1]["g"]
