@@ -103,6 +103,9 @@ typedef struct {
   double sigma_kernel_ms;    /* duration of the sigma kernel */
   int64_t partner_hits;      /* pairs whose partner existed (last forward sweep) */
   int64_t rehashes;          /* table growths during the last forward sweep */
+  int64_t compactions;       /* rehashes at its start that dropped tombstones of
+                                earlier sweeps (over 1/4 of the occupied slots) */
+  int64_t checkpoints;       /* snapshots taken by the last gradient sweep */
 } swc_stats;
 
 /*
@@ -159,6 +162,30 @@ int swc_energy(swc_ctx* ctx, const double* h1, const double* h2, double* E);
  */
 int swc_energy_and_grad(swc_ctx* ctx, const double* theta, const swc_exc* exc, int64_t M, double threshold,
                         const double* h1, const double* h2, double* E, double* grad);
+
+/*
+ * Checkpoints of the gradient sweep.  The adjoint sweep rebuilds each
+ * forward state psi_{k-1} from psi_k by inverting step k exactly (the support
+ * is rebuilt bit for bit from per-entry step tags and the truncation log);
+ * in floating point the rebuilt amplitudes drift by rounding, step after
+ * step.  With checkpoints on, swc_energy_and_grad snapshots the live
+ * (determinant, amplitude) pairs after forward steps interval, 2*interval,
+ * ... (< M), and the adjoint sweep writes each snapshot back over the state
+ * it has rebuilt for the same step, so the drift never spans more than
+ * `interval` steps.  The results match the uncheckpointed sweep within
+ * rounding; the FP32 gradient of a long circuit is closer to the FP64 one.
+ *
+ * swc_checkpoint_bytes: size of the device buffer for circuits of up to
+ * max_factors factors, snapshots of up to max_entries live determinants per
+ * batch member (12 bytes per entry in FP32, 16 in FP64), or 0 for invalid
+ * arguments.  swc_set_checkpoints: `buffer` (device, 256-byte aligned, owned
+ * by the caller, kept until the next call or swc_destroy) turns checkpoints
+ * on; interval <= 0 turns them off (buffer may be NULL).  A snapshot with
+ * more live determinants than max_entries makes swc_energy_and_grad return
+ * SWC_ECAPACITY.
+ */
+size_t swc_checkpoint_bytes(int prec, int batch, int64_t max_factors, int64_t interval, uint64_t max_entries);
+int swc_set_checkpoints(swc_ctx* ctx, int64_t interval, uint64_t max_entries, void* buffer, size_t bytes);
 
 /*
  * Copy the current state of batch member b to host arrays sorted by

@@ -161,19 +161,19 @@ struct GraphKey {
 constexpr int64_t GRAPH_CHUNK = 2048;
 constexpr size_t GRAPH_CACHE_MAX = 512;  // executable graphs kept per context
 
-// Forward steps run in chunks [2^j, 2^(j+1) - 1] below GRAPH_CHUNK and in
-// GRAPH_CHUNK-aligned chunks above: the last step of the chunk holding k.
+// Steps run in chunks [2^(j-1) + 1, 2^j] up to GRAPH_CHUNK and in chunks
+// [m GRAPH_CHUNK + 1, (m + 1) GRAPH_CHUNK] above (so a chunk ends at every
+// power of two up to GRAPH_CHUNK and at every multiple of it).
 int64_t chunk_end(int64_t k) {
-  if (k >= GRAPH_CHUNK) return (k / GRAPH_CHUNK + 1) * GRAPH_CHUNK - 1;
+  if (k > GRAPH_CHUNK) return (k + GRAPH_CHUNK - 1) / GRAPH_CHUNK * GRAPH_CHUNK;
   int64_t p = 1;
-  while (2 * p <= k) p *= 2;
-  return 2 * p - 1;
+  while (p < k) p *= 2;
+  return p;
 }
 int64_t chunk_begin(int64_t k) {
-  if (k >= GRAPH_CHUNK) return k / GRAPH_CHUNK * GRAPH_CHUNK;
-  int64_t p = 1;
-  while (2 * p <= k) p *= 2;
-  return p;
+  if (k > GRAPH_CHUNK) return (k - 1) / GRAPH_CHUNK * GRAPH_CHUNK + 1;
+  const int64_t p = chunk_end(k);
+  return p == 1 ? 1 : p / 2 + 1;
 }
 
 }  // namespace
@@ -186,7 +186,19 @@ struct swc_ctx {
   int region = 0;              // region holding the current table (tab.H slots)
   uint64_t table_min = 1024;   // smallest table after a reset (SWC_TABLE_MIN)
   int grid_override = 0;       // SWC_GRID
-  int64_t rehashes = 0;        // table growths in the last call
+  // checkpoints (swc_set_checkpoints): snapshot j holds the state after
+  // forward step (j + 1) * ck_interval, in a caller-owned buffer
+  int64_t ck_interval = 0;
+  uint64_t ck_cap = 0;
+  int64_t ck_n = 0;  // snapshots the buffer holds
+  uint64_t* ck_key = nullptr;
+  char* ck_amp = nullptr;
+  unsigned long long* ck_count = nullptr;
+  int64_t ck_taken = 0;
+  std::vector<uint64_t> ck_nmax;  // per checkpoint: most entries over the batch (last sweep)
+  int64_t fwd_launches = 0, rev_launches = 0;  // launches of the last sweeps (per-launch timing)
+  int64_t rehashes = 0;        // table growths in the last forward sweep
+  int64_t compactions = 0;     // tombstone-dropping rehashes at its start
   int64_t Mmax = 0;
   hipStream_t st = nullptr;
   char* ws = nullptr;
@@ -276,10 +288,8 @@ uint64_t table_size_for(const swc_ctx* c, uint64_t need, uint64_t Hmin) {
   return h;
 }
 
-// Rehash the current table into the other region at a larger size.
-int grow_table(swc_ctx* c, uint64_t need) {
-  const uint64_t Hn = table_size_for(c, need, 2 * c->tab.H);
-  if (Hn <= c->tab.H) return SWC_OK;
+// Rehash the current table into the other region, `Hn` slots.
+int rehash_to(swc_ctx* c, uint64_t Hn) {
   const int r = 1 - c->region;
   const Tab to{c->ws + c->lay.slots[r], c->ws + c->lay.aux[r], Hn};
   const Tab from = c->tab;
@@ -291,6 +301,15 @@ int grow_table(swc_ctx* c, uint64_t need) {
   set_table(c, r, Hn);
   ++c->rehashes;
   return SWC_OK;
+}
+
+// Grow the table (x2 at least) so that `need` occupied slots stay under the
+// growth limit of the new size.
+int grow_table(swc_ctx* c, uint64_t need) {
+  if (c->persistent || c->tab.H >= c->H) return SWC_OK;
+  uint64_t Hn = 2 * c->tab.H;
+  while (Hn < c->H && need > Hn / 40 * 9) Hn <<= 1;
+  return rehash_to(c, std::min(Hn, c->H));
 }
 
 // Reset every batch member to |Psi_0> in a table sized for it.
@@ -385,13 +404,14 @@ int cached_graph(swc_ctx* c, const GraphKey& key, hipGraphExec_t* out, F&& recor
   return SWC_OK;
 }
 
-// Forward steps k0..k1 (k1 the end of k0's chunk, or M) on the current
-// table: a cached graph from the start of a chunk, single launches for a
-// chunk resumed after a growth or when every launch is timed.
-int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint64_t lim) {
+// Forward steps k0..k1 on the current table: a cached graph (`graph_ok`:
+// the range starts where a chunk or a checkpoint interval starts, so the same
+// ranges recur call after call), else single launches (a range resumed after
+// a growth, or every launch timed).
+int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint64_t lim, bool graph_ok) {
   return dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
-    if (c->use_graph && !c->ktiming && chunk_begin(k0) == k0) {
+    if (c->use_graph && !c->ktiming && graph_ok) {
       const GraphKey key{0, k0, k1, thr, log_on, c->tab.slots, c->tab.H, lim};
       hipGraphExec_t ex = nullptr;
       const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) {
@@ -413,6 +433,45 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
   });
 }
 
+// Checkpoint j (0-based) holds the state after forward step (j+1)*interval;
+// -1 when no checkpoint is taken after step `k` of an M-step sweep.
+int64_t ckpt_index(const swc_ctx* c, int64_t k, int64_t M) {
+  const int64_t K = c->ck_interval;
+  if (K <= 0 || k <= 0 || k >= M || k % K) return -1;
+  const int64_t j = k / K - 1;
+  return j < c->ck_n ? j : -1;
+}
+
+Snap ckpt_snap(const swc_ctx* c, int64_t j) {
+  const size_t tsz = c->prec == SWC_FP32 ? 4 : 8;
+  const size_t per = static_cast<size_t>(c->B) * c->ck_cap;
+  return Snap{c->ck_key + j * per, c->ck_amp + j * per * tsz, c->ck_count + j * c->B, c->ck_cap};
+}
+
+// Last step of the range of forward steps that starts at k: the end of k's
+// chunk, cut at M and, in a gradient sweep, at the next checkpoint.
+int64_t fwd_range_end(const swc_ctx* c, int64_t k, int64_t M, int log_on) {
+  int64_t e = std::min(M, chunk_end(k));
+  if (log_on && c->ck_interval > 0) {
+    const int64_t nxt = (k + c->ck_interval - 1) / c->ck_interval * c->ck_interval;
+    if (ckpt_index(c, nxt, M) >= 0) e = std::min(e, nxt);
+  }
+  return e;
+}
+
+int take_checkpoint(swc_ctx* c, int64_t k, int64_t M, int log_on) {
+  if (!log_on) return SWC_OK;
+  const int64_t j = ckpt_index(c, k, M);
+  if (j < 0) return SWC_OK;
+  dispatch(c, [&](auto* tp) -> int {
+    launch_snapshot<std::remove_pointer_t<decltype(tp)>>(c->tab, ckpt_snap(c, j), c->B, c->grid, c->st);
+    return SWC_OK;
+  });
+  ++c->ck_taken;
+  SWC_HIP(hipGetLastError());
+  return SWC_OK;
+}
+
 uint64_t max_occupancy(const swc_ctx* c) {
   uint64_t o = 0;
   for (int b = 0; b < c->B; ++b) o = std::max<uint64_t>(o, counter_total(c->hcnt[b], C_OCC));
@@ -430,31 +489,69 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
     if (r0) return r0;
   }
   c->rehashes = 0;
+  c->compactions = 0;
   dispatch(c, [&](auto* tp) -> int {
     launch_sweep_begin<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, c->cnt, M, c->B, c->st);
     return SWC_OK;
   });
-  if (c->persistent) launch_sync_reset(c->sy, c->st);
   SWC_HIP(hipEventRecord(c->ev[0], c->st));
-  if (c->persistent && M > 0) {
-    const int r = dispatch(c, [&](auto* tp) -> int {
-      using T = std::remove_pointer_t<decltype(tp)>;
-      if (c->ktiming) (void)hipEventRecord(c->kev[0], c->st);
-      SWC_HIP(launch_fwd_sweep<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, 1, static_cast<int>(M),
-                                  thr, 1, log_on, c->sy, c->B, c->grid_fwd, c->st));
-      if (c->ktiming) (void)hipEventRecord(c->kev[1], c->st);
-      return SWC_OK;
-    });
-    if (r) return r;
+  {
+    // Tombstones of earlier sweeps (tag 0 after the sweep start) are dropped
+    // by a rehash; compact when they are over a quarter of the occupied slots.
+    // The counters are current: the theta check has just read them.
+    uint64_t live = 0;
+    bool compact = false;
+    for (int b = 0; b < c->B; ++b) {
+      const uint64_t lb = counter_total(c->hcnt[b], C_LIVE), ob = counter_total(c->hcnt[b], C_OCC);
+      live = std::max(live, lb);
+      compact = compact || (ob >= 1024 && 4 * (ob - std::min(ob, lb)) > ob);
+    }
+    if (M > 0 && compact) {
+      const int r = rehash_to(c, table_size_for(c, live, c->table_min));
+      if (r) return r;
+      --c->rehashes;
+      ++c->compactions;
+    }
+  }
+  c->ck_taken = 0;
+  if (log_on && c->ck_n > 0) launch_zero_u64(c->ck_count, static_cast<uint64_t>(c->ck_n) * c->B, c->st);
+  c->fwd_launches = 0;
+  if (c->persistent) {
+    // one cooperative launch per range between checkpoints
+    for (int64_t k = 1; k <= M;) {
+      int64_t k1 = M;
+      if (log_on && c->ck_interval > 0) {
+        const int64_t nxt = (k + c->ck_interval - 1) / c->ck_interval * c->ck_interval;
+        if (ckpt_index(c, nxt, M) >= 0) k1 = nxt;
+      }
+      launch_sync_reset(c->sy, k == 1, c->st);
+      const int r = dispatch(c, [&](auto* tp) -> int {
+        using T = std::remove_pointer_t<decltype(tp)>;
+        const int64_t i = c->fwd_launches;
+        if (c->ktiming) (void)hipEventRecord(c->kev[2 * i], c->st);
+        SWC_HIP(launch_fwd_sweep<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k),
+                                    static_cast<int>(k1), thr, k == 1, log_on, c->sy, c->B, c->grid_fwd, c->st));
+        if (c->ktiming) (void)hipEventRecord(c->kev[2 * i + 1], c->st);
+        return SWC_OK;
+      });
+      if (r) return r;
+      ++c->fwd_launches;
+      if (int rr = take_checkpoint(c, k1, M, log_on)) return rr;
+      k = k1 + 1;
+    }
   } else {
+    c->fwd_launches = M;
     int64_t k = 1;
-    double prev_occ = -1.0;
+    bool resumed = false;
+    double prev_occ = static_cast<double>(max_occupancy(c));  // counters read before the sweep
     while (k <= M) {
       const uint64_t lim = occ_limit(c);
-      const int64_t k1 = std::min(M, chunk_end(k));
-      int r = run_fwd_steps(c, k, k1, thr, log_on, lim);
+      const int64_t k1 = fwd_range_end(c, k, M, log_on);
+      int r = run_fwd_steps(c, k, k1, thr, log_on, lim, !resumed);
       if (r) return r;
       if (lim == NO_LIMIT) {
+        if ((r = take_checkpoint(c, k1, M, log_on))) return r;
+        resumed = false;
         k = k1 + 1;
         continue;
       }
@@ -467,25 +564,86 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       bool full = false;
       for (int b = 0; b < c->B; ++b) full = full || (c->hcnt[b].flags & F_TABLE_FULL);
       if (full) break;  // reported by the caller's status check
+      if (next == k1 + 1 && (r = take_checkpoint(c, k1, M, log_on))) return r;
       const double occ = static_cast<double>(max_occupancy(c));
       const int64_t done = next - k;
-      // occupancy expected at the end of the next chunk, extrapolating the
-      // per-step growth of the last one, with a margin
-      double pred = 1.5 * occ;
-      if (next <= M && prev_occ > 0.0 && done > 0) {
-        const int64_t nlen = std::min(M, chunk_end(next)) - next + 1;
-        const double rate = std::max(1.0, occ / prev_occ);
-        pred = 1.5 * occ * std::pow(rate, static_cast<double>(nlen) / static_cast<double>(done));
+      // occupancy expected at the end of the next range: the last range's
+      // growth per step, extrapolated linearly with a factor-2 margin (a
+      // growth that outruns it is caught by the stop)
+      double pred = occ;
+      if (next <= M && prev_occ >= 0.0 && done > 0) {
+        const int64_t nlen = fwd_range_end(c, next, M, log_on) - next + 1;
+        pred = occ + 2.0 * std::max(0.0, occ - prev_occ) * static_cast<double>(nlen) / static_cast<double>(done);
       }
+      if (stopped) pred = std::max(pred, 2.0 * occ);
       if (stopped || pred > static_cast<double>(lim)) {
         if ((r = grow_table(c, static_cast<uint64_t>(std::min(pred, 1e18))))) return r;
       }
       prev_occ = occ;
+      resumed = next != k1 + 1;
       k = next;
     }
   }
-  launch_sweep_end(c->sa, c->cnt, M, c->B, c->persistent ? c->sy : nullptr, 0, c->st);
+  launch_sweep_end(c->sa, c->cnt, M, c->B, (c->persistent && M > 0) ? c->sy : nullptr, 0, c->st);
   SWC_HIP(hipEventRecord(c->ev[1], c->st));
+  SWC_HIP(hipGetLastError());
+  return SWC_OK;
+}
+
+// The adjoint sweep, steps M..1, in ranges that end where a chunk or a
+// checkpoint interval ends; after the range that reconstructs the state of a
+// checkpoint, the checkpoint's amplitudes are written back over it.
+// maxn[k]: largest number of truncation-log records of step k over the batch.
+int reverse_sweep(swc_ctx* c, int64_t M, const std::vector<uint32_t>& maxn) {
+  c->rev_launches = 0;
+  for (int64_t hi = M; hi >= 1;) {
+    int64_t lo = chunk_begin(hi);
+    if (c->ck_interval > 0) lo = std::max(lo, (hi - 1) / c->ck_interval * c->ck_interval + 1);
+    const int r = dispatch(c, [&](auto* tp) -> int {
+      using T = std::remove_pointer_t<decltype(tp)>;
+      if (c->persistent) {
+        launch_sync_reset(c->sy, hi == M, c->st);
+        const int64_t i = c->rev_launches++;
+        if (c->ktiming) (void)hipEventRecord(c->kev[2 * i], c->st);
+        SWC_HIP(launch_rev_sweep<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(hi),
+                                    static_cast<int>(lo), c->sy, c->B, c->grid_rev, c->st));
+        if (c->ktiming) (void)hipEventRecord(c->kev[2 * i + 1], c->st);
+        return SWC_OK;
+      }
+      if (c->use_graph && !c->ktiming && c->log_records == 0) {
+        // no log restores interleaved: a cached graph of the range
+        const GraphKey key{1, lo, hi, 0.0, 0, c->tab.slots, c->tab.H, 0};
+        hipGraphExec_t ex = nullptr;
+        const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) {
+          for (int64_t k = hi; k >= lo; --k)
+            launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid,
+                          cs);
+        });
+        if (rr) return rr;
+        SWC_HIP(hipGraphLaunch(ex, c->st));
+        c->rev_launches += hi - lo + 1;
+        return SWC_OK;
+      }
+      for (int64_t k = hi; k >= lo; --k) {
+        if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
+        launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid, c->st);
+        if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
+        if (maxn[k]) launch_log_restore<T>(c->tab, c->lg, c->sa, static_cast<int>(k), c->B, maxn[k], c->st);
+      }
+      c->rev_launches += hi - lo + 1;
+      return SWC_OK;
+    });
+    if (r) return r;
+    const int64_t j = ckpt_index(c, lo - 1, M);
+    if (j >= 0) {
+      dispatch(c, [&](auto* tp) -> int {
+        launch_snap_restore<std::remove_pointer_t<decltype(tp)>>(c->tab, ckpt_snap(c, j), c->cnt, c->ck_nmax[j], c->B,
+                                                                 c->st);
+        return SWC_OK;
+      });
+    }
+    hi = lo - 1;
+  }
   SWC_HIP(hipGetLastError());
   return SWC_OK;
 }
@@ -700,9 +858,8 @@ int swc_apply_ucc(swc_ctx* c, const double* theta, const swc_exc* exc, int64_t M
   if ((r = read_counters(c))) return r;
   c->fwd_ms = elapsed(c->ev[0], c->ev[1]);
   if (c->ktiming) {
-    const int64_t nl = c->persistent ? (M > 0 ? 1 : 0) : M;
-    c->rot_ms = sum_pairs(c, nl);
-    c->rot_n = nl;
+    c->rot_ms = sum_pairs(c, c->fwd_launches);
+    c->rot_n = c->fwd_launches;
   }
   r = sweep_status(c);
   if (r) c->built = false;
@@ -743,11 +900,23 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
       reset_state(c);
       return fail(SWC_ECAPACITY, "truncation log full");
     }
+  if (c->ck_taken > 0) {
+    std::vector<unsigned long long> cnts(static_cast<size_t>(c->ck_taken) * c->B);
+    SWC_HIP(hipMemcpyAsync(cnts.data(), c->ck_count, 8 * cnts.size(), hipMemcpyDeviceToHost, c->st));
+    SWC_HIP(hipStreamSynchronize(c->st));
+    c->ck_nmax.assign(static_cast<size_t>(c->ck_n), 0);
+    for (int64_t j = 0; j < c->ck_taken; ++j)
+      for (int b = 0; b < c->B; ++b) c->ck_nmax[j] = std::max<uint64_t>(c->ck_nmax[j], cnts[j * c->B + b]);
+    for (int64_t j = 0; j < c->ck_taken; ++j)
+      if (c->ck_nmax[j] > c->ck_cap) {
+        reset_state(c);
+        return fail(SWC_ECAPACITY, "checkpoint holds fewer entries than the state");
+      }
+  }
   c->fwd_ms = elapsed(c->ev[0], c->ev[1]);
   if (c->ktiming) {
-    const int64_t nl = c->persistent ? (M > 0 ? 1 : 0) : M;
-    c->rot_ms = sum_pairs(c, nl);
-    c->rot_n = nl;
+    c->rot_ms = sum_pairs(c, c->fwd_launches);
+    c->rot_n = c->fwd_launches;
   }
   if ((r = energy_impl(c, h1, h2, E, true))) {
     reset_state(c);
@@ -776,54 +945,18 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   }
   if (c->persistent && M > 0) {
     SWC_HIP(hipMemcpyAsync(c->sa.rmax, maxn.data(), 4 * (M + 1), hipMemcpyHostToDevice, c->st));
-    launch_sync_reset(c->sy, c->st);
   }
   SWC_HIP(hipEventRecord(c->ev[4], c->st));
-  r = dispatch(c, [&](auto* tp) -> int {
-    using T = std::remove_pointer_t<decltype(tp)>;
-    if (c->persistent) {
-      if (M == 0) return SWC_OK;
-      if (c->ktiming) (void)hipEventRecord(c->kev[0], c->st);
-      SWC_HIP(launch_rev_sweep<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(M), 1,
-                                  c->sy, c->B, c->grid_rev, c->st));
-      if (c->ktiming) (void)hipEventRecord(c->kev[1], c->st);
-      return SWC_OK;
-    }
-    if (c->use_graph && !c->ktiming && c->log_records == 0) {
-      // no log restores interleaved: replay cached graphs, last chunk first
-      for (int64_t k1 = M; k1 >= 1; k1 -= GRAPH_CHUNK) {
-        const int64_t k0 = std::max<int64_t>(1, k1 - GRAPH_CHUNK + 1);
-        const GraphKey key{1, k0, k1, 0.0, 0, c->tab.slots, c->tab.H, 0};
-        hipGraphExec_t ex = nullptr;
-        const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) {
-          for (int64_t k = k1; k >= k0; --k)
-            launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid,
-                          cs);
-        });
-        if (rr) return rr;
-        SWC_HIP(hipGraphLaunch(ex, c->st));
-      }
-      return SWC_OK;
-    }
-    for (int64_t k = M; k >= 1; --k) {
-      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
-      launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid, c->st);
-      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
-      if (maxn[k]) launch_log_restore<T>(c->tab, c->lg, c->sa, static_cast<int>(k), c->B, maxn[k], c->st);
-    }
-    return SWC_OK;
-  });
-  if (r) return r;
+  if ((r = reverse_sweep(c, M, maxn))) return r;
   launch_grad_final(c->sa, c->cnt, grad, M, c->B, c->st);
   SWC_HIP(hipEventRecord(c->ev[5], c->st));
-  if (c->persistent) launch_sweep_end(c->sa, c->cnt, 0, c->B, c->sy, 0, c->st);  // barrier status only
+  if (c->persistent && M > 0) launch_sweep_end(c->sa, c->cnt, 0, c->B, c->sy, 0, c->st);  // barrier status only
   SWC_HIP(hipGetLastError());
   if ((r = read_counters(c))) return r;
   c->rev_ms = elapsed(c->ev[4], c->ev[5]);
   if (c->ktiming) {
-    const int64_t nl = c->persistent ? (M > 0 ? 1 : 0) : M;
-    c->revk_ms = sum_pairs(c, nl);
-    c->revk_n = nl;
+    c->revk_ms = sum_pairs(c, c->rev_launches);
+    c->revk_n = c->rev_launches;
   }
   for (int b = 0; b < c->B; ++b)
     if (c->hcnt[b].flags & (F_INCONSISTENT | F_TIMEOUT)) {
@@ -833,6 +966,42 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
     }
   if ((r = reset_state(c))) return r;
   return read_counters(c);
+}
+
+size_t swc_checkpoint_bytes(int prec, int batch, int64_t max_factors, int64_t interval, uint64_t max_entries) {
+  if ((prec != SWC_FP32 && prec != SWC_FP64) || batch < 1 || max_factors < 0 || interval < 1 || max_entries < 1 ||
+      max_entries > (1ull << 34))
+    return 0;
+  const size_t tsz = prec == SWC_FP32 ? 4 : 8;
+  const size_t n = max_factors > 0 ? static_cast<size_t>((max_factors - 1) / interval) : 0;
+  const size_t per = static_cast<size_t>(batch) * max_entries;
+  return align_up(n * per * 8) + align_up(n * per * tsz) + align_up(n * batch * 8) + ALIGN;
+}
+
+int swc_set_checkpoints(swc_ctx* c, int64_t interval, uint64_t max_entries, void* buffer, size_t bytes) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  if (interval <= 0) {
+    c->ck_interval = 0;
+    c->ck_n = 0;
+    c->ck_cap = 0;
+    return SWC_OK;
+  }
+  const size_t need = swc_checkpoint_bytes(c->prec, c->B, c->Mmax, interval, max_entries);
+  if (!need) return fail(SWC_EINVAL, "invalid checkpoint sizes");
+  if (!buffer || bytes < need) return fail(SWC_EINVAL, "checkpoint buffer missing or too small");
+  if (reinterpret_cast<uintptr_t>(buffer) % ALIGN) return fail(SWC_EINVAL, "checkpoint buffer not 256-byte aligned");
+  const size_t tsz = c->prec == SWC_FP32 ? 4 : 8;
+  const size_t n = c->Mmax > 0 ? static_cast<size_t>((c->Mmax - 1) / interval) : 0;
+  const size_t per = static_cast<size_t>(c->B) * max_entries;
+  char* p = static_cast<char*>(buffer);
+  c->ck_interval = interval;
+  c->ck_cap = max_entries;
+  c->ck_n = static_cast<int64_t>(n);
+  c->ck_key = reinterpret_cast<uint64_t*>(p);
+  c->ck_amp = p + align_up(n * per * 8);
+  c->ck_count = reinterpret_cast<unsigned long long*>(p + align_up(n * per * 8) + align_up(n * per * tsz));
+  c->ck_nmax.assign(n, 0);
+  return SWC_OK;
 }
 
 int swc_get_state(swc_ctx* c, int b, uint64_t* dets, double* amps, int64_t cap, int64_t* n_out) {
@@ -886,6 +1055,8 @@ int swc_get_stats(swc_ctx* c, swc_stats* out) {
   s.log_records = c->log_records;
   s.table_slots = static_cast<int64_t>(c->tab.H);
   s.rehashes = c->rehashes;
+  s.compactions = c->compactions;
+  s.checkpoints = c->ck_taken;
   s.fwd_ms = c->fwd_ms;
   s.energy_ms = c->energy_ms;
   s.rev_ms = c->rev_ms;

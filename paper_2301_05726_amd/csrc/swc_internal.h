@@ -151,6 +151,16 @@ struct StepArr {
 };
 constexpr int WSTAT = 8;
 
+// one checkpoint: snapshot of the live (key, raw amplitude) pairs of every
+// member after a forward step; member b's entries at b*cap, count[b] entries
+// written (a count above cap means the snapshot did not fit)
+struct Snap {
+  uint64_t* key;
+  void* amp;
+  unsigned long long* count;
+  uint64_t cap;
+};
+
 // compact copies of the live entries (energy / state export), member b at b*H
 struct Compact {
   uint64_t* key;
@@ -174,7 +184,7 @@ void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t 
 // final scale S_M
 void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, int fold_only,
                       hipStream_t st);
-void launch_sync_reset(Sync* sy, hipStream_t st);
+void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st);
 // co-resident blocks per CU of the persistent forward (which=0) / reverse (1) sweep
 template <class T>
 int coop_blocks_per_cu(int which);
@@ -216,6 +226,13 @@ void launch_energy_begin(Counters* cnt, int B, hipStream_t st);
 template <class T>
 void launch_rehash(const Tab& from, const Tab& to, Counters* cnt, int B, hipStream_t st);
 void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int64_t M, int B, hipStream_t st);
+// checkpoints: write the live entries into `sn` (count must be zero), and
+// write a snapshot's amplitudes back over the entries of the same keys
+template <class T>
+void launch_snapshot(const Tab& t, const Snap& sn, int B, int grid, hipStream_t st);
+template <class T>
+void launch_snap_restore(const Tab& t, const Snap& sn, Counters* cnt, uint64_t nmax, int B, hipStream_t st);
+void launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t st);
 
 int grid_for(uint64_t work, int block, int cap);
 

@@ -757,10 +757,13 @@ __device__ __forceinline__ void grid_barrier(Sync* sy, unsigned int target) {
   __syncthreads();
 }
 
-__global__ void k_sync_reset(Sync* sy) {
+// A sweep may take several cooperative launches (one per checkpoint
+// interval): the barrier count restarts for each, the timeout flag only at the
+// start of the sweep, so a timeout in any launch is still reported at its end.
+__global__ void k_sync_reset(Sync* sy, int clear_timeout) {
   if (threadIdx.x == 0) {
     sy->count = 0u;
-    sy->timeout = 0u;
+    if (clear_timeout) sy->timeout = 0u;
   }
 }
 
@@ -832,6 +835,70 @@ __global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cn
       cp.sig[b * H + pos] = 0.0;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// checkpoints: a snapshot of the live (key, raw amplitude) pairs after a
+// forward step; the reverse sweep writes it back over the amplitudes it has
+// reconstructed for the same step, so the rounding drift of inverted steps
+// spans at most one checkpoint interval.  The support is reconstructed
+// exactly, so every snapshot key is alive at that point.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(BLK) void k_snapshot(Tab t, Snap sn) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  const View<T> v = view<T>(t, b);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  T* amp = static_cast<T*>(sn.amp);
+  for (uint64_t s0 = blockIdx.x * blockDim.x; s0 < H; s0 += stride) {
+    const uint64_t s = s0 + threadIdx.x;
+    bool live = false;
+    Slot<T> me;
+    me.key = 0;
+    me.amp = T(0);
+    if (s < H) {
+      me = v.sl[s];
+      live = me.key != EMPTY_KEY && !(me.meta & DEAD);
+    }
+    const unsigned long long mask = __ballot(live);
+    if (!mask) continue;
+    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+    unsigned long long basep = 0;
+    if (lane == leader) basep = atomicAdd(&sn.count[b], static_cast<unsigned long long>(__popcll(mask)));
+    basep = __shfl(basep, leader, 64);
+    if (live) {
+      const unsigned long long below = lane ? (mask & ((1ull << lane) - 1ull)) : 0ull;
+      const uint64_t pos = basep + __popcll(below);
+      if (pos < sn.cap) {
+        sn.key[b * sn.cap + pos] = me.key;
+        amp[b * sn.cap + pos] = me.amp;
+      }
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_snap_restore(Tab t, Snap sn, Counters* cnt) {
+  const int b = blockIdx.y;
+  const View<T> v = view<T>(t, b);
+  const uint64_t n = sn.count[b] < sn.cap ? sn.count[b] : sn.cap;
+  const T* amp = static_cast<const T*>(sn.amp);
+  for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    uint64_t ff = t.H;
+    Slot<T> cur;
+    const int64_t s = find_slot(v.sl, t.H, sn.key[b * sn.cap + i], &ff, &cur);
+    if (s < 0 || (cur.meta & DEAD)) {
+      atomicOr(&cnt[b].flags, F_INCONSISTENT);
+      continue;
+    }
+    v.sl[s].amp = amp[b * sn.cap + i];
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, uint64_t n) {
+  for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0ull;
 }
 
 __device__ __forceinline__ uint64_t between(int lo, int hi) {  // bits lo+1 .. hi-1
@@ -1137,7 +1204,9 @@ void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const 
   hipLaunchKernelGGL(k_sweep_end, dim3(B), dim3(64), 0, st, sa, cnt, M, sy, fold_only);
 }
 
-void launch_sync_reset(Sync* sy, hipStream_t st) { hipLaunchKernelGGL(k_sync_reset, dim3(1), dim3(64), 0, st, sy); }
+void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st) {
+  hipLaunchKernelGGL(k_sync_reset, dim3(1), dim3(64), 0, st, sy, clear_timeout);
+}
 
 template <class T>
 int coop_blocks_per_cu(int which) {
@@ -1211,6 +1280,22 @@ void launch_compact(const Tab& t, const Compact& cp, Counters* cnt, int B, int g
 }
 
 template <class T>
+void launch_snapshot(const Tab& t, const Snap& sn, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_snapshot<T>, dim3(grid, B), dim3(BLK), 0, st, t, sn);
+}
+
+template <class T>
+void launch_snap_restore(const Tab& t, const Snap& sn, Counters* cnt, uint64_t nmax, int B, hipStream_t st) {
+  if (nmax == 0) return;
+  hipLaunchKernelGGL(k_snap_restore<T>, dim3(grid_for(nmax, BLK, 4096), B), dim3(BLK), 0, st, t, sn, cnt);
+}
+
+void launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(n, BLK, 256)), dim3(BLK), 0, st, p, n);
+}
+
+template <class T>
 void launch_sigma(const Tab& t, const Compact& cp, const Counters* cnt, const double* h1, const double* h2, int nq,
                   int64_t nmax, int B, hipStream_t st) {
   if (nmax <= 0) return;
@@ -1270,7 +1355,9 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
                                           hipStream_t);                                                            \
   template hipError_t launch_rev_sweep<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&,       \
                                           Counters*, const LogArr&, int, int, Sync*, int, int, hipStream_t);      \
-  template void launch_rehash<T>(const Tab&, const Tab&, Counters*, int, hipStream_t);
+  template void launch_rehash<T>(const Tab&, const Tab&, Counters*, int, hipStream_t);                          \
+  template void launch_snapshot<T>(const Tab&, const Snap&, int, int, hipStream_t);                              \
+  template void launch_snap_restore<T>(const Tab&, const Snap&, Counters*, uint64_t, int, hipStream_t);
 
 SWC_INST(float)
 SWC_INST(double)

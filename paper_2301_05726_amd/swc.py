@@ -22,7 +22,8 @@ FP64, FP32 = 0, 1
 EXPORTS = [
     "swc_workspace_bytes", "swc_create", "swc_build_state", "swc_apply_ucc", "swc_energy",
     "swc_energy_and_grad", "swc_get_state", "swc_get_stats", "swc_strerror", "swc_last_error",
-    "swc_destroy", "swc_validate_excitations", "swc_factor_masks",
+    "swc_destroy", "swc_validate_excitations", "swc_factor_masks", "swc_checkpoint_bytes",
+    "swc_set_checkpoints",
 ]
 
 
@@ -41,7 +42,7 @@ class Stats(ctypes.Structure):
         ("rotate_kernel_ms", ctypes.c_double), ("rotate_launches", ctypes.c_int64),
         ("reverse_kernel_ms", ctypes.c_double), ("reverse_launches", ctypes.c_int64),
         ("sigma_kernel_ms", ctypes.c_double), ("partner_hits", ctypes.c_int64),
-        ("rehashes", ctypes.c_int64),
+        ("rehashes", ctypes.c_int64), ("compactions", ctypes.c_int64), ("checkpoints", ctypes.c_int64),
     ]
 
 
@@ -74,6 +75,9 @@ def lib():
         L.swc_destroy.restype = None
         L.swc_validate_excitations.argtypes = [I, P, I64]
         L.swc_factor_masks.argtypes = [I, P, I64, P]
+        L.swc_checkpoint_bytes.argtypes = [I, I, I64, I64, U64]
+        L.swc_checkpoint_bytes.restype = SZ
+        L.swc_set_checkpoints.argtypes = [P, I64, U64, P, SZ]
         _lib = L
     return _lib
 
@@ -122,6 +126,7 @@ class Solver:
             raise RuntimeError("no GPU visible: the swc library runs on an MI355X only")
         self.device = torch.device(device)
         self.n_qubits, self.batch, self.prec, self.max_factors = n_qubits, batch, prec, max_factors
+        self.capacity = capacity
         nbytes = workspace_bytes(n_qubits, capacity, prec, batch, max_factors, log_capacity)
         if nbytes == 0:
             raise SwcError(EINVAL, "invalid sizes")
@@ -190,6 +195,22 @@ class Solver:
                                        ctypes.c_void_p(h1d.data_ptr()), ctypes.c_void_p(h2d.data_ptr()),
                                        ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(g.data_ptr())))
         return E, g
+
+    def set_checkpoints(self, interval: int, max_entries: int = 0):
+        """Snapshot the state every `interval` forward steps of a gradient
+        sweep (0 turns checkpoints off); `max_entries` live determinants per
+        snapshot and batch member (default: the table capacity / 2)."""
+        if interval <= 0:
+            _chk(lib().swc_set_checkpoints(self._ctx, 0, 0, None, 0))
+            self.ckpt_buffer = None
+            return
+        cap = max_entries if max_entries > 0 else self.capacity // 2
+        nbytes = int(lib().swc_checkpoint_bytes(self.prec, self.batch, self.max_factors, interval, cap))
+        if nbytes == 0:
+            raise SwcError(EINVAL, "invalid checkpoint sizes")
+        self.ckpt_buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _chk(lib().swc_set_checkpoints(self._ctx, interval, cap, ctypes.c_void_p(self.ckpt_buffer.data_ptr()),
+                                       nbytes))
 
     def get_state(self, b: int = 0, cap: int | None = None):
         n = ctypes.c_int64(0)

@@ -1,0 +1,98 @@
+"""GPU parity at the benchmark workloads' own parameters (Hamiltonian
+generator, excitation order, theta spread, threshold, capacity), through the
+C ABI: the 20-qubit workload in full against stored oracle values, the
+8-qubit workload in full, and prefixes of the 32-, 48- and 64-qubit circuits
+(the first K factors) against the oracle run on the same inputs."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import TOL, compare_states, say
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def swc():
+    from paper_2301_05726_amd import swc as s
+    s.lib()
+    assert torch.cuda.is_available()
+    return s
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_q20_full_vs_stored_oracle(swc, prec):
+    """Full 20-qubit workload (875 factors, 63,504 determinants) in the launch
+    configuration the benchmark times, against values written by
+    tests/golden/make_oracle_fixtures.py (oracle only)."""
+    from paper_2301_05726_amd import synth
+    ref = json.load(open(os.path.join(HERE, "golden", "q20_oracle.json")))
+    wl = synth.WORKLOADS["q20"]
+    p = synth.make_problem(wl, batch=1)
+    assert p.exc.shape[0] == ref["n_factors"]
+    say(f"[case] q20 full prec={prec}")
+    tol = TOL[prec]
+    s = swc.Solver(wl.n_qubits, wl.n_occ, wl.n_occ, wl.capacity, prec=prec, batch=1, max_factors=p.M)
+    s.build_state()
+    E, g = s.energy_and_grad(p.theta, p.exc, wl.threshold, p.h1, p.h2)
+    E = float(E.cpu().numpy()[0])
+    g = g.cpu().numpy()[0]
+    dg = np.max(np.abs(g - np.array(ref["grad"])))
+    say(f"  dE={abs(E - ref['energy']):.3e} max|dg|={dg:.3e}")
+    assert abs(E - ref["energy"]) <= tol["E"]
+    assert dg <= tol["g"]
+    s.apply_ucc(p.theta, p.exc, wl.threshold)
+    st = s.stats()
+    assert st["n_live"] == ref["n_det"]
+    assert st["det_updates"] == ref["det_updates"]
+    d, a = s.get_state(0)
+    pos = np.searchsorted(d, np.array(ref["sample_dets"], dtype=np.uint64))
+    assert np.array_equal(d[pos], np.array(ref["sample_dets"], dtype=np.uint64))
+    err = np.max(np.abs(a[pos] - np.array(ref["sample_amps"])))
+    say(f"  sampled amplitude err={err:.3e}")
+    assert err <= tol["amp"]
+    s.close()
+
+
+PREFIX = [
+    # (workload, factors kept, batch)
+    ("q8", None, 1),
+    ("q32", 200, 1),
+    ("q48", 150, 2),
+    ("q64", 300, 1),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", PREFIX, ids=[f"{c[0]}_{c[1] or 'all'}" for c in PREFIX])
+def test_workload_prefix_vs_oracle(swc, orc, case, prec):
+    from paper_2301_05726_amd import synth
+    name, K, B = case
+    wl = synth.WORKLOADS[name]
+    p = synth.make_problem(wl, batch=B, n_factors=K)
+    nq = wl.n_qubits
+    say(f"[case] {name} K={p.M} B={B} prec={prec} thr={wl.threshold} cap=2^{int(np.log2(wl.capacity))}")
+    tol = TOL[prec]
+    orc.set_nearcut_window(1e-5)
+    s = swc.Solver(nq, wl.n_occ, wl.n_occ, wl.capacity, prec=prec, batch=B, max_factors=p.M)
+    s.build_state()
+    E, g = s.energy_and_grad(p.theta, p.exc, wl.threshold, p.h1, p.h2)
+    E = E.cpu().numpy()
+    g = g.cpu().numpy()
+    s.apply_ucc(p.theta, p.exc, wl.threshold)
+    for b in range(B):
+        d_ref, a_ref, nc, _ = orc.apply_ucc(nq, [p.hf], [1.0], p.exc, p.theta[b], wl.threshold)
+        E_ref, g_ref, _ = orc.energy_and_grad(nq, [p.hf], [1.0], p.exc, p.theta[b], wl.threshold, p.h1, p.h2)
+        assert nc == 0, "instance must have no amplitude near the cut"
+        d, a = s.get_state(b)
+        err = compare_states(d, a, d_ref, a_ref, tol["amp"])
+        dg = np.max(np.abs(g[b] - g_ref))
+        say(f"  b={b} N={len(d)} amp_err={err:.3e} dE={abs(E[b] - E_ref):.3e} max|dg|={dg:.3e}")
+        assert abs(E[b] - E_ref) <= tol["E"]
+        assert dg <= tol["g"]
+    s.close()

@@ -268,3 +268,37 @@ def test_table_growth_batch(swc, orc, monkeypatch):
         assert nc == 0
         assert abs(grown[4][b] - E_ref) <= TOL[1]["E"]
         assert np.max(np.abs(grown[5][b] - g_ref)) <= TOL[1]["g"]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_tombstone_compaction_sequential_calls(swc, orc, monkeypatch, prec):
+    """Three apply calls on one state with no reset in between: U(theta), its
+    inverse (factors reversed, angles negated: nearly every determinant is
+    truncated away and left as a tombstone), then U(theta) again.  The third
+    sweep starts with a compacting rehash that drops the tombstones; the state
+    matches the oracle applied three times in a row."""
+    say(f"[case] compaction q20 prefix prec={prec}")
+    h1, h2, exc, theta, hf = small_problem(10, 5, 0.1, 197, 200)
+    thr = 3e-4
+    monkeypatch.setenv("SWC_TABLE_MIN", "64")
+    s = swc.Solver(20, 5, 5, 1 << 17, prec=prec, batch=1, max_factors=exc.shape[0])
+    s.build_state()
+    orc.set_nearcut_window(1e-5)
+    inv_exc = exc[::-1].copy()
+    inv_theta = -theta[:, ::-1].copy()
+    d_ref, a_ref = [hf], [1.0]
+    comp = []
+    for call, (e, t) in enumerate([(exc, theta), (inv_exc, inv_theta), (exc, theta)]):
+        s.apply_ucc(t, e, thr)
+        st = s.stats()
+        comp.append(st["compactions"])
+        d_ref, a_ref, nc, _ = orc.apply_ucc(20, d_ref, a_ref, e, t[0], thr)
+        assert nc == 0
+        d, a = s.get_state(0)
+        err = compare_states(d, a, d_ref, a_ref, TOL[prec]["amp"] * 2)
+        say(f"  call {call}: N={len(d)} used={st['slots_used']} pruned={st['pruned']} rehashes={st['rehashes']} "
+            f"compactions={st['compactions']} table={st['table_slots']} err={err:.3e}")
+    assert comp == [0, 0, 1]
+    E = s.energy(h1, h2).cpu().numpy()[0]
+    assert abs(E - orc.energy(10, h1, h2, d_ref, a_ref)) <= TOL[prec]["E"] * 2
+    s.close()
