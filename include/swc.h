@@ -93,14 +93,15 @@ typedef struct {
   double fwd_ms;         /* device time of the last forward sweep */
   double energy_ms;      /* device time of the last energy evaluation */
   double rev_ms;         /* device time of the last reverse (adjoint) sweep */
-  /* Per-kernel timing, filled only when the environment variable
+  /* *_kernel_ms are filled only when the environment variable
      SWC_KERNEL_TIMING=1 was set at swc_create (an event pair is then
-     recorded around every launch of these kernels): */
+     recorded around every launch of these kernels, one factor per launch;
+     the *_launches counts are then the timed launches): */
   double rotate_kernel_ms;   /* summed duration of the forward rotate kernels */
-  int64_t rotate_launches;
+  int64_t rotate_launches;   /* rotate launches of the last forward sweep (one or two factors each) */
   double reverse_kernel_ms;  /* summed duration of the reverse kernels */
-  int64_t reverse_launches;
-  double sigma_kernel_ms;    /* duration of the sigma kernel */
+  int64_t reverse_launches;  /* reverse launches of the last adjoint sweep (one or two factors each) */
+  double sigma_kernel_ms;    /* duration of the sigma kernel (always filled) */
   int64_t partner_hits;      /* pairs whose partner existed (last forward sweep) */
   int64_t rehashes;          /* table growths during the last forward sweep */
   int64_t compactions;       /* rehashes at its start that dropped tombstones of

@@ -184,8 +184,13 @@ struct swc_ctx {
   // The table starts small and grows by rehashing into the other of two
   // workspace regions (each sized for the capacity) between chunks of steps.
   int region = 0;              // region holding the current table (tab.H slots)
-  uint64_t table_min = 1024;   // smallest table after a reset (SWC_TABLE_MIN)
+  // smallest table after a reset (SWC_TABLE_MIN): 2^18 slots (4-8 MB) scan in
+  // well under a launch latency, so growing below that only adds host round trips
+  uint64_t table_min = 1ull << 18;
   int grid_override = 0;       // SWC_GRID
+  // two factors per launch at threshold 0 (SWC_FUSE=0 turns it off)
+  bool fuse = true;
+  std::vector<uint64_t> hmask;  // XOR mask (occ | vir) of every uploaded factor
   // checkpoints (swc_set_checkpoints): snapshot j holds the state after
   // forward step (j + 1) * ck_interval, in a caller-owned buffer
   int64_t ck_interval = 0;
@@ -259,7 +264,11 @@ int upload_masks(swc_ctx* c, const swc_exc* exc, int64_t M) {
       std::memcmp(c->exc_cache.data(), exc, sizeof(swc_exc) * M) == 0)
     return SWC_OK;
   std::vector<FacMask> f(static_cast<size_t>(M));
-  for (int64_t k = 0; k < M; ++k) f[k] = factor_mask(exc[k]);
+  c->hmask.resize(static_cast<size_t>(M));
+  for (int64_t k = 0; k < M; ++k) {
+    f[k] = factor_mask(exc[k]);
+    c->hmask[k] = f[k].occ | f[k].vir;
+  }
   SWC_HIP(hipMemcpyAsync(c->fac, f.data(), sizeof(FacMask) * M, hipMemcpyHostToDevice, c->st));
   SWC_HIP(hipStreamSynchronize(c->st));
   c->exc_cache.assign(exc, exc + M);
@@ -404,6 +413,50 @@ int cached_graph(swc_ctx* c, const GraphKey& key, hipGraphExec_t* out, F&& recor
   return SWC_OK;
 }
 
+// Steps k and k+1 can share a launch: threshold 0 (no renormalisation in
+// between), a table that cannot grow during the launch, and factors with
+// different XOR masks.
+bool fusable(const swc_ctx* c, int64_t k, double thr, uint64_t lim) {
+  return c->fuse && thr == 0.0 && lim == NO_LIMIT && c->hmask[k - 1] != c->hmask[k];
+}
+
+int64_t fwd_launch_count(const swc_ctx* c, int64_t k0, int64_t k1, double thr, uint64_t lim) {
+  int64_t n = 0;
+  for (int64_t k = k0; k <= k1; ++n) k += (k < k1 && fusable(c, k, thr, lim)) ? 2 : 1;
+  return n;
+}
+
+template <class T>
+void issue_fwd(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint64_t lim, hipStream_t st) {
+  for (int64_t k = k0; k <= k1;) {
+    if (k < k1 && fusable(c, k, thr, lim)) {
+      launch_fwd2<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid, st);
+      k += 2;
+    } else {
+      launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
+                    log_on, lim, c->B, c->grid, st);
+      k += 1;
+    }
+  }
+}
+
+// Reverse steps hi..lo (the fused pairs mirror nothing of the forward: any
+// two neighbouring steps with different masks can be undone together).
+template <class T>
+int64_t issue_rev(swc_ctx* c, int64_t hi, int64_t lo, bool fuse, hipStream_t st) {
+  int64_t n = 0;
+  for (int64_t k = hi; k >= lo; ++n) {
+    if (fuse && k > lo && c->hmask[k - 2] != c->hmask[k - 1]) {
+      launch_rev2<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k - 1), c->B, c->grid, st);
+      k -= 2;
+    } else {
+      launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid, st);
+      k -= 1;
+    }
+  }
+  return n;
+}
+
 // Forward steps k0..k1 on the current table: a cached graph (`graph_ok`:
 // the range starts where a chunk or a checkpoint interval starts, so the same
 // ranges recur call after call), else single launches (a range resumed after
@@ -414,21 +467,24 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
     if (c->use_graph && !c->ktiming && graph_ok) {
       const GraphKey key{0, k0, k1, thr, log_on, c->tab.slots, c->tab.H, lim};
       hipGraphExec_t ex = nullptr;
-      const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) {
-        for (int64_t k = k0; k <= k1; ++k)
-          launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                        log_on, lim, c->B, c->grid, cs);
-      });
+      const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { issue_fwd<T>(c, k0, k1, thr, log_on, lim, cs); });
       if (rr) return rr;
       SWC_HIP(hipGraphLaunch(ex, c->st));
+      c->fwd_launches += fwd_launch_count(c, k0, k1, thr, lim);
       return SWC_OK;
     }
-    for (int64_t k = k0; k <= k1; ++k) {
-      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
+    if (!c->ktiming) {
+      issue_fwd<T>(c, k0, k1, thr, log_on, lim, c->st);
+      c->fwd_launches += fwd_launch_count(c, k0, k1, thr, lim);
+      return SWC_OK;
+    }
+    for (int64_t k = k0; k <= k1; ++k) {  // every launch timed: one step per launch
+      (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
                     log_on, lim, c->B, c->grid, c->st);
-      if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
+      (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
     }
+    c->fwd_launches += k1 - k0 + 1;
     return SWC_OK;
   });
 }
@@ -540,7 +596,6 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       k = k1 + 1;
     }
   } else {
-    c->fwd_launches = M;
     int64_t k = 1;
     bool resumed = false;
     double prev_occ = static_cast<double>(max_occupancy(c));  // counters read before the sweep
@@ -594,7 +649,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
 // checkpoint interval ends; after the range that reconstructs the state of a
 // checkpoint, the checkpoint's amplitudes are written back over it.
 // maxn[k]: largest number of truncation-log records of step k over the batch.
-int reverse_sweep(swc_ctx* c, int64_t M, const std::vector<uint32_t>& maxn) {
+int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>& maxn) {
   c->rev_launches = 0;
   for (int64_t hi = M; hi >= 1;) {
     int64_t lo = chunk_begin(hi);
@@ -610,18 +665,24 @@ int reverse_sweep(swc_ctx* c, int64_t M, const std::vector<uint32_t>& maxn) {
         if (c->ktiming) (void)hipEventRecord(c->kev[2 * i + 1], c->st);
         return SWC_OK;
       }
-      if (c->use_graph && !c->ktiming && c->log_records == 0) {
-        // no log restores interleaved: a cached graph of the range
-        const GraphKey key{1, lo, hi, 0.0, 0, c->tab.slots, c->tab.H, 0};
+      if (!c->ktiming && c->log_records == 0) {
+        // no log restores interleaved: one or two steps per launch, from a
+        // cached graph of the range
+        const bool fz = c->fuse && thr == 0.0;
+        if (!c->use_graph) {
+          c->rev_launches += issue_rev<T>(c, hi, lo, fz, c->st);
+          return SWC_OK;
+        }
+        const GraphKey key{1, lo, hi, fz ? 0.0 : 1.0, 0, c->tab.slots, c->tab.H, 0};
         hipGraphExec_t ex = nullptr;
-        const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) {
-          for (int64_t k = hi; k >= lo; --k)
-            launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid,
-                          cs);
-        });
+        int64_t n = 0;
+        const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { n = issue_rev<T>(c, hi, lo, fz, cs); });
         if (rr) return rr;
         SWC_HIP(hipGraphLaunch(ex, c->st));
-        c->rev_launches += hi - lo + 1;
+        if (n == 0) {  // graph from the cache: count its launches the same way
+          for (int64_t k = hi; k >= lo; ++n) k -= (fz && k > lo && c->hmask[k - 2] != c->hmask[k - 1]) ? 2 : 1;
+        }
+        c->rev_launches += n;
         return SWC_OK;
       }
       for (int64_t k = hi; k >= lo; --k) {
@@ -791,6 +852,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   }
   if (const char* e = std::getenv("SWC_KERNEL_TIMING")) c->ktiming = std::atoi(e) != 0;
   if (const char* e = std::getenv("SWC_GRAPH")) c->use_graph = std::atoi(e) != 0;
+  if (const char* e = std::getenv("SWC_FUSE")) c->fuse = std::atoi(e) != 0;
   for (auto& e : c->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
       swc_destroy(c);
@@ -857,9 +919,9 @@ int swc_apply_ucc(swc_ctx* c, const double* theta, const swc_exc* exc, int64_t M
   if ((r = forward_sweep(c, M, threshold, 0))) return r;
   if ((r = read_counters(c))) return r;
   c->fwd_ms = elapsed(c->ev[0], c->ev[1]);
-  if (c->ktiming) {
-    c->rot_ms = sum_pairs(c, c->fwd_launches);
-    c->rot_n = c->fwd_launches;
+  if (c->ktiming) {  // event pairs: one per launch (persistent) or per step
+    c->rot_n = c->persistent ? c->fwd_launches : M;
+    c->rot_ms = sum_pairs(c, c->rot_n);
   }
   r = sweep_status(c);
   if (r) c->built = false;
@@ -914,9 +976,9 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
       }
   }
   c->fwd_ms = elapsed(c->ev[0], c->ev[1]);
-  if (c->ktiming) {
-    c->rot_ms = sum_pairs(c, c->fwd_launches);
-    c->rot_n = c->fwd_launches;
+  if (c->ktiming) {  // event pairs: one per launch (persistent) or per step
+    c->rot_n = c->persistent ? c->fwd_launches : M;
+    c->rot_ms = sum_pairs(c, c->rot_n);
   }
   if ((r = energy_impl(c, h1, h2, E, true))) {
     reset_state(c);
@@ -947,7 +1009,7 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
     SWC_HIP(hipMemcpyAsync(c->sa.rmax, maxn.data(), 4 * (M + 1), hipMemcpyHostToDevice, c->st));
   }
   SWC_HIP(hipEventRecord(c->ev[4], c->st));
-  if ((r = reverse_sweep(c, M, maxn))) return r;
+  if ((r = reverse_sweep(c, M, threshold, maxn))) return r;
   launch_grad_final(c->sa, c->cnt, grad, M, c->B, c->st);
   SWC_HIP(hipEventRecord(c->ev[5], c->st));
   if (c->persistent && M > 0) launch_sweep_end(c->sa, c->cnt, 0, c->B, c->sy, 0, c->st);  // barrier status only
@@ -955,8 +1017,8 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   if ((r = read_counters(c))) return r;
   c->rev_ms = elapsed(c->ev[4], c->ev[5]);
   if (c->ktiming) {
-    c->revk_ms = sum_pairs(c, c->rev_launches);
-    c->revk_n = c->rev_launches;
+    c->revk_n = c->persistent ? c->rev_launches : M;
+    c->revk_ms = sum_pairs(c, c->revk_n);
   }
   for (int b = 0; b < c->B; ++b)
     if (c->hcnt[b].flags & (F_INCONSISTENT | F_TIMEOUT)) {
@@ -1061,9 +1123,9 @@ int swc_get_stats(swc_ctx* c, swc_stats* out) {
   s.energy_ms = c->energy_ms;
   s.rev_ms = c->rev_ms;
   s.rotate_kernel_ms = c->rot_ms;
-  s.rotate_launches = c->rot_n;
+  s.rotate_launches = c->ktiming ? c->rot_n : c->fwd_launches;
   s.reverse_kernel_ms = c->revk_ms;
-  s.reverse_launches = c->revk_n;
+  s.reverse_launches = c->ktiming ? c->revk_n : c->rev_launches;
   s.sigma_kernel_ms = c->sig_ms;
   for (int b = 0; b < c->B; ++b) s.partner_hits += static_cast<int64_t>(counter_total(c->hcnt[b], C_HITS));
   *out = s;

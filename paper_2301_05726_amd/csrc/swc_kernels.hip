@@ -722,6 +722,322 @@ __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ 
   rev_step<T>(t, fac, trig, ld, sa, cnt, k);
 }
 
+// ---------------------------------------------------------------------------
+// two factors per launch (threshold 0)
+// ---------------------------------------------------------------------------
+// With no truncation there is no global reduction between steps k and k+1, so
+// one launch can apply both.  The determinants D, D^m1, D^m2, D^m1^m2 (m the
+// XOR masks of the two factors, m1 != m2) are closed under both pair maps.
+// Which pairs act follows from the keys alone: factor 1 pairs (0,1) and
+// (2,3), factor 2 pairs (0,2) and (1,3), each when its members are lower/
+// upper for that factor.  A lane whose determinant lies in a connected set
+// of acting pairs probes the other members of the set; the member with the
+// smallest key among those present when the launch starts applies step k,
+// then step k+1, to the whole set, with the same per-pair arithmetic, in the
+// same order, as two single-step launches (results are bit-identical).
+
+__device__ __forceinline__ int side(uint64_t x, const FacMask& f) {
+  if ((x & f.occ) == f.occ && !(x & f.vir)) return 1;   // lower
+  if ((x & f.vir) == f.vir && !(x & f.occ)) return -1;  // upper
+  return 0;
+}
+
+struct Quad {
+  uint64_t q[4];
+  bool e1a, e1b, e2a, e2b;  // acting pairs: f1 (0,1), (2,3); f2 (0,2), (1,3)
+  unsigned comp;            // members connected to member 0 (bit mask)
+};
+
+__device__ __forceinline__ Quad make_quad(uint64_t X, uint64_t m1, uint64_t m2, const FacMask& f1,
+                                          const FacMask& f2) {
+  Quad Q;
+  Q.q[0] = X;
+  Q.q[1] = X ^ m1;
+  Q.q[2] = X ^ m2;
+  Q.q[3] = X ^ m1 ^ m2;
+  Q.e1a = side(Q.q[0], f1) != 0;
+  Q.e1b = side(Q.q[2], f1) != 0;
+  Q.e2a = side(Q.q[0], f2) != 0;
+  Q.e2b = side(Q.q[1], f2) != 0;
+  unsigned c = 1u;
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    if (Q.e1a && (c & 3u)) c |= 3u;
+    if (Q.e1b && (c & 12u)) c |= 12u;
+    if (Q.e2a && (c & 5u)) c |= 5u;
+    if (Q.e2b && (c & 10u)) c |= 10u;
+  }
+  Q.comp = c;
+  return Q;
+}
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
+                                              int64_t ld, StepArr sa, Counters* cnt, int k) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  const View<T> v = view<T>(t, b);
+  const int lane = threadIdx.x & 63;
+  unsigned long long* wst =
+      sa.ws + (static_cast<int64_t>(b) * sa.nws + (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6))) * WSTAT;
+  const unsigned long long wold = lane < WSTAT ? wst[lane] : 0ull;
+  const FacMask f1 = fac[k - 1], f2 = fac[k];
+  const Trig t1 = trig[b * ld + k - 1], t2 = trig[b * ld + k];
+  const T sn1 = static_cast<T>(t1.s), cm1a = static_cast<T>(t1.cm1);
+  const T sn2 = static_cast<T>(t2.s), cm1b = static_cast<T>(t2.cm1);
+  const uint64_t m1 = f1.occ | f1.vir, m2 = f2.occ | f2.vir;
+  const uint32_t K1 = static_cast<uint32_t>(k), K2 = K1 + 1u;
+  // c[1] visits, c[2] pairs, c[3] creates, c[5] new slots, c[6] pairs whose partner existed
+  unsigned long long c1 = 0, c2 = 0, c3 = 0, c5 = 0, c6 = 0;
+  unsigned int flags = 0;
+
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
+    const Slot<T> me = v.sl[s];
+    if (me.key == EMPTY_KEY) continue;
+    const uint32_t m = me.meta;
+    if ((m & DEAD) || (m & TAG) == K1 || (m & TAG) == K2) continue;  // dead, or created by this launch
+    const Quad Q = make_quad(me.key, m1, m2, f1, f2);
+    if (Q.comp == 1u) {  // acted on by neither factor
+      c1 += 2;
+      continue;
+    }
+    int64_t slot[4];
+    uint64_t ff[4];
+    bool pres[4];
+    T a[4];
+    slot[0] = static_cast<int64_t>(s);
+    pres[0] = true;
+    a[0] = me.amp;
+    bool owner = true;
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      slot[j] = -1;
+      ff[j] = H;
+      pres[j] = false;
+      a[j] = T(0);
+      if (!(Q.comp & (1u << j))) continue;
+      Slot<T> pv;
+      pv.meta = 0u;
+      pv.amp = T(0);
+      slot[j] = find_slot(v.sl, H, Q.q[j], &ff[j], &pv);
+      if (slot[j] >= 0) {
+        const uint32_t pt = pv.meta & TAG;
+        // present when the launch started: alive and not created by it
+        pres[j] = !(pv.meta & DEAD) && pt != K1 && pt != K2;
+        a[j] = pv.amp;
+        if (pres[j] && Q.q[j] < Q.q[0]) owner = false;
+      }
+    }
+    if (!owner) continue;
+    bool exist[4];
+    uint32_t born[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      exist[j] = pres[j];
+      born[j] = 0u;
+      if (!pres[j]) a[j] = T(0);
+    }
+    // one pair rotation of factor f on members u, w (absent members count as 0)
+    auto rot = [&](int u, int w, const FacMask& f, T sn, T cm1, uint32_t Kt) {
+      if (!pres[u] && !pres[w]) return;
+      const int L = side(Q.q[u], f) == 1 ? u : w;
+      const int U = L == u ? w : u;
+      c2 += 1;
+      if (pres[L] && pres[U]) c6 += 1;
+      const T ss = (__popcll(Q.q[L] & f.sgn) & 1) ? -sn : sn;
+      const T x = a[L], y = a[U];
+      const T xn = x + fmaT<T>(x, cm1, -ss * y);
+      const T yn = y + fmaT<T>(y, cm1, ss * x);
+      a[L] = xn;
+      a[U] = yn;
+      if (!pres[L]) {
+        pres[L] = true;
+        born[L] = Kt;
+        c3 += 1;
+      }
+      if (!pres[U]) {
+        pres[U] = true;
+        born[U] = Kt;
+        c3 += 1;
+      }
+    };
+    c1 += static_cast<unsigned long long>(pres[0]) + pres[1] + pres[2] + pres[3];
+    if (Q.e1a) rot(0, 1, f1, sn1, cm1a, K1);
+    if (Q.e1b && (Q.comp & 4u)) rot(2, 3, f1, sn1, cm1a, K1);
+    c1 += static_cast<unsigned long long>(pres[0]) + pres[1] + pres[2] + pres[3];
+    if (Q.e2a) rot(0, 2, f2, sn2, cm1b, K2);
+    if (Q.e2b && (Q.comp & 2u)) rot(1, 3, f2, sn2, cm1b, K2);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!pres[j]) continue;
+      if (exist[j]) {
+        v.sl[slot[j]].amp = a[j];
+        continue;
+      }
+      int64_t d = slot[j];  // a tombstone of an earlier sweep is revived in place
+      if (d < 0) {
+        d = claim_slot(v.sl, H, Q.q[j], ff[j]);
+        if (d < 0) {
+          flags |= F_TABLE_FULL;
+          continue;
+        }
+        c5 += 1;
+      }
+      v.sl[d].amp = a[j];
+      v.born(d) = born[j];
+      v.sl[d].meta = born[j];
+    }
+  }
+  if (flags) atomicOr(&cnt[b].flags, flags);
+  unsigned int w1 = wave_u32(static_cast<unsigned int>(c1)), w2 = wave_u32(static_cast<unsigned int>(c2));
+  unsigned int w3 = wave_u32(static_cast<unsigned int>(c3)), w5 = wave_u32(static_cast<unsigned int>(c5));
+  unsigned int w6 = wave_u32(static_cast<unsigned int>(c6));
+  const int wsh = (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6)) & (SH - 1);
+  if (w5 && lane == 0) atomicAdd(&cnt[b].sh[wsh & (CSH - 1)].v[C_OCC], static_cast<unsigned long long>(w5));
+  if (lane < 7) {
+    const unsigned int mine = lane == 1 ? w1 : lane == 2 ? w2 : lane == 3 ? w3 : lane == 5 ? w5 : lane == 6 ? w6 : 0u;
+    wst[lane] = wold + mine;
+  }
+}
+
+// Reverse of steps k+1 then k (threshold 0: nothing was truncated, so the
+// members present after the forward step are the alive ones; members created
+// by a step are removed when it is undone).
+template <class T>
+__global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
+                                              int64_t ld, StepArr sa, Counters* cnt, int k) {
+  const int b = blockIdx.y;
+  const uint64_t H = t.H;
+  const View<T> v = view<T>(t, b);
+  const FacMask f1 = fac[k - 1], f2 = fac[k];
+  const Trig t1 = trig[b * ld + k - 1], t2 = trig[b * ld + k];
+  const T c1 = static_cast<T>(t1.c), sn1 = static_cast<T>(t1.s), cm1a = static_cast<T>(t1.cm1);
+  const T c2 = static_cast<T>(t2.c), sn2 = static_cast<T>(t2.s), cm1b = static_cast<T>(t2.cm1);
+  const uint64_t m1 = f1.occ | f1.vir, m2 = f2.occ | f2.vir;
+  const uint32_t K1 = static_cast<uint32_t>(k), K2 = K1 + 1u;
+  Fx g1 = fx_zero(), g2 = fx_zero();
+  unsigned int flags = 0;
+
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
+    const Slot<T> me = v.sl[s];
+    const T lam_me = v.lam_pre(s);
+    if (me.key == EMPTY_KEY || (me.meta & DEAD)) continue;
+    const Quad Q = make_quad(me.key, m1, m2, f1, f2);
+    if (Q.comp == 1u) continue;
+    int64_t slot[4];
+    bool pres[4];
+    uint32_t born[4];
+    T a[4], l[4];
+    slot[0] = static_cast<int64_t>(s);
+    pres[0] = true;
+    a[0] = me.amp;
+    l[0] = v.lam_fin(me, lam_me);
+    born[0] = me.meta & TAG;
+    bool owner = true;
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      slot[j] = -1;
+      pres[j] = false;
+      a[j] = T(0);
+      l[j] = T(0);
+      born[j] = 0u;
+      if (!(Q.comp & (1u << j))) continue;
+      uint64_t ff = H;
+      Slot<T> pv;
+      pv.meta = 0u;
+      pv.amp = T(0);
+      slot[j] = find_slot(v.sl, H, Q.q[j], &ff, &pv);
+      if (slot[j] < 0) continue;
+      const uint32_t pt = pv.meta & TAG;
+      // present when the launch started: alive, or removed by this launch
+      pres[j] = !(pv.meta & DEAD) || pt == K1 || pt == K2;
+      if (!pres[j]) continue;
+      if (Q.q[j] < Q.q[0]) owner = false;
+      a[j] = pv.amp;
+      l[j] = v.lam_of(pv, static_cast<uint64_t>(slot[j]));
+      born[j] = (pv.meta & DEAD) ? v.born(static_cast<uint64_t>(slot[j])) : pt;
+    }
+    if (!owner) continue;
+    bool exist[4];
+    uint32_t gone[4];  // step whose undo removed the member (0: kept)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      exist[j] = pres[j];
+      gone[j] = 0u;
+    }
+    auto unrot = [&](int u, int w, const FacMask& f, T c, T sn, T cm1, uint32_t Kt, Fx& g) {
+      if (!pres[u] && !pres[w]) return;
+      const int L = side(Q.q[u], f) == 1 ? u : w;
+      const int U = L == u ? w : u;
+      const T ss = (__popcll(Q.q[L] & f.sgn) & 1) ? -sn : sn;
+      const T lL = pres[L] ? l[L] : T(0), lU = pres[U] ? l[U] : T(0);
+      const T xp = pres[L] ? a[L] : T(0), yp = pres[U] ? a[U] : T(0);
+      const T wL = lL + fmaT<T>(lL, cm1, ss * lU);
+      const T wU = lU + fmaT<T>(lU, cm1, -ss * lL);
+      T x, y;
+      if (pres[L] && pres[U]) {
+        x = xp + fmaT<T>(xp, cm1, ss * yp);
+        y = yp + fmaT<T>(yp, cm1, -ss * xp);
+      } else if (pres[L]) {
+        x = xp / c;
+        y = T(0);
+      } else {
+        x = T(0);
+        y = yp / c;
+      }
+      const double sgn = (__popcll(Q.q[L] & f.sgn) & 1) ? -1.0 : 1.0;
+      g = fx_add(g, fx_from(sgn * (static_cast<double>(wU) * static_cast<double>(x) -
+                                   static_cast<double>(wL) * static_cast<double>(y))));
+      const bool hL = pres[L], hU = pres[U];
+      if (hL) {
+        if (born[L] == Kt) {
+          if (!hU) flags |= F_INCONSISTENT;
+          pres[L] = false;
+          gone[L] = Kt;
+        } else {
+          a[L] = x;
+          l[L] = wL;
+        }
+      }
+      if (hU) {
+        if (born[U] == Kt) {
+          if (!hL) flags |= F_INCONSISTENT;
+          pres[U] = false;
+          gone[U] = Kt;
+        } else {
+          a[U] = y;
+          l[U] = wU;
+        }
+      }
+    };
+    if (Q.e2a) unrot(0, 2, f2, c2, sn2, cm1b, K2, g2);
+    if (Q.e2b && (Q.comp & 2u)) unrot(1, 3, f2, c2, sn2, cm1b, K2, g2);
+    if (Q.e1a) unrot(0, 1, f1, c1, sn1, cm1a, K1, g1);
+    if (Q.e1b && (Q.comp & 4u)) unrot(2, 3, f1, c1, sn1, cm1a, K1, g1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!exist[j]) continue;
+      const uint64_t d = static_cast<uint64_t>(slot[j]);
+      if (gone[j]) {
+        v.sl[d].meta = DEAD | gone[j];
+      } else {
+        v.sl[d].amp = a[j];
+        v.lam(d) = l[j];
+        v.sl[d].meta = born[j];
+      }
+    }
+  }
+  if (flags) atomicOr(&cnt[b].flags, flags);
+  const Fx w1 = wave_fx(g1), w2 = wave_fx(g2);
+  const int wsh = (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6)) & (SH - 1);
+  if ((threadIdx.x & 63) == 0) {
+    if (fx_nonzero(w1)) fx_atomic_add(&sa.gacc[sidx(sa, b, wsh, k)], w1);
+    if (fx_nonzero(w2)) fx_atomic_add(&sa.gacc[sidx(sa, b, wsh, k + 1)], w2);
+  }
+}
+
 template <class T>
 __global__ void k_log_restore(Tab t, LogArr lg, StepArr sa, int k) {
   restore_step<T>(t, lg, sa, k);
@@ -1269,6 +1585,18 @@ void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, 
 }
 
 template <class T>
+void launch_fwd2(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
+                 int k, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_fwd2<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
+}
+
+template <class T>
+void launch_rev2(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
+                 int k, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_rev2<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
+}
+
+template <class T>
 void launch_log_restore(const Tab& t, const LogArr& lg, const StepArr& sa, int k, int B, uint32_t maxcnt,
                         hipStream_t st) {
   hipLaunchKernelGGL(k_log_restore<T>, dim3(grid_for(maxcnt, BLK, 1024), B), dim3(BLK), 0, st, t, lg, sa, k);
@@ -1356,6 +1684,10 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
   template hipError_t launch_rev_sweep<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&,       \
                                           Counters*, const LogArr&, int, int, Sync*, int, int, hipStream_t);      \
   template void launch_rehash<T>(const Tab&, const Tab&, Counters*, int, hipStream_t);                          \
+  template void launch_fwd2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \
+                               int, int, hipStream_t);                                                             \
+  template void launch_rev2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \
+                               int, int, hipStream_t);                                                             \
   template void launch_snapshot<T>(const Tab&, const Snap&, int, int, hipStream_t);                              \
   template void launch_snap_restore<T>(const Tab&, const Snap&, Counters*, uint64_t, int, hipStream_t);
 

@@ -302,3 +302,60 @@ def test_tombstone_compaction_sequential_calls(swc, orc, monkeypatch, prec):
     E = s.energy(h1, h2).cpu().numpy()[0]
     assert abs(E - orc.energy(10, h1, h2, d_ref, a_ref)) <= TOL[prec]["E"] * 2
     s.close()
+
+
+FUSE_CASES = [
+    ("q16", 8, 4, 0.1, 104, None),
+    ("q20_pre", 10, 5, 0.05, 106, 161),
+    ("q12_dup", 6, 3, 0.2, 102, None),
+]
+
+
+@pytest.mark.parametrize("mode", ["graph", "direct"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", FUSE_CASES, ids=[c[0] for c in FUSE_CASES])
+def test_two_factor_launches_bitwise(swc, orc, monkeypatch, case, prec, mode):
+    """At threshold 0 two neighbouring factors share a launch (forward and
+    adjoint); the results, state and counters are bit-identical to one
+    factor per launch.  q12_dup repeats factors so that some neighbours have
+    equal masks (never fused), q20_pre has an odd factor count."""
+    name, n_orb, n_occ, sigma, seed, nf = case
+    say(f"[case] fused {name} prec={prec} mode={mode}")
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed, nf)
+    if name.endswith("_dup"):
+        idx = np.repeat(np.arange(exc.shape[0]), 2)[: exc.shape[0] + 7]
+        exc = exc[idx].copy()
+        theta = theta[:, idx].copy() * 0.5
+    nq = 2 * n_orb
+    out = {}
+    for fuse in ("0", "1"):
+        for k in ("SWC_GRAPH", "SWC_FUSE"):
+            monkeypatch.delenv(k, raising=False)
+        monkeypatch.setenv("SWC_FUSE", fuse)
+        if mode == "direct":
+            monkeypatch.setenv("SWC_GRAPH", "0")
+        s = swc.Solver(nq, n_occ, n_occ, capacity_for(n_orb, n_occ), prec=prec, batch=1, max_factors=exc.shape[0])
+        s.build_state()
+        reps = []
+        for rep in range(2):
+            E, g = s.energy_and_grad(theta, exc, 0.0, h1, h2)
+            st_g = s.stats()
+            s.apply_ucc(theta, exc, 0.0)
+            st = s.stats()
+            d, a = s.get_state(0)
+            s.build_state()
+            reps.append((E.cpu().numpy().tobytes(), g.cpu().numpy().tobytes(), d.tobytes(), a.tobytes(),
+                         st["det_updates"], st["pair_updates"], st["inserts"], st["partner_hits"], st["n_live"]))
+        assert reps[0] == reps[1]
+        out[fuse] = (reps[0], st["rotate_launches"], st_g["reverse_launches"])
+        s.close()
+    say(f"  launches fwd {out['0'][1]} -> {out['1'][1]}, rev {out['0'][2]} -> {out['1'][2]}")
+    assert out["0"][0] == out["1"][0]
+    M = exc.shape[0]
+    assert out["0"][1] == M and out["0"][2] == M
+    assert out["1"][1] < M and out["1"][2] < M
+    E_ref, g_ref, _ = orc.energy_and_grad(nq, [hf], [1.0], exc, theta[0], 0.0, h1, h2)
+    E = np.frombuffer(out["1"][0][0], dtype=np.float64)[0]
+    g = np.frombuffer(out["1"][0][1], dtype=np.float64)
+    assert abs(E - E_ref) <= TOL[prec]["E"]
+    assert np.max(np.abs(g - g_ref)) <= TOL[prec]["g"]
