@@ -75,9 +75,9 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   l.lborn = take(BL * 4);
   l.lamp = take(BL * tsz);
   l.scale = take(BS * 8);
-  l.pw = take(BS * SH * sizeof(Fx));
+  l.pw = take(BS * SH * sizeof(Fx3));
   l.pcnt = take(BS * SH * 4);
-  l.gacc = take(BS * SH * sizeof(Fx));
+  l.gacc = take(BS * SH * sizeof(Fx3));
   l.logn = take(BS * 4);
   l.logoff = take(BS * 4);
   l.rmax = take(static_cast<size_t>(Mmax + 1) * 4);
@@ -812,8 +812,8 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   c->tab = Tab{w + l.slots[0], w + l.aux[0], c->H};
   c->lg = LogArr{reinterpret_cast<uint64_t*>(w + l.lkey), reinterpret_cast<uint32_t*>(w + l.lmeta),
                  reinterpret_cast<uint32_t*>(w + l.lborn), w + l.lamp, c->L};
-  c->sa = StepArr{reinterpret_cast<double*>(w + l.scale),   reinterpret_cast<Fx*>(w + l.pw),
-                  reinterpret_cast<uint32_t*>(w + l.pcnt),  reinterpret_cast<Fx*>(w + l.gacc),
+  c->sa = StepArr{reinterpret_cast<double*>(w + l.scale),   reinterpret_cast<Fx3*>(w + l.pw),
+                  reinterpret_cast<uint32_t*>(w + l.pcnt),  reinterpret_cast<Fx3*>(w + l.gacc),
                   reinterpret_cast<uint32_t*>(w + l.logn),  reinterpret_cast<uint32_t*>(w + l.logoff),
                   reinterpret_cast<uint32_t*>(w + l.rmax),
                   reinterpret_cast<unsigned long long*>(w + l.ws),

@@ -47,6 +47,15 @@ struct Fx {
   unsigned long long hi;
 };
 
+// Accumulator of Fx terms updated by atomics that return nothing (a wave
+// does not wait for them): the 128-bit term is split into 42-bit limbs
+// (the top one signed), each summed in its own 64-bit word; a word takes at
+// most 2^22 additions before the value is read back, so no limb overflows
+// and the sum is exact.
+struct Fx3 {
+  unsigned long long l[3];
+};
+
 // Event counters are sharded: a block adds to shard (blockIdx.x % CSH), each
 // shard in its own 128-byte line, so concurrent atomics rarely meet.
 constexpr int CSH = 32;
@@ -139,9 +148,9 @@ struct LogArr {
 // (b*SH + shard)*stride + k, so different shards live in different lines.
 struct StepArr {
   double* scale;   // scale[j] = S after step j
-  Fx* pw;          // removed raw weight at step k
+  Fx3* pw;         // removed raw weight at step k
   uint32_t* pcnt;  // removed count at step k
-  Fx* gacc;        // gradient dot product of step k
+  Fx3* gacc;       // gradient dot product of step k
   uint32_t* logn;  // log records pushed at step k
   uint32_t* logoff;
   uint32_t* rmax;  // max over the batch of logn at step k (index k only)

@@ -112,6 +112,31 @@ __device__ __forceinline__ void fx_atomic_add(Fx* dst, Fx v) {
   atomicAdd(&dst->hi, v.hi + carry);
 }
 
+__device__ __forceinline__ void fx3_atomic_add(Fx3* dst, Fx v) {
+  constexpr unsigned long long M42 = (1ull << 42) - 1ull;
+  const unsigned long long l0 = v.lo & M42;
+  const unsigned long long l1 = ((v.lo >> 42) | (v.hi << 22)) & M42;
+  const long long l2 = static_cast<long long>(v.hi) >> 20;
+  atomicAdd(&dst->l[0], l0);
+  atomicAdd(&dst->l[1], l1);
+  atomicAdd(&dst->l[2], static_cast<unsigned long long>(l2));
+}
+
+__device__ __forceinline__ Fx fx3_value(const Fx3& a) {
+  Fx r;
+  r.lo = 0ull;
+  r.hi = static_cast<unsigned long long>(static_cast<long long>(a.l[2])) << 20;
+  Fx t;
+  t.lo = a.l[1] << 42;
+  t.hi = a.l[1] >> 22;
+  r = fx_add(r, t);
+  t.lo = a.l[0];
+  t.hi = 0ull;
+  return fx_add(r, t);
+}
+
+__device__ __forceinline__ Fx3 fx3_zero() { return Fx3{{0ull, 0ull, 0ull}}; }
+
 __device__ __forceinline__ Fx wave_fx(Fx v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -175,6 +200,29 @@ __device__ __forceinline__ int64_t find_slot(const Slot<T>* __restrict__ sl, uin
   return -1;
 }
 
+// find_slot with the home slot already loaded (`v` = sl[home]), so several
+// probes can have their first loads in flight together.
+template <class T>
+__device__ __forceinline__ int64_t find_slot_from(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key,
+                                                  uint64_t home, Slot<T> v, uint64_t* first_free, Slot<T>* out) {
+  const uint64_t mask = H - 1;
+  uint64_t s = home;
+  for (uint64_t i = 0; i < H; ++i) {
+    if (v.key == key) {
+      *out = v;
+      return static_cast<int64_t>(s);
+    }
+    if (v.key == EMPTY_KEY) {
+      *first_free = s;
+      return -1;
+    }
+    s = (s + 1) & mask;
+    v = sl[s];
+  }
+  *first_free = H;
+  return -1;
+}
+
 // Claim an EMPTY slot for `key` (known to be absent), starting the linear
 // probe at `start`.  Returns the slot or -1 when the table is full.
 template <class T>
@@ -226,7 +274,7 @@ __device__ __forceinline__ double wave_scale(const StepArr& sa, int b, int k) {
     Fx w = fx_zero();
     unsigned long long c = 0;
     if (lane < SH) {
-      w = sa.pw[sidx(sa, b, lane, k - 1)];
+      w = fx3_value(sa.pw[sidx(sa, b, lane, k - 1)]);
       c = sa.pcnt[sidx(sa, b, lane, k - 1)];
     }
     w = wave_fx(w);
@@ -324,9 +372,9 @@ __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
   for (uint64_t i = gtid; i < static_cast<uint64_t>((M + 1) * SH); i += gsz) {
     const int sh = static_cast<int>(i / (M + 1));
     const int64_t k = static_cast<int64_t>(i % (M + 1));
-    sa.pw[sidx(sa, b, sh, k)] = fx_zero();
+    sa.pw[sidx(sa, b, sh, k)] = fx3_zero();
     sa.pcnt[sidx(sa, b, sh, k)] = 0u;
-    sa.gacc[sidx(sa, b, sh, k)] = fx_zero();
+    sa.gacc[sidx(sa, b, sh, k)] = fx3_zero();
   }
   for (uint64_t i = gtid; i < static_cast<uint64_t>(M + 1); i += gsz) {
     sa.logn[base + i] = 0u;
@@ -535,7 +583,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   if (c[0]) {
     const Fx w = wave_fx(r.f);
     if (lane == 0) {
-      fx_atomic_add(&sa.pw[sidx(sa, b, wsh, k)], w);
+      fx3_atomic_add(&sa.pw[sidx(sa, b, wsh, k)], w);
       atomicAdd(&sa.pcnt[sidx(sa, b, wsh, k)], c[0]);
     }
   }
@@ -682,7 +730,7 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
   // wave total of the gradient dot product -> sharded exact accumulator
   const Fx g = wave_fx(r.f);
   const int wsh = (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6)) & (SH - 1);
-  if ((threadIdx.x & 63) == 0 && fx_nonzero(g)) fx_atomic_add(&sa.gacc[sidx(sa, b, wsh, k)], g);
+  if ((threadIdx.x & 63) == 0 && fx_nonzero(g)) fx3_atomic_add(&sa.gacc[sidx(sa, b, wsh, k)], g);
 }
 
 // Tombstones overwritten by a resurrection in forward step k get their old
@@ -810,6 +858,14 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
     pres[0] = true;
     a[0] = me.amp;
     bool owner = true;
+    // home slots of the other members, loaded together
+    uint64_t home[4];
+    Slot<T> hv[4];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      home[j] = mix64(Q.q[j]) & (H - 1);
+      if (Q.comp & (1u << j)) hv[j] = v.sl[home[j]];
+    }
 #pragma unroll
     for (int j = 1; j < 4; ++j) {
       slot[j] = -1;
@@ -820,7 +876,7 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
       Slot<T> pv;
       pv.meta = 0u;
       pv.amp = T(0);
-      slot[j] = find_slot(v.sl, H, Q.q[j], &ff[j], &pv);
+      slot[j] = find_slot_from(v.sl, H, Q.q[j], home[j], hv[j], &ff[j], &pv);
       if (slot[j] >= 0) {
         const uint32_t pt = pv.meta & TAG;
         // present when the launch started: alive and not created by it
@@ -936,6 +992,18 @@ __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__
     l[0] = v.lam_fin(me, lam_me);
     born[0] = me.meta & TAG;
     bool owner = true;
+    // home slots (and adjoint values there) of the other members, loaded together
+    uint64_t home[4];
+    Slot<T> hv[4];
+    T hl[4];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      home[j] = mix64(Q.q[j]) & (H - 1);
+      if (Q.comp & (1u << j)) {
+        hv[j] = v.sl[home[j]];
+        hl[j] = v.lam_pre(home[j]);
+      }
+    }
 #pragma unroll
     for (int j = 1; j < 4; ++j) {
       slot[j] = -1;
@@ -948,7 +1016,7 @@ __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__
       Slot<T> pv;
       pv.meta = 0u;
       pv.amp = T(0);
-      slot[j] = find_slot(v.sl, H, Q.q[j], &ff, &pv);
+      slot[j] = find_slot_from(v.sl, H, Q.q[j], home[j], hv[j], &ff, &pv);
       if (slot[j] < 0) continue;
       const uint32_t pt = pv.meta & TAG;
       // present when the launch started: alive, or removed by this launch
@@ -956,7 +1024,8 @@ __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__
       if (!pres[j]) continue;
       if (Q.q[j] < Q.q[0]) owner = false;
       a[j] = pv.amp;
-      l[j] = v.lam_of(pv, static_cast<uint64_t>(slot[j]));
+      l[j] = static_cast<uint64_t>(slot[j]) == home[j] ? v.lam_fin(pv, hl[j])
+                                                       : v.lam_of(pv, static_cast<uint64_t>(slot[j]));
       born[j] = (pv.meta & DEAD) ? v.born(static_cast<uint64_t>(slot[j])) : pt;
     }
     if (!owner) continue;
@@ -1033,8 +1102,8 @@ __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__
   const Fx w1 = wave_fx(g1), w2 = wave_fx(g2);
   const int wsh = (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6)) & (SH - 1);
   if ((threadIdx.x & 63) == 0) {
-    if (fx_nonzero(w1)) fx_atomic_add(&sa.gacc[sidx(sa, b, wsh, k)], w1);
-    if (fx_nonzero(w2)) fx_atomic_add(&sa.gacc[sidx(sa, b, wsh, k + 1)], w2);
+    if (fx_nonzero(w1)) fx3_atomic_add(&sa.gacc[sidx(sa, b, wsh, k)], w1);
+    if (fx_nonzero(w2)) fx3_atomic_add(&sa.gacc[sidx(sa, b, wsh, k + 1)], w2);
   }
 }
 
@@ -1477,7 +1546,7 @@ __global__ void k_grad_final(StepArr sa, const Counters* cnt, double* grad, int6
   const double den = fx_to_d(cnt[b].den);
   for (int64_t k = blockIdx.x * blockDim.x + threadIdx.x; k < M; k += gridDim.x * blockDim.x) {
     Fx g = fx_zero();
-    for (int q = 0; q < SH; ++q) g = fx_add(g, sa.gacc[sidx(sa, b, q, k + 1)]);
+    for (int q = 0; q < SH; ++q) g = fx_add(g, fx3_value(sa.gacc[sidx(sa, b, q, k + 1)]));
     grad[b * M + k] = 2.0 * fx_to_d(g) / den;
   }
 }
