@@ -26,6 +26,7 @@
 namespace swc {
 
 constexpr int BLK = 256;
+constexpr int SCAN_U = 4;  // table slots each lane of a sweep step loads per pass
 
 // ---------------------------------------------------------------------------
 // table views
@@ -523,53 +524,89 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     r.c[3] += 1;
   };
 
+  // SCAN_U slots per lane per pass, their loads (and then the home slots of
+  // their partners) in flight together
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
-    const Slot<T> me = v.sl[s];
-    if (me.key == EMPTY_KEY) continue;
-    const uint32_t m = me.meta;
-    if ((m & DEAD) || (m & TAG) == K) continue;  // dead, or created in this step
-    r.c[1] += 1;
-    const uint64_t key = me.key;
-    const bool lower = ((key & f.occ) == f.occ) && !(key & f.vir);
-    const bool upper = ((key & f.vir) == f.vir) && !(key & f.occ);
-    if (!lower && !upper) {
-      if (prune_all && !(fabs(S * static_cast<double>(me.amp)) >= thr)) kill(s, me.amp);
-      continue;
-    }
-    const uint64_t pk = key ^ pm;
-    uint64_t free_start = H;
-    Slot<T> pv;
-    pv.meta = 0u;
-    pv.amp = T(0);
-    const int64_t ps = find_slot(v.sl, H, pk, &free_start, &pv);
-    bool p_alive = false, p_start = false;
-    if (ps >= 0) {
-      p_alive = !(pv.meta & DEAD);
-      p_start = p_alive || ((pv.meta & TAG) == K);
-    }
-    if (upper && p_start) continue;  // the lower member owns the pair
-    r.c[2] += 1;
-    if (lower && p_alive) r.c[6] += 1;
-    const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
-    const T x = lower ? me.amp : T(0);
-    const T y = lower ? (p_alive ? pv.amp : T(0)) : me.amp;
-    const T xn = x + fmaT<T>(x, cm1, -ss * y);
-    const T yn = y + fmaT<T>(y, cm1, ss * x);
-    const bool keepx = fabs(S * static_cast<double>(xn)) >= thr;
-    const bool keepy = fabs(S * static_cast<double>(yn)) >= thr;
-    if (lower) {
-      if (keepx) v.sl[s].amp = xn; else kill(s, xn);
-      if (p_alive) {
-        if (keepy) v.sl[ps].amp = yn; else kill(static_cast<uint64_t>(ps), yn);
-      } else if (keepy) {
-        create(pk, yn, ps, pv, free_start);
+  for (uint64_t s0 = blockIdx.x * blockDim.x + threadIdx.x; s0 < H; s0 += SCAN_U * stride) {
+    Slot<T> mes[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      const uint64_t s = s0 + u * stride;
+      if (s < H) {
+        mes[u] = v.sl[s];
       } else {
-        drop_new(yn);
+        mes[u].key = EMPTY_KEY;
+        mes[u].meta = DEAD;
       }
-    } else {
-      if (keepy) v.sl[s].amp = yn; else kill(s, yn);
-      if (keepx) create(pk, xn, ps, pv, free_start); else drop_new(xn);
+    }
+    uint64_t home[SCAN_U];
+    Slot<T> hv[SCAN_U];
+    bool act[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      const Slot<T>& me = mes[u];
+      act[u] = false;
+      if (me.key == EMPTY_KEY) continue;
+      const uint32_t m = me.meta;
+      if (m & DEAD) {
+        // removed by its pair's owner earlier in this step: it was live when
+        // the step began, so it counts as visited
+        if ((m & TAG) == K) r.c[1] += 1;
+        continue;
+      }
+      if ((m & TAG) == K) continue;  // created in this step
+      r.c[1] += 1;
+      const bool lower = ((me.key & f.occ) == f.occ) && !(me.key & f.vir);
+      const bool upper = ((me.key & f.vir) == f.vir) && !(me.key & f.occ);
+      if (!lower && !upper) {
+        if (prune_all && !(fabs(S * static_cast<double>(me.amp)) >= thr)) kill(s0 + u * stride, me.amp);
+        continue;
+      }
+      act[u] = true;
+      home[u] = mix64(me.key ^ pm) & (H - 1);
+      hv[u] = v.sl[home[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      if (!act[u]) continue;
+      const Slot<T>& me = mes[u];
+      const uint64_t s = s0 + u * stride;
+      const uint64_t key = me.key;
+      const bool lower = ((key & f.occ) == f.occ) && !(key & f.vir);
+      const uint64_t pk = key ^ pm;
+      uint64_t free_start = H;
+      Slot<T> pv;
+      pv.meta = 0u;
+      pv.amp = T(0);
+      const int64_t ps = find_slot_from(v.sl, H, pk, home[u], hv[u], &free_start, &pv);
+      bool p_alive = false, p_start = false;
+      if (ps >= 0) {
+        p_alive = !(pv.meta & DEAD);
+        p_start = p_alive || ((pv.meta & TAG) == K);
+      }
+      if (!lower && p_start) continue;  // the lower member owns the pair
+      r.c[2] += 1;
+      if (lower && p_alive) r.c[6] += 1;
+      const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
+      const T x = lower ? me.amp : T(0);
+      const T y = lower ? (p_alive ? pv.amp : T(0)) : me.amp;
+      const T xn = x + fmaT<T>(x, cm1, -ss * y);
+      const T yn = y + fmaT<T>(y, cm1, ss * x);
+      const bool keepx = fabs(S * static_cast<double>(xn)) >= thr;
+      const bool keepy = fabs(S * static_cast<double>(yn)) >= thr;
+      if (lower) {
+        if (keepx) v.sl[s].amp = xn; else kill(s, xn);
+        if (p_alive) {
+          if (keepy) v.sl[ps].amp = yn; else kill(static_cast<uint64_t>(ps), yn);
+        } else if (keepy) {
+          create(pk, yn, ps, pv, free_start);
+        } else {
+          drop_new(yn);
+        }
+      } else {
+        if (keepy) v.sl[s].amp = yn; else kill(s, yn);
+        if (keepx) create(pk, xn, ps, pv, free_start); else drop_new(xn);
+      }
     }
   }
 
@@ -628,101 +665,136 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
   for (int i = 0; i < 7; ++i) r.c[i] = 0;
   unsigned int flags = 0;
 
+  // SCAN_U slots per lane per pass, their loads (and then the home slots of
+  // their partners) in flight together
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
-    const Slot<T> me = v.sl[s];
-    const T lam_me = v.lam_pre(s);  // issued together with the slot load
-    if (me.key == EMPTY_KEY) continue;
-    const uint32_t m = me.meta;
-    const bool dead = (m & DEAD) != 0u;
-    if (dead && (m & TAG) != K) continue;
-    const uint64_t key = me.key;
-    const bool lower = ((key & f.occ) == f.occ) && !(key & f.vir);
-    const bool upper = ((key & f.vir) == f.vir) && !(key & f.occ);
-    if (!lower && !upper) {
-      if (dead) {  // truncated at step k without being rotated (first step of a sweep)
-        v.sl[s].meta = v.born(s);
-        v.lam(s) = T(0);
+  for (uint64_t s0 = blockIdx.x * blockDim.x + threadIdx.x; s0 < H; s0 += SCAN_U * stride) {
+    Slot<T> mes[SCAN_U];
+    T lms[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      const uint64_t s = s0 + u * stride;
+      if (s < H) {
+        mes[u] = v.sl[s];
+        lms[u] = v.lam_pre(s);  // issued together with the slot load
+      } else {
+        mes[u].key = EMPTY_KEY;
+        mes[u].meta = DEAD;
+        lms[u] = T(0);
       }
-      continue;
     }
-    const uint64_t pk = key ^ pm;
-    // the partner usually sits in its home slot: fetch its adjoint value
-    // there while the probe runs
-    const uint64_t home = mix64(pk) & (H - 1);
-    const T lam_home = v.lam_pre(home);
-    uint64_t free_start = H;
-    Slot<T> pv;
-    pv.meta = 0u;
-    pv.amp = T(0);
-    const int64_t ps = find_slot(v.sl, H, pk, &free_start, &pv);
-    bool p_pres = false;
-    if (ps >= 0) p_pres = !(pv.meta & DEAD) || ((pv.meta & TAG) == K);
-    if (upper && p_pres) continue;  // the lower member owns the pair
-    const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
+    uint64_t home[SCAN_U];
+    Slot<T> hv[SCAN_U];
+    T hl[SCAN_U];
+    bool act[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      const Slot<T>& me = mes[u];
+      act[u] = false;
+      if (me.key == EMPTY_KEY) continue;
+      const uint32_t m = me.meta;
+      const bool dead = (m & DEAD) != 0u;
+      if (dead && (m & TAG) != K) continue;
+      const bool lower = ((me.key & f.occ) == f.occ) && !(me.key & f.vir);
+      const bool upper = ((me.key & f.vir) == f.vir) && !(me.key & f.occ);
+      if (!lower && !upper) {
+        if (dead) {  // truncated at step k without being rotated (first step of a sweep)
+          const uint64_t s = s0 + u * stride;
+          v.sl[s].meta = v.born(s);
+          v.lam(s) = T(0);
+        }
+        continue;
+      }
+      act[u] = true;
+      // the partner usually sits in its home slot: fetch it, and its adjoint
+      // value there, while the other probes start
+      home[u] = mix64(me.key ^ pm) & (H - 1);
+      hv[u] = v.sl[home[u]];
+      hl[u] = v.lam_pre(home[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      if (!act[u]) continue;
+      const Slot<T>& me = mes[u];
+      const uint64_t s = s0 + u * stride;
+      const uint32_t m = me.meta;
+      const bool dead = (m & DEAD) != 0u;
+      const uint64_t key = me.key;
+      const bool lower = ((key & f.occ) == f.occ) && !(key & f.vir);
+      const uint64_t pk = key ^ pm;
+      uint64_t free_start = H;
+      Slot<T> pv;
+      pv.meta = 0u;
+      pv.amp = T(0);
+      const int64_t ps = find_slot_from(v.sl, H, pk, home[u], hv[u], &free_start, &pv);
+      bool p_pres = false;
+      if (ps >= 0) p_pres = !(pv.meta & DEAD) || ((pv.meta & TAG) == K);
+      if (!lower && p_pres) continue;  // the lower member owns the pair
+      const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
 
-    int64_t sL, sU;
-    uint32_t mL, mU;
-    bool hL, hU;
-    T xp, yp, lL, lU;
-    if (lower) {
-      sL = static_cast<int64_t>(s); mL = m; hL = true;
-      sU = ps; mU = pv.meta; hU = p_pres;
-      xp = me.amp;
-      yp = hU ? pv.amp : T(0);
-      lL = dead ? T(0) : v.lam_fin(me, lam_me);
-      lU = (hU && !(mU & DEAD))
-               ? (static_cast<uint64_t>(ps) == home ? v.lam_fin(pv, lam_home)
-                                                    : v.lam_of(pv, static_cast<uint64_t>(ps)))
-               : T(0);
-    } else {
-      sU = static_cast<int64_t>(s); mU = m; hU = true;
-      sL = ps; mL = pv.meta; hL = false;
-      xp = T(0);
-      yp = me.amp;
-      lL = T(0);
-      lU = dead ? T(0) : v.lam_fin(me, lam_me);
-    }
-    const T wL = lL + fmaT<T>(lL, cm1, ss * lU);
-    const T wU = lU + fmaT<T>(lU, cm1, -ss * lL);
-    T x, y;
-    if (hL && hU) {
-      x = xp + fmaT<T>(xp, cm1, ss * yp);
-      y = yp + fmaT<T>(yp, cm1, -ss * xp);
-    } else if (hL) {
-      x = xp / c;
-      y = T(0);
-    } else {
-      x = T(0);
-      y = yp / c;
-    }
-    const double sgn = (__popcll(key & f.sgn) & 1) ? -1.0 : 1.0;
-    const double term = sgn * (static_cast<double>(wU) * static_cast<double>(x) -
-                               static_cast<double>(wL) * static_cast<double>(y));
-    r.f = fx_add(r.f, fx_from(term));
-    r.c[2] += 1;
-    if (hL) {
-      const uint32_t bL = (mL & DEAD) ? v.born(sL) : (mL & TAG);
-      if (bL == K) {
-        if (!hU) flags |= F_INCONSISTENT;
-        v.sl[sL].meta = DEAD | K;
-        r.c[4] += 1;
+      int64_t sL, sU;
+      uint32_t mL, mU;
+      bool hL, hU;
+      T xp, yp, lL, lU;
+      if (lower) {
+        sL = static_cast<int64_t>(s); mL = m; hL = true;
+        sU = ps; mU = pv.meta; hU = p_pres;
+        xp = me.amp;
+        yp = hU ? pv.amp : T(0);
+        lL = dead ? T(0) : v.lam_fin(me, lms[u]);
+        lU = (hU && !(mU & DEAD))
+                 ? (static_cast<uint64_t>(ps) == home[u] ? v.lam_fin(pv, hl[u])
+                                                         : v.lam_of(pv, static_cast<uint64_t>(ps)))
+                 : T(0);
       } else {
-        v.sl[sL].amp = x;
-        v.lam(sL) = wL;
-        v.sl[sL].meta = bL;
+        sU = static_cast<int64_t>(s); mU = m; hU = true;
+        sL = ps; mL = pv.meta; hL = false;
+        xp = T(0);
+        yp = me.amp;
+        lL = T(0);
+        lU = dead ? T(0) : v.lam_fin(me, lms[u]);
       }
-    }
-    if (hU) {
-      const uint32_t bU = (mU & DEAD) ? v.born(sU) : (mU & TAG);
-      if (bU == K) {
-        if (!hL) flags |= F_INCONSISTENT;
-        v.sl[sU].meta = DEAD | K;
-        r.c[4] += 1;
+      const T wL = lL + fmaT<T>(lL, cm1, ss * lU);
+      const T wU = lU + fmaT<T>(lU, cm1, -ss * lL);
+      T x, y;
+      if (hL && hU) {
+        x = xp + fmaT<T>(xp, cm1, ss * yp);
+        y = yp + fmaT<T>(yp, cm1, -ss * xp);
+      } else if (hL) {
+        x = xp / c;
+        y = T(0);
       } else {
-        v.sl[sU].amp = y;
-        v.lam(sU) = wU;
-        v.sl[sU].meta = bU;
+        x = T(0);
+        y = yp / c;
+      }
+      const double sgn = (__popcll(key & f.sgn) & 1) ? -1.0 : 1.0;
+      const double term = sgn * (static_cast<double>(wU) * static_cast<double>(x) -
+                                 static_cast<double>(wL) * static_cast<double>(y));
+      r.f = fx_add(r.f, fx_from(term));
+      r.c[2] += 1;
+      if (hL) {
+        const uint32_t bL = (mL & DEAD) ? v.born(sL) : (mL & TAG);
+        if (bL == K) {
+          if (!hU) flags |= F_INCONSISTENT;
+          v.sl[sL].meta = DEAD | K;
+          r.c[4] += 1;
+        } else {
+          v.sl[sL].amp = x;
+          v.lam(sL) = wL;
+          v.sl[sL].meta = bL;
+        }
+      }
+      if (hU) {
+        const uint32_t bU = (mU & DEAD) ? v.born(sU) : (mU & TAG);
+        if (bU == K) {
+          if (!hL) flags |= F_INCONSISTENT;
+          v.sl[sU].meta = DEAD | K;
+          r.c[4] += 1;
+        } else {
+          v.sl[sU].amp = y;
+          v.lam(sU) = wU;
+          v.sl[sU].meta = bU;
+        }
       }
     }
   }
@@ -1342,24 +1414,74 @@ __device__ double h_diag(uint64_t I, const double* __restrict__ h1, const double
 }
 
 constexpr int SG = 16;               // lanes per determinant in the sigma kernel
+constexpr int SGU = 4;               // excitations each lane probes together
 constexpr int TRI = 32 * 31 / 2;     // index pairs i1 < i2 < 32
-constexpr int LROW = 132;            // bytes per lane of orbital lists (padded: no LDS bank conflicts)
+constexpr int LROW = 132;            // bytes per group of orbital lists (padded: no LDS bank conflicts)
+
+// Orbital lists of one determinant: occupied alpha, occupied beta, empty
+// alpha, empty beta (spin-orbital indices), in one LDS row.
+struct Lists {
+  const uint8_t* oa;
+  const uint8_t* ob;
+  const uint8_t* va;
+  const uint8_t* vb;
+  int nA, nB, mA, mB;  // occupied / empty counts per spin
+  int sA, sB, dAA, dBB, dAB;  // sizes of the excitation classes
+};
+
+// Excitation number e (0 <= e < total) of I: alpha singles, beta singles,
+// alpha-alpha doubles, beta-beta doubles, alpha-beta doubles, each a flat
+// range.  Returns J and sets *rank to 2 (single) or 4 (double).
+__device__ __forceinline__ uint64_t excite(uint64_t I, int e, const Lists& L, const uint16_t* tri, int* rank) {
+  if (e < L.sA) {
+    const int x = e / L.mA;
+    *rank = 2;
+    return I ^ (1ull << L.oa[x]) ^ (1ull << L.va[e - x * L.mA]);
+  }
+  e -= L.sA;
+  if (e < L.sB) {
+    const int x = e / L.mB;
+    *rank = 2;
+    return I ^ (1ull << L.ob[x]) ^ (1ull << L.vb[e - x * L.mB]);
+  }
+  e -= L.sB;
+  *rank = 4;
+  if (e < L.dAA + L.dBB) {
+    const bool beta = e >= L.dAA;
+    if (beta) e -= L.dAA;
+    const uint8_t* oc = beta ? L.ob : L.oa;
+    const uint8_t* vi = beta ? L.vb : L.va;
+    const int nv = beta ? L.mB : L.mA;
+    const int npv = nv * (nv - 1) / 2;
+    const int x = e / npv;
+    const uint16_t po = tri[x], pv = tri[e - x * npv];
+    return I ^ (1ull << oc[po & 255]) ^ (1ull << oc[po >> 8]) ^ (1ull << vi[pv & 255]) ^ (1ull << vi[pv >> 8]);
+  }
+  e -= L.dAA + L.dBB;
+  const int xa = e % L.mA;
+  e /= L.mA;
+  const int xb = e % L.mB;
+  e /= L.mB;
+  const int jb = e % L.nB;
+  const int ia = e / L.nB;
+  return I ^ (1ull << L.oa[ia]) ^ (1ull << L.ob[jb]) ^ (1ull << L.va[xa]) ^ (1ull << L.vb[xb]);
+}
 
 // sigma_I = sum_J <I|H|J> c_J over the single and double excitations J of I
 // that are alive in the table (off-diagonal part; the diagonal is added in
-// k_energy_reduce).  SG lanes share one I.  Every excitation class
-// (alpha/beta singles, alpha-alpha, beta-beta, alpha-beta doubles) is a flat
-// index range; lane g takes indices g, g+SG, ... so all lanes of a wave probe
-// in lockstep.  Each lane keeps the orbital lists of I in its own LDS row
-// (occupied alpha, occupied beta, empty alpha, empty beta) and a block-shared
-// table maps a pair index to (i1 < i2).  The SG partial sums are combined by
-// a fixed shuffle tree, so sigma is bit-reproducible.
+// k_energy_reduce).  SG lanes of one wave share I and its orbital lists (one
+// LDS row per group, written identically by all its lanes before any of them
+// reads it: a wave executes its LDS instructions in order).  The excitations
+// of I form one flat index range; lane g takes g, g+SG, ..., SGU at a time,
+// loading the home slots of the SGU determinants together before resolving
+// the probes.  Each lane adds its terms in index order and the SG partial
+// sums are combined by a fixed shuffle tree: sigma is bit-reproducible.
 template <class T>
 __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters* cnt,
                                                const double* __restrict__ h1, const double* __restrict__ h2,
                                                int nq) {
   __shared__ uint16_t tri[TRI];
-  __shared__ uint8_t lists[BLK * LROW];
+  __shared__ uint8_t lists[(BLK / SG) * LROW];
   for (int e = threadIdx.x; e < TRI; e += blockDim.x) {
     int i2 = 1;
     while ((i2 + 1) * i2 / 2 <= e) ++i2;
@@ -1376,18 +1498,7 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
   const uint64_t full = nq >= 64 ? ~0ull : ((1ull << nq) - 1ull);
   const uint64_t ALPHA = 0x5555555555555555ull & full, BETA = 0xAAAAAAAAAAAAAAAAull & full;
   const int64_t gstride = static_cast<int64_t>(gridDim.x) * (blockDim.x / SG);
-  uint8_t* occA = lists + threadIdx.x * LROW;
-  uint8_t* occB = occA + 32;
-  uint8_t* virA = occA + 64;
-  uint8_t* virB = occA + 96;
-  auto probe = [&](uint64_t J, double* a) -> bool {
-    uint64_t ff;
-    Slot<T> pv;
-    const int64_t s = find_slot(v.sl, H, J, &ff, &pv);
-    if (s < 0 || (pv.meta & DEAD)) return false;
-    *a = static_cast<double>(pv.amp);
-    return true;
-  };
+  uint8_t* row = lists + (threadIdx.x / SG) * LROW;
   auto fill = [](uint8_t* dst, uint64_t m) -> int {
     int c = 0;
     for (; m; m &= m - 1ull) dst[c++] = static_cast<uint8_t>(__ffsll(static_cast<long long>(m)) - 1);
@@ -1395,49 +1506,42 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
   };
   for (int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / SG; i < N; i += gstride) {
     const uint64_t I = cp.key[b * H + i];
-    const int oA = fill(occA, I & ALPHA), oB = fill(occB, I & BETA);
-    const int vA = fill(virA, ~I & ALPHA), vB = fill(virB, ~I & BETA);
+    Lists L;
+    L.nA = fill(row, I & ALPHA);
+    L.nB = fill(row + 32, I & BETA);
+    L.mA = fill(row + 64, ~I & ALPHA);
+    L.mB = fill(row + 96, ~I & BETA);
+    L.oa = row;
+    L.ob = row + 32;
+    L.va = row + 64;
+    L.vb = row + 96;
+    L.sA = L.nA * L.mA;
+    L.sB = L.nB * L.mB;
+    L.dAA = L.nA * (L.nA - 1) / 2 * (L.mA * (L.mA - 1) / 2);
+    L.dBB = L.nB * (L.nB - 1) / 2 * (L.mB * (L.mB - 1) / 2);
+    L.dAB = L.nA * L.nB * L.mA * L.mB;
+    const int total = L.sA + L.sB + L.dAA + L.dBB + L.dAB;
     double acc = 0.0;
-    double a;
-    // singles
-    for (int e = g; e < oA * vA; e += SG) {
-      const int x = e / vA;
-      const uint64_t J = I ^ (1ull << occA[x]) ^ (1ull << virA[e - x * vA]);
-      if (probe(J, &a)) acc += h_offdiag(I, J, 2, h1, h2, n) * a;
-    }
-    for (int e = g; e < oB * vB; e += SG) {
-      const int x = e / vB;
-      const uint64_t J = I ^ (1ull << occB[x]) ^ (1ull << virB[e - x * vB]);
-      if (probe(J, &a)) acc += h_offdiag(I, J, 2, h1, h2, n) * a;
-    }
-    // same-spin doubles
-    for (int sp = 0; sp < 2; ++sp) {
-      const uint8_t* oc = sp ? occB : occA;
-      const uint8_t* vi = sp ? virB : virA;
-      const int no = sp ? oB : oA, nv = sp ? vB : vA;
-      const int npv = nv * (nv - 1) / 2;
-      const int tot = no * (no - 1) / 2 * npv;
-      for (int e = g; e < tot; e += SG) {
-        const int x = e / npv;
-        const uint16_t po = tri[x], pv = tri[e - x * npv];
-        const uint64_t J = I ^ (1ull << oc[po & 255]) ^ (1ull << oc[po >> 8]) ^ (1ull << vi[pv & 255]) ^
-                           (1ull << vi[pv >> 8]);
-        if (probe(J, &a)) acc += h_offdiag(I, J, 4, h1, h2, n) * a;
+    for (int e0 = g; e0 < total; e0 += SG * SGU) {
+      uint64_t J[SGU], home[SGU];
+      int rank[SGU];
+      Slot<T> hv[SGU];
+#pragma unroll
+      for (int u = 0; u < SGU; ++u) {
+        const int e = e0 + u * SG;
+        if (e < total) {
+          J[u] = excite(I, e, L, tri, &rank[u]);
+          home[u] = mix64(J[u]) & (H - 1);
+          hv[u] = v.sl[home[u]];
+        }
       }
-    }
-    // opposite-spin doubles
-    {
-      const int tot = oA * oB * vA * vB;
-      for (int e = g; e < tot; e += SG) {
-        int rr = e;
-        const int xa = rr % vA;
-        rr /= vA;
-        const int xb = rr % vB;
-        rr /= vB;
-        const int jb = rr % oB;
-        const int ia = rr / oB;
-        const uint64_t J = I ^ (1ull << occA[ia]) ^ (1ull << occB[jb]) ^ (1ull << virA[xa]) ^ (1ull << virB[xb]);
-        if (probe(J, &a)) acc += h_offdiag(I, J, 4, h1, h2, n) * a;
+#pragma unroll
+      for (int u = 0; u < SGU; ++u) {
+        if (e0 + u * SG >= total) break;
+        uint64_t ff;
+        Slot<T> pv;
+        const int64_t sj = find_slot_from(v.sl, H, J[u], home[u], hv[u], &ff, &pv);
+        if (sj >= 0 && !(pv.meta & DEAD)) acc += h_offdiag(I, J[u], rank[u], h1, h2, n) * static_cast<double>(pv.amp);
       }
     }
 #pragma unroll

@@ -85,8 +85,11 @@ def test_workload_prefix_vs_oracle(swc, orc, case, prec):
     E = E.cpu().numpy()
     g = g.cpu().numpy()
     s.apply_ucc(p.theta, p.exc, wl.threshold)
+    du_gpu = s.stats()["det_updates"]  # summed over the batch
+    du_ref = 0
     for b in range(B):
-        d_ref, a_ref, nc, _ = orc.apply_ucc(nq, [p.hf], [1.0], p.exc, p.theta[b], wl.threshold)
+        d_ref, a_ref, nc, du_b = orc.apply_ucc(nq, [p.hf], [1.0], p.exc, p.theta[b], wl.threshold)
+        du_ref += du_b
         E_ref, g_ref, _ = orc.energy_and_grad(nq, [p.hf], [1.0], p.exc, p.theta[b], wl.threshold, p.h1, p.h2)
         assert nc == 0, "instance must have no amplitude near the cut"
         d, a = s.get_state(b)
@@ -95,4 +98,5 @@ def test_workload_prefix_vs_oracle(swc, orc, case, prec):
         say(f"  b={b} N={len(d)} amp_err={err:.3e} dE={abs(E[b] - E_ref):.3e} max|dg|={dg:.3e}")
         assert abs(E[b] - E_ref) <= tol["E"]
         assert dg <= tol["g"]
+    assert du_gpu == du_ref
     s.close()

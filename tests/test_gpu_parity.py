@@ -38,7 +38,7 @@ def test_forward_energy_grad_vs_oracle(swc, orc, case, prec):
     nq = 2 * n_orb
     tol = TOL[prec]
     orc.set_nearcut_window(1e-5)
-    d_ref, a_ref, nc, _ = orc.apply_ucc(nq, [hf], [1.0], exc, theta[0], thr)
+    d_ref, a_ref, nc, du_ref = orc.apply_ucc(nq, [hf], [1.0], exc, theta[0], thr)
     E_ref, g_ref, nc2 = orc.energy_and_grad(nq, [hf], [1.0], exc, theta[0], thr, h1, h2)
     say(f"  oracle N={len(d_ref)} nearcut={nc} E={E_ref:.12f}")
     assert nc == 0, "test instance must have no amplitude near the cut"
@@ -46,6 +46,8 @@ def test_forward_energy_grad_vs_oracle(swc, orc, case, prec):
     s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=1, max_factors=exc.shape[0])
     s.build_state()
     s.apply_ucc(theta, exc, thr)
+    # det-updates: live determinants when each step begins, summed (exact count)
+    assert s.stats()["det_updates"] == du_ref
     d, a = s.get_state(0)
     err = compare_states(d, a, d_ref, a_ref, tol["amp"])
     E = s.energy(h1, h2).cpu().numpy()[0]
