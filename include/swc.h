@@ -114,7 +114,9 @@ typedef struct {
  * to `capacity` slots per state (a power of two, >= 64; determinants plus
  * tombstones of the current sweep must stay below 0.9 * capacity), `batch`
  * independent states, circuits of up to `max_factors` factors, and
- * `log_capacity` truncation-log records per state (0 selects capacity / 4).
+ * `log_capacity` truncation-log records per state (0 selects capacity; a
+ * record, 20 bytes in FP32, saves a tombstone of the current sweep that a
+ * later factor revives, for the adjoint sweep).
  * The table starts small after every reset to |Psi_0> and is rehashed into a
  * larger one (x2 or more) during a forward sweep when its occupancy nears a
  * growth limit, so the per-factor scan covers the current table, not the

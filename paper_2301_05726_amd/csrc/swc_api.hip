@@ -778,7 +778,7 @@ size_t swc_workspace_bytes(int n_qubits, uint64_t capacity, int prec, int batch,
   if ((prec != SWC_FP32 && prec != SWC_FP64) || batch < 1 || batch > 1024 || max_factors < 0 ||
       max_factors > (1ll << 30))
     return 0;
-  const uint64_t L = log_capacity ? log_capacity : capacity / 4;
+  const uint64_t L = log_capacity ? log_capacity : capacity;
   if (L > (1ull << 32)) return 0;
   return make_layout(capacity, prec == SWC_FP32 ? 4 : 8, batch, max_factors, L).total;
 }
@@ -802,7 +802,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   c->B = batch;
   c->H = capacity;
   c->Mmax = max_factors;
-  c->L = log_capacity ? log_capacity : capacity / 4;
+  c->L = log_capacity ? log_capacity : capacity;
   c->st = static_cast<hipStream_t>(stream);
   c->ws = static_cast<char*>(workspace);
   const int tsz = prec == SWC_FP32 ? 4 : 8;
@@ -959,8 +959,10 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   }
   for (int b = 0; b < c->B; ++b)
     if (c->hcnt[b].flags & F_LOG_FULL) {
+      const unsigned long long need = c->hcnt[b].logcnt;
       reset_state(c);
-      return fail(SWC_ECAPACITY, "truncation log full");
+      return fail(SWC_ECAPACITY, "truncation log full: " + std::to_string(need) + " records needed, capacity " +
+                                     std::to_string(c->L));
     }
   if (c->ck_taken > 0) {
     std::vector<unsigned long long> cnts(static_cast<size_t>(c->ck_taken) * c->B);

@@ -670,22 +670,19 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t s0 = blockIdx.x * blockDim.x + threadIdx.x; s0 < H; s0 += SCAN_U * stride) {
     Slot<T> mes[SCAN_U];
-    T lms[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
       const uint64_t s = s0 + u * stride;
       if (s < H) {
         mes[u] = v.sl[s];
-        lms[u] = v.lam_pre(s);  // issued together with the slot load
       } else {
         mes[u].key = EMPTY_KEY;
         mes[u].meta = DEAD;
-        lms[u] = T(0);
       }
     }
     uint64_t home[SCAN_U];
     Slot<T> hv[SCAN_U];
-    T hl[SCAN_U];
+    T hl[SCAN_U], lms[SCAN_U];
     bool act[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
@@ -706,8 +703,10 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
         continue;
       }
       act[u] = true;
-      // the partner usually sits in its home slot: fetch it, and its adjoint
-      // value there, while the other probes start
+      // the adjoint value of this member (only members of a pair need it),
+      // and the partner's home slot with the adjoint value there: the
+      // partner usually sits in its home slot
+      lms[u] = v.lam_pre(s0 + u * stride);
       home[u] = mix64(me.key ^ pm) & (H - 1);
       hv[u] = v.sl[home[u]];
       hl[u] = v.lam_pre(home[u]);
