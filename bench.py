@@ -37,19 +37,14 @@ def rotate_bytes(st: dict, tsz: int) -> float:
             + st["inserts"] * (8 + tsz))
 
 
-def sources_sha() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("swc_kernels.hip", "swc_api.hip", "swc_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2301_05726_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str, prec: str) -> dict:
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary (calibrated against a copy kernel), only while the kernel sources
     are the ones that were profiled; otherwise empty (traffic reported null)."""
-    path = os.path.join(ROOT, "profiles", f"k_fwd_k_rev_{workload}_traffic.txt")
+    from paper_2301_05726_amd.profiling import sources_sha
+    path = os.path.join(ROOT, "profiles", f"sweep_kernels_{workload}_traffic.txt")
     if prec != "fp32" or not os.path.exists(path):
         return {}
     vals, sha = {}, None

@@ -9,6 +9,13 @@
         Turn a rocprofv3 kernel_stats.csv or counter_collection.csv into a
         short text table (per-kernel calls, total and mean duration, or mean
         counter value per dispatch).
+
+    python -m paper_2301_05726_amd.profiling traffic --fetch <csv> --write <csv>
+            --cal-fetch <csv> --cal-write <csv> --cal-mib M --cal-reps R [--cmd "..."]
+        HBM bytes per dispatch of each kernel: FETCH_SIZE and WRITE_SIZE (KiB
+        per dispatch, one rocprofv3 pass each) scaled by what the same counters
+        read for the plain copy above; prints `traffic_kib <kernel> <KiB>` lines
+        and the hash of the kernel sources they were measured on.
 """
 from __future__ import annotations
 
@@ -60,9 +67,59 @@ def summarize(path: str, top: int, cmd: str | None) -> None:
         print(f"{k[:60]:60s} {c:>12s} {n:9d} {s / n:14.1f}")
 
 
+def _mean_per_kernel(path: str, counter: str) -> dict:
+    acc = defaultdict(lambda: [0.0, 0])
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name", counter) != counter:
+            continue
+        name = _short(r.get("Kernel_Name", r.get("Kernel-Name", "?")))
+        key = name.replace("swc::", "").split("<")[0]
+        acc[key][0] += float(r.get("Counter_Value", 0.0))
+        acc[key][1] += 1
+    return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
+
+
+def sources_sha() -> str:
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for f in ("swc_kernels.hip", "swc_api.hip", "swc_internal.h"):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic(a) -> None:
+    fetch, write = _mean_per_kernel(a.fetch, "FETCH_SIZE"), _mean_per_kernel(a.write, "WRITE_SIZE")
+    cf, cw = _mean_per_kernel(a.cal_fetch, "FETCH_SIZE"), _mean_per_kernel(a.cal_write, "WRITE_SIZE")
+    moved_kib = a.cal_mib * 1024.0  # per copy: read this much and write this much
+    # the copy kernel is the one dispatch of the calibration run with the most traffic
+    cfk = max(cf.values(), key=lambda x: x[0])[0]
+    cwk = max(cw.values(), key=lambda x: x[0])[0]
+    ff, fw = moved_kib / cfk, moved_kib / cwk
+    if a.cmd:
+        for c in a.cmd:
+            print(f"# command: {c}")
+    print(f"# calibration: {a.cal_mib} MiB device copy: FETCH_SIZE {cfk:.1f} KiB -> factor {ff:.3f}; "
+          f"WRITE_SIZE {cwk:.1f} KiB -> factor {fw:.3f}")
+    print(f"# kernel sources sha256[:16]: {sources_sha()}")
+    print(f"{'kernel':28s} {'dispatches':>10s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s} {'traffic_KiB':>12s}")
+    rows = []
+    for k in sorted(set(fetch) | set(write), key=lambda k: -(fetch.get(k, (0, 0))[0] + write.get(k, (0, 0))[0])):
+        fv, n = fetch.get(k, (0.0, 0))
+        wv, _ = write.get(k, (0.0, 0))
+        t = fv * ff + wv * fw
+        rows.append((k, t))
+        print(f"{k:28s} {n:10d} {fv:12.1f} {wv:12.1f} {t:12.1f}")
+    print("# per dispatch, calibrated (read by bench.py while the sources are unchanged):")
+    for k, t in rows:
+        print(f"traffic_kib {k} {t:.1f}")
+    print(f"sources_sha {sources_sha()}")
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    sub = ap.add_subparsers(dest="cmd", required=True)
+    sub = ap.add_subparsers(dest="sub", required=True)
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=512)
     c.add_argument("--reps", type=int, default=4)
@@ -70,9 +127,16 @@ def main(argv=None) -> int:
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=12)
     s.add_argument("--cmd", default=None)
+    t = sub.add_parser("traffic")
+    for f in ("--fetch", "--write", "--cal-fetch", "--cal-write"):
+        t.add_argument(f, required=True)
+    t.add_argument("--cal-mib", type=int, default=512)
+    t.add_argument("--cmd", action="append")
     a = ap.parse_args(argv)
-    if a.cmd == "copy":
+    if a.sub == "copy":
         copy_kernel(a.mib, a.reps)
+    elif a.sub == "traffic":
+        traffic(a)
     else:
         summarize(a.csv, a.top, a.cmd)
     return 0
