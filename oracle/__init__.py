@@ -47,6 +47,7 @@ def lib():
         L.orc_set_nearcut_window.argtypes = [D]
         L.orc_set_nearcut_window.restype = None
         L.orc_apply_inverse.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, P, P, I64, P]
+        L.orc_entropy_trajectory.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, D, P]
         _lib = L
     return _lib
 
@@ -105,6 +106,17 @@ def apply_ucc(nq, dets0, amps0, exc, theta, thr=0.0, cap=None):
             continue
         _chk(r)
         return do[: n.value].copy(), ao[: n.value].copy(), nc.value, du.value
+
+
+def entropy_trajectory(nq, dets0, amps0, exc, theta, thr=0.0):
+    """Entropy (Eq. 6) of the initial state and after each factor: [M+1]."""
+    d, a = _init(dets0, amps0)
+    e = np.ascontiguousarray(exc, dtype=np.int8)
+    t = np.ascontiguousarray(theta, dtype=np.float64)
+    M = e.shape[0]
+    out = np.empty(M + 1, np.float64)
+    _chk(lib().orc_entropy_trajectory(nq, _p(d), _p(a), len(d), _p(e), _p(t), M, float(thr), _p(out)))
+    return out
 
 
 def energy(n_orb, h1, h2, dets, amps, mode=1):

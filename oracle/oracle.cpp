@@ -426,6 +426,39 @@ int orc_apply_ucc(int nq, const uint64_t* dets0, const double* amps0, int64_t n0
   return write_state(psi, dets_out, amps_out, cap, n_out);
 }
 
+// Wavefunction entropy (Eq. 6): S = -sum_I p_I ln p_I with p_I = c_I^2 / sum c^2
+// (terms with c_I = 0 contribute 0), of the initial state and after every
+// factor of the truncated forward circuit: S_out[0..M].
+int orc_entropy_trajectory(int nq, const uint64_t* dets0, const double* amps0, int64_t n0, const int8_t* exc,
+                           const double* theta, int64_t M, double thr, double* S_out) {
+  int r = check_common(nq, theta, M, thr);
+  if (r) return r;
+  std::vector<Exc> ex;
+  if ((r = parse_excitations(exc, M, nq, ex))) return r;
+  State psi;
+  if ((r = load_state(nq, dets0, amps0, n0, psi))) return r;
+  auto entropy = [](const State& st) {
+    double n2 = 0.0;
+    for (const auto& kv : st) n2 += kv.second * kv.second;
+    double S = 0.0;
+    for (const auto& kv : st) {
+      const double p = kv.second * kv.second / n2;
+      if (p > 0.0) S -= p * std::log(p);
+    }
+    return S;
+  };
+  S_out[0] = entropy(psi);
+  State phi;
+  for (int64_t k = 0; k < M; ++k) {
+    apply_factor(ex[k], std::cos(theta[k]), std::sin(theta[k]), psi, phi);
+    double nu = 1.0;
+    if ((r = prune_renorm(phi, thr, &nu, nullptr)) < 0) return r;
+    psi.swap(phi);
+    S_out[k + 1] = entropy(psi);
+  }
+  return OK;
+}
+
 // Energy <psi|H|psi>/<psi|psi> of a given state; mode 0 literal, 1 Slater-Condon.
 int orc_energy(int mode, int n_orb, const double* h1, const double* h2, const uint64_t* dets,
                const double* amps, int64_t n, double* E) {

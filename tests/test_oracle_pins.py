@@ -277,3 +277,49 @@ def test_error_classification(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.apply_ucc(8, [hf], [1.0], ok, [0.1], thr=2.0)
     assert e.value.code == orc.EEMPTY
+
+
+# ---------------------------------------------------------------- entropy (Eq. 6)
+
+
+def _binary_entropy(t):
+    c2, s2 = math.cos(t) ** 2, math.sin(t) ** 2
+    return -sum(p * math.log(p) for p in (c2, s2) if p > 0.0)
+
+
+def test_entropy_single_factor_closed_form(orc):
+    """One factor on a single determinant gives cos(t)|D> + s sin(t)|D'>: the
+    entropy is the binary entropy of (cos^2 t, sin^2 t)."""
+    hf = synth.hf_det(3)
+    for row, t in [((0, 1, 6, 7), 0.3), ((2, -1, 8, -1), -1.1), ((1, 3, 7, 9), 0.05)]:
+        S = orc.entropy_trajectory(12, [hf], [1.0], np.array([row], np.int8), [t])
+        assert S[0] == 0.0
+        assert abs(S[1] - _binary_entropy(t)) < 1e-14
+
+
+def test_entropy_additive_for_disjoint_factors(orc):
+    """Factors on disjoint spin-orbital sets acting on one determinant make a
+    product distribution, whose entropy is the sum."""
+    hf = synth.hf_det(3)
+    rows = np.array([(0, 1, 6, 7), (2, 3, 8, 9), (4, -1, 10, -1)], np.int8)
+    t = [0.4, -0.7, 1.2]
+    S = orc.entropy_trajectory(12, [hf], [1.0], rows, t)
+    acc = 0.0
+    for k in range(3):
+        acc += _binary_entropy(t[k])
+        assert abs(S[k + 1] - acc) < 1e-13
+
+
+def test_entropy_trajectory_matches_dense_statevector(orc):
+    """Against probabilities |psi|^2 of the dense Jordan-Wigner statevector
+    after every factor (threshold 0), and zero at theta = 0."""
+    h1, h2, exc, theta, hf = small_problem(4, 2, 0.3, 31)
+    jw = DenseJW(8)
+    S = orc.entropy_trajectory(8, [hf], [1.0], exc, theta)
+    psi = jw.basis([hf])
+    for k in range(exc.shape[0]):
+        psi = jw.apply_factors(psi, exc[k:k + 1], theta[k:k + 1])
+        p = psi ** 2
+        p = p[p > 0]
+        assert abs(S[k + 1] + np.sum(p * np.log(p))) < 1e-12
+    assert np.all(orc.entropy_trajectory(8, [hf], [1.0], exc, np.zeros_like(theta)) == 0.0)
