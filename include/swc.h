@@ -191,6 +191,19 @@ size_t swc_checkpoint_bytes(int prec, int batch, int64_t max_factors, int64_t in
 int swc_set_checkpoints(swc_ctx* ctx, int64_t interval, uint64_t max_entries, void* buffer, size_t bytes);
 
 /*
+ * Wavefunction entropy along the circuit (Eq. 6: S = -sum_I |c_I|^2 ln |c_I|^2
+ * over the normalised state).  swc_track_entropy(ctx, 1) makes every later
+ * forward sweep (swc_apply_ucc, swc_energy_and_grad) record S of the state it
+ * starts from and after each of its M factors (after truncation); the sums are
+ * exact fixed-point reductions, so S is bit-reproducible.  While on, factors
+ * are applied one per launch.  swc_get_entropy copies those M + 1 values of
+ * batch member b into the host array S (n >= M + 1); SWC_ESTATE if the last
+ * forward sweep did not track it.
+ */
+int swc_track_entropy(swc_ctx* ctx, int on);
+int swc_get_entropy(swc_ctx* ctx, int b, double* S, int64_t n);
+
+/*
  * Copy the current state of batch member b to host arrays sorted by
  * determinant (amplitudes normalised, in double).  *n_out receives the
  * number of determinants; SWC_ECAPACITY if it exceeds `cap` (nothing copied).

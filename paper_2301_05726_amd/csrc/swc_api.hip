@@ -41,7 +41,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
   size_t slots[2], aux[2];
   size_t lkey, lmeta, lborn, lamp;
-  size_t scale, pw, pcnt, gacc, logn, logoff, rmax, ws;
+  size_t scale, pw, pcnt, gacc, logn, logoff, rmax, ws, ea, eb, ent;
   size_t ckey, camp, cslot, csig;
   size_t cnt, fac, trig, init_d, init_a, sync;
   size_t total;
@@ -82,6 +82,9 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   l.logoff = take(BS * 4);
   l.rmax = take(static_cast<size_t>(Mmax + 1) * 4);
   l.ws = take(static_cast<size_t>(B) * max_waves(H) * WSTAT * 8);
+  l.ea = take(BS * ES * sizeof(Fx3));
+  l.eb = take(BS * ES * sizeof(Fx3));
+  l.ent = take(BS * 8);
   l.ckey = take(BH * 8);
   l.camp = take(BH * 8);
   l.cslot = take(BH * 4);
@@ -153,9 +156,10 @@ struct GraphKey {
   int log_on;
   const void* slots;
   uint64_t H, lim;
+  int ent = 0;
   bool operator==(const GraphKey& o) const {
     return dir == o.dir && k0 == o.k0 && k1 == o.k1 && thr == o.thr && log_on == o.log_on && slots == o.slots &&
-           H == o.H && lim == o.lim;
+           H == o.H && lim == o.lim && ent == o.ent;
   }
 };
 constexpr int64_t GRAPH_CHUNK = 2048;
@@ -190,6 +194,12 @@ struct swc_ctx {
   int grid_override = 0;       // SWC_GRID
   // two factors per launch at threshold 0 (SWC_FUSE=0 turns it off)
   bool fuse = true;
+  // entropy of every forward step (swc_track_entropy); sa.ea/eb are set
+  // while it is on; ent_M: factors of the last tracked sweep (-1: none)
+  bool entropy = false;
+  Fx3* ent_ea = nullptr;
+  Fx3* ent_eb = nullptr;
+  int64_t ent_M = -1;
   std::vector<uint64_t> hmask;  // XOR mask (occ | vir) of every uploaded factor
   // checkpoints (swc_set_checkpoints): snapshot j holds the state after
   // forward step (j + 1) * ck_interval, in a caller-owned buffer
@@ -417,7 +427,7 @@ int cached_graph(swc_ctx* c, const GraphKey& key, hipGraphExec_t* out, F&& recor
 // between), a table that cannot grow during the launch, and factors with
 // different XOR masks.
 bool fusable(const swc_ctx* c, int64_t k, double thr, uint64_t lim) {
-  return c->fuse && thr == 0.0 && lim == NO_LIMIT && c->hmask[k - 1] != c->hmask[k];
+  return c->fuse && !c->entropy && thr == 0.0 && lim == NO_LIMIT && c->hmask[k - 1] != c->hmask[k];
 }
 
 int64_t fwd_launch_count(const swc_ctx* c, int64_t k0, int64_t k1, double thr, uint64_t lim) {
@@ -465,7 +475,7 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
   return dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
     if (c->use_graph && !c->ktiming && graph_ok) {
-      const GraphKey key{0, k0, k1, thr, log_on, c->tab.slots, c->tab.H, lim};
+      const GraphKey key{0, k0, k1, thr, log_on, c->tab.slots, c->tab.H, lim, c->entropy ? 1 : 0};
       hipGraphExec_t ex = nullptr;
       const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { issue_fwd<T>(c, k0, k1, thr, log_on, lim, cs); });
       if (rr) return rr;
@@ -546,6 +556,9 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   }
   c->rehashes = 0;
   c->compactions = 0;
+  c->sa.ea = c->entropy ? c->ent_ea : nullptr;
+  c->sa.eb = c->entropy ? c->ent_eb : nullptr;
+  c->ent_M = -1;
   dispatch(c, [&](auto* tp) -> int {
     launch_sweep_begin<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, c->cnt, M, c->B, c->st);
     return SWC_OK;
@@ -568,6 +581,12 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       --c->rehashes;
       ++c->compactions;
     }
+  }
+  if (c->entropy) {  // entropy of the state the sweep starts from
+    dispatch(c, [&](auto* tp) -> int {
+      launch_entropy_scan<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, 0, c->B, c->grid, c->st);
+      return SWC_OK;
+    });
   }
   c->ck_taken = 0;
   if (log_on && c->ck_n > 0) launch_zero_u64(c->ck_count, static_cast<uint64_t>(c->ck_n) * c->B, c->st);
@@ -641,6 +660,10 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   }
   launch_sweep_end(c->sa, c->cnt, M, c->B, (c->persistent && M > 0) ? c->sy : nullptr, 0, c->st);
   SWC_HIP(hipEventRecord(c->ev[1], c->st));
+  if (c->entropy) {
+    launch_entropy_final(c->sa, M, c->B, c->st);
+    c->ent_M = M;
+  }
   SWC_HIP(hipGetLastError());
   return SWC_OK;
 }
@@ -818,7 +841,10 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
                   reinterpret_cast<uint32_t*>(w + l.rmax),
                   reinterpret_cast<unsigned long long*>(w + l.ws),
                   static_cast<int64_t>(max_waves(c->H)),
-                  c->Mmax + 1};
+                  c->Mmax + 1,
+                  nullptr, nullptr, reinterpret_cast<double*>(w + l.ent)};
+  c->ent_ea = reinterpret_cast<Fx3*>(w + l.ea);
+  c->ent_eb = reinterpret_cast<Fx3*>(w + l.eb);
   c->cp = Compact{reinterpret_cast<uint64_t*>(w + l.ckey), reinterpret_cast<double*>(w + l.camp),
                   reinterpret_cast<uint32_t*>(w + l.cslot), reinterpret_cast<double*>(w + l.csig)};
   c->cnt = reinterpret_cast<Counters*>(w + l.cnt);
@@ -1065,6 +1091,22 @@ int swc_set_checkpoints(swc_ctx* c, int64_t interval, uint64_t max_entries, void
   c->ck_amp = p + align_up(n * per * 8);
   c->ck_count = reinterpret_cast<unsigned long long*>(p + align_up(n * per * 8) + align_up(n * per * tsz));
   c->ck_nmax.assign(n, 0);
+  return SWC_OK;
+}
+
+int swc_track_entropy(swc_ctx* c, int on) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  c->entropy = on != 0;
+  return SWC_OK;
+}
+
+int swc_get_entropy(swc_ctx* c, int b, double* S, int64_t n) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  if (c->ent_M < 0) return fail(SWC_ESTATE, "entropy was not tracked in the last forward sweep");
+  if (b < 0 || b >= c->B || !S) return fail(SWC_EINVAL, "bad batch index or output");
+  if (n < c->ent_M + 1) return fail(SWC_EINVAL, "output holds fewer than M + 1 values");
+  SWC_HIP(hipMemcpyAsync(S, c->sa.ent + b * c->sa.stride, 8 * (c->ent_M + 1), hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipStreamSynchronize(c->st));
   return SWC_OK;
 }
 

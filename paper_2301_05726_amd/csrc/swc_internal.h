@@ -157,8 +157,15 @@ struct StepArr {
   unsigned long long* ws;  // per-wave forward statistics, WSTAT per wave, nws waves per state
   int64_t nws;
   int64_t stride;
+  // entropy tracking (null when off): sum r^2 ln r^2 and sum r^2 over the
+  // live raw amplitudes r after step k, ES shards each at (b*ES + shard)*stride + k;
+  // ent[b*stride + k] the resulting entropy
+  Fx3* ea;
+  Fx3* eb;
+  double* ent;
 };
 constexpr int WSTAT = 8;
+constexpr int ES = 16;
 
 // one checkpoint: snapshot of the live (key, raw amplitude) pairs of every
 // member after a forward step; member b's entries at b*cap, count[b] entries
@@ -250,6 +257,11 @@ void launch_snapshot(const Tab& t, const Snap& sn, int B, int grid, hipStream_t 
 template <class T>
 void launch_snap_restore(const Tab& t, const Snap& sn, Counters* cnt, uint64_t nmax, int B, hipStream_t st);
 void launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t st);
+// entropy tracking: add the live entries of the table to step k's sums;
+// turn the sums of steps 0..M into entropies
+template <class T>
+void launch_entropy_scan(const Tab& t, const StepArr& sa, int k, int B, int grid, hipStream_t st);
+void launch_entropy_final(const StepArr& sa, int64_t M, int B, hipStream_t st);
 
 int grid_for(uint64_t work, int block, int cap);
 

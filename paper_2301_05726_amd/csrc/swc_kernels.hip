@@ -264,6 +264,25 @@ __device__ __forceinline__ double fmaT<double>(double a, double b, double c) {
   return fma(a, b, c);
 }
 
+// Entropy terms of one raw amplitude r: r^2 ln r^2 (0 for r = 0) and r^2.
+__device__ __forceinline__ void ent_add(Fx& a, Fx& b, double r) {
+  const double r2 = r * r;
+  if (r2 > 0.0) a = fx_add(a, fx_from(r2 * log(r2)));
+  b = fx_add(b, fx_from(r2));
+}
+
+// Wave totals of the entropy sums into step k's shard (sa.ea non-null).
+__device__ __forceinline__ void ent_flush(const StepArr& sa, int b, int k, Fx a, Fx e) {
+  a = wave_fx(a);
+  e = wave_fx(e);
+  if ((threadIdx.x & 63) == 0 && (fx_nonzero(a) || fx_nonzero(e))) {
+    const int sh = (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6)) & (ES - 1);
+    const int64_t idx = (static_cast<int64_t>(b) * ES + sh) * sa.stride + k;
+    fx3_atomic_add(&sa.ea[idx], a);
+    fx3_atomic_add(&sa.eb[idx], e);
+  }
+}
+
 // Renormalisation scale before step k (1-based): S_{k-1}, from S_{k-2} and the
 // removed weight of step k-1.  Every wave computes it (its first SH lanes read
 // the shards) with identical arithmetic: no LDS and no block barrier.
@@ -380,6 +399,14 @@ __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
   for (uint64_t i = gtid; i < static_cast<uint64_t>(M + 1); i += gsz) {
     sa.logn[base + i] = 0u;
     sa.scale[base + i] = cnt[b].S;  // steps that remove nothing keep the scale
+  }
+  if (sa.ea) {
+    for (uint64_t i = gtid; i < static_cast<uint64_t>((M + 1) * ES); i += gsz) {
+      const int64_t idx = (static_cast<int64_t>(b) * ES + static_cast<int64_t>(i / (M + 1))) * sa.stride +
+                          static_cast<int64_t>(i % (M + 1));
+      sa.ea[idx] = fx3_zero();
+      sa.eb[idx] = fx3_zero();
+    }
   }
   for (uint64_t i = gtid; i < static_cast<uint64_t>(sa.nws * WSTAT); i += gsz) sa.ws[b * sa.nws * WSTAT + i] = 0ull;
   for (uint64_t i = gtid; i < static_cast<uint64_t>(CSH); i += gsz) {
@@ -524,6 +551,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     r.c[3] += 1;
   };
 
+  Fx ent_a = fx_zero(), ent_b = fx_zero();  // entropy sums (when tracked)
   // SCAN_U slots per lane per pass, their loads (and then the home slots of
   // their partners) in flight together
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
@@ -559,7 +587,11 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       const bool lower = ((me.key & f.occ) == f.occ) && !(me.key & f.vir);
       const bool upper = ((me.key & f.vir) == f.vir) && !(me.key & f.occ);
       if (!lower && !upper) {
-        if (prune_all && !(fabs(S * static_cast<double>(me.amp)) >= thr)) kill(s0 + u * stride, me.amp);
+        if (prune_all && !(fabs(S * static_cast<double>(me.amp)) >= thr)) {
+          kill(s0 + u * stride, me.amp);
+        } else if (sa.ea) {
+          ent_add(ent_a, ent_b, static_cast<double>(me.amp));
+        }
         continue;
       }
       act[u] = true;
@@ -594,6 +626,10 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       const T yn = y + fmaT<T>(y, cm1, ss * x);
       const bool keepx = fabs(S * static_cast<double>(xn)) >= thr;
       const bool keepy = fabs(S * static_cast<double>(yn)) >= thr;
+      if (sa.ea) {  // the pair's members that stay live after the step
+        if (keepx) ent_add(ent_a, ent_b, static_cast<double>(xn));
+        if (keepy) ent_add(ent_a, ent_b, static_cast<double>(yn));
+      }
       if (lower) {
         if (keepx) v.sl[s].amp = xn; else kill(s, xn);
         if (p_alive) {
@@ -611,6 +647,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   }
 
   if (flags) atomicOr(&cnt[b].flags, flags);
+  if (sa.ea) ent_flush(sa, b, k, ent_a, ent_b);
   // wave totals: statistics go to the wave's private slot (plain stores, no
   // block barrier); removed weight, when there is any, to a sharded atomic
   unsigned int c[7];
@@ -1353,6 +1390,35 @@ __global__ __launch_bounds__(BLK) void k_snap_restore(Tab t, Snap sn, Counters* 
   }
 }
 
+// entropy of the state in the table (alive entries) into step k's sums
+template <class T>
+__global__ __launch_bounds__(BLK) void k_entropy_scan(Tab t, StepArr sa, int k) {
+  const int b = blockIdx.y;
+  const View<T> v = view<T>(t, b);
+  Fx a = fx_zero(), e = fx_zero();
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
+    const Slot<T> x = v.sl[s];
+    if (x.key != EMPTY_KEY && !(x.meta & DEAD)) ent_add(a, e, static_cast<double>(x.amp));
+  }
+  ent_flush(sa, b, k, a, e);
+}
+
+// Entropy (Eq. 6) after step k from the exact sums A = sum r^2 ln r^2 and
+// B = sum r^2 of the raw amplitudes: with p = r^2 / B, -sum p ln p = ln B - A / B.
+__global__ void k_entropy_final(StepArr sa, int64_t M) {
+  const int b = blockIdx.y;
+  for (int64_t k = blockIdx.x * blockDim.x + threadIdx.x; k <= M; k += gridDim.x * blockDim.x) {
+    Fx A = fx_zero(), Bs = fx_zero();
+    for (int q = 0; q < ES; ++q) {
+      const int64_t idx = (static_cast<int64_t>(b) * ES + q) * sa.stride + k;
+      A = fx_add(A, fx3_value(sa.ea[idx]));
+      Bs = fx_add(Bs, fx3_value(sa.eb[idx]));
+    }
+    const double a = fx_to_d(A), bb = fx_to_d(Bs);
+    sa.ent[static_cast<int64_t>(b) * sa.stride + k] = bb > 0.0 ? log(bb) - a / bb : 0.0;
+  }
+}
+
 __global__ void k_zero_u64(unsigned long long* p, uint64_t n) {
   for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0ull;
 }
@@ -1790,6 +1856,16 @@ void launch_snap_restore(const Tab& t, const Snap& sn, Counters* cnt, uint64_t n
   hipLaunchKernelGGL(k_snap_restore<T>, dim3(grid_for(nmax, BLK, 4096), B), dim3(BLK), 0, st, t, sn, cnt);
 }
 
+template <class T>
+void launch_entropy_scan(const Tab& t, const StepArr& sa, int k, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_entropy_scan<T>, dim3(grid, B), dim3(BLK), 0, st, t, sa, k);
+}
+
+void launch_entropy_final(const StepArr& sa, int64_t M, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_entropy_final, dim3(grid_for(static_cast<uint64_t>(M + 1), BLK, 1024), B), dim3(BLK), 0, st,
+                     sa, M);
+}
+
 void launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t st) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(n, BLK, 256)), dim3(BLK), 0, st, p, n);
@@ -1861,6 +1937,7 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
   template void launch_rev2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \
                                int, int, hipStream_t);                                                             \
   template void launch_snapshot<T>(const Tab&, const Snap&, int, int, hipStream_t);                              \
+  template void launch_entropy_scan<T>(const Tab&, const StepArr&, int, int, int, hipStream_t);                   \
   template void launch_snap_restore<T>(const Tab&, const Snap&, Counters*, uint64_t, int, hipStream_t);
 
 SWC_INST(float)

@@ -23,7 +23,7 @@ EXPORTS = [
     "swc_workspace_bytes", "swc_create", "swc_build_state", "swc_apply_ucc", "swc_energy",
     "swc_energy_and_grad", "swc_get_state", "swc_get_stats", "swc_strerror", "swc_last_error",
     "swc_destroy", "swc_validate_excitations", "swc_factor_masks", "swc_checkpoint_bytes",
-    "swc_set_checkpoints",
+    "swc_set_checkpoints", "swc_track_entropy", "swc_get_entropy",
 ]
 
 
@@ -78,6 +78,8 @@ def lib():
         L.swc_checkpoint_bytes.argtypes = [I, I, I64, I64, U64]
         L.swc_checkpoint_bytes.restype = SZ
         L.swc_set_checkpoints.argtypes = [P, I64, U64, P, SZ]
+        L.swc_track_entropy.argtypes = [P, I]
+        L.swc_get_entropy.argtypes = [P, I, P, I64]
         _lib = L
     return _lib
 
@@ -211,6 +213,18 @@ class Solver:
         self.ckpt_buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         _chk(lib().swc_set_checkpoints(self._ctx, interval, cap, ctypes.c_void_p(self.ckpt_buffer.data_ptr()),
                                        nbytes))
+
+    def track_entropy(self, on: bool = True):
+        """Record the entropy (Eq. 6) of the state before and after every
+        factor of later forward sweeps."""
+        _chk(lib().swc_track_entropy(self._ctx, 1 if on else 0))
+
+    def entropy(self, b: int = 0, n: int | None = None) -> np.ndarray:
+        """Entropy trajectory [M + 1] of member b from the last forward sweep."""
+        n = n if n is not None else self.max_factors + 1
+        out = np.full(n, np.nan)
+        _chk(lib().swc_get_entropy(self._ctx, b, _ptr(out), n))
+        return out[: np.count_nonzero(~np.isnan(out))].copy()
 
     def get_state(self, b: int = 0, cap: int | None = None):
         n = ctypes.c_int64(0)

@@ -361,3 +361,51 @@ def test_two_factor_launches_bitwise(swc, orc, monkeypatch, case, prec, mode):
     g = np.frombuffer(out["1"][0][1], dtype=np.float64)
     assert abs(E - E_ref) <= TOL[prec]["E"]
     assert np.max(np.abs(g - g_ref)) <= TOL[prec]["g"]
+
+
+ENT_CASES = [
+    ("q16", 8, 4, 0.1, 104, None, 0.0),
+    ("q12_thr", 6, 3, 0.25, 103, None, 2e-3),
+    ("q20_pre_thr", 10, 5, 0.05, 107, 300, 1e-5),
+]
+
+
+@pytest.mark.parametrize("mode", ["graph", "persistent"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", ENT_CASES, ids=[c[0] for c in ENT_CASES])
+def test_entropy_trajectory_vs_oracle(swc, orc, monkeypatch, case, prec, mode):
+    """Entropy (Eq. 6) of the state before and after every factor, tracked by
+    the forward sweep (table growth on, batch of 2), against the oracle;
+    tracking leaves every result unchanged."""
+    name, n_orb, n_occ, sigma, seed, nf, thr = case
+    say(f"[case] entropy {name} prec={prec} mode={mode}")
+    for k in ("SWC_SWEEP", "SWC_TABLE_MIN"):
+        monkeypatch.delenv(k, raising=False)
+    monkeypatch.setenv("SWC_TABLE_MIN", "64")
+    if mode == "persistent":
+        monkeypatch.setenv("SWC_SWEEP", "persistent")
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed, nf, batch=2)
+    nq, M = 2 * n_orb, exc.shape[0]
+    s = swc.Solver(nq, n_occ, n_occ, capacity_for(n_orb, n_occ), prec=prec, batch=2, max_factors=M)
+    s.build_state()
+    E0, g0 = s.energy_and_grad(theta, exc, thr, h1, h2)
+    with pytest.raises(swc.SwcError) as e:
+        s.entropy(0)
+    assert e.value.code == swc.ESTATE
+    s.track_entropy(True)
+    E1, g1 = s.energy_and_grad(theta, exc, thr, h1, h2)
+    assert E1.cpu().numpy().tobytes() == E0.cpu().numpy().tobytes()
+    assert g1.cpu().numpy().tobytes() == g0.cpu().numpy().tobytes()
+    S_grad = [s.entropy(b) for b in range(2)]
+    s.apply_ucc(theta, exc, thr)
+    tol = 1e-11 if prec == 0 else 2e-5
+    orc.set_nearcut_window(1e-5)
+    for b in range(2):
+        S = s.entropy(b)
+        assert S.shape == (M + 1,)
+        assert S.tobytes() == S_grad[b].tobytes()
+        S_ref = orc.entropy_trajectory(nq, [hf], [1.0], exc, theta[b], thr)
+        err = np.max(np.abs(S - S_ref))
+        say(f"  b={b} S_M={S[-1]:.6f} max|dS|={err:.3e}")
+        assert err <= tol
+    s.close()
