@@ -48,6 +48,7 @@ def lib():
         L.orc_set_nearcut_window.restype = None
         L.orc_apply_inverse.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, P, P, I64, P]
         L.orc_entropy_trajectory.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, D, P]
+        L.orc_set_topk.argtypes = [I64, I64]
         _lib = L
     return _lib
 
@@ -76,6 +77,11 @@ def _init(dets0, amps0):
 def set_nearcut_window(rel: float):
     """Relative width of the near-cut window (default 1e-3)."""
     lib().orc_set_nearcut_window(float(rel))
+
+
+def set_topk(n_max: int, n_cut: int):
+    """N_MAX / N_CUT truncation after every factor for later calls (0, 0: off)."""
+    _chk(lib().orc_set_topk(int(n_max), int(n_cut)))
 
 
 def tau(exc4, D):

@@ -28,6 +28,7 @@
 // norm preservation, reversibility, central finite differences,
 // the variational bound, and literal-vs-Slater-Condon energies.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -48,6 +49,9 @@ using State = std::map<uint64_t, double>;
 // ||c| - thr| <= window * thr after some factor is reported, because a
 // different rounding order could flip its truncation decision.
 double g_nearcut_window = 1e-3;
+// N_MAX / N_CUT truncation (Methods section): when more than g_nmax
+// determinants survive a factor, keep the g_ncut largest |c|; 0 = off.
+int64_t g_nmax = 0, g_ncut = 0;
 
 // ---------------------------------------------------------------------------
 // single fermionic operators (Jordan-Wigner sign by explicit counting)
@@ -192,6 +196,25 @@ int prune_renorm(State& phi, double thr, double* nu, int64_t* nearcut) {
     }
   }
   if (phi.empty()) return EEMPTY_;
+  // N_MAX / N_CUT: order by |c| descending, then determinant ascending (the
+  // paper leaves ties open), and keep the first N_CUT.  Two neighbours at the
+  // cut closer than the near-cut window (relative) count as a near-cut event.
+  if (g_nmax > 0 && static_cast<int64_t>(phi.size()) > g_nmax) {
+    std::vector<std::pair<double, uint64_t>> order;
+    order.reserve(phi.size());
+    for (const auto& kv : phi) order.emplace_back(std::fabs(kv.second), kv.first);
+    std::sort(order.begin(), order.end(), [](const std::pair<double, uint64_t>& x, const std::pair<double, uint64_t>& y) {
+      return x.first != y.first ? x.first > y.first : x.second < y.second;
+    });
+    if (nearcut) {
+      const double a = order[g_ncut - 1].first, b = order[g_ncut].first;
+      if (a - b <= g_nearcut_window * a) ++*nearcut;
+    }
+    for (size_t i = static_cast<size_t>(g_ncut); i < order.size(); ++i) {
+      phi.erase(order[i].second);
+      ++removed;
+    }
+  }
   if (removed) {
     double n2 = 0.0;
     for (const auto& kv : phi) n2 += kv.second * kv.second;
@@ -397,6 +420,18 @@ int write_state(const State& psi, uint64_t* dets, double* amps, int64_t cap, int
 extern "C" {
 
 void orc_set_nearcut_window(double rel) { g_nearcut_window = rel; }
+
+// N_MAX / N_CUT truncation for every later call (0, 0 turns it off).
+int orc_set_topk(int64_t n_max, int64_t n_cut) {
+  if (n_max == 0 && n_cut == 0) {
+    g_nmax = g_ncut = 0;
+    return OK;
+  }
+  if (n_cut < 1 || n_cut > n_max) return EINVAL_;
+  g_nmax = n_max;
+  g_ncut = n_cut;
+  return OK;
+}
 
 // tau|D> for one excitation row (i, j, a, b): sign in {-1, 0, +1}.
 int orc_tau(const int8_t* exc4, uint64_t D, uint64_t* out) {

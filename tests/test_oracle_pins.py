@@ -323,3 +323,84 @@ def test_entropy_trajectory_matches_dense_statevector(orc):
         p = p[p > 0]
         assert abs(S[k + 1] + np.sum(p * np.log(p))) < 1e-12
     assert np.all(orc.entropy_trajectory(8, [hf], [1.0], exc, np.zeros_like(theta)) == 0.0)
+
+
+# ---------------------------------------------------------------- N_MAX / N_CUT truncation (Methods)
+
+
+@pytest.fixture
+def topk(orc):
+    yield orc
+    orc.set_topk(0, 0)
+
+
+def test_topk_keeps_the_ncut_largest(topk):
+    """One factor applied with N_MAX / N_CUT equals the same factor applied
+    without truncation followed by an independent numpy selection of the
+    N_CUT largest |c| (ties: smaller determinant first) and renormalisation."""
+    orc = topk
+    h1, h2, exc, theta, hf = small_problem(6, 3, 0.4, 71)
+    K = 40
+    d0, a0, _, _ = orc.apply_ucc(12, [hf], [1.0], exc[:K], theta[:K], 0.0)
+    for k in range(K, K + 20):
+        d1, a1, _, _ = orc.apply_ucc(12, d0, a0, exc[k:k + 1], theta[k:k + 1], 0.0)
+        n_cut = max(1, len(d1) // 2)
+        order = np.lexsort((d1, -np.abs(a1)))[:n_cut]
+        keep = np.sort(order)
+        d_ref, a_ref = d1[keep], a1[keep] / np.linalg.norm(a1[keep])
+        orc.set_topk(len(d1) - 1, n_cut)
+        d2, a2, _, _ = orc.apply_ucc(12, d0, a0, exc[k:k + 1], theta[k:k + 1], 0.0)
+        orc.set_topk(0, 0)
+        assert np.array_equal(d2, d_ref)
+        assert np.max(np.abs(a2 - a_ref)) < 1e-14
+        d0, a0 = d1, a1
+
+
+def test_topk_tie_keeps_smaller_determinant(topk):
+    """theta = pi/4 makes |c| equal on both members; N_CUT = 1 keeps the
+    determinant with the smaller bit pattern, renormalised to +-1."""
+    orc = topk
+    hf = synth.hf_det(2)
+    row = np.array([(0, 1, 4, 5)], np.int8)
+    orc.set_topk(1, 1)
+    d, a, nc, _ = orc.apply_ucc(8, [hf], [1.0], row, [math.pi / 4], 0.0)
+    assert list(d) == [min(hf, hf ^ 0b110011)]
+    assert abs(abs(a[0]) - 1.0) < 1e-15
+    assert nc == 1  # the two candidates at the cut are equal: flagged
+
+
+def test_topk_inactive_below_nmax(topk):
+    orc = topk
+    h1, h2, exc, theta, hf = small_problem(6, 3, 0.2, 72)
+    d0, a0, _, _ = orc.apply_ucc(12, [hf], [1.0], exc, theta, 1e-4)
+    orc.set_topk(len(d0) * 4, len(d0))
+    d1, a1, _, _ = orc.apply_ucc(12, [hf], [1.0], exc, theta, 1e-4)
+    assert np.array_equal(d0, d1) and np.array_equal(a0, a1)
+    with pytest.raises(orc.OracleError):
+        orc.set_topk(10, 11)
+
+
+def test_topk_gradient_vs_fd(topk):
+    """With N_MAX / N_CUT active at many factors, FD with a step far below the
+    gap at every cut equals the gradient with the decisions held fixed."""
+    orc = topk
+    h1, h2, exc, theta, hf = small_problem(5, 2, 0.3, 73)
+    orc.set_topk(60, 45)
+    orc.set_nearcut_window(1e-3)
+    E, g, nc = orc.energy_and_grad(10, [hf], [1.0], exc, theta, 0.0, h1, h2)
+    assert nc == 0
+    d0, _, _, _ = orc.apply_ucc(10, [hf], [1.0], exc, theta, 0.0)
+    assert len(d0) <= 60
+    idx = synth.fd_subset(exc.shape[0], 20, 3073)
+    h = 1e-7
+    for p in idx:
+        for sgn in (1, -1):
+            t = theta.copy()
+            t[p] += sgn * h
+            d1, _, _, _ = orc.apply_ucc(10, [hf], [1.0], exc, t, 0.0)
+            assert np.array_equal(d0, d1)
+    fd = orc.fd_grad(10, [hf], [1.0], exc, theta, 0.0, h1, h2, idx, h=h)
+    assert np.max(np.abs(fd - g[idx])) < 5e-7
+    orc.set_topk(0, 0)
+    _, g0, _ = orc.energy_and_grad(10, [hf], [1.0], exc, theta, 0.0, h1, h2)
+    assert np.max(np.abs(g0 - g)) > 1e-6
