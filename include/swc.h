@@ -201,6 +201,17 @@ int swc_set_checkpoints(swc_ctx* ctx, int64_t interval, uint64_t max_entries, vo
  * forward sweep did not track it.
  */
 int swc_track_entropy(swc_ctx* ctx, int on);
+
+/*
+ * N_MAX / N_CUT truncation (Methods section): after the threshold cut of every
+ * factor of later forward sweeps, when more than n_max determinants are live,
+ * keep the n_cut of largest |c| (ties: the smaller determinant bit pattern) and
+ * remove the rest like a threshold cut (renormalisation, exact adjoint).  The
+ * n_cut-th |c| is found by a radix selection on the device after every
+ * factor (several small launches per factor while on).  n_max = n_cut = 0
+ * turns it off; otherwise 1 <= n_cut <= n_max, else SWC_EINVAL.
+ */
+int swc_set_topk(swc_ctx* ctx, uint64_t n_max, uint64_t n_cut);
 int swc_get_entropy(swc_ctx* ctx, int b, double* S, int64_t n);
 
 /*

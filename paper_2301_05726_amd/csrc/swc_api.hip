@@ -43,7 +43,7 @@ struct Layout {
   size_t lkey, lmeta, lborn, lamp;
   size_t scale, pw, pcnt, gacc, logn, logoff, rmax, ws, ea, eb, ent;
   size_t ckey, camp, cslot, csig;
-  size_t cnt, fac, trig, init_d, init_a, sync;
+  size_t cnt, fac, trig, init_d, init_a, sync, topk;
   size_t total;
 };
 
@@ -95,6 +95,7 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   l.init_d = take(H / 2 * 8);
   l.init_a = take(H / 2 * 8);
   l.sync = take(sizeof(Sync));
+  l.topk = take(static_cast<size_t>(B) * sizeof(TopK));
   l.total = off;
   return l;
 }
@@ -157,9 +158,10 @@ struct GraphKey {
   const void* slots;
   uint64_t H, lim;
   int ent = 0;
+  uint64_t tk_max = 0, tk_cut = 0;
   bool operator==(const GraphKey& o) const {
     return dir == o.dir && k0 == o.k0 && k1 == o.k1 && thr == o.thr && log_on == o.log_on && slots == o.slots &&
-           H == o.H && lim == o.lim && ent == o.ent;
+           H == o.H && lim == o.lim && ent == o.ent && tk_max == o.tk_max && tk_cut == o.tk_cut;
   }
 };
 constexpr int64_t GRAPH_CHUNK = 2048;
@@ -200,6 +202,9 @@ struct swc_ctx {
   Fx3* ent_ea = nullptr;
   Fx3* ent_eb = nullptr;
   int64_t ent_M = -1;
+  // N_MAX / N_CUT truncation after every factor (swc_set_topk; 0 = off)
+  uint64_t tk_max = 0, tk_cut = 0;
+  TopK* tk = nullptr;
   std::vector<uint64_t> hmask;  // XOR mask (occ | vir) of every uploaded factor
   // checkpoints (swc_set_checkpoints): snapshot j holds the state after
   // forward step (j + 1) * ck_interval, in a caller-owned buffer
@@ -427,7 +432,7 @@ int cached_graph(swc_ctx* c, const GraphKey& key, hipGraphExec_t* out, F&& recor
 // between), a table that cannot grow during the launch, and factors with
 // different XOR masks.
 bool fusable(const swc_ctx* c, int64_t k, double thr, uint64_t lim) {
-  return c->fuse && !c->entropy && thr == 0.0 && lim == NO_LIMIT && c->hmask[k - 1] != c->hmask[k];
+  return c->fuse && !c->entropy && c->tk_max == 0 && thr == 0.0 && lim == NO_LIMIT && c->hmask[k - 1] != c->hmask[k];
 }
 
 int64_t fwd_launch_count(const swc_ctx* c, int64_t k0, int64_t k1, double thr, uint64_t lim) {
@@ -445,6 +450,8 @@ void issue_fwd(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint6
     } else {
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
                     log_on, lim, c->B, c->grid, st);
+      if (c->tk_max)
+        launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid, st);
       k += 1;
     }
   }
@@ -475,7 +482,7 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
   return dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
     if (c->use_graph && !c->ktiming && graph_ok) {
-      const GraphKey key{0, k0, k1, thr, log_on, c->tab.slots, c->tab.H, lim, c->entropy ? 1 : 0};
+      const GraphKey key{0, k0, k1, thr, log_on, c->tab.slots, c->tab.H, lim, c->entropy ? 1 : 0, c->tk_max, c->tk_cut};
       hipGraphExec_t ex = nullptr;
       const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { issue_fwd<T>(c, k0, k1, thr, log_on, lim, cs); });
       if (rr) return rr;
@@ -493,6 +500,9 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
                     log_on, lim, c->B, c->grid, c->st);
       (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
+      if (c->tk_max)
+        launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid,
+                       c->st);
     }
     c->fwd_launches += k1 - k0 + 1;
     return SWC_OK;
@@ -591,8 +601,9 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   c->ck_taken = 0;
   if (log_on && c->ck_n > 0) launch_zero_u64(c->ck_count, static_cast<uint64_t>(c->ck_n) * c->B, c->st);
   c->fwd_launches = 0;
-  if (c->persistent) {
-    // one cooperative launch per range between checkpoints
+  if (c->persistent && c->tk_max == 0) {
+    // one cooperative launch per range between checkpoints (the N_MAX / N_CUT
+    // selection needs launches of its own after every step: per-step path)
     for (int64_t k = 1; k <= M;) {
       int64_t k1 = M;
       if (log_on && c->ck_interval > 0) {
@@ -861,6 +872,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   set_table(c, 0, c->H);
   const int g = c->grid;
   c->sy = reinterpret_cast<Sync*>(w + l.sync);
+  c->tk = reinterpret_cast<TopK*>(w + l.topk);
   if (const char* e = std::getenv("SWC_SWEEP")) c->persistent = std::strcmp(e, "persistent") == 0;
   {
     int dev = 0, ncu = 0;
@@ -887,6 +899,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   }
   if (hipMemsetAsync(c->cnt, 0, sizeof(Counters) * batch, c->st) != hipSuccess ||
       hipMemsetAsync(c->sy, 0, sizeof(Sync), c->st) != hipSuccess ||
+      hipMemsetAsync(c->tk, 0, sizeof(TopK) * batch, c->st) != hipSuccess ||
       hipStreamSynchronize(c->st) != hipSuccess) {
     swc_destroy(c);
     return fail(SWC_EDEVICE, "initialisation failed");
@@ -1091,6 +1104,18 @@ int swc_set_checkpoints(swc_ctx* c, int64_t interval, uint64_t max_entries, void
   c->ck_amp = p + align_up(n * per * 8);
   c->ck_count = reinterpret_cast<unsigned long long*>(p + align_up(n * per * 8) + align_up(n * per * tsz));
   c->ck_nmax.assign(n, 0);
+  return SWC_OK;
+}
+
+int swc_set_topk(swc_ctx* c, uint64_t n_max, uint64_t n_cut) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  if (n_max == 0 && n_cut == 0) {
+    c->tk_max = c->tk_cut = 0;
+    return SWC_OK;
+  }
+  if (n_cut < 1 || n_cut > n_max) return fail(SWC_EINVAL, "need 1 <= n_cut <= n_max");
+  c->tk_max = n_max;
+  c->tk_cut = n_cut;
   return SWC_OK;
 }
 

@@ -167,6 +167,21 @@ struct StepArr {
 constexpr int WSTAT = 8;
 constexpr int ES = 16;
 
+// N_MAX / N_CUT truncation: radix selection state of one batch member.  The
+// rank of an entry is the 96-bit (FP32) or 128-bit (FP64) number
+// (|amp| bits, ~key): larger rank = larger |c|, then smaller determinant.
+constexpr int TK_BITS = 12;              // digit width of one selection pass
+constexpr int TK_BINS = 1 << TK_BITS;
+struct alignas(256) TopK {
+  unsigned int hist[TK_BINS];
+  unsigned long long pre_hi, pre_lo;  // selected leading digits (right-aligned 128-bit)
+  unsigned long long remaining;       // entries still to keep among those matching the prefix
+  int depth;                          // digits selected
+  int done;                           // selection finished
+  int nokill;                         // at most N_MAX live entries: nothing to remove
+  int pad;
+};
+
 // one checkpoint: snapshot of the live (key, raw amplitude) pairs of every
 // member after a forward step; member b's entries at b*cap, count[b] entries
 // written (a count above cap means the snapshot did not fit)
@@ -257,6 +272,11 @@ void launch_snapshot(const Tab& t, const Snap& sn, int B, int grid, hipStream_t 
 template <class T>
 void launch_snap_restore(const Tab& t, const Snap& sn, Counters* cnt, uint64_t nmax, int B, hipStream_t st);
 void launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t st);
+// N_MAX / N_CUT after forward step k: the selection passes and the removal
+// (kernels only, so a captured graph may hold them); tk must start zeroed
+template <class T>
+void launch_topk(const Tab& t, const StepArr& sa, Counters* cnt, TopK* tk, int k, uint64_t n_max, uint64_t n_cut,
+                 int B, int grid, hipStream_t st);
 // entropy tracking: add the live entries of the table to step k's sums;
 // turn the sums of steps 0..M into entropies
 template <class T>

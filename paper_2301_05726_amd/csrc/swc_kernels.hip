@@ -1419,6 +1419,186 @@ __global__ void k_entropy_final(StepArr sa, int64_t M) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// N_MAX / N_CUT truncation (Methods section): when more than N_MAX entries
+// are live after step k, keep the N_CUT of largest rank (|c|, then smaller
+// determinant) and remove the rest like a threshold cut (tombstone with the
+// pre-truncation amplitude, removed weight into step k's renormalisation).
+// The N_CUT-th rank is found by a radix selection, TK_BITS per pass from the
+// top: each pass histograms the digit of the entries that match the digits
+// chosen so far, and one block picks the digit holding the boundary.
+// ---------------------------------------------------------------------------
+struct R128 {
+  unsigned long long hi, lo;
+};
+
+__device__ __forceinline__ R128 shr128(R128 r, int s) {
+  if (s <= 0) return r;
+  if (s >= 128) return R128{0ull, 0ull};
+  if (s >= 64) return R128{0ull, r.hi >> (s - 64)};
+  return R128{r.hi >> s, (r.lo >> s) | (r.hi << (64 - s))};
+}
+
+__device__ __forceinline__ bool lt128(R128 a, R128 b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+
+template <class T>
+__device__ __forceinline__ R128 rank_of(uint64_t key, T amp);
+template <>
+__device__ __forceinline__ R128 rank_of<float>(uint64_t key, float amp) {
+  return R128{static_cast<unsigned long long>(__float_as_uint(fabsf(amp))), ~key};
+}
+template <>
+__device__ __forceinline__ R128 rank_of<double>(uint64_t key, double amp) {
+  return R128{static_cast<unsigned long long>(__double_as_longlong(fabs(amp))), ~key};
+}
+template <class T>
+constexpr int rank_bits() {
+  return sizeof(T) == 4 ? 96 : 128;
+}
+
+// digit of pass p: bits [top - w, top) with top = nbits - TK_BITS p
+__device__ __forceinline__ unsigned digit_of(R128 r, int nbits, int pass) {
+  const int top = nbits - TK_BITS * pass;
+  const int low = top > TK_BITS ? top - TK_BITS : 0;
+  return static_cast<unsigned>(shr128(r, low).lo) & ((1u << (top - low)) - 1u);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_topk_hist(Tab t, TopK* tk, const Counters* cnt, int k, int pass) {
+  const int b = blockIdx.y;
+  if (static_cast<uint32_t>(k) >= cnt[0].stop) return;
+  TopK& st = tk[b];
+  if (pass > 0 && st.done) return;
+  constexpr int nbits = rank_bits<T>();
+  __shared__ unsigned int h[TK_BINS];
+  for (int i = threadIdx.x; i < TK_BINS; i += blockDim.x) h[i] = 0u;
+  __syncthreads();
+  const R128 pre{st.pre_hi, st.pre_lo};
+  const int shift = nbits - TK_BITS * pass;
+  const View<T> v = view<T>(t, b);
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
+    const Slot<T> x = v.sl[s];
+    if (x.key == EMPTY_KEY || (x.meta & DEAD)) continue;
+    const R128 r = rank_of<T>(x.key, x.amp);
+    if (pass > 0) {
+      const R128 top = shr128(r, shift);
+      if (top.hi != pre.hi || top.lo != pre.lo) continue;
+    }
+    atomicAdd(&h[digit_of(r, nbits, pass)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < TK_BINS; i += blockDim.x)
+    if (h[i]) atomicAdd(&st.hist[i], h[i]);
+}
+
+// one block per member: choose the digit of pass `pass`, then clear the histogram
+template <class T>
+__global__ __launch_bounds__(BLK) void k_topk_select(TopK* tk, const Counters* cnt, int k, int pass,
+                                                     unsigned long long n_max, unsigned long long n_cut) {
+  const int b = blockIdx.y;
+  if (static_cast<uint32_t>(k) >= cnt[0].stop) return;
+  TopK& st = tk[b];
+  if (pass > 0 && st.done) return;
+  constexpr int nbits = rank_bits<T>();
+  constexpr int PER = TK_BINS / BLK;
+  __shared__ unsigned long long part[BLK];
+  unsigned long long my = 0;
+  for (int j = 0; j < PER; ++j) my += st.hist[TK_BINS - 1 - (threadIdx.x * PER + j)];
+  part[threadIdx.x] = my;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool go = true;
+    if (pass == 0) {
+      unsigned long long total = 0;
+      for (int i = 0; i < BLK; ++i) total += part[i];
+      st.pre_hi = st.pre_lo = 0ull;
+      st.depth = 0;
+      st.done = 0;
+      st.nokill = 0;
+      st.remaining = n_cut;
+      if (total <= n_max) {
+        st.done = 1;
+        st.nokill = 1;
+        go = false;
+      }
+    }
+    if (go) {
+      const unsigned long long rem = st.remaining;
+      unsigned long long cum = 0;  // entries of higher digits
+      int i = 0;
+      while (i < BLK - 1 && cum + part[i] < rem) cum += part[i++];
+      int d = TK_BINS - 1 - i * PER;
+      for (int j = 0; j < PER; ++j) {
+        d = TK_BINS - 1 - (i * PER + j);
+        const unsigned long long hd = st.hist[d];
+        if (cum + hd >= rem) break;
+        cum += hd;
+      }
+      const unsigned long long need = rem - cum;  // to keep inside digit d
+      const int top = nbits - TK_BITS * pass;
+      const int w = top > TK_BITS ? TK_BITS : top;
+      // prefix = (prefix << w) | d
+      R128 pre{st.pre_hi, st.pre_lo};
+      pre = R128{(pre.hi << w) | (pre.lo >> (64 - w)), (pre.lo << w) | static_cast<unsigned long long>(d)};
+      st.pre_hi = pre.hi;
+      st.pre_lo = pre.lo;
+      st.depth = pass + 1;
+      st.remaining = need;
+      if (st.hist[d] == need || top <= TK_BITS) st.done = 1;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < TK_BINS; i += blockDim.x) st.hist[i] = 0u;
+}
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_topk_kill(Tab t, StepArr sa, Counters* cnt, const TopK* tk, int k) {
+  const int b = blockIdx.y;
+  if (static_cast<uint32_t>(k) >= cnt[0].stop) return;
+  const TopK& st = tk[b];
+  if (st.nokill || st.depth == 0) return;
+  constexpr int nbits = rank_bits<T>();
+  const int sel = TK_BITS * st.depth < nbits ? TK_BITS * st.depth : nbits;
+  const R128 pre{st.pre_hi, st.pre_lo};
+  const View<T> v = view<T>(t, b);
+  const uint32_t K = static_cast<uint32_t>(k);
+  Fx w = fx_zero(), ea = fx_zero(), eb = fx_zero();
+  unsigned int n = 0;
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
+    const Slot<T> x = v.sl[s];
+    if (x.key == EMPTY_KEY || (x.meta & DEAD)) continue;
+    if (!lt128(shr128(rank_of<T>(x.key, x.amp), nbits - sel), pre)) continue;
+    v.sl[s].meta = DEAD | K;  // tombstone keeps the pre-truncation amplitude
+    const double r = static_cast<double>(x.amp);
+    w = fx_add(w, fx_from(r * r));
+    ++n;
+    if (sa.ea) ent_add(ea, eb, r);
+  }
+  const unsigned int c = wave_u32(n);
+  const int lane = threadIdx.x & 63;
+  const int wv = blockIdx.x * (BLK / 64) + (threadIdx.x >> 6);
+  if (c) {
+    const Fx ws = wave_fx(w);
+    if (lane == 0) {
+      fx3_atomic_add(&sa.pw[sidx(sa, b, wv & (SH - 1), k)], ws);
+      atomicAdd(&sa.pcnt[sidx(sa, b, wv & (SH - 1), k)], c);
+    }
+    if (sa.ea) {  // removed entries leave the entropy sums
+      ea = wave_fx(ea);
+      eb = wave_fx(eb);
+      if (lane == 0) {
+        const int64_t idx = (static_cast<int64_t>(b) * ES + (wv & (ES - 1))) * sa.stride + k;
+        fx3_atomic_add(&sa.ea[idx], Fx{~ea.lo + 1ull, ~ea.hi + (ea.lo == 0ull ? 1ull : 0ull)});
+        fx3_atomic_add(&sa.eb[idx], Fx{~eb.lo + 1ull, ~eb.hi + (eb.lo == 0ull ? 1ull : 0ull)});
+      }
+    }
+    // statistics: removed count (slot 0) and removals of live entries (slot 4)
+    unsigned long long* wst = sa.ws + (static_cast<int64_t>(b) * sa.nws + wv) * WSTAT;
+    if (lane == 0) wst[0] += c;
+    if (lane == 4) wst[4] += c;
+  }
+}
+
 __global__ void k_zero_u64(unsigned long long* p, uint64_t n) {
   for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0ull;
 }
@@ -1866,6 +2046,18 @@ void launch_entropy_final(const StepArr& sa, int64_t M, int B, hipStream_t st) {
                      sa, M);
 }
 
+template <class T>
+void launch_topk(const Tab& t, const StepArr& sa, Counters* cnt, TopK* tk, int k, uint64_t n_max, uint64_t n_cut,
+                 int B, int grid, hipStream_t st) {
+  constexpr int npass = (rank_bits<T>() + TK_BITS - 1) / TK_BITS;
+  for (int pass = 0; pass < npass; ++pass) {
+    hipLaunchKernelGGL(k_topk_hist<T>, dim3(grid, B), dim3(BLK), 0, st, t, tk, cnt, k, pass);
+    hipLaunchKernelGGL(k_topk_select<T>, dim3(1, B), dim3(BLK), 0, st, tk, cnt, k, pass,
+                       static_cast<unsigned long long>(n_max), static_cast<unsigned long long>(n_cut));
+  }
+  hipLaunchKernelGGL(k_topk_kill<T>, dim3(grid, B), dim3(BLK), 0, st, t, sa, cnt, tk, k);
+}
+
 void launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t st) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(n, BLK, 256)), dim3(BLK), 0, st, p, n);
@@ -1938,6 +2130,8 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
                                int, int, hipStream_t);                                                             \
   template void launch_snapshot<T>(const Tab&, const Snap&, int, int, hipStream_t);                              \
   template void launch_entropy_scan<T>(const Tab&, const StepArr&, int, int, int, hipStream_t);                   \
+  template void launch_topk<T>(const Tab&, const StepArr&, Counters*, TopK*, int, uint64_t, uint64_t, int, int,   \
+                               hipStream_t);                                                                       \
   template void launch_snap_restore<T>(const Tab&, const Snap&, Counters*, uint64_t, int, hipStream_t);
 
 SWC_INST(float)

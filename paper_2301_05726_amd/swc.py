@@ -23,7 +23,7 @@ EXPORTS = [
     "swc_workspace_bytes", "swc_create", "swc_build_state", "swc_apply_ucc", "swc_energy",
     "swc_energy_and_grad", "swc_get_state", "swc_get_stats", "swc_strerror", "swc_last_error",
     "swc_destroy", "swc_validate_excitations", "swc_factor_masks", "swc_checkpoint_bytes",
-    "swc_set_checkpoints", "swc_track_entropy", "swc_get_entropy",
+    "swc_set_checkpoints", "swc_track_entropy", "swc_get_entropy", "swc_set_topk",
 ]
 
 
@@ -80,6 +80,7 @@ def lib():
         L.swc_set_checkpoints.argtypes = [P, I64, U64, P, SZ]
         L.swc_track_entropy.argtypes = [P, I]
         L.swc_get_entropy.argtypes = [P, I, P, I64]
+        L.swc_set_topk.argtypes = [P, U64, U64]
         _lib = L
     return _lib
 
@@ -213,6 +214,11 @@ class Solver:
         self.ckpt_buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         _chk(lib().swc_set_checkpoints(self._ctx, interval, cap, ctypes.c_void_p(self.ckpt_buffer.data_ptr()),
                                        nbytes))
+
+    def set_topk(self, n_max: int, n_cut: int):
+        """Keep the n_cut largest |c| after a factor that leaves more than
+        n_max determinants (0, 0: off)."""
+        _chk(lib().swc_set_topk(self._ctx, int(n_max), int(n_cut)))
 
     def track_entropy(self, on: bool = True):
         """Record the entropy (Eq. 6) of the state before and after every

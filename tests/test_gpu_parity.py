@@ -409,3 +409,70 @@ def test_entropy_trajectory_vs_oracle(swc, orc, monkeypatch, case, prec, mode):
         say(f"  b={b} S_M={S[-1]:.6f} max|dS|={err:.3e}")
         assert err <= tol
     s.close()
+
+
+TOPK_CASES = [
+    # (name, n_orb, n_occ, sigma, seed, n_factors, threshold, n_max, n_cut)
+    ("q12_t0", 6, 3, 0.3, 201, None, 0.0, 150, 100),
+    ("q16_thr", 8, 4, 0.1, 201, None, 1e-4, 1200, 800),
+    ("q16_t0", 8, 4, 0.15, 201, None, 0.0, 2000, 1500),
+    ("q20_pre_thr", 10, 5, 0.05, 201, 300, 1e-5, 3000, 2000),
+    ("q20_pre_t0", 10, 5, 0.08, 201, 200, 0.0, 2500, 1200),
+]
+
+
+@pytest.mark.parametrize("mode", ["graph", "grow_batch", "persistent"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", TOPK_CASES, ids=[c[0] for c in TOPK_CASES])
+def test_topk_truncation_vs_oracle(swc, orc, monkeypatch, case, prec, mode):
+    """N_MAX / N_CUT truncation after every factor (radix selection on the
+    device) against the oracle: surviving set bit-exact, amplitudes, E, the
+    frozen-decision gradient and det-updates."""
+    name, n_orb, n_occ, sigma, seed, nf, thr, n_max, n_cut = case
+    say(f"[case] topk {name} prec={prec} mode={mode}")
+    for k in ("SWC_SWEEP", "SWC_TABLE_MIN"):
+        monkeypatch.delenv(k, raising=False)
+    B = 2 if mode == "grow_batch" else 1
+    if mode == "grow_batch":
+        monkeypatch.setenv("SWC_TABLE_MIN", "64")
+    elif mode == "persistent":
+        monkeypatch.setenv("SWC_SWEEP", "persistent")
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed, nf, batch=B)
+    if B == 2:
+        theta[1] = theta[0]  # member 1 repeats member 0 under a second table layout of the batch
+    nq = 2 * n_orb
+    tol = TOL[prec]
+    orc.set_nearcut_window(1e-5)
+    orc.set_topk(n_max, n_cut)
+    try:
+        d_ref, a_ref, nc, du_ref = orc.apply_ucc(nq, [hf], [1.0], exc, theta[0], thr)
+        E_ref, g_ref, _ = orc.energy_and_grad(nq, [hf], [1.0], exc, theta[0], thr, h1, h2)
+    finally:
+        orc.set_topk(0, 0)
+    assert nc == 0
+    cap = capacity_for(n_orb, n_occ)
+    # determinants flicker across the N_CUT boundary: many tombstones are
+    # revived, each saved in the truncation log
+    s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=B, max_factors=exc.shape[0], log_capacity=64 * cap)
+    s.set_topk(n_max, n_cut)
+    s.build_state()
+    s.apply_ucc(theta, exc, thr)
+    st = s.stats()
+    assert st["det_updates"] == B * du_ref
+    for b in range(B):
+        d, a = s.get_state(b)
+        err = compare_states(d, a, d_ref, a_ref, tol["amp"])
+    E, g = s.energy_and_grad(theta, exc, thr, h1, h2)
+    E, g = E.cpu().numpy(), g.cpu().numpy()
+    for b in range(B):
+        dg = np.max(np.abs(g[b] - g_ref))
+        say(f"  b={b} N={len(d_ref)} amp_err={err:.3e} dE={abs(E[b] - E_ref):.3e} max|dg|={dg:.3e}")
+        assert abs(E[b] - E_ref) <= tol["E"]
+        assert dg <= tol["g"]
+    s.set_topk(0, 0)
+    s.build_state()
+    s.apply_ucc(theta, exc, thr)
+    assert s.stats()["n_live"] > len(d_ref)  # the truncation was active
+    with pytest.raises(swc.SwcError):
+        s.set_topk(10, 11)
+    s.close()
