@@ -83,6 +83,8 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=1, help="theta vectors per call")
     ap.add_argument("--capacity-log2", type=int, default=0, help="hash capacity 2^c (0: the workload's)")
     ap.add_argument("--log-capacity-log2", type=int, default=0, help="truncation-log records 2^c (0: capacity)")
+    ap.add_argument("--topk", default="", help="N_MAX,N_CUT truncation after every factor (paper's rule)")
+    ap.add_argument("--entropy", action="store_true", help="track the entropy (Eq. 6) after every factor")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -107,6 +109,11 @@ def main() -> int:
 
     logcap = (1 << args.log_capacity_log2) if args.log_capacity_log2 else 0
     s = swc.Solver(nq, wl.n_occ, wl.n_occ, cap, prec=prec, batch=B, max_factors=M, log_capacity=logcap, device=dev)
+    topk = tuple(int(x) for x in args.topk.split(",")) if args.topk else None
+    if topk:
+        s.set_topk(*topk)
+    if args.entropy:
+        s.track_entropy(True)
     s.build_state()
     for _ in range(args.warmup):
         s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
@@ -182,7 +189,9 @@ def main() -> int:
                          + (f"first {M} factors of spin-conserving UCCSD" if args.factors
                             else f"full spin-conserving UCCSD ({M} factors)")
                          + f", theta~N(0,{wl.theta_sigma}), threshold {wl.threshold}, "
-                         f"capacity 2^{int(np.log2(cap))}" + (f", batch {B}" if B > 1 else "")),
+                         f"capacity 2^{int(np.log2(cap))}" + (f", batch {B}" if B > 1 else "")
+                         + (f", N_MAX/N_CUT {topk[0]}/{topk[1]}" if topk else "")
+                         + (", entropy tracked" if args.entropy else "")),
             "amplitudes": args.prec, "reductions": "f64 (exact fixed point)",
             "n_det_final": n_live,
         },
@@ -192,6 +201,7 @@ def main() -> int:
         "table_slots_final": st["table_slots"],
         "det_updates_per_s_forward": round(det_updates / (fwd_ms / args.steps * 1e-3), 1) if fwd_ms else None,
         "energy": E0,
+        **({"entropy_final": float(s.entropy(0)[-1])} if args.entropy else {}),
         "roofline": roofline,
     }
 
@@ -233,6 +243,8 @@ def main() -> int:
 
     if not args.no_cpu_baseline:
         import oracle
+        if topk:
+            oracle.set_topk(*topk)
         if wl.name in ("q8", "q20"):
             # the whole evaluation fits the CPU budget (about 10 s at 20 qubits)
             c0 = time.perf_counter()
