@@ -107,6 +107,7 @@ typedef struct {
   int64_t compactions;       /* rehashes at its start that dropped tombstones of
                                 earlier sweeps (over 1/4 of the occupied slots) */
   int64_t checkpoints;       /* snapshots taken by the last gradient sweep */
+  int64_t sigma_partitions;  /* partitions of the last pairing sigma (0: hash probes were used) */
 } swc_stats;
 
 /*
@@ -212,6 +213,25 @@ int swc_track_entropy(swc_ctx* ctx, int on);
  * turns it off; otherwise 1 <= n_cut <= n_max, else SWC_EINVAL.
  */
 int swc_set_topk(swc_ctx* ctx, uint64_t n_max, uint64_t n_cut);
+
+/*
+ * Scratch for sigma = H psi (energy; Results section) by pairing instead of
+ * hash probes.  Two determinants differ by a double excitation exactly when
+ * removing two electrons from each leaves the same pattern K: every live
+ * determinant emits one record (K, index) per pair of its occupied
+ * spin-orbitals, the records are radix-sorted by K on the device, and each
+ * group sums <I|H|J> c_J over its members (exact fixed-point partial sums).
+ * Only connections present in the state are touched; absent ones are never
+ * probed.  Singles and the diagonal keep their own paths.  `buffer` (device,
+ * 256-byte aligned, caller-owned, kept until the next call or swc_destroy):
+ * about 41 bytes per record plus 24 bytes per live determinant; records
+ * beyond it are processed in hash partitions of K (pairing is skipped when
+ * the buffer cannot hold the accumulators and 4096 records).  mode: 0 = pairing when the record
+ * count (live determinants x pairs of electrons) reaches 2^22, 1 = always,
+ * 2 = never (NULL buffer: never).  Results agree with the probing path to
+ * rounding; both are bit-reproducible.
+ */
+int swc_set_sigma_scratch(swc_ctx* ctx, void* buffer, size_t bytes, int mode);
 int swc_get_entropy(swc_ctx* ctx, int b, double* S, int64_t n);
 
 /*

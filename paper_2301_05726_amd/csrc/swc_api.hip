@@ -166,6 +166,7 @@ struct GraphKey {
 };
 constexpr int64_t GRAPH_CHUNK = 2048;
 constexpr size_t GRAPH_CACHE_MAX = 512;  // executable graphs kept per context
+constexpr uint64_t RS_CAP_SLACK = 4096;  // records kept below the sort's 2^28 limit
 
 // Steps run in chunks [2^(j-1) + 1, 2^j] up to GRAPH_CHUNK and in chunks
 // [m GRAPH_CHUNK + 1, (m + 1) GRAPH_CHUNK] above (so a chunk ends at every
@@ -202,6 +203,12 @@ struct swc_ctx {
   Fx3* ent_ea = nullptr;
   Fx3* ent_eb = nullptr;
   int64_t ent_M = -1;
+  // sigma of doubles by pairing (swc_set_sigma_scratch): caller's scratch;
+  // mode 0 auto, 1 always, 2 never (probes)
+  char* sig_buf = nullptr;
+  size_t sig_bytes = 0;
+  int sig_mode = 2;
+  int64_t sig_parts = 0;  // partitions used by the last pairing sigma (0: probes)
   // N_MAX / N_CUT truncation after every factor (swc_set_topk; 0 = off)
   uint64_t tk_max = 0, tk_cut = 0;
   TopK* tk = nullptr;
@@ -756,6 +763,94 @@ int sweep_status(swc_ctx* c) {
   return SWC_OK;
 }
 
+// Pairing scratch: six record arrays, the radix histogram and scan sums, a
+// counter and the per-determinant accumulators (one member at a time).
+struct PairScratch {
+  uint64_t *k0, *k1, *rI;
+  uint32_t *v0, *v1, *hist, *sums;
+  double* rc;
+  unsigned long long* count;
+  Fx3* acc;
+  uint64_t cap;  // records per partition
+};
+
+bool pair_scratch(const swc_ctx* c, uint64_t nacc, PairScratch* ps) {
+  if (!c->sig_buf) return false;
+  const size_t fixed = align_up(sizeof(Fx3) * nacc) + align_up(4 * 4096) + align_up(8) + 16 * ALIGN;
+  if (c->sig_bytes <= fixed) return false;
+  uint64_t cap = static_cast<uint64_t>((c->sig_bytes - fixed) / 41);  // 40 B per record + histogram share
+  cap = std::min<uint64_t>(cap, (1ull << 28) - RS_CAP_SLACK);
+  if (cap < 4096) return false;
+  char* p = c->sig_buf;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += align_up(bytes);
+    return q;
+  };
+  ps->k0 = reinterpret_cast<uint64_t*>(take(8 * cap));
+  ps->k1 = reinterpret_cast<uint64_t*>(take(8 * cap));
+  ps->rI = reinterpret_cast<uint64_t*>(take(8 * cap));
+  ps->rc = reinterpret_cast<double*>(take(8 * cap));
+  ps->v0 = reinterpret_cast<uint32_t*>(take(4 * cap));
+  ps->v1 = reinterpret_cast<uint32_t*>(take(4 * cap));
+  ps->hist = reinterpret_cast<uint32_t*>(take(4 * 256 * ((cap + 4095) / 4096)));
+  ps->sums = reinterpret_cast<uint32_t*>(take(4 * 4096));
+  ps->count = reinterpret_cast<unsigned long long*>(take(8));
+  ps->acc = reinterpret_cast<Fx3*>(take(sizeof(Fx3) * nacc));
+  ps->cap = cap;
+  return static_cast<size_t>(p - c->sig_buf) <= c->sig_bytes;
+}
+
+int electrons(const swc_ctx* c) { return c->na + c->nb; }
+
+bool use_pairs(const swc_ctx* c, int64_t nmax) {
+  if (c->sig_mode == 2) return false;
+  PairScratch ps;
+  if (!pair_scratch(c, static_cast<uint64_t>(nmax), &ps)) return false;
+  if (c->sig_mode == 1) return true;
+  const uint64_t P = static_cast<uint64_t>(electrons(c)) * (electrons(c) - 1) / 2;
+  return static_cast<uint64_t>(nmax) * P >= (1ull << 22);
+}
+
+// Double-excitation part of sigma by pairing, member by member, partition by
+// partition; the singles are already in cp.sig.
+int pair_sigma(swc_ctx* c, const double* h1, const double* h2, int64_t nmax) {
+  PairScratch ps;
+  if (!pair_scratch(c, static_cast<uint64_t>(nmax), &ps)) return fail(SWC_EINVAL, "sigma scratch too small");
+  const uint64_t P = static_cast<uint64_t>(electrons(c)) * (electrons(c) - 1) / 2;
+  const uint64_t H = c->tab.H;
+  for (int b = 0; b < c->B; ++b) {
+    const uint64_t N = c->hcnt[b].ncompact;
+    if (N == 0) continue;
+    int nparts = static_cast<int>(std::max<uint64_t>(1, (N * P + N * P / 4 + ps.cap - 1) / ps.cap));
+    for (int attempt = 0;; ++attempt) {
+      launch_fx3_zero(ps.acc, N, c->st);
+      bool overflow = false;
+      for (int part = 0; part < nparts; ++part) {
+        launch_zero_u64(ps.count, 1, c->st);
+        launch_pair_emit(c->cp, H, b, N, part, nparts, ps.k0, ps.v0, ps.count, ps.cap, c->st);
+        unsigned long long n = 0;
+        SWC_HIP(hipMemcpyAsync(&n, ps.count, 8, hipMemcpyDeviceToHost, c->st));
+        SWC_HIP(hipStreamSynchronize(c->st));
+        if (n > ps.cap) {
+          overflow = true;
+          break;
+        }
+        const int flip = launch_radix_sort(ps.k0, ps.v0, ps.k1, ps.v1, n, c->nq, ps.hist, ps.sums, c->st);
+        launch_pair_groups(c->cp, H, b, flip ? ps.k1 : ps.k0, flip ? ps.v1 : ps.v0, n, ps.rI, ps.rc, h1, h2,
+                           c->nq / 2, ps.acc, c->st);
+      }
+      if (!overflow) break;
+      if (attempt >= 8) return fail(SWC_ECAPACITY, "sigma scratch: a partition exceeds the scratch");
+      nparts *= 2;  // an unlucky partition: split finer and start the member again
+    }
+    c->sig_parts = std::max<int64_t>(c->sig_parts, nparts);
+    launch_pair_finish(c->cp, H, b, N, ps.acc, c->st);
+  }
+  SWC_HIP(hipGetLastError());
+  return SWC_OK;
+}
+
 // compact + sigma + E (+ lambda); leaves counters read back
 int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool want_lambda) {
   if (!h1 || !h2) return fail(SWC_EINVAL, "null integrals");
@@ -774,12 +869,15 @@ int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool 
   if (nmax == 0) return fail(SWC_EEMPTY, "empty state");
   const int n = c->nq / 2;
   SWC_HIP(hipEventRecord(c->ev[6], c->st));
+  const bool pairs = use_pairs(c, nmax);
   r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
-    launch_sigma<T>(c->tab, c->cp, c->cnt, h1, h2, c->nq, nmax, c->B, c->st);
+    launch_sigma<T>(c->tab, c->cp, c->cnt, h1, h2, c->nq, nmax, c->B, pairs ? 1 : 0, c->st);
     return SWC_OK;
   });
   if (r) return r;
+  c->sig_parts = 0;
+  if (pairs && (r = pair_sigma(c, h1, h2, nmax))) return r;
   SWC_HIP(hipEventRecord(c->ev[7], c->st));
   launch_energy_reduce(c->cp, c->cnt, c->tab.H, h1, h2, n, nmax, c->B, c->st);
   launch_energy_final(c->cnt, E, c->B, c->st);
@@ -1107,6 +1205,18 @@ int swc_set_checkpoints(swc_ctx* c, int64_t interval, uint64_t max_entries, void
   return SWC_OK;
 }
 
+int swc_set_sigma_scratch(swc_ctx* c, void* buffer, size_t bytes, int mode) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  if (mode < 0 || mode > 2) return fail(SWC_EINVAL, "mode must be 0 (auto), 1 (always) or 2 (never)");
+  if (buffer && reinterpret_cast<uintptr_t>(buffer) % ALIGN) return fail(SWC_EINVAL, "scratch not 256-byte aligned");
+  c->sig_buf = static_cast<char*>(buffer);
+  c->sig_bytes = buffer ? bytes : 0;
+  c->sig_mode = buffer ? mode : 2;
+  PairScratch ps;
+  if (buffer && mode != 2 && !pair_scratch(c, 1, &ps)) return fail(SWC_EINVAL, "sigma scratch too small");
+  return SWC_OK;
+}
+
 int swc_set_topk(swc_ctx* c, uint64_t n_max, uint64_t n_cut) {
   if (!c) return fail(SWC_EINVAL, "null context");
   if (n_max == 0 && n_cut == 0) {
@@ -1188,6 +1298,7 @@ int swc_get_stats(swc_ctx* c, swc_stats* out) {
   s.rehashes = c->rehashes;
   s.compactions = c->compactions;
   s.checkpoints = c->ck_taken;
+  s.sigma_partitions = c->sig_parts;
   s.fwd_ms = c->fwd_ms;
   s.energy_ms = c->energy_ms;
   s.rev_ms = c->rev_ms;

@@ -1724,7 +1724,7 @@ __device__ __forceinline__ uint64_t excite(uint64_t I, int e, const Lists& L, co
 template <class T>
 __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters* cnt,
                                                const double* __restrict__ h1, const double* __restrict__ h2,
-                                               int nq) {
+                                               int nq, int singles_only) {
   __shared__ uint16_t tri[TRI];
   __shared__ uint8_t lists[(BLK / SG) * LROW];
   for (int e = threadIdx.x; e < TRI; e += blockDim.x) {
@@ -1765,7 +1765,7 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
     L.dAA = L.nA * (L.nA - 1) / 2 * (L.mA * (L.mA - 1) / 2);
     L.dBB = L.nB * (L.nB - 1) / 2 * (L.mB * (L.mB - 1) / 2);
     L.dAB = L.nA * L.nB * L.mA * L.mB;
-    const int total = L.sA + L.sB + L.dAA + L.dBB + L.dAB;
+    const int total = singles_only ? L.sA + L.sB : L.sA + L.sB + L.dAA + L.dBB + L.dAB;
     double acc = 0.0;
     for (int e0 = g; e0 < total; e0 += SG * SGU) {
       uint64_t J[SGU], home[SGU];
@@ -2065,10 +2065,10 @@ void launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t st) {
 
 template <class T>
 void launch_sigma(const Tab& t, const Compact& cp, const Counters* cnt, const double* h1, const double* h2, int nq,
-                  int64_t nmax, int B, hipStream_t st) {
+                  int64_t nmax, int B, int singles_only, hipStream_t st) {
   if (nmax <= 0) return;
   hipLaunchKernelGGL(k_sigma<T>, dim3(grid_for(static_cast<uint64_t>(nmax) * SG, BLK, 16384), B), dim3(BLK), 0, st,
-                     t, cp, cnt, h1, h2, nq);
+                     t, cp, cnt, h1, h2, nq, singles_only);
 }
 
 void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
@@ -2102,6 +2102,284 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
   hipLaunchKernelGGL(k_grad_final, dim3(grid_for(M, BLK, 1024), B), dim3(BLK), 0, st, sa, cnt, grad, M);
 }
 
+// ---------------------------------------------------------------------------
+// sigma, double excitations, by pairing (a sort instead of hash probes)
+// ---------------------------------------------------------------------------
+// I and J differ by a double excitation exactly when removing two occupied
+// spin-orbitals from each leaves the same (N-2)-electron pattern K, the
+// removed pairs being disjoint.  Every determinant emits one record (K, i) per
+// pair of its occupied spin-orbitals; records sorted by K form groups, and a
+// record's share of sigma_I is the sum over the other members J of its group
+// with a disjoint removed pair of <I|H|J> c_J.  Each double connection present
+// in the state is met exactly once from each side, and nothing absent is
+// probed.  Partial sums are exact fixed point, so the order of a group does
+// not matter; records are split into partitions by a hash of K to bound the
+// scratch memory.
+
+constexpr int RS_ITEMS = 16;             // elements per thread of a sort tile
+constexpr int RS_TILE = BLK * RS_ITEMS;  // elements per block of a sort pass
+constexpr int SCAN_CH = BLK * 16;        // scan chunk
+
+__device__ __forceinline__ int pair_part(uint64_t K, int nparts) {
+  return static_cast<int>((mix64(K) >> 40) % static_cast<uint64_t>(nparts));
+}
+
+// digit histogram of every tile: hist[digit * blocks + block]
+__global__ __launch_bounds__(BLK) void k_rs_hist(const uint64_t* __restrict__ keys, uint64_t n, int shift,
+                                                 uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * RS_TILE;
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const uint64_t e = base + static_cast<uint64_t>(r) * BLK + threadIdx.x;
+    if (e < n) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[static_cast<uint64_t>(threadIdx.x) * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of 256 values held one per thread (block-wide)
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
+  tmp[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < BLK; o <<= 1) {
+    const uint32_t add = threadIdx.x >= static_cast<unsigned>(o) ? tmp[threadIdx.x - o] : 0u;
+    __syncthreads();
+    tmp[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const uint32_t incl = tmp[threadIdx.x];
+  *total = tmp[BLK - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// exclusive scan of each SCAN_CH chunk in place; chunk totals into sums
+__global__ __launch_bounds__(BLK) void k_scan_local(uint32_t* __restrict__ a, uint64_t L, uint32_t* __restrict__ sums) {
+  __shared__ uint32_t tmp[BLK];
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * SCAN_CH + static_cast<uint64_t>(threadIdx.x) * 16;
+  uint32_t v[16], tsum = 0;
+  for (int j = 0; j < 16; ++j) {
+    v[j] = base + j < L ? a[base + j] : 0u;
+    tsum += v[j];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(tsum, tmp, &total);
+  for (int j = 0; j < 16; ++j) {
+    if (base + j < L) a[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// exclusive scan of the chunk totals (one block, nchunks <= BLK * 16)
+__global__ __launch_bounds__(BLK) void k_scan_top(uint32_t* __restrict__ sums, uint64_t nchunks) {
+  __shared__ uint32_t tmp[BLK];
+  const uint64_t base = static_cast<uint64_t>(threadIdx.x) * 16;
+  uint32_t v[16], tsum = 0;
+  for (int j = 0; j < 16; ++j) {
+    v[j] = base + j < nchunks ? sums[base + j] : 0u;
+    tsum += v[j];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(tsum, tmp, &total);
+  for (int j = 0; j < 16; ++j) {
+    if (base + j < nchunks) sums[base + j] = run;
+    run += v[j];
+  }
+}
+
+__global__ void k_scan_add(uint32_t* __restrict__ a, uint64_t L, const uint32_t* __restrict__ sums) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < L;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    a[i] += sums[i / SCAN_CH];
+}
+
+// stable scatter of one radix pass: a tile is taken RS_ITEMS times 256
+// elements in order; lanes with equal digits are ranked by ballots, waves by
+// LDS counts
+__global__ __launch_bounds__(BLK) void k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                    uint64_t n, int shift, const uint32_t* __restrict__ offs) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[BLK / 64][256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  run[t] = offs[static_cast<uint64_t>(t) * gridDim.x + blockIdx.x];
+  for (int q = 0; q < BLK / 64; ++q) wcnt[q][t] = 0u;
+  __syncthreads();
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * RS_TILE;
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const uint64_t e = base + static_cast<uint64_t>(r) * BLK + t;
+    const bool valid = e < n;
+    const uint64_t key = valid ? kin[e] : 0ull;
+    const uint32_t val = valid ? vin[e] : 0u;
+    const uint32_t d = static_cast<uint32_t>(key >> shift) & 255u;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const unsigned long long bb = __ballot(on);
+      peers &= on ? bb : ~bb;
+    }
+    const uint32_t rank = static_cast<uint32_t>(__popcll(peers & ((1ull << lane) - 1ull)));
+    if (valid && rank == 0) wcnt[w][d] = static_cast<uint32_t>(__popcll(peers));
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = 0;
+      for (int q = 0; q < w; ++q) pre += wcnt[q][d];
+      const uint32_t pos = run[d] + pre + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int q = 0; q < BLK / 64; ++q) {
+      add += wcnt[q][t];
+      wcnt[q][t] = 0u;
+    }
+    run[t] += add;
+    __syncthreads();
+  }
+}
+
+// records (K, i) of partition `part` for determinants i < N of member b
+__global__ __launch_bounds__(BLK) void k_pair_emit(Compact cp, uint64_t H, int b, uint64_t N, int part, int nparts,
+                                                   uint64_t* __restrict__ rk, uint32_t* __restrict__ ri,
+                                                   unsigned long long* __restrict__ count, uint64_t cap) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  // loop bound uniform across the wave so the ballot-free prefix below is safe
+  for (uint64_t i0 = blockIdx.x * static_cast<uint64_t>(blockDim.x) + (threadIdx.x & ~63u); i0 < N; i0 += stride) {
+    const uint64_t i = i0 + lane;
+    const uint64_t I = i < N ? cp.key[b * H + i] : 0ull;
+    unsigned int c = 0;
+    for (uint64_t m1 = I; m1; m1 &= m1 - 1ull) {
+      const uint64_t b1 = m1 & (~m1 + 1ull);
+      for (uint64_t m2 = m1 & (m1 - 1ull); m2; m2 &= m2 - 1ull)
+        c += pair_part(I ^ b1 ^ (m2 & (~m2 + 1ull)), nparts) == part;
+    }
+    // wave prefix of the counts, one atomic per wave
+    unsigned int incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    const unsigned int tot = __shfl(incl, 63, 64);
+    unsigned long long basep = 0;
+    if (lane == 63 && tot) basep = atomicAdd(count, static_cast<unsigned long long>(tot));
+    basep = __shfl(basep, 63, 64);
+    uint64_t pos = basep + incl - c;
+    for (uint64_t m1 = I; m1; m1 &= m1 - 1ull) {
+      const uint64_t b1 = m1 & (~m1 + 1ull);
+      for (uint64_t m2 = m1 & (m1 - 1ull); m2; m2 &= m2 - 1ull) {
+        const uint64_t K = I ^ b1 ^ (m2 & (~m2 + 1ull));
+        if (pair_part(K, nparts) != part) continue;
+        if (pos < cap) {
+          rk[pos] = K;
+          ri[pos] = static_cast<uint32_t>(i);
+        }
+        ++pos;
+      }
+    }
+  }
+}
+
+// each sorted record: its determinant and amplitude, next to it
+__global__ void k_pair_gather(Compact cp, uint64_t H, int b, const uint32_t* __restrict__ ri, uint64_t n,
+                              uint64_t* __restrict__ rI, double* __restrict__ rc) {
+  for (uint64_t j = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; j < n;
+       j += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    rI[j] = cp.key[b * H + ri[j]];
+    rc[j] = cp.amp[b * H + ri[j]];
+  }
+}
+
+// a record's share of sigma: the other members of its group (same K) whose
+// removed pair is disjoint from its own
+__global__ __launch_bounds__(BLK) void k_pair_sigma(const uint64_t* __restrict__ K, const uint64_t* __restrict__ rI,
+                                                    const double* __restrict__ rc, const uint32_t* __restrict__ ri,
+                                                    uint64_t n, const double* __restrict__ h1,
+                                                    const double* __restrict__ h2, int n_orb,
+                                                    Fx3* __restrict__ acc) {
+  for (uint64_t j = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; j < n;
+       j += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t k = K[j];
+    uint64_t s = j, e = j + 1;
+    while (s > 0 && K[s - 1] == k) --s;
+    while (e < n && K[e] == k) ++e;
+    if (e - s < 2) continue;
+    const uint64_t I = rI[j], dI = I ^ k;
+    Fx a = fx_zero();
+    for (uint64_t u = s; u < e; ++u) {
+      if (u == j) continue;
+      const uint64_t J = rI[u];
+      if ((J ^ k) & dI) continue;  // shared removed orbital: a single (or none), handled elsewhere
+      a = fx_add(a, fx_from(h_offdiag(I, J, 4, h1, h2, n_orb) * rc[u]));
+    }
+    if (fx_nonzero(a)) fx3_atomic_add(&acc[ri[j]], a);
+  }
+}
+
+__global__ void k_pair_finish(Compact cp, uint64_t H, int b, uint64_t N, Fx3* __restrict__ acc) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < N;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    cp.sig[b * H + i] += fx_to_d(fx3_value(acc[i]));
+    acc[i] = fx3_zero();
+  }
+}
+
+void launch_pair_emit(const Compact& cp, uint64_t H, int b, uint64_t N, int part, int nparts, uint64_t* rk,
+                      uint32_t* ri, unsigned long long* count, uint64_t cap, hipStream_t st) {
+  hipLaunchKernelGGL(k_pair_emit, dim3(grid_for(N, BLK, 8192)), dim3(BLK), 0, st, cp, H, b, N, part, nparts, rk, ri,
+                     count, cap);
+}
+
+// LSD radix sort of (key, value) by the low `bits` bits of the key, 8 per
+// pass, ping-ponging between (k0, v0) and (k1, v1); returns 1 when the
+// result ended in (k1, v1)
+int launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t n, int bits, uint32_t* hist,
+                      uint32_t* sums, hipStream_t st) {
+  if (n == 0) return 0;
+  const uint64_t nblk = (n + RS_TILE - 1) / RS_TILE;
+  const uint64_t L = 256 * nblk;
+  const uint64_t nch = (L + SCAN_CH - 1) / SCAN_CH;
+  int flip = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    uint64_t* ki = flip ? k1 : k0;
+    uint32_t* vi = flip ? v1 : v0;
+    uint64_t* ko = flip ? k0 : k1;
+    uint32_t* vo = flip ? v0 : v1;
+    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(BLK), 0, st, ki, n, shift, hist);
+    hipLaunchKernelGGL(k_scan_local, dim3(nch), dim3(BLK), 0, st, hist, L, sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLK), 0, st, sums, nch);
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(L, BLK, 4096)), dim3(BLK), 0, st, hist, L, sums);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(BLK), 0, st, ki, vi, ko, vo, n, shift, hist);
+    flip ^= 1;
+  }
+  return flip;
+}
+
+void launch_pair_groups(const Compact& cp, uint64_t H, int b, const uint64_t* K, const uint32_t* ri, uint64_t n,
+                        uint64_t* rI, double* rc, const double* h1, const double* h2, int n_orb, Fx3* acc,
+                        hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_pair_gather, dim3(grid_for(n, BLK, 8192)), dim3(BLK), 0, st, cp, H, b, ri, n, rI, rc);
+  hipLaunchKernelGGL(k_pair_sigma, dim3(grid_for(n, BLK, 16384)), dim3(BLK), 0, st, K, rI, rc, ri, n, h1, h2, n_orb,
+                     acc);
+}
+
+void launch_pair_finish(const Compact& cp, uint64_t H, int b, uint64_t N, Fx3* acc, hipStream_t st) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_pair_finish, dim3(grid_for(N, BLK, 4096)), dim3(BLK), 0, st, cp, H, b, N, acc);
+}
+
+void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
+  if (n == 0) return;
+  launch_zero_u64(reinterpret_cast<unsigned long long*>(a), 3 * n, st);
+}
+
 #define SWC_INST(T)                                                                                                \
   template void launch_fill<T>(const Tab&, int, hipStream_t);                                                      \
   template void launch_insert_init<T>(const Tab&, Counters*, const uint64_t*, const double*, int64_t, int,         \
@@ -2116,7 +2394,7 @@ void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int
   template void launch_compact<T>(const Tab&, const Compact&, Counters*, int, int, hipStream_t);                  \
   template void launch_lambda<T>(const Tab&, const Compact&, const Counters*, int64_t, int, hipStream_t);        \
   template void launch_sigma<T>(const Tab&, const Compact&, const Counters*, const double*, const double*, int,   \
-                                int64_t, int, hipStream_t);                                                        \
+                                int64_t, int, int, hipStream_t);                                                   \
   template int coop_blocks_per_cu<T>(int);                                                                         \
   template hipError_t launch_fwd_sweep<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&,       \
                                           Counters*, const LogArr&, int, int, double, int, int, Sync*, int, int,   \

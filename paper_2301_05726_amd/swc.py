@@ -23,7 +23,7 @@ EXPORTS = [
     "swc_workspace_bytes", "swc_create", "swc_build_state", "swc_apply_ucc", "swc_energy",
     "swc_energy_and_grad", "swc_get_state", "swc_get_stats", "swc_strerror", "swc_last_error",
     "swc_destroy", "swc_validate_excitations", "swc_factor_masks", "swc_checkpoint_bytes",
-    "swc_set_checkpoints", "swc_track_entropy", "swc_get_entropy", "swc_set_topk",
+    "swc_set_checkpoints", "swc_track_entropy", "swc_get_entropy", "swc_set_topk", "swc_set_sigma_scratch",
 ]
 
 
@@ -43,6 +43,7 @@ class Stats(ctypes.Structure):
         ("reverse_kernel_ms", ctypes.c_double), ("reverse_launches", ctypes.c_int64),
         ("sigma_kernel_ms", ctypes.c_double), ("partner_hits", ctypes.c_int64),
         ("rehashes", ctypes.c_int64), ("compactions", ctypes.c_int64), ("checkpoints", ctypes.c_int64),
+        ("sigma_partitions", ctypes.c_int64),
     ]
 
 
@@ -81,6 +82,7 @@ def lib():
         L.swc_track_entropy.argtypes = [P, I]
         L.swc_get_entropy.argtypes = [P, I, P, I64]
         L.swc_set_topk.argtypes = [P, U64, U64]
+        L.swc_set_sigma_scratch.argtypes = [P, P, SZ, I]
         _lib = L
     return _lib
 
@@ -214,6 +216,17 @@ class Solver:
         self.ckpt_buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         _chk(lib().swc_set_checkpoints(self._ctx, interval, cap, ctypes.c_void_p(self.ckpt_buffer.data_ptr()),
                                        nbytes))
+
+    def set_sigma_scratch(self, nbytes: int, mode: int = 0):
+        """Device scratch for sigma by pairing two-electron-removed keys
+        (mode 0 auto, 1 always, 2 never; nbytes 0 frees it)."""
+        if nbytes <= 0:
+            _chk(lib().swc_set_sigma_scratch(self._ctx, None, 0, 2))
+            self.sigma_buffer = None
+            return
+        self.sigma_buffer = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        _chk(lib().swc_set_sigma_scratch(self._ctx, ctypes.c_void_p(self.sigma_buffer.data_ptr()), int(nbytes),
+                                         int(mode)))
 
     def set_topk(self, n_max: int, n_cut: int):
         """Keep the n_cut largest |c| after a factor that leaves more than
