@@ -85,6 +85,8 @@ def main() -> int:
     ap.add_argument("--log-capacity-log2", type=int, default=0, help="truncation-log records 2^c (0: capacity)")
     ap.add_argument("--topk", default="", help="N_MAX,N_CUT truncation after every factor (paper's rule)")
     ap.add_argument("--entropy", action="store_true", help="track the entropy (Eq. 6) after every factor")
+    ap.add_argument("--sigma-scratch-gib", type=float, default=0.0,
+                    help="device scratch for sigma by pairing (0: hash probes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -114,6 +116,8 @@ def main() -> int:
         s.set_topk(*topk)
     if args.entropy:
         s.track_entropy(True)
+    if args.sigma_scratch_gib > 0:
+        s.set_sigma_scratch(int(args.sigma_scratch_gib * (1 << 30)), mode=0)
     s.build_state()
     for _ in range(args.warmup):
         s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
@@ -198,6 +202,7 @@ def main() -> int:
         "det_updates_per_step": det_updates,
         "pair_updates_per_step": st["pair_updates"],
         "truncation_log_records": log_records,
+        "sigma_partitions": st["sigma_partitions"],
         "table_slots_final": st["table_slots"],
         "det_updates_per_s_forward": round(det_updates / (fwd_ms / args.steps * 1e-3), 1) if fwd_ms else None,
         "energy": E0,
