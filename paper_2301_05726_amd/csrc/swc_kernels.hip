@@ -2297,26 +2297,56 @@ __global__ void k_pair_gather(Compact cp, uint64_t H, int b, const uint32_t* __r
 }
 
 // a record's share of sigma: the other members of its group (same K) whose
-// removed pair is disjoint from its own
+// removed pair is disjoint from its own.  A wave takes 64 consecutive
+// records: group bounds come from wave scans of the group heads and tails,
+// with a walk only for the groups that cross the wave's edges; members are
+// read four at a time so their loads are in flight together.
 __global__ __launch_bounds__(BLK) void k_pair_sigma(const uint64_t* __restrict__ K, const uint64_t* __restrict__ rI,
                                                     const double* __restrict__ rc, const uint32_t* __restrict__ ri,
                                                     uint64_t n, const double* __restrict__ h1,
                                                     const double* __restrict__ h2, int n_orb,
                                                     Fx3* __restrict__ acc) {
-  for (uint64_t j = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; j < n;
-       j += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t k = K[j];
-    uint64_t s = j, e = j + 1;
-    while (s > 0 && K[s - 1] == k) --s;
-    while (e < n && K[e] == k) ++e;
-    if (e - s < 2) continue;
+  const int lane = threadIdx.x & 63;
+  const uint64_t wstride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t j0 = blockIdx.x * static_cast<uint64_t>(blockDim.x) + (threadIdx.x & ~63u); j0 < n; j0 += wstride) {
+    const uint64_t j = j0 + lane;
+    const bool valid = j < n;
+    const uint64_t k = valid ? K[j] : ~0ull;
+    const bool head = valid && (j == 0 || K[j - 1] != k);
+    const bool tail = valid && (j + 1 == n || K[j + 1] != k);
+    // start: last head at or before this lane; end: first tail at or after it
+    long long sv = head ? static_cast<long long>(j) : -1;
+    unsigned long long ev = tail ? j + 1 : ~0ull;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const long long a = __shfl_up(sv, o, 64);
+      if (lane >= o && a > sv) sv = a;
+      const unsigned long long c = __shfl_down(ev, o, 64);
+      if (lane + o < 64 && c < ev) ev = c;
+    }
+    if (!valid) continue;
+    uint64_t s0 = sv >= 0 ? static_cast<uint64_t>(sv) : j0;
+    if (sv < 0) while (s0 > 0 && K[s0 - 1] == k) --s0;  // group began in an earlier wave
+    uint64_t e0 = ev != ~0ull ? ev : j0 + 64;
+    if (ev == ~0ull) while (e0 < n && K[e0] == k) ++e0;  // group goes on past this wave
+    if (e0 - s0 < 2) continue;
     const uint64_t I = rI[j], dI = I ^ k;
     Fx a = fx_zero();
-    for (uint64_t u = s; u < e; ++u) {
-      if (u == j) continue;
-      const uint64_t J = rI[u];
-      if ((J ^ k) & dI) continue;  // shared removed orbital: a single (or none), handled elsewhere
-      a = fx_add(a, fx_from(h_offdiag(I, J, 4, h1, h2, n_orb) * rc[u]));
+    for (uint64_t u0 = s0; u0 < e0; u0 += 4) {
+      uint64_t J[4];
+      double c[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t u = u0 + q;
+        J[q] = u < e0 ? rI[u] : I;
+        c[q] = u < e0 ? rc[u] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // same determinant, or a shared removed orbital (a single): not a double
+        if (J[q] == I || ((J[q] ^ k) & dI)) continue;
+        a = fx_add(a, fx_from(h_offdiag(I, J[q], 4, h1, h2, n_orb) * c[q]));
+      }
     }
     if (fx_nonzero(a)) fx3_atomic_add(&acc[ri[j]], a);
   }
