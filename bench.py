@@ -87,6 +87,7 @@ def main() -> int:
     ap.add_argument("--entropy", action="store_true", help="track the entropy (Eq. 6) after every factor")
     ap.add_argument("--sigma-scratch-gib", type=float, default=0.0,
                     help="device scratch for sigma by pairing (0: hash probes)")
+    ap.add_argument("--sigma-mode", type=int, default=0, help="pairing: 0 auto, 1 always, 2 never")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -117,7 +118,7 @@ def main() -> int:
     if args.entropy:
         s.track_entropy(True)
     if args.sigma_scratch_gib > 0:
-        s.set_sigma_scratch(int(args.sigma_scratch_gib * (1 << 30)), mode=0)
+        s.set_sigma_scratch(int(args.sigma_scratch_gib * (1 << 30)), mode=args.sigma_mode)
     s.build_state()
     for _ in range(args.warmup):
         s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
