@@ -135,6 +135,8 @@ def main() -> int:
         sig_ms += st["sigma_kernel_ms"]
     n_fwd, n_rev = st["rotate_launches"], st["reverse_launches"]
     log_records = st["log_records"]
+    scans = {"forward": st["fwd_slots_scanned"], "reverse": st["rev_slots_scanned"],
+             "reverse_shrinks": st["shrinks"], "growths": st["rehashes"]}
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -205,6 +207,7 @@ def main() -> int:
         "truncation_log_records": log_records,
         "sigma_partitions": st["sigma_partitions"],
         "table_slots_final": st["table_slots"],
+        "slots_scanned_per_step": scans,
         "det_updates_per_s_forward": round(det_updates / (fwd_ms / args.steps * 1e-3), 1) if fwd_ms else None,
         "energy": E0,
         **({"entropy_final": float(s.entropy(0)[-1])} if args.entropy else {}),

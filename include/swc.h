@@ -108,6 +108,9 @@ typedef struct {
                                 earlier sweeps (over 1/4 of the occupied slots) */
   int64_t checkpoints;       /* snapshots taken by the last gradient sweep */
   int64_t sigma_partitions;  /* partitions of the last pairing sigma (0: hash probes were used) */
+  int64_t shrinks;           /* rehashes into a smaller table during the last reverse sweep */
+  int64_t fwd_slots_scanned; /* sum over the last forward sweep's launches of the table size */
+  int64_t rev_slots_scanned; /* the same for the last reverse sweep */
 } swc_stats;
 
 /*

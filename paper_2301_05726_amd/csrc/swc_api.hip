@@ -197,6 +197,9 @@ struct swc_ctx {
   int grid_override = 0;       // SWC_GRID
   // two factors per launch at threshold 0 (SWC_FUSE=0 turns it off)
   bool fuse = true;
+  // the reverse sweep rehashes into a smaller table as its support shrinks
+  // (SWC_SHRINK=0 turns it off)
+  bool shrink = true;
   // entropy of every forward step (swc_track_entropy); sa.ea/eb are set
   // while it is on; ent_M: factors of the last tracked sweep (-1: none)
   bool entropy = false;
@@ -226,6 +229,9 @@ struct swc_ctx {
   int64_t fwd_launches = 0, rev_launches = 0;  // launches of the last sweeps (per-launch timing)
   int64_t rehashes = 0;        // table growths in the last forward sweep
   int64_t compactions = 0;     // tombstone-dropping rehashes at its start
+  int64_t shrinks = 0;         // rehashes into smaller tables in the last reverse sweep
+  // slots the sweep launches scanned (sum over launches of the table size)
+  int64_t fwd_slots = 0, rev_slots = 0;
   int64_t Mmax = 0;
   hipStream_t st = nullptr;
   char* ws = nullptr;
@@ -306,10 +312,10 @@ void set_table(swc_ctx* c, int r, uint64_t Hn) {
   c->grid = g;
 }
 
-// Occupancy above which a forward step stops the sweep for a growth: with at
-// most a doubling per step and a stop that takes effect two steps later, the
-// table never passes 4 x 0.225 = 90% occupancy.
-uint64_t occ_limit(const swc_ctx* c) { return c->tab.H < c->H ? c->tab.H / 40 * 9 : NO_LIMIT; }
+// Occupancy above which the guard after a forward step stops the sweep for a
+// growth: a step at most doubles the occupied slots, so the table never
+// passes 2 x 0.45 = 90% occupancy.
+uint64_t occ_limit(const swc_ctx* c) { return c->tab.H < c->H ? c->tab.H / 20 * 9 : NO_LIMIT; }
 
 // Smallest table, at least Hmin, that holds `need` occupied slots at <= 10% load.
 uint64_t table_size_for(const swc_ctx* c, uint64_t need, uint64_t Hmin) {
@@ -319,13 +325,14 @@ uint64_t table_size_for(const swc_ctx* c, uint64_t need, uint64_t Hmin) {
   return h;
 }
 
-// Rehash the current table into the other region, `Hn` slots.
-int rehash_to(swc_ctx* c, uint64_t Hn) {
+// Rehash the current table into the other region, `Hn` slots, keeping the
+// alive entries and the tombstones tagged 1..tag_max.
+int rehash_to(swc_ctx* c, uint64_t Hn, uint32_t tag_max = ~0u) {
   const int r = 1 - c->region;
   const Tab to{c->ws + c->lay.slots[r], c->ws + c->lay.aux[r], Hn};
   const Tab from = c->tab;
   dispatch(c, [&](auto* tp) -> int {
-    launch_rehash<std::remove_pointer_t<decltype(tp)>>(from, to, c->cnt, c->B, c->st);
+    launch_rehash<std::remove_pointer_t<decltype(tp)>>(from, to, c->cnt, c->B, tag_max, c->st);
     return SWC_OK;
   });
   SWC_HIP(hipGetLastError());
@@ -339,7 +346,7 @@ int rehash_to(swc_ctx* c, uint64_t Hn) {
 int grow_table(swc_ctx* c, uint64_t need) {
   if (c->persistent || c->tab.H >= c->H) return SWC_OK;
   uint64_t Hn = 2 * c->tab.H;
-  while (Hn < c->H && need > Hn / 40 * 9) Hn <<= 1;
+  while (Hn < c->H && need > Hn / 20 * 9) Hn <<= 1;
   return rehash_to(c, std::min(Hn, c->H));
 }
 
@@ -494,12 +501,16 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
       const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { issue_fwd<T>(c, k0, k1, thr, log_on, lim, cs); });
       if (rr) return rr;
       SWC_HIP(hipGraphLaunch(ex, c->st));
-      c->fwd_launches += fwd_launch_count(c, k0, k1, thr, lim);
+      const int64_t n = fwd_launch_count(c, k0, k1, thr, lim);
+      c->fwd_launches += n;
+      c->fwd_slots += n * static_cast<int64_t>(c->tab.H);
       return SWC_OK;
     }
     if (!c->ktiming) {
       issue_fwd<T>(c, k0, k1, thr, log_on, lim, c->st);
-      c->fwd_launches += fwd_launch_count(c, k0, k1, thr, lim);
+      const int64_t n = fwd_launch_count(c, k0, k1, thr, lim);
+      c->fwd_launches += n;
+      c->fwd_slots += n * static_cast<int64_t>(c->tab.H);
       return SWC_OK;
     }
     for (int64_t k = k0; k <= k1; ++k) {  // every launch timed: one step per launch
@@ -512,6 +523,7 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
                        c->st);
     }
     c->fwd_launches += k1 - k0 + 1;
+    c->fwd_slots += (k1 - k0 + 1) * static_cast<int64_t>(c->tab.H);
     return SWC_OK;
   });
 }
@@ -608,6 +620,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   c->ck_taken = 0;
   if (log_on && c->ck_n > 0) launch_zero_u64(c->ck_count, static_cast<uint64_t>(c->ck_n) * c->B, c->st);
   c->fwd_launches = 0;
+  c->fwd_slots = 0;
   if (c->persistent && c->tk_max == 0) {
     // one cooperative launch per range between checkpoints (the N_MAX / N_CUT
     // selection needs launches of its own after every step: per-step path)
@@ -629,6 +642,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       });
       if (r) return r;
       ++c->fwd_launches;
+      c->fwd_slots += (k1 - k + 1) * static_cast<int64_t>(c->tab.H);
       if (int rr = take_checkpoint(c, k1, M, log_on)) return rr;
       k = k1 + 1;
     }
@@ -653,6 +667,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       const uint32_t stop = c->hcnt[0].stop;
       const bool stopped = stop != ~0u;
       const int64_t next = stopped ? std::min<int64_t>(static_cast<int64_t>(stop), k1 + 1) : k1 + 1;
+      c->fwd_slots -= (k1 + 1 - next) * static_cast<int64_t>(c->tab.H);  // stopped steps scanned nothing
       bool full = false;
       for (int b = 0; b < c->B; ++b) full = full || (c->hcnt[b].flags & F_TABLE_FULL);
       if (full) break;  // reported by the caller's status check
@@ -660,12 +675,12 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       const double occ = static_cast<double>(max_occupancy(c));
       const int64_t done = next - k;
       // occupancy expected at the end of the next range: the last range's
-      // growth per step, extrapolated linearly with a factor-2 margin (a
-      // growth that outruns it is caught by the stop)
+      // growth per step, extrapolated linearly with a 1.5x margin (a growth
+      // that outruns it is caught by the guard's stop)
       double pred = occ;
       if (next <= M && prev_occ >= 0.0 && done > 0) {
         const int64_t nlen = fwd_range_end(c, next, M, log_on) - next + 1;
-        pred = occ + 2.0 * std::max(0.0, occ - prev_occ) * static_cast<double>(nlen) / static_cast<double>(done);
+        pred = occ + 1.5 * std::max(0.0, occ - prev_occ) * static_cast<double>(nlen) / static_cast<double>(done);
       }
       if (stopped) pred = std::max(pred, 2.0 * occ);
       if (stopped || pred > static_cast<double>(lim)) {
@@ -686,15 +701,46 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   return SWC_OK;
 }
 
+// Before the reverse sweep undoes steps hi, hi-1, ...: the entries it still
+// needs are the alive ones and the tombstones of steps <= hi (members that
+// undoing a later step removed, and tombstones of earlier sweeps, are dead
+// weight).  The reverse sweep never adds a slot, so when those fit a table of
+// at most half the size at <= 45% occupancy, they move into one: every later
+// step scans fewer slots.  The truncation log and the checkpoints locate
+// entries by determinant, so they stay valid.
+int shrink_table(swc_ctx* c, int64_t hi) {
+  if (!c->shrink || c->persistent || c->tab.H <= c->table_min) return SWC_OK;
+  const uint32_t tag_max = static_cast<uint32_t>(hi);
+  dispatch(c, [&](auto* tp) -> int {
+    launch_count_keep<std::remove_pointer_t<decltype(tp)>>(c->tab, c->cnt, c->B, tag_max, c->st);
+    return SWC_OK;
+  });
+  if (int r = read_counters(c)) return r;
+  uint64_t keep = 0;
+  for (int b = 0; b < c->B; ++b) keep = std::max<uint64_t>(keep, counter_total(c->hcnt[b], C_COPY));
+  uint64_t Hn = c->table_min;
+  while (Hn < c->tab.H && keep > Hn / 20 * 9) Hn <<= 1;
+  if (Hn > c->tab.H / 2) return SWC_OK;
+  const int64_t g = c->rehashes;
+  if (int r = rehash_to(c, Hn, tag_max)) return r;
+  c->rehashes = g;  // growths are counted for the forward sweep only
+  ++c->shrinks;
+  return SWC_OK;
+}
+
 // The adjoint sweep, steps M..1, in ranges that end where a chunk or a
 // checkpoint interval ends; after the range that reconstructs the state of a
 // checkpoint, the checkpoint's amplitudes are written back over it.
 // maxn[k]: largest number of truncation-log records of step k over the batch.
 int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>& maxn) {
   c->rev_launches = 0;
+  c->rev_slots = 0;
+  c->shrinks = 0;
   for (int64_t hi = M; hi >= 1;) {
     int64_t lo = chunk_begin(hi);
     if (c->ck_interval > 0) lo = std::max(lo, (hi - 1) / c->ck_interval * c->ck_interval + 1);
+    if (int rr = shrink_table(c, hi)) return rr;
+    const int64_t launches0 = c->rev_launches;
     const int r = dispatch(c, [&](auto* tp) -> int {
       using T = std::remove_pointer_t<decltype(tp)>;
       if (c->persistent) {
@@ -736,6 +782,7 @@ int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>
       return SWC_OK;
     });
     if (r) return r;
+    c->rev_slots += (c->rev_launches - launches0) * static_cast<int64_t>(c->tab.H);
     const int64_t j = ckpt_index(c, lo - 1, M);
     if (j >= 0) {
       dispatch(c, [&](auto* tp) -> int {
@@ -989,6 +1036,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   if (const char* e = std::getenv("SWC_KERNEL_TIMING")) c->ktiming = std::atoi(e) != 0;
   if (const char* e = std::getenv("SWC_GRAPH")) c->use_graph = std::atoi(e) != 0;
   if (const char* e = std::getenv("SWC_FUSE")) c->fuse = std::atoi(e) != 0;
+  if (const char* e = std::getenv("SWC_SHRINK")) c->shrink = std::atoi(e) != 0;
   for (auto& e : c->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
       swc_destroy(c);
@@ -1159,12 +1207,17 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
     c->revk_n = c->persistent ? c->rev_launches : M;
     c->revk_ms = sum_pairs(c, c->revk_n);
   }
-  for (int b = 0; b < c->B; ++b)
+  for (int b = 0; b < c->B; ++b) {
     if (c->hcnt[b].flags & (F_INCONSISTENT | F_TIMEOUT)) {
       reset_state(c);
       return fail(SWC_EDEVICE, (c->hcnt[b].flags & F_TIMEOUT) ? "grid barrier of a persistent sweep timed out"
                                                                : "inconsistent pair state in the reverse sweep");
     }
+    if (c->hcnt[b].flags & F_TABLE_FULL) {  // a rehash found no free slot (cannot happen at <= 45% occupancy)
+      reset_state(c);
+      return fail(SWC_ECAPACITY, "hash table full in the reverse sweep");
+    }
+  }
   if ((r = reset_state(c))) return r;
   return read_counters(c);
 }
@@ -1297,6 +1350,9 @@ int swc_get_stats(swc_ctx* c, swc_stats* out) {
   s.table_slots = static_cast<int64_t>(c->tab.H);
   s.rehashes = c->rehashes;
   s.compactions = c->compactions;
+  s.shrinks = c->shrinks;
+  s.fwd_slots_scanned = c->fwd_slots;
+  s.rev_slots_scanned = c->rev_slots;
   s.checkpoints = c->ck_taken;
   s.sigma_partitions = c->sig_parts;
   s.fwd_ms = c->fwd_ms;

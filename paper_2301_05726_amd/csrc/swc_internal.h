@@ -270,11 +270,15 @@ void launch_energy_final(Counters* cnt, double* E, int B, hipStream_t st);
 template <class T>
 void launch_lambda(const Tab& t, const Compact& cp, const Counters* cnt, int64_t nmax, int B, hipStream_t st);
 void launch_energy_begin(Counters* cnt, int B, hipStream_t st);
-// rehash every slot of `from` that is alive or a tombstone of the current
-// sweep into the empty table `to` (larger); the occupancy counter becomes the
-// number of slots copied
+// rehash every slot of `from` that is alive or a tombstone with a step tag in
+// [1, tag_max] into the table `to` (cleared first; larger when the forward
+// sweep grows, smaller when the reverse sweep shrinks); the occupancy counter
+// becomes the number of slots copied
 template <class T>
-void launch_rehash(const Tab& from, const Tab& to, Counters* cnt, int B, hipStream_t st);
+void launch_rehash(const Tab& from, const Tab& to, Counters* cnt, int B, uint32_t tag_max, hipStream_t st);
+// number of slots such a rehash would copy, into the C_COPY counters
+template <class T>
+void launch_count_keep(const Tab& t, Counters* cnt, int B, uint32_t tag_max, hipStream_t st);
 void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int64_t M, int B, hipStream_t st);
 // checkpoints: write the live entries into `sn` (count must be zero), and
 // write a snapshot's amplitudes back over the entries of the same keys

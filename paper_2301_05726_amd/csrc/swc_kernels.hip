@@ -473,19 +473,8 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
   const int lane = threadIdx.x & 63;
   const uint32_t K = static_cast<uint32_t>(k);
-  if (occ_lim != NO_LIMIT) {
-    // Growth guard.  A step adds at most one slot per live entry, so the
-    // occupancy at most doubles per step.  Wave 0 of block 0 compares the
-    // occupancy it sees (>= that after step k-1) with the limit and, above
-    // it, stops every step from k+1 on: a step that runs saw occupancy
-    // <= limit two steps earlier, so it ends at <= 4 x limit.
-    if (K >= cnt[0].stop) return;
-    if (blockIdx.x == 0 && threadIdx.x < 64) {
-      unsigned long long o = lane < CSH ? cnt[b].sh[lane].v[C_OCC] : 0ull;
-      o = wave_u64(o);
-      if (lane == 0 && o > occ_lim) atomicMin(&cnt[0].stop, K + 1u);
-    }
-  }
+  // a growth guard after an earlier step found the table too full for this one
+  if (occ_lim != NO_LIMIT && K >= cnt[0].stop) return;
   // this wave's statistics slot (read now, written back at the end)
   unsigned long long* wst = sa.ws + (static_cast<int64_t>(b) * sa.nws + (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6))) * WSTAT;
   const unsigned long long wold = lane < WSTAT ? wst[lane] : 0ull;
@@ -861,6 +850,22 @@ __device__ __forceinline__ void restore_step(const Tab& t, const LogArr& lg, con
     v.sl[s].meta = lg.meta[li];
     v.born(s) = lg.born[li];
     v.sl[s].amp = static_cast<const T*>(lg.amp)[li];
+  }
+}
+
+// Growth guard, launched after forward step next-1 while the table can still
+// grow.  A step adds at most one slot per live entry, so it at most doubles
+// the occupied slots.  The occupancy read here is complete (the step has
+// finished); when some batch member's is above the limit, step `next` and all
+// later ones return at once (every block sees the same flag), and the host
+// grows the table and runs them again.  A step that runs therefore started at
+// <= limit and ends at <= 2 x limit.
+__global__ void k_grow_guard(Counters* cnt, int B, uint64_t occ_lim, uint32_t next) {
+  const int lane = threadIdx.x & 63;
+  for (int b = 0; b < B; ++b) {
+    unsigned long long o = lane < CSH ? cnt[b].sh[lane].v[C_OCC] : 0ull;
+    o = wave_u64(o);
+    if (lane == 0 && o > occ_lim) atomicMin(&cnt[0].stop, next);
   }
 }
 
@@ -1827,18 +1832,26 @@ __global__ void k_rehash_begin(Counters* cnt) {
   for (int i = threadIdx.x; i < CSH; i += blockDim.x) cnt[blockIdx.x].sh[i].v[C_COPY] = 0ull;
 }
 
-// Alive entries and tombstones of the current sweep (tag != 0; the reverse
-// sweep still needs their values) move to the new table; older tombstones are
-// dropped.  Keys are unique, so every copy claims its own slot.
+// Which entries a rehash keeps: alive ones, and tombstones with a step tag in
+// [1, tag_max] (the reverse sweep still needs their values).  Tombstones of
+// earlier sweeps (tag 0) are dropped; so, in the reverse sweep, are the
+// members that undoing a step above tag_max has removed (tag > tag_max).
+__device__ __forceinline__ bool keep_entry(uint64_t key, uint32_t meta, uint32_t tag_max) {
+  if (key == EMPTY_KEY) return false;
+  if (!(meta & DEAD)) return true;
+  const uint32_t tag = meta & TAG;
+  return tag != 0u && tag <= tag_max;
+}
+
+// Keys are unique, so every copy claims its own slot.
 template <class T>
-__global__ void k_rehash(Tab from, Tab to, Counters* cnt) {
+__global__ void k_rehash(Tab from, Tab to, Counters* cnt, uint32_t tag_max) {
   const int b = blockIdx.y;
   const View<T> vf = view<T>(from, b), vt = view<T>(to, b);
   unsigned long long n = 0;
   for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < from.H; s += gridDim.x * blockDim.x) {
     const Slot<T> x = vf.sl[s];
-    if (x.key == EMPTY_KEY) continue;
-    if ((x.meta & DEAD) && (x.meta & TAG) == 0u) continue;
+    if (!keep_entry(x.key, x.meta, tag_max)) continue;
     const int64_t d = claim_slot(vt.sl, to.H, x.key, mix64(x.key) & (to.H - 1));
     if (d < 0) {
       atomicOr(&cnt[b].flags, F_TABLE_FULL);
@@ -1849,6 +1862,20 @@ __global__ void k_rehash(Tab from, Tab to, Counters* cnt) {
     vt.born(d) = vf.born(s);
     vt.lam(d) = vf.lam(s);
     ++n;
+  }
+  n = wave_u64(n);
+  if ((threadIdx.x & 63) == 0 && n) atomicAdd(&cnt[b].sh[cshard()].v[C_COPY], n);
+}
+
+// entries a rehash with this tag_max would keep, into the C_COPY counters
+template <class T>
+__global__ void k_count_keep(Tab t, Counters* cnt, uint32_t tag_max) {
+  const int b = blockIdx.y;
+  const View<T> v = view<T>(t, b);
+  unsigned long long n = 0;
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
+    const Slot<T> x = v.sl[s];
+    n += keep_entry(x.key, x.meta, tag_max) ? 1ull : 0ull;
   }
   n = wave_u64(n);
   if ((threadIdx.x & 63) == 0 && n) atomicAdd(&cnt[b].sh[cshard()].v[C_COPY], n);
@@ -1994,6 +2021,8 @@ void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, 
                 hipStream_t st) {
   hipLaunchKernelGGL(k_fwd<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all,
                      log_on, occ_lim);
+  if (occ_lim != NO_LIMIT)
+    hipLaunchKernelGGL(k_grow_guard, dim3(1), dim3(64), 0, st, cnt, B, occ_lim, static_cast<uint32_t>(k + 1));
 }
 
 template <class T>
@@ -2081,11 +2110,17 @@ void launch_energy_begin(Counters* cnt, int B, hipStream_t st) {
 }
 
 template <class T>
-void launch_rehash(const Tab& from, const Tab& to, Counters* cnt, int B, hipStream_t st) {
+void launch_rehash(const Tab& from, const Tab& to, Counters* cnt, int B, uint32_t tag_max, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(to.H, BLK, 8192), B), dim3(BLK), 0, st, to);
   hipLaunchKernelGGL(k_rehash_begin, dim3(B), dim3(64), 0, st, cnt);
-  hipLaunchKernelGGL(k_rehash<T>, dim3(grid_for(from.H, BLK, 8192), B), dim3(BLK), 0, st, from, to, cnt);
+  hipLaunchKernelGGL(k_rehash<T>, dim3(grid_for(from.H, BLK, 8192), B), dim3(BLK), 0, st, from, to, cnt, tag_max);
   hipLaunchKernelGGL(k_rehash_end, dim3(B), dim3(64), 0, st, cnt);
+}
+
+template <class T>
+void launch_count_keep(const Tab& t, Counters* cnt, int B, uint32_t tag_max, hipStream_t st) {
+  hipLaunchKernelGGL(k_rehash_begin, dim3(B), dim3(64), 0, st, cnt);
+  hipLaunchKernelGGL(k_count_keep<T>, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t, cnt, tag_max);
 }
 
 void launch_energy_final(Counters* cnt, double* E, int B, hipStream_t st) {
@@ -2431,7 +2466,8 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
                                           hipStream_t);                                                            \
   template hipError_t launch_rev_sweep<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&,       \
                                           Counters*, const LogArr&, int, int, Sync*, int, int, hipStream_t);      \
-  template void launch_rehash<T>(const Tab&, const Tab&, Counters*, int, hipStream_t);                          \
+  template void launch_rehash<T>(const Tab&, const Tab&, Counters*, int, uint32_t, hipStream_t);                \
+  template void launch_count_keep<T>(const Tab&, Counters*, int, uint32_t, hipStream_t);                        \
   template void launch_fwd2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \
                                int, int, hipStream_t);                                                             \
   template void launch_rev2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \

@@ -44,6 +44,9 @@ class Stats(ctypes.Structure):
         ("sigma_kernel_ms", ctypes.c_double), ("partner_hits", ctypes.c_int64),
         ("rehashes", ctypes.c_int64), ("compactions", ctypes.c_int64), ("checkpoints", ctypes.c_int64),
         ("sigma_partitions", ctypes.c_int64),
+        ("shrinks", ctypes.c_int64),
+        ("fwd_slots_scanned", ctypes.c_int64),
+        ("rev_slots_scanned", ctypes.c_int64),
     ]
 
 

@@ -236,7 +236,8 @@ def test_table_growth_exact(swc, orc, monkeypatch, case, prec):
     say(f"  grown: rehashes={grown[0]['rehashes']}/{grown[1]['rehashes']} table={grown[0]['table_slots']} "
         f"fixed: rehashes={fixed[0]['rehashes']} table={fixed[0]['table_slots']}")
     assert grown[0]["rehashes"] >= 2 and grown[1]["rehashes"] >= 2
-    assert fixed[0]["rehashes"] == 0 and fixed[0]["table_slots"] == cap
+    assert grown[1]["shrinks"] >= 1  # the reverse sweep moved into smaller tables
+    assert fixed[0]["rehashes"] == 0 and fixed[0]["table_slots"] == cap and fixed[1]["shrinks"] == 0
     assert grown[0]["n_live"] == fixed[0]["n_live"]
     for x, y in zip(grown[2][0], fixed[2][0]):
         assert x.tobytes() == y.tobytes()
@@ -270,6 +271,61 @@ def test_table_growth_batch(swc, orc, monkeypatch):
         assert nc == 0
         assert abs(grown[4][b] - E_ref) <= TOL[1]["E"]
         assert np.max(np.abs(grown[5][b] - g_ref)) <= TOL[1]["g"]
+
+
+SHRINK_CASES = [
+    ("q16", 8, 4, 0.1, 104, None, 0.0, 0),
+    ("q16_thr_ckpt", 8, 4, 0.1, 105, None, 1e-4, 16),
+    ("q20_pre_thr", 10, 5, 0.05, 107, 300, 1e-5, 0),
+    ("q20_pre_thr_ckpt", 10, 5, 0.05, 107, 300, 1e-5, 64),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", SHRINK_CASES, ids=[c[0] for c in SHRINK_CASES])
+def test_reverse_sweep_shrink_bitwise(swc, orc, monkeypatch, case, prec):
+    """The adjoint sweep rehashes into smaller tables as undoing steps removes
+    members (tombstones of later steps dropped, log records and checkpoints
+    found by determinant): energy and gradient are bit-identical to a sweep
+    that keeps its table, fewer slots are scanned, and both match the oracle."""
+    name, n_orb, n_occ, sigma, seed, nf, thr, ck = case
+    say(f"[case] shrink {name} prec={prec} thr={thr} ckpt={ck}")
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed, nf)
+    nq = 2 * n_orb
+    cap = capacity_for(n_orb, n_occ)
+    out = {}
+    for shrink in ("0", "1"):
+        monkeypatch.setenv("SWC_TABLE_MIN", "64")
+        monkeypatch.setenv("SWC_SHRINK", shrink)
+        s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=1, max_factors=exc.shape[0])
+        if ck:
+            s.set_checkpoints(ck, cap)
+        s.build_state()
+        reps = []
+        for _ in range(2):
+            E, g = s.energy_and_grad(theta, exc, thr, h1, h2)
+            reps.append((E.cpu().numpy().tobytes(), g.cpu().numpy().tobytes()))
+            st = s.stats()
+        assert reps[0] == reps[1]
+        # the state after the call is |Psi_0> again
+        d, a = s.get_state(0)
+        assert d.tolist() == [hf] and a.tolist() == [1.0]
+        out[shrink] = (reps[0], st)
+        s.close()
+    st0, st1 = out["0"][1], out["1"][1]
+    say(f"  shrinks {st1['shrinks']}, reverse slots scanned {st0['rev_slots_scanned']} -> "
+        f"{st1['rev_slots_scanned']}, log records {st1['log_records']}")
+    assert st0["shrinks"] == 0 and st1["shrinks"] >= 1
+    assert st1["rev_slots_scanned"] < st0["rev_slots_scanned"]
+    assert st0["fwd_slots_scanned"] == st1["fwd_slots_scanned"] > 0
+    assert out["0"][0] == out["1"][0]
+    orc.set_nearcut_window(1e-5)
+    E_ref, g_ref, nc = orc.energy_and_grad(nq, [hf], [1.0], exc, theta[0], thr, h1, h2)
+    assert nc == 0
+    E = np.frombuffer(out["1"][0][0], dtype=np.float64)[0]
+    g = np.frombuffer(out["1"][0][1], dtype=np.float64)
+    assert abs(E - E_ref) <= TOL[prec]["E"]
+    assert np.max(np.abs(g - g_ref)) <= TOL[prec]["g"]
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
