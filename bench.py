@@ -88,6 +88,10 @@ def main() -> int:
     ap.add_argument("--sigma-scratch-gib", type=float, default=0.0,
                     help="device scratch for sigma by pairing (0: hash probes)")
     ap.add_argument("--sigma-mode", type=int, default=0, help="pairing: 0 auto, 1 always, 2 never")
+    ap.add_argument("--checkpoint-interval", type=int, default=0,
+                    help="snapshot psi every K factors of the gradient sweep (0: off)")
+    ap.add_argument("--checkpoint-entries-log2", type=int, default=24,
+                    help="live determinants per snapshot the checkpoint buffer holds, 2^c")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -119,6 +123,8 @@ def main() -> int:
         s.track_entropy(True)
     if args.sigma_scratch_gib > 0:
         s.set_sigma_scratch(int(args.sigma_scratch_gib * (1 << 30)), mode=args.sigma_mode)
+    if args.checkpoint_interval > 0:
+        s.set_checkpoints(args.checkpoint_interval, 1 << args.checkpoint_entries_log2)
     s.build_state()
     for _ in range(args.warmup):
         s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
@@ -135,6 +141,7 @@ def main() -> int:
         sig_ms += st["sigma_kernel_ms"]
     n_fwd, n_rev = st["rotate_launches"], st["reverse_launches"]
     log_records = st["log_records"]
+    ck_taken = st["checkpoints"]
     scans = {"forward": st["fwd_slots_scanned"], "reverse": st["rev_slots_scanned"],
              "reverse_shrinks": st["shrinks"], "growths": st["rehashes"]}
     torch.cuda.synchronize()
@@ -198,7 +205,9 @@ def main() -> int:
                          + f", theta~N(0,{wl.theta_sigma}), threshold {wl.threshold}, "
                          f"capacity 2^{int(np.log2(cap))}" + (f", batch {B}" if B > 1 else "")
                          + (f", N_MAX/N_CUT {topk[0]}/{topk[1]}" if topk else "")
-                         + (", entropy tracked" if args.entropy else "")),
+                         + (", entropy tracked" if args.entropy else "")
+                         + (f", checkpoints every {args.checkpoint_interval} factors"
+                            if args.checkpoint_interval > 0 else "")),
             "amplitudes": args.prec, "reductions": "f64 (exact fixed point)",
             "n_det_final": n_live,
         },
@@ -208,6 +217,7 @@ def main() -> int:
         "sigma_partitions": st["sigma_partitions"],
         "table_slots_final": st["table_slots"],
         "slots_scanned_per_step": scans,
+        "checkpoints_per_step": ck_taken,
         "det_updates_per_s_forward": round(det_updates / (fwd_ms / args.steps * 1e-3), 1) if fwd_ms else None,
         "energy": E0,
         **({"entropy_final": float(s.entropy(0)[-1])} if args.entropy else {}),
@@ -217,6 +227,8 @@ def main() -> int:
     if not args.no_fd:
         # same-GPU FP64 forward + central finite differences (h = 1e-5)
         sf = swc.Solver(nq, wl.n_occ, wl.n_occ, cap, prec=swc.FP64, batch=1, max_factors=M, device=dev)
+        if args.sigma_scratch_gib > 0:  # the same sigma method as the adjoint run
+            sf.set_sigma_scratch(int(args.sigma_scratch_gib * (1 << 30)), mode=args.sigma_mode)
         sf.build_state()
         idx = synth.fd_subset(M, args.fd_params, 3000 + wl.cfg)
         h = 1e-5

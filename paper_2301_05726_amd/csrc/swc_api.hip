@@ -312,10 +312,10 @@ void set_table(swc_ctx* c, int r, uint64_t Hn) {
   c->grid = g;
 }
 
-// Occupancy above which the guard after a forward step stops the sweep for a
-// growth: a step at most doubles the occupied slots, so the table never
-// passes 2 x 0.45 = 90% occupancy.
-uint64_t occ_limit(const swc_ctx* c) { return c->tab.H < c->H ? c->tab.H / 20 * 9 : NO_LIMIT; }
+// Occupancy above which a forward step stops the sweep for a growth: with at
+// most a doubling per step and a stop that takes effect two steps later, the
+// table never passes 4 x 0.225 = 90% occupancy.
+uint64_t occ_limit(const swc_ctx* c) { return c->tab.H < c->H ? c->tab.H / 40 * 9 : NO_LIMIT; }
 
 // Smallest table, at least Hmin, that holds `need` occupied slots at <= 10% load.
 uint64_t table_size_for(const swc_ctx* c, uint64_t need, uint64_t Hmin) {
@@ -346,7 +346,7 @@ int rehash_to(swc_ctx* c, uint64_t Hn, uint32_t tag_max = ~0u) {
 int grow_table(swc_ctx* c, uint64_t need) {
   if (c->persistent || c->tab.H >= c->H) return SWC_OK;
   uint64_t Hn = 2 * c->tab.H;
-  while (Hn < c->H && need > Hn / 20 * 9) Hn <<= 1;
+  while (Hn < c->H && need > Hn / 40 * 9) Hn <<= 1;
   return rehash_to(c, std::min(Hn, c->H));
 }
 
@@ -675,12 +675,12 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       const double occ = static_cast<double>(max_occupancy(c));
       const int64_t done = next - k;
       // occupancy expected at the end of the next range: the last range's
-      // growth per step, extrapolated linearly with a 1.5x margin (a growth
-      // that outruns it is caught by the guard's stop)
+      // growth per step, extrapolated linearly with a factor-2 margin (a
+      // growth that outruns it is caught by the stop)
       double pred = occ;
       if (next <= M && prev_occ >= 0.0 && done > 0) {
         const int64_t nlen = fwd_range_end(c, next, M, log_on) - next + 1;
-        pred = occ + 1.5 * std::max(0.0, occ - prev_occ) * static_cast<double>(nlen) / static_cast<double>(done);
+        pred = occ + 2.0 * std::max(0.0, occ - prev_occ) * static_cast<double>(nlen) / static_cast<double>(done);
       }
       if (stopped) pred = std::max(pred, 2.0 * occ);
       if (stopped || pred > static_cast<double>(lim)) {

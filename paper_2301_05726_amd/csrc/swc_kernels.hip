@@ -473,8 +473,19 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
   const int lane = threadIdx.x & 63;
   const uint32_t K = static_cast<uint32_t>(k);
-  // a growth guard after an earlier step found the table too full for this one
-  if (occ_lim != NO_LIMIT && K >= cnt[0].stop) return;
+  if (occ_lim != NO_LIMIT) {
+    // Growth guard.  A step adds at most one slot per live entry, so the
+    // occupancy at most doubles per step.  Wave 0 of block 0 compares the
+    // occupancy it sees (>= that after step k-1) with the limit and, above
+    // it, stops every step from k+1 on: a step that runs saw occupancy
+    // <= limit two steps earlier, so it ends at <= 4 x limit.
+    if (K >= cnt[0].stop) return;
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+      unsigned long long o = lane < CSH ? cnt[b].sh[lane].v[C_OCC] : 0ull;
+      o = wave_u64(o);
+      if (lane == 0 && o > occ_lim) atomicMin(&cnt[0].stop, K + 1u);
+    }
+  }
   // this wave's statistics slot (read now, written back at the end)
   unsigned long long* wst = sa.ws + (static_cast<int64_t>(b) * sa.nws + (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6))) * WSTAT;
   const unsigned long long wold = lane < WSTAT ? wst[lane] : 0ull;
@@ -850,22 +861,6 @@ __device__ __forceinline__ void restore_step(const Tab& t, const LogArr& lg, con
     v.sl[s].meta = lg.meta[li];
     v.born(s) = lg.born[li];
     v.sl[s].amp = static_cast<const T*>(lg.amp)[li];
-  }
-}
-
-// Growth guard, launched after forward step next-1 while the table can still
-// grow.  A step adds at most one slot per live entry, so it at most doubles
-// the occupied slots.  The occupancy read here is complete (the step has
-// finished); when some batch member's is above the limit, step `next` and all
-// later ones return at once (every block sees the same flag), and the host
-// grows the table and runs them again.  A step that runs therefore started at
-// <= limit and ends at <= 2 x limit.
-__global__ void k_grow_guard(Counters* cnt, int B, uint64_t occ_lim, uint32_t next) {
-  const int lane = threadIdx.x & 63;
-  for (int b = 0; b < B; ++b) {
-    unsigned long long o = lane < CSH ? cnt[b].sh[lane].v[C_OCC] : 0ull;
-    o = wave_u64(o);
-    if (lane == 0 && o > occ_lim) atomicMin(&cnt[0].stop, next);
   }
 }
 
@@ -2021,8 +2016,6 @@ void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, 
                 hipStream_t st) {
   hipLaunchKernelGGL(k_fwd<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all,
                      log_on, occ_lim);
-  if (occ_lim != NO_LIMIT)
-    hipLaunchKernelGGL(k_grow_guard, dim3(1), dim3(64), 0, st, cnt, B, occ_lim, static_cast<uint32_t>(k + 1));
 }
 
 template <class T>
