@@ -88,6 +88,8 @@ def main() -> int:
     ap.add_argument("--sigma-scratch-gib", type=float, default=0.0,
                     help="device scratch for sigma by pairing (0: hash probes)")
     ap.add_argument("--sigma-mode", type=int, default=0, help="pairing: 0 auto, 1 always, 2 never")
+    ap.add_argument("--fp64-check", action="store_true",
+                    help="also run one FP64 energy_and_grad and report its differences from the timed path")
     ap.add_argument("--checkpoint-interval", type=int, default=0,
                     help="snapshot psi every K factors of the gradient sweep (0: off)")
     ap.add_argument("--checkpoint-entries-log2", type=int, default=24,
@@ -126,19 +128,28 @@ def main() -> int:
     if args.checkpoint_interval > 0:
         s.set_checkpoints(args.checkpoint_interval, 1 << args.checkpoint_entries_log2)
     s.build_state()
-    for _ in range(args.warmup):
+
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    tw = time.perf_counter()
+    for i in range(args.warmup):
         s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
+        torch.cuda.synchronize()
+        progress(f"warmup {i + 1}/{args.warmup} done, {time.perf_counter() - tw:.1f} s")
     torch.cuda.synchronize()
     # HIP events recorded by the library on its stream bracket each sweep
     # (forward, reverse) and the sigma kernel inside every timed step
     fwd_ms = rev_ms = sig_ms = 0.0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         E, g = s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
         st = s.stats()
         fwd_ms += st["fwd_ms"]
         rev_ms += st["rev_ms"]
         sig_ms += st["sigma_kernel_ms"]
+        if args.steps <= 20 or (i + 1) % 20 == 0:
+            progress(f"step {i + 1}/{args.steps} done")
     n_fwd, n_rev = st["rotate_launches"], st["reverse_launches"]
     log_records = st["log_records"]
     ck_taken = st["checkpoints"]
@@ -154,6 +165,7 @@ def main() -> int:
     # forward sweep statistics of one step (identical every step)
     s.apply_ucc(theta, p.exc, wl.threshold)
     st = s.stats()
+    progress("statistics sweep done")
     n_live = st["n_live"]
     det_updates = st["det_updates"]
     s.build_state()
@@ -224,6 +236,28 @@ def main() -> int:
         "roofline": roofline,
     }
 
+    if args.fp64_check and prec == swc.FP32:
+        # the same evaluation with FP64 amplitudes: the FP32 path's error at this depth
+        s.close()
+        s = swc.Solver(nq, wl.n_occ, wl.n_occ, cap, prec=swc.FP64, batch=B, max_factors=M, log_capacity=logcap,
+                       device=dev)
+        if args.sigma_scratch_gib > 0:
+            s.set_sigma_scratch(int(args.sigma_scratch_gib * (1 << 30)), mode=args.sigma_mode)
+        s.build_state()
+        c0 = time.perf_counter()
+        E64, g64 = s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
+        torch.cuda.synchronize()
+        c1 = time.perf_counter()
+        progress("FP64 evaluation done")
+        E64, g64 = E64.cpu().numpy(), g64.cpu().numpy()
+        out["fp64_check"] = {
+            "seconds": round(c1 - c0, 3),
+            "max_abs_dE": float(np.max(np.abs(E.cpu().numpy() - E64))),
+            "max_abs_dg": float(np.max(np.abs(g.cpu().numpy() - g64))),
+            "rms_dg": float(np.sqrt(np.mean((g.cpu().numpy() - g64) ** 2))),
+            "max_abs_g": float(np.max(np.abs(g64))),
+        }
+
     if not args.no_fd:
         # same-GPU FP64 forward + central finite differences (h = 1e-5)
         sf = swc.Solver(nq, wl.n_occ, wl.n_occ, cap, prec=swc.FP64, batch=1, max_factors=M, device=dev)
@@ -237,6 +271,7 @@ def main() -> int:
         sf.energy(h1, h2)
         sf.build_state()
         torch.cuda.synchronize()
+        progress("finite differences: warm-up evaluation done")
         fd = np.empty(len(idx))
         f0 = time.perf_counter()
         for q, k in enumerate(idx):
@@ -247,6 +282,7 @@ def main() -> int:
                 sf.build_state()
                 sf.apply_ucc(tp, p.exc, wl.threshold)
                 ev.append(sf.energy(h1, h2).item())
+                progress(f"finite differences: parameter {q + 1}/{len(idx)}, sign {sgn:+.0f} done")
             fd[q] = (ev[0] - ev[1]) / (2 * h)
         torch.cuda.synchronize()
         f1 = time.perf_counter()
