@@ -283,6 +283,23 @@ __device__ __forceinline__ void ent_flush(const StepArr& sa, int b, int k, Fx a,
   }
 }
 
+// The SCAN_U slots s0, s0 + stride, ... of one pass of a sweep step (slots
+// past the table read as empty).
+template <class T>
+__device__ __forceinline__ void load_pass(const View<T>& v, uint64_t H, uint64_t s0, uint64_t stride,
+                                          Slot<T>* out) {
+#pragma unroll
+  for (int u = 0; u < SCAN_U; ++u) {
+    const uint64_t s = s0 + u * stride;
+    if (s < H) {
+      out[u] = v.sl[s];
+    } else {
+      out[u].key = EMPTY_KEY;
+      out[u].meta = DEAD;
+    }
+  }
+}
+
 // Renormalisation scale before step k (1-based): S_{k-1}, from S_{k-2} and the
 // removed weight of step k-1.  Every wave computes it (its first SH lanes read
 // the shards) with identical arithmetic: no LDS and no block barrier.
@@ -490,6 +507,18 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   unsigned long long* wst = sa.ws + (static_cast<int64_t>(b) * sa.nws + (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6))) * WSTAT;
   const unsigned long long wold = lane < WSTAT ? wst[lane] : 0ull;
 
+  // SCAN_U slots per lane per pass.  The first pass's slots are requested
+  // before the scale is reduced, and each pass requests the next pass's slots
+  // before it probes partners, so a lane keeps two passes of loads in flight.
+  // (A slot read early is safe for the same reason a partner's is: whatever
+  // other lanes write during the step keeps its presence at the start of
+  // the step, and the owner of its pair, unchanged.)
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const uint64_t pass = SCAN_U * stride;
+  uint64_t s0 = blockIdx.x * blockDim.x + threadIdx.x;
+  Slot<T> nxt[SCAN_U];
+  load_pass<T>(v, H, s0, stride, nxt);
+
   // threshold 0 never truncates, so the scale is not needed
   const bool trunc = thr > 0.0;
   const double S = trunc ? wave_scale(sa, b, k) : 1.0;
@@ -552,21 +581,12 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   };
 
   Fx ent_a = fx_zero(), ent_b = fx_zero();  // entropy sums (when tracked)
-  // SCAN_U slots per lane per pass, their loads (and then the home slots of
-  // their partners) in flight together
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t s0 = blockIdx.x * blockDim.x + threadIdx.x; s0 < H; s0 += SCAN_U * stride) {
+  for (; s0 < H; s0 += pass) {
     Slot<T> mes[SCAN_U];
 #pragma unroll
-    for (int u = 0; u < SCAN_U; ++u) {
-      const uint64_t s = s0 + u * stride;
-      if (s < H) {
-        mes[u] = v.sl[s];
-      } else {
-        mes[u].key = EMPTY_KEY;
-        mes[u].meta = DEAD;
-      }
-    }
+    for (int u = 0; u < SCAN_U; ++u) mes[u] = nxt[u];
+    if (s0 + pass < H) load_pass<T>(v, H, s0 + pass, stride, nxt);
+    // the home slots of this pass's partners are then loaded together
     uint64_t home[SCAN_U];
     Slot<T> hv[SCAN_U];
     bool act[SCAN_U];
@@ -702,21 +722,17 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
   for (int i = 0; i < 7; ++i) r.c[i] = 0;
   unsigned int flags = 0;
 
-  // SCAN_U slots per lane per pass, their loads (and then the home slots of
-  // their partners) in flight together
+  // SCAN_U slots per lane per pass, the next pass's slots requested before
+  // this pass probes partners (as in the forward step)
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t s0 = blockIdx.x * blockDim.x + threadIdx.x; s0 < H; s0 += SCAN_U * stride) {
+  const uint64_t pass = SCAN_U * stride;
+  Slot<T> nxt[SCAN_U];
+  load_pass<T>(v, H, blockIdx.x * blockDim.x + threadIdx.x, stride, nxt);
+  for (uint64_t s0 = blockIdx.x * blockDim.x + threadIdx.x; s0 < H; s0 += pass) {
     Slot<T> mes[SCAN_U];
 #pragma unroll
-    for (int u = 0; u < SCAN_U; ++u) {
-      const uint64_t s = s0 + u * stride;
-      if (s < H) {
-        mes[u] = v.sl[s];
-      } else {
-        mes[u].key = EMPTY_KEY;
-        mes[u].meta = DEAD;
-      }
-    }
+    for (int u = 0; u < SCAN_U; ++u) mes[u] = nxt[u];
+    if (s0 + pass < H) load_pass<T>(v, H, s0 + pass, stride, nxt);
     uint64_t home[SCAN_U];
     Slot<T> hv[SCAN_U];
     T hl[SCAN_U], lms[SCAN_U];

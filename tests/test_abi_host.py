@@ -28,6 +28,18 @@ def test_library_exports_every_declared_symbol():
     assert sorted(names) == sorted(swc.EXPORTS)
 
 
+def test_stats_binding_matches_header():
+    """The ctypes mirror of swc_stats has the header's fields, in order and
+    with the same C types (a mismatch would shift every later field)."""
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{(.*?)\} swc_stats;", text, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    decl = re.findall(r"\b(int64_t|double)\s+(\w+)\s*;", body)
+    ctype = {"int64_t": ctypes.c_int64, "double": ctypes.c_double}
+    assert [(n, ctype[t]) for t, n in decl] == list(swc.Stats._fields_)
+    assert ctypes.sizeof(swc.Stats) == 8 * len(decl)
+
+
 def test_workspace_bytes_validation():
     assert swc.workspace_bytes(20, 1 << 17, swc.FP32, 1, 875) > 0
     assert swc.workspace_bytes(20, 1 << 17, swc.FP64, 1, 875) > swc.workspace_bytes(20, 1 << 17, swc.FP32, 1, 875)
