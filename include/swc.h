@@ -49,6 +49,16 @@
  * nothing throws across the ABI.  After SWC_ECAPACITY, SWC_EEMPTY or
  * SWC_EDEVICE the state held by the context is undefined until the next
  * swc_build_state; the context can always be destroyed.
+ *
+ * Environment (read by swc_create; results are bit-identical in every
+ * setting): SWC_SWEEP=persistent runs each sweep as cooperative launches with
+ * grid barriers instead of one launch per step; SWC_GRAPH=0 launches steps
+ * directly instead of replaying captured graphs; SWC_FUSE=0 applies one
+ * factor per launch at threshold 0; SWC_TABLE_MIN=n sets the smallest table
+ * (default 2^18 slots); SWC_SHRINK=0 keeps the table size in the adjoint
+ * sweep; SWC_PROGRESS=1 waits after each range of steps and reports it on
+ * stderr; SWC_KERNEL_TIMING=1 times every step launch (one step per launch);
+ * SWC_GRID=n caps the sweep launches at n blocks (tuning).
  */
 #ifndef SWC_H
 #define SWC_H

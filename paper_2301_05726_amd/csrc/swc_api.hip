@@ -263,6 +263,9 @@ struct swc_ctx {
   std::vector<Counters> hcnt;
   // per-step sweeps replayed from captured hipGraphs (SWC_GRAPH=0 disables)
   bool use_graph = true;
+  // SWC_PROGRESS=1: after each range of steps, wait for it and report it on
+  // stderr (long sweeps at large sizes; off by default: it adds a host wait)
+  bool progress = false;
   hipStream_t cap_st = nullptr;
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
   // optional per-launch timing (SWC_KERNEL_TIMING=1)
@@ -567,6 +570,16 @@ int take_checkpoint(swc_ctx* c, int64_t k, int64_t M, int log_on) {
   return SWC_OK;
 }
 
+// SWC_PROGRESS: wait for the work issued so far and report `done` of `total` steps
+int report_progress(swc_ctx* c, const char* what, int64_t done, int64_t total) {
+  if (!c->progress) return SWC_OK;
+  SWC_HIP(hipStreamSynchronize(c->st));
+  std::fprintf(stderr, "[swc] %s sweep: %lld of %lld steps done\n", what, static_cast<long long>(done),
+               static_cast<long long>(total));
+  std::fflush(stderr);
+  return SWC_OK;
+}
+
 uint64_t max_occupancy(const swc_ctx* c) {
   uint64_t o = 0;
   for (int b = 0; b < c->B; ++b) o = std::max<uint64_t>(o, counter_total(c->hcnt[b], C_OCC));
@@ -657,6 +670,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       if (r) return r;
       if (lim == NO_LIMIT) {
         if ((r = take_checkpoint(c, k1, M, log_on))) return r;
+        if ((r = report_progress(c, "forward", k1, M))) return r;
         resumed = false;
         k = k1 + 1;
         continue;
@@ -672,6 +686,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       for (int b = 0; b < c->B; ++b) full = full || (c->hcnt[b].flags & F_TABLE_FULL);
       if (full) break;  // reported by the caller's status check
       if (next == k1 + 1 && (r = take_checkpoint(c, k1, M, log_on))) return r;
+      if ((r = report_progress(c, "forward", next - 1, M))) return r;
       const double occ = static_cast<double>(max_occupancy(c));
       const int64_t done = next - k;
       // occupancy expected at the end of the next range: the last range's
@@ -783,6 +798,7 @@ int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>
     });
     if (r) return r;
     c->rev_slots += (c->rev_launches - launches0) * static_cast<int64_t>(c->tab.H);
+    if (int rr = report_progress(c, "reverse", M - lo + 1, M)) return rr;
     const int64_t j = ckpt_index(c, lo - 1, M);
     if (j >= 0) {
       dispatch(c, [&](auto* tp) -> int {
@@ -1035,6 +1051,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   }
   if (const char* e = std::getenv("SWC_KERNEL_TIMING")) c->ktiming = std::atoi(e) != 0;
   if (const char* e = std::getenv("SWC_GRAPH")) c->use_graph = std::atoi(e) != 0;
+  if (const char* e = std::getenv("SWC_PROGRESS")) c->progress = std::atoi(e) != 0;
   if (const char* e = std::getenv("SWC_FUSE")) c->fuse = std::atoi(e) != 0;
   if (const char* e = std::getenv("SWC_SHRINK")) c->shrink = std::atoi(e) != 0;
   for (auto& e : c->ev) {
