@@ -202,23 +202,43 @@ __device__ __forceinline__ int64_t find_slot(const Slot<T>* __restrict__ sl, uin
 }
 
 // find_slot with the home slot already loaded (`v` = sl[home]), so several
-// probes can have their first loads in flight together.
+// probes can have their first loads in flight together.  Past the home slot
+// the probe loads PG slots at a time and checks them in order (the same
+// answer as one slot at a time: the loads are only issued together), so a
+// long probe sequence costs one round trip per PG slots rather than per slot;
+// the longest sequence in a launch sets the launch's duration.
+constexpr int PG = 4;
+
 template <class T>
 __device__ __forceinline__ int64_t find_slot_from(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key,
                                                   uint64_t home, Slot<T> v, uint64_t* first_free, Slot<T>* out) {
   const uint64_t mask = H - 1;
+  if (v.key == key) {
+    *out = v;
+    return static_cast<int64_t>(home);
+  }
+  if (v.key == EMPTY_KEY) {
+    *first_free = home;
+    return -1;
+  }
   uint64_t s = home;
-  for (uint64_t i = 0; i < H; ++i) {
-    if (v.key == key) {
-      *out = v;
-      return static_cast<int64_t>(s);
+  for (uint64_t i = 1; i < H; i += PG) {
+    Slot<T> w[PG];
+#pragma unroll
+    for (int j = 0; j < PG; ++j) w[j] = sl[(s + 1 + j) & mask];
+#pragma unroll
+    for (int j = 0; j < PG; ++j) {
+      const uint64_t t = (s + 1 + j) & mask;
+      if (w[j].key == key) {
+        *out = w[j];
+        return static_cast<int64_t>(t);
+      }
+      if (w[j].key == EMPTY_KEY) {
+        *first_free = t;
+        return -1;
+      }
     }
-    if (v.key == EMPTY_KEY) {
-      *first_free = s;
-      return -1;
-    }
-    s = (s + 1) & mask;
-    v = sl[s];
+    s = (s + PG) & mask;
   }
   *first_free = H;
   return -1;
