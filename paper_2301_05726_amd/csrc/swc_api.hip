@@ -253,7 +253,13 @@ struct swc_ctx {
   hipEvent_t ev[8] = {};
   double fwd_ms = 0, energy_ms = 0, rev_ms = 0;
   int64_t log_records = 0;
-  int grid = 1;
+  int grid = 1;  // blocks of a sweep launch: one per 256 slots, up to MAX_SWEEP_BLOCKS
+  // The one-factor step kernels are latency-bound while the table is small:
+  // they run fastest with as many lanes as can be resident at once (one wave
+  // round, the SCAN_U slots of a lane loaded together), and no more.
+  // res_fwd / res_rev: resident blocks of k_fwd / k_rev on the whole device.
+  int grid_fs = 1, grid_rs = 1;
+  int res_fwd = 0, res_rev = 0;
   // persistent (cooperative) sweeps, one launch per sweep: opt-in with
   // SWC_SWEEP=persistent (per-step launches are faster on MI355X: a
   // device-wide barrier needs agent-scope fences in every block)
@@ -313,6 +319,8 @@ void set_table(swc_ctx* c, int r, uint64_t Hn) {
   int g = grid_for(Hn, 256, MAX_SWEEP_BLOCKS);
   if (c->grid_override > 0) g = std::min(c->grid_override, g);
   c->grid = g;
+  c->grid_fs = c->res_fwd > 0 ? std::min(g, c->res_fwd) : g;
+  c->grid_rs = c->res_rev > 0 ? std::min(g, c->res_rev) : g;
 }
 
 // Occupancy above which a forward step stops the sweep for a growth: with at
@@ -466,7 +474,7 @@ void issue_fwd(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint6
       k += 2;
     } else {
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, c->grid, st);
+                    log_on, lim, c->B, c->grid_fs, st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid, st);
       k += 1;
@@ -484,7 +492,7 @@ int64_t issue_rev(swc_ctx* c, int64_t hi, int64_t lo, bool fuse, hipStream_t st)
       launch_rev2<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k - 1), c->B, c->grid, st);
       k -= 2;
     } else {
-      launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid, st);
+      launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid_rs, st);
       k -= 1;
     }
   }
@@ -519,7 +527,7 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
     for (int64_t k = k0; k <= k1; ++k) {  // every launch timed: one step per launch
       (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, c->grid, c->st);
+                    log_on, lim, c->B, c->grid_fs, c->st);
       (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid,
@@ -789,7 +797,8 @@ int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>
       }
       for (int64_t k = hi; k >= lo; --k) {
         if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
-        launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid, c->st);
+        launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid_rs,
+                      c->st);
         if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
         if (maxn[k]) launch_log_restore<T>(c->tab, c->lg, c->sa, static_cast<int>(k), c->B, maxn[k], c->st);
       }
@@ -1048,6 +1057,12 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     c->grid_fwd = std::min(g, bf * ncu / batch);
     c->grid_rev = std::min(g, br * ncu / batch);
     if (c->grid_fwd < 1 || c->grid_rev < 1) c->persistent = false;
+    // resident step blocks, shared by the batch members (grid.y = batch)
+    const int sf = prec == SWC_FP32 ? coop_blocks_per_cu<float>(2) : coop_blocks_per_cu<double>(2);
+    const int sr = prec == SWC_FP32 ? coop_blocks_per_cu<float>(3) : coop_blocks_per_cu<double>(3);
+    c->res_fwd = std::max(1, sf * ncu / batch);
+    c->res_rev = std::max(1, sr * ncu / batch);
+    set_table(c, 0, c->H);  // step grids with the resident limits
   }
   if (const char* e = std::getenv("SWC_KERNEL_TIMING")) c->ktiming = std::atoi(e) != 0;
   if (const char* e = std::getenv("SWC_GRAPH")) c->use_graph = std::atoi(e) != 0;

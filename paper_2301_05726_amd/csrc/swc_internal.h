@@ -165,6 +165,8 @@ struct StepArr {
   double* ent;
 };
 constexpr int WSTAT = 8;
+// table slots each lane of a one-factor sweep step loads per pass
+constexpr int SCAN_U = 4;
 constexpr int ES = 16;
 
 // N_MAX / N_CUT truncation: radix selection state of one batch member.  The
@@ -216,7 +218,8 @@ void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t 
 void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, int fold_only,
                       hipStream_t st);
 void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st);
-// co-resident blocks per CU of the persistent forward (which=0) / reverse (1) sweep
+// co-resident blocks per CU of the persistent forward (which=0) / reverse (1)
+// sweep, and of the one-factor forward (2) / reverse (3) step kernels
 template <class T>
 int coop_blocks_per_cu(int which);
 template <class T>

@@ -26,7 +26,6 @@
 namespace swc {
 
 constexpr int BLK = 256;
-constexpr int SCAN_U = 4;  // table slots each lane of a sweep step loads per pass
 
 // ---------------------------------------------------------------------------
 // table views
@@ -2003,9 +2002,14 @@ void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st) {
 template <class T>
 int coop_blocks_per_cu(int which) {
   int nb = 0;
-  const hipError_t e = which == 0
-                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_sweep<T>, BLK, 0)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev_sweep<T>, BLK, 0);
+  hipError_t e = hipErrorInvalidValue;
+  switch (which) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_sweep<T>, BLK, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev_sweep<T>, BLK, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd<T>, BLK, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev<T>, BLK, 0); break;
+    default: break;
+  }
   return e == hipSuccess ? nb : 0;
 }
 
