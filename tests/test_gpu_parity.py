@@ -273,6 +273,34 @@ def test_table_growth_batch(swc, orc, monkeypatch):
         assert np.max(np.abs(grown[5][b] - g_ref)) <= TOL[1]["g"]
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_launch_grid_bitwise(swc, monkeypatch, prec):
+    """The number of blocks of the sweep launches (resident-sized by default,
+    capped at 16 or 3 here, so every lane takes many passes) changes no bit
+    of the state, energy or gradient: every sum is an exact fixed-point sum
+    and every pair has one owner, wherever it sits in the launch."""
+    say(f"[case] grid caps q16_thr prec={prec}")
+    h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 105)
+    thr = 1e-4
+    cap = capacity_for(8, 4)
+    out = []
+    for g in (None, "16", "3"):
+        monkeypatch.delenv("SWC_GRID", raising=False)
+        monkeypatch.setenv("SWC_TABLE_MIN", "64")
+        if g:
+            monkeypatch.setenv("SWC_GRID", g)
+        s = swc.Solver(16, 4, 4, cap, prec=prec, batch=1, max_factors=exc.shape[0])
+        s.build_state()
+        s.apply_ucc(theta, exc, thr)
+        d, a = s.get_state(0)
+        st = s.stats()
+        E, gr = s.energy_and_grad(theta, exc, thr, h1, h2)
+        out.append((d.tobytes(), a.tobytes(), st["det_updates"], E.cpu().numpy().tobytes(),
+                    gr.cpu().numpy().tobytes()))
+        s.close()
+    assert out[0] == out[1] == out[2]
+
+
 SHRINK_CASES = [
     ("q16", 8, 4, 0.1, 104, None, 0.0, 0),
     ("q16_thr_ckpt", 8, 4, 0.1, 105, None, 1e-4, 16),
