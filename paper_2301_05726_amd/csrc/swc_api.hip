@@ -1051,15 +1051,15 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
       delete c;
       return fail(SWC_EDEVICE, "cannot query the device");
     }
-    const int bf = prec == SWC_FP32 ? coop_blocks_per_cu<float>(0) : coop_blocks_per_cu<double>(0);
-    const int br = prec == SWC_FP32 ? coop_blocks_per_cu<float>(1) : coop_blocks_per_cu<double>(1);
+    const int bf = prec == SWC_FP32 ? resident_blocks_per_cu<float>(0) : resident_blocks_per_cu<double>(0);
+    const int br = prec == SWC_FP32 ? resident_blocks_per_cu<float>(1) : resident_blocks_per_cu<double>(1);
     // co-resident blocks shared by the batch members (grid.y = batch)
     c->grid_fwd = std::min(g, bf * ncu / batch);
     c->grid_rev = std::min(g, br * ncu / batch);
     if (c->grid_fwd < 1 || c->grid_rev < 1) c->persistent = false;
     // resident step blocks, shared by the batch members (grid.y = batch)
-    const int sf = prec == SWC_FP32 ? coop_blocks_per_cu<float>(2) : coop_blocks_per_cu<double>(2);
-    const int sr = prec == SWC_FP32 ? coop_blocks_per_cu<float>(3) : coop_blocks_per_cu<double>(3);
+    const int sf = prec == SWC_FP32 ? resident_blocks_per_cu<float>(2) : resident_blocks_per_cu<double>(2);
+    const int sr = prec == SWC_FP32 ? resident_blocks_per_cu<float>(3) : resident_blocks_per_cu<double>(3);
     c->res_fwd = std::max(1, sf * ncu / batch);
     c->res_rev = std::max(1, sr * ncu / batch);
     set_table(c, 0, c->H);  // step grids with the resident limits

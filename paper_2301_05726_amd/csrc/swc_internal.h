@@ -221,7 +221,7 @@ void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st);
 // co-resident blocks per CU of the persistent forward (which=0) / reverse (1)
 // sweep, and of the one-factor forward (2) / reverse (3) step kernels
 template <class T>
-int coop_blocks_per_cu(int which);
+int resident_blocks_per_cu(int which);
 template <class T>
 hipError_t launch_fwd_sweep(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa,
                             Counters* cnt, const LogArr& lg, int k0, int k1, double thr, int prune_first, int log_on,

@@ -2000,7 +2000,7 @@ void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st) {
 }
 
 template <class T>
-int coop_blocks_per_cu(int which) {
+int resident_blocks_per_cu(int which) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (which) {
@@ -2493,7 +2493,7 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
   template void launch_lambda<T>(const Tab&, const Compact&, const Counters*, int64_t, int, hipStream_t);        \
   template void launch_sigma<T>(const Tab&, const Compact&, const Counters*, const double*, const double*, int,   \
                                 int64_t, int, int, hipStream_t);                                                   \
-  template int coop_blocks_per_cu<T>(int);                                                                         \
+  template int resident_blocks_per_cu<T>(int);                                                                    \
   template hipError_t launch_fwd_sweep<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&,       \
                                           Counters*, const LogArr&, int, int, double, int, int, Sync*, int, int,   \
                                           hipStream_t);                                                            \
