@@ -754,7 +754,7 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
     if (s0 + pass < H) load_pass<T>(v, H, s0 + pass, stride, nxt);
     uint64_t home[SCAN_U];
     Slot<T> hv[SCAN_U];
-    T hl[SCAN_U], lms[SCAN_U];
+    T lms[SCAN_U];
     bool act[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
@@ -775,13 +775,13 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
         continue;
       }
       act[u] = true;
-      // the adjoint value of this member (only members of a pair need it),
-      // and the partner's home slot with the adjoint value there: the
-      // partner usually sits in its home slot
+      // the adjoint value of this member (only members of a pair need it)
+      // and the partner's home slot; the partner's adjoint value is loaded
+      // only by the pair's owner once the partner is found (a speculative
+      // load there cost more traffic than the round trip it saved)
       lms[u] = v.lam_pre(s0 + u * stride);
       home[u] = mix64(me.key ^ pm) & (H - 1);
       hv[u] = v.sl[home[u]];
-      hl[u] = v.lam_pre(home[u]);
     }
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
@@ -813,10 +813,7 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
         xp = me.amp;
         yp = hU ? pv.amp : T(0);
         lL = dead ? T(0) : v.lam_fin(me, lms[u]);
-        lU = (hU && !(mU & DEAD))
-                 ? (static_cast<uint64_t>(ps) == home[u] ? v.lam_fin(pv, hl[u])
-                                                         : v.lam_of(pv, static_cast<uint64_t>(ps)))
-                 : T(0);
+        lU = (hU && !(mU & DEAD)) ? v.lam_of(pv, static_cast<uint64_t>(ps)) : T(0);
       } else {
         sU = static_cast<int64_t>(s); mU = m; hU = true;
         sL = ps; mL = pv.meta; hL = false;
