@@ -166,7 +166,7 @@ struct StepArr {
 };
 constexpr int WSTAT = 8;
 // table slots each lane of a one-factor sweep step loads per pass
-constexpr int SCAN_U = 4;
+constexpr int SCAN_U = 2;
 constexpr int ES = 16;
 
 // N_MAX / N_CUT truncation: radix selection state of one batch member.  The
