@@ -259,7 +259,11 @@ struct swc_ctx {
   // round, the SCAN_U slots of a lane loaded together), and no more.
   // res_fwd / res_rev: resident blocks of k_fwd / k_rev on the whole device.
   int grid_fs = 1, grid_rs = 1;
-  int res_fwd = 0, res_rev = 0;
+  int res_fwd = 0, res_rev = 0, res_fwd5 = 0;
+  // forward steps use the five-wave build of k_fwd when the table takes more
+  // than one pass of the resident lanes (a latency-bound one-pass table runs
+  // faster without its register spills)
+  int fwd_wide = 0;
   // persistent (cooperative) sweeps, one launch per sweep: opt-in with
   // SWC_SWEEP=persistent (per-step launches are faster on MI355X: a
   // device-wide barrier needs agent-scope fences in every block)
@@ -319,7 +323,10 @@ void set_table(swc_ctx* c, int r, uint64_t Hn) {
   int g = grid_for(Hn, 256, MAX_SWEEP_BLOCKS);
   if (c->grid_override > 0) g = std::min(c->grid_override, g);
   c->grid = g;
-  c->grid_fs = c->res_fwd > 0 ? std::min(g, c->res_fwd) : g;
+  c->fwd_wide = (c->res_fwd > 0 && c->res_fwd5 > 0 &&
+                 Hn > static_cast<uint64_t>(c->res_fwd) * 256 * SCAN_U) ? 1 : 0;
+  const int rf = c->fwd_wide ? c->res_fwd5 : c->res_fwd;
+  c->grid_fs = rf > 0 ? std::min(g, rf) : g;
   c->grid_rs = c->res_rev > 0 ? std::min(g, c->res_rev) : g;
 }
 
@@ -474,7 +481,7 @@ void issue_fwd(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint6
       k += 2;
     } else {
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, c->grid_fs, st);
+                    log_on, lim, c->B, c->grid_fs, c->fwd_wide, st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid, st);
       k += 1;
@@ -527,7 +534,7 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
     for (int64_t k = k0; k <= k1; ++k) {  // every launch timed: one step per launch
       (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, c->grid_fs, c->st);
+                    log_on, lim, c->B, c->grid_fs, c->fwd_wide, c->st);
       (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid,
@@ -1060,8 +1067,10 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     // resident step blocks, shared by the batch members (grid.y = batch)
     const int sf = prec == SWC_FP32 ? resident_blocks_per_cu<float>(2) : resident_blocks_per_cu<double>(2);
     const int sr = prec == SWC_FP32 ? resident_blocks_per_cu<float>(3) : resident_blocks_per_cu<double>(3);
+    const int s5 = prec == SWC_FP32 ? resident_blocks_per_cu<float>(4) : resident_blocks_per_cu<double>(4);
     c->res_fwd = std::max(1, sf * ncu / batch);
     c->res_rev = std::max(1, sr * ncu / batch);
+    c->res_fwd5 = std::max(1, s5 * ncu / batch);
     set_table(c, 0, c->H);  // step grids with the resident limits
   }
   if (const char* e = std::getenv("SWC_KERNEL_TIMING")) c->ktiming = std::atoi(e) != 0;

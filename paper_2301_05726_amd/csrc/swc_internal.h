@@ -219,7 +219,8 @@ void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const 
                       hipStream_t st);
 void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st);
 // co-resident blocks per CU of the persistent forward (which=0) / reverse (1)
-// sweep, and of the one-factor forward (2) / reverse (3) step kernels
+// sweep, and of the one-factor forward (2; 4: the five-wave build) / reverse
+// (3) step kernels
 template <class T>
 int resident_blocks_per_cu(int which);
 template <class T>
@@ -232,11 +233,12 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
                             hipStream_t st);
 // occ_lim: a step that sees a member's occupancy above it stops the steps
 // after the next one (Counters::stop) so the host can grow the table;
-// NO_LIMIT for a table at full capacity
+// NO_LIMIT for a table at full capacity.  wide: the kernel built for five
+// resident waves per SIMD (tables scanned in many passes)
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
-                hipStream_t st);
+                int wide, hipStream_t st);
 template <class T>
 void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 int k, int B, int grid, hipStream_t st);

@@ -154,17 +154,21 @@ __device__ __forceinline__ unsigned long long wave_u64(unsigned long long v) {
   return v;
 }
 
-// block-wide sums of one Fx and up to 7 counters; result valid in thread 0
+// block-wide sums of one Fx and up to 7 counters (32-bit: per-launch counts
+// of one state stay below 2^32); result valid in thread 0
 struct Red {
   Fx f;
-  unsigned long long c[7];
+  unsigned int c[7];
 };
 
 __device__ __forceinline__ Red block_reduce(Red r) {
   __shared__ Red part[BLK / 64];
   r.f = wave_fx(r.f);
 #pragma unroll
-  for (int i = 0; i < 7; ++i) r.c[i] = wave_u64(r.c[i]);
+  for (int i = 0; i < 7; ++i) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) r.c[i] += __shfl_xor(r.c[i], o, 64);
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) part[w] = r;
   __syncthreads();
@@ -498,7 +502,7 @@ __global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy
 // Truncation (Methods section): a member whose |S x'| < thr is removed; its
 // tombstone keeps x' for the reverse sweep.  The removed weight feeds the
 // renormalisation scale of the next step.
-template <class T>
+template <class T, bool ENT>
 __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict__ fac,
                                          const Trig* __restrict__ trig, int64_t ld, const StepArr& sa, Counters* cnt,
                                          const LogArr& lg, int k, double thr, int prune_all, int log_on,
@@ -628,7 +632,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       if (!lower && !upper) {
         if (prune_all && !(fabs(S * static_cast<double>(me.amp)) >= thr)) {
           kill(s0 + u * stride, me.amp);
-        } else if (sa.ea) {
+        } else if (ENT) {
           ent_add(ent_a, ent_b, static_cast<double>(me.amp));
         }
         continue;
@@ -665,7 +669,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       const T yn = y + fmaT<T>(y, cm1, ss * x);
       const bool keepx = fabs(S * static_cast<double>(xn)) >= thr;
       const bool keepy = fabs(S * static_cast<double>(yn)) >= thr;
-      if (sa.ea) {  // the pair's members that stay live after the step
+      if (ENT) {  // the pair's members that stay live after the step
         if (keepx) ent_add(ent_a, ent_b, static_cast<double>(xn));
         if (keepy) ent_add(ent_a, ent_b, static_cast<double>(yn));
       }
@@ -686,7 +690,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   }
 
   if (flags) atomicOr(&cnt[b].flags, flags);
-  if (sa.ea) ent_flush(sa, b, k, ent_a, ent_b);
+  if (ENT) ent_flush(sa, b, k, ent_a, ent_b);
   // wave totals: statistics go to the wave's private slot (plain stores, no
   // block barrier); removed weight, when there is any, to a sharded atomic
   unsigned int c[7];
@@ -896,12 +900,18 @@ __device__ __forceinline__ void restore_step(const Tab& t, const LogArr& lg, con
   }
 }
 
-// one launch per step
-template <class T>
-__global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
-                                             int64_t ld, StepArr sa, Counters* cnt, LogArr lg, int k, double thr,
-                                             int prune_all, int log_on, uint64_t occ_lim) {
-  fwd_step<T>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on, occ_lim);
+// one launch per step.  ENT: the entropy sums are tracked (a separate
+// instantiation keeps their registers out of the common case).  MINW: waves
+// per SIMD the register allocation must allow; 5 (a few registers spill) for
+// tables scanned in many passes, where more resident waves hide more memory
+// latency, 1 (no constraint) for tables one resident wave round covers,
+// where each wave's own latency counts.
+template <class T, bool ENT, int MINW>
+__global__ __launch_bounds__(BLK, MINW) void k_fwd(Tab t, const FacMask* __restrict__ fac,
+                                                   const Trig* __restrict__ trig, int64_t ld, StepArr sa,
+                                                   Counters* cnt, LogArr lg, int k, double thr, int prune_all,
+                                                   int log_on, uint64_t occ_lim) {
+  fwd_step<T, ENT>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on, occ_lim);
 }
 
 template <class T>
@@ -1301,7 +1311,10 @@ __global__ __launch_bounds__(BLK) void k_fwd_sweep(Tab t, const FacMask* __restr
   const unsigned int nblk = gridDim.x * gridDim.y;
   unsigned int epoch = 0;
   for (int k = k0; k <= k1; ++k) {
-    fwd_step<T>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_first && k == k0, log_on, NO_LIMIT);
+    if (sa.ea)
+      fwd_step<T, true>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_first && k == k0, log_on, NO_LIMIT);
+    else
+      fwd_step<T, false>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_first && k == k0, log_on, NO_LIMIT);
     grid_barrier(sy, ++epoch * nblk);
   }
 }
@@ -2003,8 +2016,9 @@ int resident_blocks_per_cu(int which) {
   switch (which) {
     case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_sweep<T>, BLK, 0); break;
     case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev_sweep<T>, BLK, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd<T>, BLK, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd<T, false, 1>, BLK, 0); break;
     case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev<T>, BLK, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd<T, false, 5>, BLK, 0); break;
     default: break;
   }
   return e == hipSuccess ? nb : 0;
@@ -2050,9 +2064,16 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
-                hipStream_t st) {
-  hipLaunchKernelGGL(k_fwd<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all,
-                     log_on, occ_lim);
+                int wide, hipStream_t st) {
+  if (sa.ea)
+    hipLaunchKernelGGL((k_fwd<T, true, 1>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
+                       prune_all, log_on, occ_lim);
+  else if (wide)
+    hipLaunchKernelGGL((k_fwd<T, false, 5>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
+                       prune_all, log_on, occ_lim);
+  else
+    hipLaunchKernelGGL((k_fwd<T, false, 1>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
+                       prune_all, log_on, occ_lim);
 }
 
 template <class T>
@@ -2481,7 +2502,7 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
                                       hipStream_t);                                                                \
   template void launch_sweep_begin<T>(const Tab&, const StepArr&, Counters*, int64_t, int, hipStream_t);          \
   template void launch_fwd<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*,        \
-                              const LogArr&, int, double, int, int, uint64_t, int, int, hipStream_t);              \
+                              const LogArr&, int, double, int, int, uint64_t, int, int, int, hipStream_t);         \
   template void launch_rev<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,   \
                               int, int, hipStream_t);                                                              \
   template void launch_log_restore<T>(const Tab&, const LogArr&, const StepArr&, int, int, uint32_t,              \
