@@ -57,6 +57,16 @@ def measured_traffic(workload: str, prec: str) -> dict:
     return vals if sha == sources_sha() else {}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def reverse_bytes(st: dict, tsz: int) -> float:
     """Algorithmic bytes of one reverse sweep, counted on the forward's
     pairs (the reverse visits the same pairs): 8 B key per visited
@@ -162,11 +172,16 @@ def main() -> int:
     E0 = float(E[0].item())
     g0 = g.cpu().numpy()[0]
 
-    # forward sweep statistics of one step (identical every step)
+    # forward sweep statistics of one step (identical every step), with the
+    # live count of every step
+    s.track_live(True)
     s.apply_ucc(theta, p.exc, wl.threshold)
     st = s.stats()
     progress("statistics sweep done")
     n_live = st["n_live"]
+    traj = s.live_counts(0)  # live determinants before each factor, then after the last
+    marks = sorted({int(round(M * q / 8)) for q in range(9)})
+    live_traj = {"factor": marks, "n_live": [int(traj[k]) for k in marks], "max": int(traj.max())}
     det_updates = st["det_updates"]
     s.build_state()
 
@@ -228,6 +243,7 @@ def main() -> int:
         "truncation_log_records": log_records,
         "sigma_partitions": st["sigma_partitions"],
         "table_slots_final": st["table_slots"],
+        "live_trajectory": live_traj,
         "slots_scanned_per_step": scans,
         "checkpoints_per_step": ck_taken,
         "det_updates_per_s_forward": round(det_updates / (fwd_ms / args.steps * 1e-3), 1) if fwd_ms else None,
@@ -315,6 +331,7 @@ def main() -> int:
                 "sample": f"one full E+grad evaluation of {wl.name} ({M} factors), single-threaded std::map FP64",
                 "seconds": round(c1 - c0, 3),
                 "host_cpus": os.cpu_count(),
+                "host_cpu_model": cpu_model(),
             }
             out["parity_vs_oracle"] = {"abs_dE": abs(E0 - E_ref), "max_abs_dg": float(np.max(np.abs(g0 - g_ref)))}
         else:
@@ -332,6 +349,7 @@ def main() -> int:
                           "single-threaded std::map FP64",
                 "seconds": round(c1 - c0, 3),
                 "host_cpus": os.cpu_count(),
+                "host_cpu_model": cpu_model(),
             }
 
     s.close()

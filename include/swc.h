@@ -248,6 +248,19 @@ int swc_set_sigma_scratch(swc_ctx* ctx, void* buffer, size_t bytes, int mode);
 int swc_get_entropy(swc_ctx* ctx, int b, double* S, int64_t n);
 
 /*
+ * State size along the circuit.  swc_track_live(ctx, 1) makes every later
+ * forward sweep (swc_apply_ucc, swc_energy_and_grad) count the live
+ * determinants of each step (one more sharded atomic per wave and step; off
+ * by default).  swc_get_live_counts: n[k] (k = 0..M-1) is the number of live
+ * determinants of batch member b when step k+1 of the last forward sweep
+ * began, after the truncation of step k; n[M] is the number after the last
+ * step.  n is a host array of len >= M + 1; the sum of n[0..M-1] is the
+ * sweep's det-updates.  SWC_ESTATE if the last forward sweep did not count.
+ */
+int swc_track_live(swc_ctx* ctx, int on);
+int swc_get_live_counts(swc_ctx* ctx, int b, int64_t* n, int64_t len);
+
+/*
  * Copy the current state of batch member b to host arrays sorted by
  * determinant (amplitudes normalised, in double).  *n_out receives the
  * number of determinants; SWC_ECAPACITY if it exceeds `cap` (nothing copied).

@@ -48,6 +48,7 @@ def lib():
         L.orc_set_nearcut_window.restype = None
         L.orc_apply_inverse.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, P, P, I64, P]
         L.orc_entropy_trajectory.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, D, P]
+        L.orc_live_trajectory.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, D, P]
         L.orc_set_topk.argtypes = [I64, I64]
         _lib = L
     return _lib
@@ -112,6 +113,17 @@ def apply_ucc(nq, dets0, amps0, exc, theta, thr=0.0, cap=None):
             continue
         _chk(r)
         return do[: n.value].copy(), ao[: n.value].copy(), nc.value, du.value
+
+
+def live_trajectory(nq, dets0, amps0, exc, theta, thr=0.0):
+    """Determinants held initially and after each factor: int64 [M+1]."""
+    d, a = _init(dets0, amps0)
+    e = np.ascontiguousarray(exc, dtype=np.int8)
+    t = np.ascontiguousarray(theta, dtype=np.float64)
+    M = e.shape[0]
+    out = np.zeros(M + 1, np.int64)
+    _chk(lib().orc_live_trajectory(nq, _p(d), _p(a), len(d), _p(e), _p(t), M, float(thr), _p(out)))
+    return out
 
 
 def entropy_trajectory(nq, dets0, amps0, exc, theta, thr=0.0):

@@ -494,6 +494,28 @@ int orc_entropy_trajectory(int nq, const uint64_t* dets0, const double* amps0, i
   return OK;
 }
 
+// Number of determinants the sparse state holds: initially, and after each
+// factor with its truncation (Eq. 3 applied in order): n_out[0..M].
+int orc_live_trajectory(int nq, const uint64_t* dets0, const double* amps0, int64_t n0, const int8_t* exc,
+                        const double* theta, int64_t M, double thr, int64_t* n_out) {
+  int r = check_common(nq, theta, M, thr);
+  if (r) return r;
+  std::vector<Exc> ex;
+  if ((r = parse_excitations(exc, M, nq, ex))) return r;
+  State psi;
+  if ((r = load_state(nq, dets0, amps0, n0, psi))) return r;
+  n_out[0] = static_cast<int64_t>(psi.size());
+  State phi;
+  for (int64_t k = 0; k < M; ++k) {
+    apply_factor(ex[k], std::cos(theta[k]), std::sin(theta[k]), psi, phi);
+    double nu = 1.0;
+    if ((r = prune_renorm(phi, thr, &nu, nullptr)) < 0) return r;
+    psi.swap(phi);
+    n_out[k + 1] = static_cast<int64_t>(psi.size());
+  }
+  return OK;
+}
+
 // Energy <psi|H|psi>/<psi|psi> of a given state; mode 0 literal, 1 Slater-Condon.
 int orc_energy(int mode, int n_orb, const double* h1, const double* h2, const uint64_t* dets,
                const double* amps, int64_t n, double* E) {

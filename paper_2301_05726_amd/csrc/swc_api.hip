@@ -41,7 +41,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
   size_t slots[2], aux[2];
   size_t lkey, lmeta, lborn, lamp;
-  size_t scale, pw, pcnt, gacc, logn, logoff, rmax, ws, ea, eb, ent;
+  size_t scale, pw, pcnt, gacc, logn, logoff, rmax, ws, ea, eb, ent, pvis;
   size_t ckey, camp, cslot, csig;
   size_t cnt, fac, trig, init_d, init_a, sync, topk;
   size_t total;
@@ -85,6 +85,7 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   l.ea = take(BS * ES * sizeof(Fx3));
   l.eb = take(BS * ES * sizeof(Fx3));
   l.ent = take(BS * 8);
+  l.pvis = take(BS * SH * 4);
   l.ckey = take(BH * 8);
   l.camp = take(BH * 8);
   l.cslot = take(BH * 4);
@@ -206,6 +207,11 @@ struct swc_ctx {
   Fx3* ent_ea = nullptr;
   Fx3* ent_eb = nullptr;
   int64_t ent_M = -1;
+  // live count before every forward step (swc_track_live): sa.pvis is set
+  // while it is on; live_M: factors of the last tracked sweep (-1: none)
+  bool live = false;
+  uint32_t* live_pvis = nullptr;
+  int64_t live_M = -1;
   // sigma of doubles by pairing (swc_set_sigma_scratch): caller's scratch;
   // mode 0 auto, 1 always, 2 never (probes)
   char* sig_buf = nullptr;
@@ -616,6 +622,8 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   c->sa.ea = c->entropy ? c->ent_ea : nullptr;
   c->sa.eb = c->entropy ? c->ent_eb : nullptr;
   c->ent_M = -1;
+  c->live_M = -1;
+  c->sa.pvis = c->live ? c->live_pvis : nullptr;
   dispatch(c, [&](auto* tp) -> int {
     launch_sweep_begin<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, c->cnt, M, c->B, c->st);
     return SWC_OK;
@@ -727,6 +735,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
     launch_entropy_final(c->sa, M, c->B, c->st);
     c->ent_M = M;
   }
+  if (c->live) c->live_M = M;
   SWC_HIP(hipGetLastError());
   return SWC_OK;
 }
@@ -1030,7 +1039,8 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
                   reinterpret_cast<unsigned long long*>(w + l.ws),
                   static_cast<int64_t>(max_waves(c->H)),
                   c->Mmax + 1,
-                  nullptr, nullptr, reinterpret_cast<double*>(w + l.ent)};
+                  nullptr, nullptr, reinterpret_cast<double*>(w + l.ent), nullptr};
+  c->live_pvis = reinterpret_cast<uint32_t*>(w + l.pvis);
   c->ent_ea = reinterpret_cast<Fx3*>(w + l.ea);
   c->ent_eb = reinterpret_cast<Fx3*>(w + l.eb);
   c->cp = Compact{reinterpret_cast<uint64_t*>(w + l.ckey), reinterpret_cast<double*>(w + l.camp),
@@ -1329,6 +1339,12 @@ int swc_track_entropy(swc_ctx* c, int on) {
   return SWC_OK;
 }
 
+int swc_track_live(swc_ctx* c, int on) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  c->live = on != 0;
+  return SWC_OK;
+}
+
 int swc_get_entropy(swc_ctx* c, int b, double* S, int64_t n) {
   if (!c) return fail(SWC_EINVAL, "null context");
   if (c->ent_M < 0) return fail(SWC_ESTATE, "entropy was not tracked in the last forward sweep");
@@ -1336,6 +1352,32 @@ int swc_get_entropy(swc_ctx* c, int b, double* S, int64_t n) {
   if (n < c->ent_M + 1) return fail(SWC_EINVAL, "output holds fewer than M + 1 values");
   SWC_HIP(hipMemcpyAsync(S, c->sa.ent + b * c->sa.stride, 8 * (c->ent_M + 1), hipMemcpyDeviceToHost, c->st));
   SWC_HIP(hipStreamSynchronize(c->st));
+  return SWC_OK;
+}
+
+int swc_get_live_counts(swc_ctx* c, int b, int64_t* n, int64_t len) {
+  if (!c) return fail(SWC_EINVAL, "null context");
+  if (c->live_M < 0) return fail(SWC_ESTATE, "live counts were not tracked in the last forward sweep");
+  if (b < 0 || b >= c->B || !n) return fail(SWC_EINVAL, "bad batch index or output");
+  const int64_t M = c->live_M;
+  if (len < M + 1) return fail(SWC_EINVAL, "output holds fewer than M + 1 values");
+  if (M == 0) {  // no step ran: the state the sweep started from is still there
+    if (int r = read_counters(c)) return r;
+    n[0] = static_cast<int64_t>(counter_total(c->hcnt[b], C_LIVE));
+    return SWC_OK;
+  }
+  // the SH shards of member b: (b*SH + sh)*stride + k, one block
+  const int64_t stride = c->sa.stride;
+  std::vector<uint32_t> h(static_cast<size_t>(SH * stride));
+  SWC_HIP(hipMemcpyAsync(h.data(), c->live_pvis + static_cast<int64_t>(b) * SH * stride, 4 * h.size(),
+                         hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipStreamSynchronize(c->st));
+  for (int64_t k = 1; k <= M; ++k) {
+    int64_t v = 0;
+    for (int sh = 0; sh < SH; ++sh) v += h[static_cast<size_t>(sh * stride + k)];
+    n[k - 1] = v;
+  }
+  n[M] = h[0];
   return SWC_OK;
 }
 

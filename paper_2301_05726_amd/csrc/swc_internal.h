@@ -163,6 +163,10 @@ struct StepArr {
   Fx3* ea;
   Fx3* eb;
   double* ent;
+  // live determinants visited by forward step k (= live when it began),
+  // sharded like pcnt; shard 0 at k = 0 holds the live count after the sweep
+  // (null unless tracked)
+  uint32_t* pvis;
 };
 constexpr int WSTAT = 8;
 // table slots each lane of a one-factor sweep step loads per pass

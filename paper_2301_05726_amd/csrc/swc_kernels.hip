@@ -434,6 +434,7 @@ __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
     const int64_t k = static_cast<int64_t>(i % (M + 1));
     sa.pw[sidx(sa, b, sh, k)] = fx3_zero();
     sa.pcnt[sidx(sa, b, sh, k)] = 0u;
+    if (sa.pvis) sa.pvis[sidx(sa, b, sh, k)] = 0u;
     sa.gacc[sidx(sa, b, sh, k)] = fx3_zero();
   }
   for (uint64_t i = gtid; i < static_cast<uint64_t>(M + 1); i += gsz) {
@@ -478,10 +479,14 @@ __global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy
       sa.ws[(b * sa.nws + w) * WSTAT + i] = 0ull;  // folded: a later chunk starts from zero
     }
   for (int i = 0; i < WSTAT; ++i) tot[i] = wave_u64(tot[i]);
+  // live count over the shards, before this fold (one wave: threads 0..63)
+  unsigned long long live = threadIdx.x < CSH ? cnt[b].sh[threadIdx.x].v[C_LIVE] : 0ull;
+  live = wave_u64(live);
   if (threadIdx.x == 0) {
     if (!fold_only) {
       sa.scale[static_cast<int64_t>(b) * sa.stride + M] = S;
       cnt[b].S = S;
+      if (sa.pvis) sa.pvis[sidx(sa, b, 0, 0)] = static_cast<uint32_t>(live + tot[3] - tot[4]);  // after the sweep
     }
     CShard& c0 = cnt[b].sh[0];
     c0.v[C_PRUNED] += tot[0];
@@ -704,6 +709,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       atomicAdd(&sa.pcnt[sidx(sa, b, wsh, k)], c[0]);
     }
   }
+  if (sa.pvis && c[1] && lane == 0) atomicAdd(&sa.pvis[sidx(sa, b, wsh, k)], c[1]);
   // occupancy is live: the growth guard of later steps reads it
   if (c[5] && lane == 0) atomicAdd(&cnt[b].sh[wsh & (CSH - 1)].v[C_OCC], static_cast<unsigned long long>(c[5]));
   if (lane < 7) {
@@ -986,7 +992,8 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
   const uint64_t m1 = f1.occ | f1.vir, m2 = f2.occ | f2.vir;
   const uint32_t K1 = static_cast<uint32_t>(k), K2 = K1 + 1u;
   // c[1] visits, c[2] pairs, c[3] creates, c[5] new slots, c[6] pairs whose partner existed
-  unsigned long long c1 = 0, c2 = 0, c3 = 0, c5 = 0, c6 = 0;
+  // c1a / c1b: visits of step k / k+1 (c1 of the statistics is their sum)
+  unsigned long long c1a = 0, c1b = 0, c2 = 0, c3 = 0, c5 = 0, c6 = 0;
   unsigned int flags = 0;
 
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
@@ -997,7 +1004,8 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
     if ((m & DEAD) || (m & TAG) == K1 || (m & TAG) == K2) continue;  // dead, or created by this launch
     const Quad Q = make_quad(me.key, m1, m2, f1, f2);
     if (Q.comp == 1u) {  // acted on by neither factor
-      c1 += 2;
+      c1a += 1;
+      c1b += 1;
       continue;
     }
     int64_t slot[4];
@@ -1068,10 +1076,10 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
         c3 += 1;
       }
     };
-    c1 += static_cast<unsigned long long>(pres[0]) + pres[1] + pres[2] + pres[3];
+    c1a += static_cast<unsigned long long>(pres[0]) + pres[1] + pres[2] + pres[3];
     if (Q.e1a) rot(0, 1, f1, sn1, cm1a, K1);
     if (Q.e1b && (Q.comp & 4u)) rot(2, 3, f1, sn1, cm1a, K1);
-    c1 += static_cast<unsigned long long>(pres[0]) + pres[1] + pres[2] + pres[3];
+    c1b += static_cast<unsigned long long>(pres[0]) + pres[1] + pres[2] + pres[3];
     if (Q.e2a) rot(0, 2, f2, sn2, cm1b, K2);
     if (Q.e2b && (Q.comp & 2u)) rot(1, 3, f2, sn2, cm1b, K2);
 #pragma unroll
@@ -1096,10 +1104,15 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
     }
   }
   if (flags) atomicOr(&cnt[b].flags, flags);
-  unsigned int w1 = wave_u32(static_cast<unsigned int>(c1)), w2 = wave_u32(static_cast<unsigned int>(c2));
+  const unsigned int w1a = wave_u32(static_cast<unsigned int>(c1a)), w1b = wave_u32(static_cast<unsigned int>(c1b));
+  const unsigned int w1 = w1a + w1b, w2 = wave_u32(static_cast<unsigned int>(c2));
   unsigned int w3 = wave_u32(static_cast<unsigned int>(c3)), w5 = wave_u32(static_cast<unsigned int>(c5));
   unsigned int w6 = wave_u32(static_cast<unsigned int>(c6));
   const int wsh = (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6)) & (SH - 1);
+  if (sa.pvis && lane == 0) {
+    if (w1a) atomicAdd(&sa.pvis[sidx(sa, b, wsh, k)], w1a);
+    if (w1b) atomicAdd(&sa.pvis[sidx(sa, b, wsh, k + 1)], w1b);
+  }
   if (w5 && lane == 0) atomicAdd(&cnt[b].sh[wsh & (CSH - 1)].v[C_OCC], static_cast<unsigned long long>(w5));
   if (lane < 7) {
     const unsigned int mine = lane == 1 ? w1 : lane == 2 ? w2 : lane == 3 ? w3 : lane == 5 ? w5 : lane == 6 ? w6 : 0u;

@@ -5,6 +5,12 @@
         `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` to calibrate what the
         counters report per byte actually moved.
 
+    python -m paper_2301_05726_amd.profiling peaks [--gib 4] [--reps 5]
+        Achievable device peaks to hold the kernels against: a streaming copy
+        (GB/s) and random gathers of 8- and 16-byte elements over a buffer the
+        size of a large hash table (elements/s and GB/s of useful bytes), timed
+        with HIP events on torch's own copy and indexing kernels.
+
     python -m paper_2301_05726_amd.profiling summarize <csv> [--top N] [--cmd "..."]
         Turn a rocprofv3 kernel_stats.csv or counter_collection.csv into a
         short text table (per-kernel calls, total and mean duration, or mean
@@ -34,6 +40,41 @@ def copy_kernel(mib: int, reps: int) -> None:
         dst.copy_(src)
     torch.cuda.synchronize()
     print(f"copied {mib} MiB x {reps} (each copy reads {n} B and writes {n} B)", flush=True)
+
+
+def peaks(gib: float, reps: int) -> None:
+    import torch
+    dev = torch.device("cuda")
+    n8 = int(gib * (1 << 30)) // 8
+    src = torch.randint(0, 1 << 62, (n8,), dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            ev[0].record()
+            fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            best = min(best, ev[0].elapsed_time(ev[1]) * 1e-3)
+        return best
+
+    t = timed(lambda: dst.copy_(src))
+    print(f"copy {gib:g} GiB: {2 * n8 * 8 / t / 1e9:.0f} GB/s (read + write), best of {reps}", flush=True)
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    for width in (8, 16):
+        rows = src.view(-1, width // 8)
+        m = rows.shape[0] // 4
+        idx = torch.randint(0, rows.shape[0], (m,), dtype=torch.int64, device=dev, generator=g)
+        out = torch.empty((m, width // 8), dtype=torch.int64, device=dev)
+        t = timed(lambda: torch.index_select(rows, 0, idx, out=out))
+        print(f"random gather of {width}-byte elements over {gib:g} GiB: {m / t / 1e9:.2f} G elements/s, "
+              f"{m * width / t / 1e9:.0f} GB/s useful (plus {m * (8 + width) / t / 1e9:.0f} GB/s of index reads and "
+              f"output writes, streamed)", flush=True)
 
 
 def _short(name: str) -> str:
@@ -127,6 +168,9 @@ def main(argv=None) -> int:
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=12)
     s.add_argument("--cmd", default=None)
+    pk = sub.add_parser("peaks")
+    pk.add_argument("--gib", type=float, default=4.0)
+    pk.add_argument("--reps", type=int, default=5)
     t = sub.add_parser("traffic")
     for f in ("--fetch", "--write", "--cal-fetch", "--cal-write"):
         t.add_argument(f, required=True)
@@ -135,6 +179,8 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     if a.sub == "copy":
         copy_kernel(a.mib, a.reps)
+    elif a.sub == "peaks":
+        peaks(a.gib, a.reps)
     elif a.sub == "traffic":
         traffic(a)
     else:

@@ -24,6 +24,7 @@ EXPORTS = [
     "swc_energy_and_grad", "swc_get_state", "swc_get_stats", "swc_strerror", "swc_last_error",
     "swc_destroy", "swc_validate_excitations", "swc_factor_masks", "swc_checkpoint_bytes",
     "swc_set_checkpoints", "swc_track_entropy", "swc_get_entropy", "swc_set_topk", "swc_set_sigma_scratch",
+    "swc_track_live", "swc_get_live_counts",
 ]
 
 
@@ -84,6 +85,8 @@ def lib():
         L.swc_set_checkpoints.argtypes = [P, I64, U64, P, SZ]
         L.swc_track_entropy.argtypes = [P, I]
         L.swc_get_entropy.argtypes = [P, I, P, I64]
+        L.swc_get_live_counts.argtypes = [P, I, P, I64]
+        L.swc_track_live.argtypes = [P, I]
         L.swc_set_topk.argtypes = [P, U64, U64]
         L.swc_set_sigma_scratch.argtypes = [P, P, SZ, I]
         _lib = L
@@ -247,6 +250,17 @@ class Solver:
         out = np.full(n, np.nan)
         _chk(lib().swc_get_entropy(self._ctx, b, _ptr(out), n))
         return out[: np.count_nonzero(~np.isnan(out))].copy()
+
+    def track_live(self, on: bool = True):
+        """Count the live determinants of every step of later forward sweeps."""
+        _chk(lib().swc_track_live(self._ctx, int(bool(on))))
+
+    def live_counts(self, b: int = 0) -> np.ndarray:
+        """Live determinants of member b when each step of the last forward
+        sweep began, then after its last step: [M + 1] (int64)."""
+        out = np.full(self.max_factors + 1, -1, np.int64)
+        _chk(lib().swc_get_live_counts(self._ctx, b, _ptr(out), out.shape[0]))
+        return out[: np.count_nonzero(out >= 0)].copy()
 
     def get_state(self, b: int = 0, cap: int | None = None):
         n = ctypes.c_int64(0)

@@ -44,10 +44,14 @@ def test_forward_energy_grad_vs_oracle(swc, orc, case, prec):
     assert nc == 0, "test instance must have no amplitude near the cut"
     cap = capacity_for(n_orb, n_occ)
     s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=1, max_factors=exc.shape[0])
+    s.track_live(True)
     s.build_state()
     s.apply_ucc(theta, exc, thr)
     # det-updates: live determinants when each step begins, summed (exact count)
     assert s.stats()["det_updates"] == du_ref
+    # and the live count before every step and after the last (exact)
+    n_ref = orc.live_trajectory(nq, [hf], [1.0], exc, theta[0], thr)
+    assert np.array_equal(s.live_counts(0), n_ref)
     d, a = s.get_state(0)
     err = compare_states(d, a, d_ref, a_ref, tol["amp"])
     E = s.energy(h1, h2).cpu().numpy()[0]
@@ -59,6 +63,7 @@ def test_forward_energy_grad_vs_oracle(swc, orc, case, prec):
     say(f"  grad: dE={abs(E2 - E_ref):.3e} max|dg|={np.max(np.abs(g - g_ref)):.3e}")
     assert abs(E2 - E_ref) <= tol["E"]
     assert np.max(np.abs(g - g_ref)) <= tol["g"]
+    assert np.array_equal(s.live_counts(0), n_ref)  # the gradient's forward sweep
     # energy_and_grad leaves |Psi_0>
     d0, a0 = s.get_state(0)
     assert list(d0) == [hf] and abs(a0[0] - 1.0) < 1e-15
@@ -125,6 +130,9 @@ def test_error_paths(swc):
     s = swc.Solver(8, 2, 2, 256, prec=0, batch=1, max_factors=exc.shape[0])
     with pytest.raises(swc.SwcError) as e:
         s.apply_ucc(theta, exc, 0.0)
+    assert e.value.code == swc.ESTATE
+    with pytest.raises(swc.SwcError) as e:  # live counts are kept only while tracked
+        s.live_counts(0)
     assert e.value.code == swc.ESTATE
     s.build_state()
     bad = exc.copy()
@@ -208,6 +216,7 @@ GROW_CASES = [
 def _run_with_table_min(swc, monkeypatch, tmin, nq, n_occ, cap, prec, batch, exc, theta, thr, h1, h2):
     monkeypatch.setenv("SWC_TABLE_MIN", str(tmin))
     s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=batch, max_factors=exc.shape[0])
+    s.track_live(True)
     s.build_state()
     s.apply_ucc(theta, exc, thr)
     st = s.stats()
@@ -215,6 +224,7 @@ def _run_with_table_min(swc, monkeypatch, tmin, nq, n_occ, cap, prec, batch, exc
     E = s.energy(h1, h2).cpu().numpy()
     E2, g = s.energy_and_grad(theta, exc, thr, h1, h2)
     st2 = s.stats()
+    st2["live_counts"] = s.live_counts(0).tolist()
     s.close()
     return st, st2, states, E, E2.cpu().numpy(), g.cpu().numpy()
 
@@ -239,6 +249,7 @@ def test_table_growth_exact(swc, orc, monkeypatch, case, prec):
     assert grown[1]["shrinks"] >= 1  # the reverse sweep moved into smaller tables
     assert fixed[0]["rehashes"] == 0 and fixed[0]["table_slots"] == cap and fixed[1]["shrinks"] == 0
     assert grown[0]["n_live"] == fixed[0]["n_live"]
+    assert grown[1]["live_counts"] == fixed[1]["live_counts"]
     for x, y in zip(grown[2][0], fixed[2][0]):
         assert x.tobytes() == y.tobytes()
     for i in (3, 4, 5):
@@ -531,6 +542,7 @@ def test_topk_truncation_vs_oracle(swc, orc, monkeypatch, case, prec, mode):
     try:
         d_ref, a_ref, nc, du_ref = orc.apply_ucc(nq, [hf], [1.0], exc, theta[0], thr)
         E_ref, g_ref, _ = orc.energy_and_grad(nq, [hf], [1.0], exc, theta[0], thr, h1, h2)
+        n_ref = orc.live_trajectory(nq, [hf], [1.0], exc, theta[0], thr)
     finally:
         orc.set_topk(0, 0)
     assert nc == 0
@@ -539,11 +551,13 @@ def test_topk_truncation_vs_oracle(swc, orc, monkeypatch, case, prec, mode):
     # revived, each saved in the truncation log
     s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=B, max_factors=exc.shape[0], log_capacity=64 * cap)
     s.set_topk(n_max, n_cut)
+    s.track_live(True)
     s.build_state()
     s.apply_ucc(theta, exc, thr)
     st = s.stats()
     assert st["det_updates"] == B * du_ref
     for b in range(B):
+        assert np.array_equal(s.live_counts(b), n_ref)
         d, a = s.get_state(b)
         err = compare_states(d, a, d_ref, a_ref, tol["amp"])
     E, g = s.energy_and_grad(theta, exc, thr, h1, h2)

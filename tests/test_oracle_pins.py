@@ -325,6 +325,38 @@ def test_entropy_trajectory_matches_dense_statevector(orc):
     assert np.all(orc.entropy_trajectory(8, [hf], [1.0], exc, np.zeros_like(theta)) == 0.0)
 
 
+# ---------------------------------------------------------------- state size along the circuit
+
+
+def test_live_trajectory_matches_dense_support_and_truncation(orc):
+    """Sizes after every factor: at threshold 0 they equal the support of the
+    dense Jordan-Wigner statevector (generic angles make no exact zeros); with
+    a threshold, a dense run truncated and renormalised after every factor
+    (the Methods section's rule, written here on the dense vector) gives the
+    same counts; the counts before the factors sum to the det-updates and end
+    at the final state's size."""
+    h1, h2, exc, theta, hf = small_problem(4, 2, 0.3, 32)
+    jw = DenseJW(8)
+    n = orc.live_trajectory(8, [hf], [1.0], exc, theta)
+    psi = jw.basis([hf])
+    assert n[0] == 1
+    for k in range(exc.shape[0]):
+        psi = jw.apply_factors(psi, exc[k:k + 1], theta[k:k + 1])
+        assert n[k + 1] == np.count_nonzero(psi)
+    thr = 0.02
+    n = orc.live_trajectory(8, [hf], [1.0], exc, theta, thr)
+    psi = jw.basis([hf])
+    for k in range(exc.shape[0]):
+        psi = jw.apply_factors(psi, exc[k:k + 1], theta[k:k + 1])
+        cut = (np.abs(psi) < thr) & (psi != 0)
+        if np.any(cut):
+            psi[cut] = 0.0
+            psi /= np.linalg.norm(psi)
+        assert n[k + 1] == np.count_nonzero(psi), k
+    d, a, nc, du = orc.apply_ucc(8, [hf], [1.0], exc, theta, thr)
+    assert int(np.sum(n[:-1])) == du and n[-1] == len(d)
+
+
 # ---------------------------------------------------------------- N_MAX / N_CUT truncation (Methods)
 
 
