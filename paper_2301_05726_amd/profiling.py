@@ -7,9 +7,9 @@
 
     python -m paper_2301_05726_amd.profiling peaks [--gib 4] [--reps 5]
         Achievable device peaks to hold the kernels against: a streaming copy
-        (GB/s) and random gathers of 8- and 16-byte elements over a buffer the
-        size of a large hash table (elements/s and GB/s of useful bytes), timed
-        with HIP events on torch's own copy and indexing kernels.
+        (GB/s) and a random gather of 8-byte elements over a buffer the size of
+        a large hash table (elements/s), timed with HIP events on torch's own
+        copy and gather kernels.
 
     python -m paper_2301_05726_amd.profiling summarize <csv> [--top N] [--cmd "..."]
         Turn a rocprofv3 kernel_stats.csv or counter_collection.csv into a
@@ -66,17 +66,12 @@ def peaks(gib: float, reps: int) -> None:
     print(f"copy {gib:g} GiB: {2 * n8 * 8 / t / 1e9:.0f} GB/s (read + write), best of {reps}", flush=True)
     g = torch.Generator(device=dev)
     g.manual_seed(7)
-    for width in (8, 16):
-        rows = src.view(-1, width // 8)
-        m = min(rows.shape[0] // 4, 1 << 24)
-        idx = torch.randint(0, rows.shape[0], (m,), dtype=torch.int64, device=dev, generator=g)
-        if width == 8:
-            t = timed(lambda: torch.take(src, idx))
-        else:
-            t = timed(lambda: rows[idx])
-        print(f"random gather of {width}-byte elements over {gib:g} GiB: {m / t / 1e9:.2f} G elements/s, "
-              f"{m * width / t / 1e9:.0f} GB/s useful (plus {m * (8 + width) / t / 1e9:.0f} GB/s of index reads and "
-              f"output writes, streamed)", flush=True)
+    m = min(n8 // 4, 1 << 24)
+    idx = torch.randint(0, n8, (m,), dtype=torch.int64, device=dev, generator=g)
+    t = timed(lambda: torch.take(src, idx))
+    print(f"random gather of 8-byte elements over {gib:g} GiB: {m / t / 1e9:.2f} G elements/s, "
+          f"{m * 8 / t / 1e9:.0f} GB/s useful (plus {m * 16 / t / 1e9:.0f} GB/s of index reads and "
+          f"output writes, streamed)", flush=True)
 
 
 def _short(name: str) -> str:
