@@ -401,11 +401,16 @@ int reset_state(swc_ctx* c) {
   return SWC_OK;
 }
 
-int check_theta(swc_ctx* c, const double* theta, int64_t M) {
+// Angles -> cos/sin table.  A non-finite angle sets F_BAD_THETA; with
+// wait = false the caller reads that flag later with other counters (the
+// sweep meanwhile runs on values it cannot overflow the table with: every
+// comparison with a NaN amplitude removes it).
+int check_theta(swc_ctx* c, const double* theta, int64_t M, bool wait = true) {
   if (M == 0) return SWC_OK;
   if (!theta) return fail(SWC_EINVAL, "null theta");
   launch_trig(theta, c->trig, M, c->Mmax + 1, c->B, c->cnt, c->st);
   SWC_HIP(hipGetLastError());
+  if (!wait) return SWC_OK;
   int r = read_counters(c);
   if (r) return r;
   if (c->hcnt[0].flags & F_BAD_THETA) {
@@ -940,8 +945,8 @@ int pair_sigma(swc_ctx* c, const double* h1, const double* h2, int64_t nmax) {
 }
 
 // compact + sigma + E (+ lambda); leaves counters read back
-int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool want_lambda) {
-  if (!h1 || !h2) return fail(SWC_EINVAL, "null integrals");
+// Energy, part 1: compact the live entries (their counts land in the counters).
+int energy_compact(swc_ctx* c) {
   launch_energy_begin(c->cnt, c->B, c->st);
   SWC_HIP(hipEventRecord(c->ev[2], c->st));
   int r = dispatch(c, [&](auto* tp) -> int {
@@ -951,7 +956,13 @@ int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool 
   });
   if (r) return r;
   SWC_HIP(hipGetLastError());
-  if ((r = read_counters(c))) return r;
+  return SWC_OK;
+}
+
+// Energy, part 2 (the compact counts read into hcnt): sigma, E and, for the
+// gradient, lambda_M.  Nothing here waits for the device.
+int energy_run(swc_ctx* c, const double* h1, const double* h2, double* E, bool want_lambda) {
+  int r = SWC_OK;
   int64_t nmax = 0;
   for (int b = 0; b < c->B; ++b) nmax = std::max<int64_t>(nmax, static_cast<int64_t>(c->hcnt[b].ncompact));
   if (nmax == 0) return fail(SWC_EEMPTY, "empty state");
@@ -979,6 +990,13 @@ int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool 
   }
   SWC_HIP(hipEventRecord(c->ev[3], c->st));
   SWC_HIP(hipGetLastError());
+  return SWC_OK;
+}
+
+int energy_impl(swc_ctx* c, const double* h1, const double* h2, double* E, bool want_lambda) {
+  if (!h1 || !h2) return fail(SWC_EINVAL, "null integrals");
+  int r = energy_compact(c);
+  if (r || (r = read_counters(c)) || (r = energy_run(c, h1, h2, E, want_lambda))) return r;
   return read_counters(c);
 }
 
@@ -1182,13 +1200,29 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   if (M < 0 || M > c->Mmax) return fail(SWC_EINVAL, "factor count above max_factors");
   if (!(threshold >= 0.0) || !std::isfinite(threshold)) return fail(SWC_EINVAL, "threshold must be finite and >= 0");
   if (!E || (M > 0 && !grad)) return fail(SWC_EINVAL, "null output");
+  if (!h1 || !h2) return fail(SWC_EINVAL, "null integrals");
   int r = check_exc(c->nq, exc, M);
   if (r) return r;
   if ((r = upload_masks(c, exc, M))) return r;
-  if ((r = check_theta(c, theta, M))) return r;
   if ((r = reset_state(c))) return r;
+  // the angle check's flag is read with the forward sweep's status below
+  if ((r = check_theta(c, theta, M, false))) return r;
   if ((r = forward_sweep(c, M, threshold, 1))) return r;
-  if ((r = read_counters(c))) return r;
+  if ((r = energy_compact(c))) return r;
+  // One host wait for the sweep's status, the compact counts, the per-step
+  // log sizes and the checkpoint sizes.
+  const int64_t S = c->Mmax + 1;
+  std::vector<uint32_t> logn(static_cast<size_t>(c->B * S)), logoff(static_cast<size_t>(c->B * S), 0u);
+  std::vector<unsigned long long> cnts(static_cast<size_t>(c->ck_taken) * c->B);
+  SWC_HIP(hipMemcpyAsync(c->hcnt.data(), c->cnt, sizeof(Counters) * c->B, hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipMemcpyAsync(logn.data(), c->sa.logn, 4 * c->B * S, hipMemcpyDeviceToHost, c->st));
+  if (c->ck_taken > 0)
+    SWC_HIP(hipMemcpyAsync(cnts.data(), c->ck_count, 8 * cnts.size(), hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipStreamSynchronize(c->st));
+  if (M > 0 && (c->hcnt[0].flags & F_BAD_THETA)) {
+    reset_state(c);
+    return fail(SWC_EINVAL, "theta contains a non-finite value");
+  }
   if ((r = sweep_status(c))) {
     reset_state(c);
     return r;
@@ -1201,9 +1235,6 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
                                      std::to_string(c->L));
     }
   if (c->ck_taken > 0) {
-    std::vector<unsigned long long> cnts(static_cast<size_t>(c->ck_taken) * c->B);
-    SWC_HIP(hipMemcpyAsync(cnts.data(), c->ck_count, 8 * cnts.size(), hipMemcpyDeviceToHost, c->st));
-    SWC_HIP(hipStreamSynchronize(c->st));
     c->ck_nmax.assign(static_cast<size_t>(c->ck_n), 0);
     for (int64_t j = 0; j < c->ck_taken; ++j)
       for (int b = 0; b < c->B; ++b) c->ck_nmax[j] = std::max<uint64_t>(c->ck_nmax[j], cnts[j * c->B + b]);
@@ -1218,17 +1249,11 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
     c->rot_n = c->persistent ? c->fwd_launches : M;
     c->rot_ms = sum_pairs(c, c->rot_n);
   }
-  if ((r = energy_impl(c, h1, h2, E, true))) {
+  if ((r = energy_run(c, h1, h2, E, true))) {
     reset_state(c);
     return r;
   }
-  c->energy_ms = elapsed(c->ev[2], c->ev[3]);
-  c->sig_ms = elapsed(c->ev[6], c->ev[7]);
   // offsets of the per-step truncation-log records
-  const int64_t S = c->Mmax + 1;
-  std::vector<uint32_t> logn(static_cast<size_t>(c->B * S)), logoff(static_cast<size_t>(c->B * S), 0u);
-  SWC_HIP(hipMemcpyAsync(logn.data(), c->sa.logn, 4 * c->B * S, hipMemcpyDeviceToHost, c->st));
-  SWC_HIP(hipStreamSynchronize(c->st));
   std::vector<uint32_t> maxn(static_cast<size_t>(M + 1), 0u);
   c->log_records = 0;
   for (int b = 0; b < c->B; ++b) {
@@ -1252,25 +1277,28 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   SWC_HIP(hipEventRecord(c->ev[5], c->st));
   if (c->persistent && M > 0) launch_sweep_end(c->sa, c->cnt, 0, c->B, c->sy, 0, c->st);  // barrier status only
   SWC_HIP(hipGetLastError());
-  if ((r = read_counters(c))) return r;
+  // One host wait for the adjoint sweep's status and the counters of the
+  // state it leaves (|Psi_0> again, rebuilt right away).
+  std::vector<Counters> after(static_cast<size_t>(c->B));
+  SWC_HIP(hipMemcpyAsync(after.data(), c->cnt, sizeof(Counters) * c->B, hipMemcpyDeviceToHost, c->st));
+  if ((r = reset_state(c))) return r;
+  SWC_HIP(hipMemcpyAsync(c->hcnt.data(), c->cnt, sizeof(Counters) * c->B, hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipStreamSynchronize(c->st));
+  c->energy_ms = elapsed(c->ev[2], c->ev[3]);
+  c->sig_ms = elapsed(c->ev[6], c->ev[7]);
   c->rev_ms = elapsed(c->ev[4], c->ev[5]);
   if (c->ktiming) {
     c->revk_n = c->persistent ? c->rev_launches : M;
     c->revk_ms = sum_pairs(c, c->revk_n);
   }
   for (int b = 0; b < c->B; ++b) {
-    if (c->hcnt[b].flags & (F_INCONSISTENT | F_TIMEOUT)) {
-      reset_state(c);
-      return fail(SWC_EDEVICE, (c->hcnt[b].flags & F_TIMEOUT) ? "grid barrier of a persistent sweep timed out"
-                                                               : "inconsistent pair state in the reverse sweep");
-    }
-    if (c->hcnt[b].flags & F_TABLE_FULL) {  // a rehash found no free slot (cannot happen at <= 45% occupancy)
-      reset_state(c);
+    if (after[b].flags & (F_INCONSISTENT | F_TIMEOUT))
+      return fail(SWC_EDEVICE, (after[b].flags & F_TIMEOUT) ? "grid barrier of a persistent sweep timed out"
+                                                            : "inconsistent pair state in the reverse sweep");
+    if (after[b].flags & F_TABLE_FULL)  // a rehash found no free slot (cannot happen at <= 45% occupancy)
       return fail(SWC_ECAPACITY, "hash table full in the reverse sweep");
-    }
   }
-  if ((r = reset_state(c))) return r;
-  return read_counters(c);
+  return SWC_OK;
 }
 
 size_t swc_checkpoint_bytes(int prec, int batch, int64_t max_factors, int64_t interval, uint64_t max_entries) {

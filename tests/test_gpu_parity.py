@@ -145,6 +145,17 @@ def test_error_paths(swc):
     with pytest.raises(swc.SwcError) as e:
         s.apply_ucc(t, exc, 0.0)
     assert e.value.code == swc.EINVAL
+    # the gradient call checks the angles together with the forward sweep's
+    # status; the context stays usable and the next call is exact
+    E_ok, g_ok = s.energy_and_grad(theta, exc, 0.0, h1, h2)
+    with pytest.raises(swc.SwcError) as e:
+        s.energy_and_grad(t, exc, 0.0, h1, h2)
+    assert e.value.code == swc.EINVAL
+    E_2, g_2 = s.energy_and_grad(theta, exc, 0.0, h1, h2)
+    assert E_2.cpu().numpy().tobytes() == E_ok.cpu().numpy().tobytes()
+    assert g_2.cpu().numpy().tobytes() == g_ok.cpu().numpy().tobytes()
+    d0, a0 = s.get_state(0)
+    assert list(d0) == [hf]
     with pytest.raises(swc.SwcError) as e:
         s.apply_ucc(theta, exc, -1.0)
     assert e.value.code == swc.EINVAL
