@@ -573,9 +573,12 @@ Snap ckpt_snap(const swc_ctx* c, int64_t j) {
 }
 
 // Last step of the range of forward steps that starts at k: the end of k's
-// chunk, cut at M and, in a gradient sweep, at the next checkpoint.
-int64_t fwd_range_end(const swc_ctx* c, int64_t k, int64_t M, int log_on) {
-  int64_t e = std::min(M, chunk_end(k));
+// chunk, cut at M and, in a gradient sweep, at the next checkpoint.  A table
+// that can no longer grow needs no look between the power-of-two chunks
+// (wide): its ranges end only at multiples of GRAPH_CHUNK, so a short circuit
+// is one graph.
+int64_t fwd_range_end(const swc_ctx* c, int64_t k, int64_t M, int log_on, bool wide = false) {
+  int64_t e = std::min(M, wide ? (k - 1) / GRAPH_CHUNK * GRAPH_CHUNK + GRAPH_CHUNK : chunk_end(k));
   if (log_on && c->ck_interval > 0) {
     const int64_t nxt = (k + c->ck_interval - 1) / c->ck_interval * c->ck_interval;
     if (ckpt_index(c, nxt, M) >= 0) e = std::min(e, nxt);
@@ -693,7 +696,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
     double prev_occ = static_cast<double>(max_occupancy(c));  // counters read before the sweep
     while (k <= M) {
       const uint64_t lim = occ_limit(c);
-      const int64_t k1 = fwd_range_end(c, k, M, log_on);
+      const int64_t k1 = fwd_range_end(c, k, M, log_on, lim == NO_LIMIT);
       int r = run_fwd_steps(c, k, k1, thr, log_on, lim, !resumed);
       if (r) return r;
       if (lim == NO_LIMIT) {
@@ -780,8 +783,11 @@ int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>
   c->rev_launches = 0;
   c->rev_slots = 0;
   c->shrinks = 0;
+  // ranges between the shrink checks; a table at the minimum size cannot
+  // shrink, so its ranges only stop at multiples of GRAPH_CHUNK
+  const bool wide = !c->shrink || c->persistent || c->tab.H <= c->table_min;
   for (int64_t hi = M; hi >= 1;) {
-    int64_t lo = chunk_begin(hi);
+    int64_t lo = wide ? (hi - 1) / GRAPH_CHUNK * GRAPH_CHUNK + 1 : chunk_begin(hi);
     if (c->ck_interval > 0) lo = std::max(lo, (hi - 1) / c->ck_interval * c->ck_interval + 1);
     if (int rr = shrink_table(c, hi)) return rr;
     const int64_t launches0 = c->rev_launches;
