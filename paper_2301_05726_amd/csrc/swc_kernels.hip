@@ -1356,12 +1356,16 @@ __global__ __launch_bounds__(BLK) void k_rev_sweep(Tab t, const FacMask* __restr
 
 template <class T>
 __global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cnt) {
+  // one counter claim per block and pass (the waves' counts combined in LDS),
+  // not per wave: the claims all go to one address
+  __shared__ unsigned int wcount[BLK / 64];
+  __shared__ unsigned long long wbase[BLK / 64];
   const int b = blockIdx.y;
   const uint64_t H = t.H;
   const View<T> v = view<T>(t, b);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  const int lane = threadIdx.x & 63;
-  for (uint64_t s0 = blockIdx.x * blockDim.x; s0 < H; s0 += stride) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (uint64_t s0 = blockIdx.x * blockDim.x; s0 < H; s0 += stride) {  // the same passes for the whole block
     const uint64_t s = s0 + threadIdx.x;
     bool live = false;
     Slot<T> me;
@@ -1372,11 +1376,20 @@ __global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cn
       live = me.key != EMPTY_KEY && !(me.meta & DEAD);
     }
     const unsigned long long mask = __ballot(live);
-    if (!mask) continue;
-    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
-    unsigned long long basep = 0;
-    if (lane == leader) basep = atomicAdd(&cnt[b].ncompact, static_cast<unsigned long long>(__popcll(mask)));
-    basep = __shfl(basep, leader, 64);
+    if (lane == 0) wcount[w] = static_cast<unsigned int>(__popcll(mask));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long tot = 0;
+      for (int i = 0; i < BLK / 64; ++i) tot += wcount[i];
+      unsigned long long base = tot ? atomicAdd(&cnt[b].ncompact, tot) : 0ull;
+      for (int i = 0; i < BLK / 64; ++i) {
+        wbase[i] = base;
+        base += wcount[i];
+      }
+    }
+    __syncthreads();
+    const unsigned long long basep = wbase[w];
+    __syncthreads();  // wcount / wbase are rewritten by the next pass
     if (live) {
       const unsigned long long below = lane ? (mask & ((1ull << lane) - 1ull)) : 0ull;
       const uint64_t pos = basep + __popcll(below);
@@ -2166,7 +2179,10 @@ void launch_sigma(const Tab& t, const Compact& cp, const Counters* cnt, const do
 
 void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
                           int64_t nmax, int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_energy_reduce, dim3(grid_for(nmax, BLK, 2048), B), dim3(BLK), 0, st, cp, cnt, H, h1, h2, n);
+  // eight entries per thread at least: every block ends in two exact atomic
+  // additions to one address, so fewer blocks serialize less
+  hipLaunchKernelGGL(k_energy_reduce, dim3(grid_for(nmax, BLK * 8, 2048), B), dim3(BLK), 0, st, cp, cnt, H, h1, h2,
+                     n);
 }
 
 void launch_energy_begin(Counters* cnt, int B, hipStream_t st) {
