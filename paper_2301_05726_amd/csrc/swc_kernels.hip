@@ -2179,10 +2179,7 @@ void launch_sigma(const Tab& t, const Compact& cp, const Counters* cnt, const do
 
 void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
                           int64_t nmax, int B, hipStream_t st) {
-  // eight entries per thread at least: every block ends in two exact atomic
-  // additions to one address, so fewer blocks serialize less
-  hipLaunchKernelGGL(k_energy_reduce, dim3(grid_for(nmax, BLK * 8, 2048), B), dim3(BLK), 0, st, cp, cnt, H, h1, h2,
-                     n);
+  hipLaunchKernelGGL(k_energy_reduce, dim3(grid_for(nmax, BLK, 2048), B), dim3(BLK), 0, st, cp, cnt, H, h1, h2, n);
 }
 
 void launch_energy_begin(Counters* cnt, int B, hipStream_t st) {
