@@ -72,6 +72,24 @@ def peaks(gib: float, reps: int) -> None:
     print(f"random gather of 8-byte elements over {gib:g} GiB: {m / t / 1e9:.2f} G elements/s, "
           f"{m * 8 / t / 1e9:.0f} GB/s useful (plus {m * 16 / t / 1e9:.0f} GB/s of index reads and "
           f"output writes, streamed)", flush=True)
+    del src, dst, idx
+    # the floor of a dependent chain of launches: a captured graph of tiny
+    # kernels, each on one element (what a sweep step costs with no work)
+    nodes = 1000
+    x = torch.zeros(1, device=dev)
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        x.add_(1.0)  # warm the kernel before capture
+    torch.cuda.current_stream(dev).wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(nodes):
+            x.add_(1.0)
+    t = timed(graph.replay)
+    torch.cuda.synchronize()
+    print(f"graph of {nodes} one-element kernels: {t / nodes * 1e6:.2f} us per node "
+          f"(x = {x.item():.0f}, expected {1 + (1 + reps) * nodes}: every node ran)", flush=True)
 
 
 def _short(name: str) -> str:
