@@ -86,6 +86,8 @@ def main() -> int:
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fd-params", type=int, default=32)
     ap.add_argument("--no-fd", action="store_true")
+    ap.add_argument("--fd-full-max-s", type=float, default=60.0,
+                    help="run the finite differences over every parameter when the sampled estimate is below this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--factors", type=int, default=0, help="keep only the first K factors (0: all)")
     ap.add_argument("--cpu-factors", type=int, default=600,
@@ -303,10 +305,29 @@ def main() -> int:
         torch.cuda.synchronize()
         f1 = time.perf_counter()
         t_full = (f1 - f0) / len(idx) * M
+        extrapolated = True
+        if t_full <= args.fd_full_max_s and len(idx) < M:
+            # cheap enough: every parameter, timed as a whole
+            idx = np.arange(M)
+            fd = np.empty(M)
+            f0 = time.perf_counter()
+            for q, k in enumerate(idx):
+                ev = []
+                for sgn in (1.0, -1.0):
+                    tp.copy_(theta[0:1])
+                    tp[0, k] += sgn * h
+                    sf.build_state()
+                    sf.apply_ucc(tp, p.exc, wl.threshold)
+                    ev.append(sf.energy(h1, h2).item())
+                fd[q] = (ev[0] - ev[1]) / (2 * h)
+            torch.cuda.synchronize()
+            t_full = time.perf_counter() - f0
+            extrapolated = False
+            progress(f"finite differences over all {M} parameters done, {t_full:.1f} s")
         out["fd_baseline"] = {
             "what": "same GPU, FP64 amplitudes: E(theta +- h e_p) by forward sweep + energy, h=1e-5",
             "params_timed": int(len(idx)),
-            "extrapolated": True,
+            "extrapolated": extrapolated,
             "seconds_per_full_gradient": round(t_full, 4),
             "evals_per_s": round(1.0 / t_full, 6),
             "adjoint_speedup": round(value * t_full, 2),
