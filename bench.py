@@ -108,8 +108,9 @@ def main() -> int:
                     help="live determinants per snapshot the checkpoint buffer holds, 2^c")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); run it with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(batch members and finite-difference parameters would shard across GPUs with only a gather "
+              "of E and g); run it with --gpus 1", file=sys.stderr)
         return 2
     import numpy as np
     import torch
