@@ -152,25 +152,27 @@ def main() -> int:
         progress(f"warmup {i + 1}/{args.warmup} done, {time.perf_counter() - tw:.1f} s")
     torch.cuda.synchronize()
     # HIP events recorded by the library on its stream bracket each sweep
-    # (forward, reverse) and the sigma kernel inside every timed step
-    fwd_ms = rev_ms = sig_ms = 0.0
+    # (forward, reverse) and the sigma kernel inside every timed step; the
+    # library sums them over its calls, read before and after the timed steps
+    st0 = s.stats()
     t0 = time.perf_counter()
     for i in range(args.steps):
         E, g = s.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
-        st = s.stats()
-        fwd_ms += st["fwd_ms"]
-        rev_ms += st["rev_ms"]
-        sig_ms += st["sigma_kernel_ms"]
         if args.steps <= 20 or (i + 1) % 20 == 0:
             progress(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    st = s.stats()
+    assert st["grad_calls"] - st0["grad_calls"] == args.steps
+    fwd_ms = st["fwd_ms_total"] - st0["fwd_ms_total"]
+    rev_ms = st["rev_ms_total"] - st0["rev_ms_total"]
+    sig_ms = st["sigma_kernel_ms_total"] - st0["sigma_kernel_ms_total"]
     n_fwd, n_rev = st["rotate_launches"], st["reverse_launches"]
     log_records = st["log_records"]
     ck_taken = st["checkpoints"]
     scans = {"forward": st["fwd_slots_scanned"], "reverse": st["rev_slots_scanned"],
              "reverse_shrinks": st["shrinks"], "growths": st["rehashes"]}
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
     value = args.steps * B / elapsed  # theta vectors evaluated per second
     E0 = float(E[0].item())
     g0 = g.cpu().numpy()[0]

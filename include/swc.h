@@ -121,6 +121,13 @@ typedef struct {
   int64_t shrinks;           /* rehashes into a smaller table during the last reverse sweep */
   int64_t fwd_slots_scanned; /* sum over the last forward sweep's launches of the table size */
   int64_t rev_slots_scanned; /* the same for the last reverse sweep */
+  /* Totals over every swc_energy_and_grad call that completed since
+     swc_create (a caller reads them before and after a series of calls
+     instead of after each one): */
+  int64_t grad_calls;           /* completed swc_energy_and_grad calls */
+  double fwd_ms_total;          /* fwd_ms summed over those calls */
+  double rev_ms_total;          /* rev_ms summed over those calls */
+  double sigma_kernel_ms_total; /* sigma_kernel_ms summed over those calls */
 } swc_stats;
 
 /*

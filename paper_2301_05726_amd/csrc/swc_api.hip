@@ -288,6 +288,8 @@ struct swc_ctx {
   bool ktiming = false;
   std::vector<hipEvent_t> kev;
   double rot_ms = 0, revk_ms = 0, sig_ms = 0;
+  int64_t grad_calls = 0;  // completed energy_and_grad calls, and their summed sweep and sigma times
+  double fwd_ms_total = 0, rev_ms_total = 0, sig_ms_total = 0;
   int64_t rot_n = 0, revk_n = 0;
 };
 
@@ -387,10 +389,11 @@ int reset_state(swc_ctx* c) {
     z.stop = ~0u;
     c->hcnt[b] = z;
   }
-  SWC_HIP(hipMemcpyAsync(c->cnt, c->hcnt.data(), sizeof(Counters) * c->B, hipMemcpyHostToDevice, c->st));
+  // the device counters are set by a kernel and the initial determinants are
+  // already on the device (copied by swc_build_state): a reset issues no copy
+  // from pageable host memory, which would wait for the stream
+  launch_counters_reset(c->cnt, c->B, c->S0, c->st);
   const int64_t n = static_cast<int64_t>(c->h_init_d.size());
-  SWC_HIP(hipMemcpyAsync(c->init_d, c->h_init_d.data(), 8 * n, hipMemcpyHostToDevice, c->st));
-  SWC_HIP(hipMemcpyAsync(c->init_a, c->h_init_a.data(), 8 * n, hipMemcpyHostToDevice, c->st));
   int r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
     launch_insert_init<T>(c->tab, c->cnt, c->init_d, c->init_a, n, c->B, c->st);
@@ -1158,6 +1161,10 @@ int swc_build_state(swc_ctx* c, const uint64_t* dets, const double* amps, int64_
   c->h_init_d = std::move(d);
   c->h_init_a = std::move(a);
   c->S0 = 1.0 / std::sqrt(n2);
+  // |Psi_0> stays on the device for every later reset
+  const size_t n0 = c->h_init_d.size();
+  SWC_HIP(hipMemcpyAsync(c->init_d, c->h_init_d.data(), 8 * n0, hipMemcpyHostToDevice, c->st));
+  SWC_HIP(hipMemcpyAsync(c->init_a, c->h_init_a.data(), 8 * n0, hipMemcpyHostToDevice, c->st));
   int r = reset_state(c);
   if (r) return r;
   if ((r = read_counters(c))) return r;
@@ -1297,6 +1304,10 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
     c->revk_n = c->persistent ? c->rev_launches : M;
     c->revk_ms = sum_pairs(c, c->revk_n);
   }
+  ++c->grad_calls;
+  c->fwd_ms_total += c->fwd_ms;
+  c->rev_ms_total += c->rev_ms;
+  c->sig_ms_total += c->sig_ms;
   for (int b = 0; b < c->B; ++b) {
     if (after[b].flags & (F_INCONSISTENT | F_TIMEOUT))
       return fail(SWC_EDEVICE, (after[b].flags & F_TIMEOUT) ? "grid barrier of a persistent sweep timed out"
@@ -1481,6 +1492,10 @@ int swc_get_stats(swc_ctx* c, swc_stats* out) {
   s.reverse_launches = c->ktiming ? c->revk_n : c->rev_launches;
   s.sigma_kernel_ms = c->sig_ms;
   for (int b = 0; b < c->B; ++b) s.partner_hits += static_cast<int64_t>(counter_total(c->hcnt[b], C_HITS));
+  s.grad_calls = c->grad_calls;
+  s.fwd_ms_total = c->fwd_ms_total;
+  s.rev_ms_total = c->rev_ms_total;
+  s.sigma_kernel_ms_total = c->sig_ms_total;
   *out = s;
   return SWC_OK;
 }

@@ -278,6 +278,7 @@ void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const do
 void launch_energy_final(Counters* cnt, double* E, int B, hipStream_t st);
 template <class T>
 void launch_lambda(const Tab& t, const Compact& cp, const Counters* cnt, int64_t nmax, int B, hipStream_t st);
+void launch_counters_reset(Counters* cnt, int B, double S0, hipStream_t st);
 void launch_energy_begin(Counters* cnt, int B, hipStream_t st);
 // rehash every slot of `from` that is alive or a tombstone with a step tag in
 // [1, tag_max] into the table `to` (cleared first; larger when the forward

@@ -21,6 +21,8 @@
 //    spread over shards in separate cache lines.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "swc_internal.h"
 
 namespace swc {
@@ -1953,6 +1955,20 @@ __global__ void k_rehash_end(Counters* cnt) {
   if (blockIdx.x == 0 && threadIdx.x == 0) cnt[0].stop = ~0u;  // the grown table lets the stopped steps run
 }
 
+// Counters of a fresh state: everything zero, the scale S0, no stop step.
+// One block per batch member, each lane writing whole 8-byte words.
+static_assert(sizeof(Counters) % 8 == 0 && offsetof(Counters, S) % 8 == 0, "Counters word layout");
+static_assert(offsetof(Counters, flags) % 8 == 0 && offsetof(Counters, stop) == offsetof(Counters, flags) + 4,
+              "flags and stop share one word");
+__global__ void k_counters_reset(Counters* cnt, double S0) {
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(cnt + blockIdx.x);
+  constexpr unsigned int nw = sizeof(Counters) / 8;
+  constexpr unsigned int w_stop = offsetof(Counters, flags) / 8, w_s = offsetof(Counters, S) / 8;
+  for (unsigned int i = threadIdx.x; i < nw; i += blockDim.x)
+    w[i] = i == w_stop ? (0xffffffffull << 32) : i == w_s ? static_cast<unsigned long long>(__double_as_longlong(S0))
+                                                            : 0ull;
+}
+
 __global__ void k_energy_begin(Counters* cnt, int B) {
   const int b = threadIdx.x;
   if (b >= B) return;
@@ -2180,6 +2196,10 @@ void launch_sigma(const Tab& t, const Compact& cp, const Counters* cnt, const do
 void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
                           int64_t nmax, int B, hipStream_t st) {
   hipLaunchKernelGGL(k_energy_reduce, dim3(grid_for(nmax, BLK, 2048), B), dim3(BLK), 0, st, cp, cnt, H, h1, h2, n);
+}
+
+void launch_counters_reset(Counters* cnt, int B, double S0, hipStream_t st) {
+  hipLaunchKernelGGL(k_counters_reset, dim3(B), dim3(BLK), 0, st, cnt, S0);
 }
 
 void launch_energy_begin(Counters* cnt, int B, hipStream_t st) {

@@ -48,6 +48,8 @@ class Stats(ctypes.Structure):
         ("shrinks", ctypes.c_int64),
         ("fwd_slots_scanned", ctypes.c_int64),
         ("rev_slots_scanned", ctypes.c_int64),
+        ("grad_calls", ctypes.c_int64), ("fwd_ms_total", ctypes.c_double), ("rev_ms_total", ctypes.c_double),
+        ("sigma_kernel_ms_total", ctypes.c_double),
     ]
 
 
