@@ -1680,34 +1680,35 @@ __device__ __forceinline__ uint64_t between(int lo, int hi) {  // bits lo+1 .. h
   return ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
 }
 
+// (pq|rs) of the n^4 array.  n <= 32, so every partial index stays below
+// 2^20 and the full-rate 24-bit multiplier computes it exactly.
 __device__ __forceinline__ double eri(const double* __restrict__ h2, int n, int p, int q, int r, int s) {
-  return h2[((static_cast<int64_t>(p) * n + q) * n + r) * n + s];
+  const unsigned int un = static_cast<unsigned int>(n);
+  const unsigned int i = __umul24(__umul24(__umul24(static_cast<unsigned int>(p), un) + q, un) + r, un) + s;
+  return h2[i];
 }
 
-// <I|H|J> for determinants differing in pc = 2 (single) or 4 (double) bits
-// (Slater-Condon rules; sign from the occupied orbitals common to I and J
-// strictly between the moved ones).
-__device__ double h_offdiag(uint64_t I, uint64_t J, int pc, const double* __restrict__ h1,
-                            const double* __restrict__ h2, int n) {
-  const uint64_t d = I ^ J, C = I & J;
-  if (pc == 2) {
-    const int p = __ffsll(static_cast<long long>(I & d)) - 1;
-    const int q = __ffsll(static_cast<long long>(J & d)) - 1;
-    if ((p ^ q) & 1) return 0.0;
-    const int lo = p < q ? p : q, hi = p < q ? q : p;
-    const int P = p >> 1, Q = q >> 1, sp = p & 1;
-    double v = h1[P * n + Q];
-    for (uint64_t mm = C; mm; mm &= mm - 1ull) {
-      const int kk = __ffsll(static_cast<long long>(mm)) - 1;
-      const int Kk = kk >> 1;
-      v += eri(h2, n, P, Q, Kk, Kk);
-      if ((kk & 1) == sp) v -= eri(h2, n, P, Kk, Kk, Q);
-    }
-    return (__popcll(C & between(lo, hi)) & 1) ? -v : v;
+// <I|J> parts of H by the Slater-Condon rules; C = the orbitals occupied in
+// both, the sign from those strictly between the moved ones.
+// Single: spin-orbital p of I replaced by q.
+__device__ __forceinline__ double h_single(uint64_t C, int p, int q, const double* __restrict__ h1,
+                                           const double* __restrict__ h2, int n) {
+  if ((p ^ q) & 1) return 0.0;
+  const int lo = p < q ? p : q, hi = p < q ? q : p;
+  const int P = p >> 1, Q = q >> 1, sp = p & 1;
+  double v = h1[__umul24(static_cast<unsigned int>(P), static_cast<unsigned int>(n)) + Q];
+  for (uint64_t mm = C; mm; mm &= mm - 1ull) {
+    const int kk = __ffsll(static_cast<long long>(mm)) - 1;
+    const int Kk = kk >> 1;
+    v += eri(h2, n, P, Q, Kk, Kk);
+    if ((kk & 1) == sp) v -= eri(h2, n, P, Kk, Kk, Q);
   }
-  const uint64_t dI = I & d, dJ = J & d;
-  const int p1 = __ffsll(static_cast<long long>(dI)) - 1, p2 = 63 - __clzll(static_cast<long long>(dI));
-  const int q1 = __ffsll(static_cast<long long>(dJ)) - 1, q2 = 63 - __clzll(static_cast<long long>(dJ));
+  return (__popcll(C & between(lo, hi)) & 1) ? -v : v;
+}
+
+// Double: spin-orbitals p1 < p2 of I replaced by q1 < q2.
+__device__ __forceinline__ double h_double(uint64_t C, int p1, int p2, int q1, int q2,
+                                           const double* __restrict__ h2, int n) {
   double v = 0.0;
   if (((p1 ^ q1) & 1) == 0 && ((p2 ^ q2) & 1) == 0) v += eri(h2, n, p1 >> 1, q1 >> 1, p2 >> 1, q2 >> 1);
   if (((p1 ^ q2) & 1) == 0 && ((p2 ^ q1) & 1) == 0) v -= eri(h2, n, p1 >> 1, q2 >> 1, p2 >> 1, q1 >> 1);
@@ -1715,12 +1716,24 @@ __device__ double h_offdiag(uint64_t I, uint64_t J, int pc, const double* __rest
   return (par & 1) ? -v : v;
 }
 
+// <I|H|J> for determinants differing in pc = 2 (single) or 4 (double) bits.
+__device__ double h_offdiag(uint64_t I, uint64_t J, int pc, const double* __restrict__ h1,
+                            const double* __restrict__ h2, int n) {
+  const uint64_t d = I ^ J, C = I & J;
+  if (pc == 2)
+    return h_single(C, __ffsll(static_cast<long long>(I & d)) - 1, __ffsll(static_cast<long long>(J & d)) - 1, h1,
+                    h2, n);
+  const uint64_t dI = I & d, dJ = J & d;
+  return h_double(C, __ffsll(static_cast<long long>(dI)) - 1, 63 - __clzll(static_cast<long long>(dI)),
+                  __ffsll(static_cast<long long>(dJ)) - 1, 63 - __clzll(static_cast<long long>(dJ)), h2, n);
+}
+
 __device__ double h_diag(uint64_t I, const double* __restrict__ h1, const double* __restrict__ h2, int n) {
   double v = 0.0;
   for (uint64_t a = I; a; a &= a - 1ull) {
     const int p = __ffsll(static_cast<long long>(a)) - 1;
     const int P = p >> 1;
-    v += h1[P * n + P];
+    v += h1[__umul24(static_cast<unsigned int>(P), static_cast<unsigned int>(n)) + P];
     for (uint64_t bb = a & (a - 1ull); bb; bb &= bb - 1ull) {
       const int q = __ffsll(static_cast<long long>(bb)) - 1;
       const int Q = q >> 1;
@@ -1745,44 +1758,75 @@ struct Lists {
   const uint8_t* vb;
   int nA, nB, mA, mB;  // occupied / empty counts per spin
   int sA, sB, dAA, dBB, dAB;  // sizes of the excitation classes
+  int pA, pB;                 // empty-orbital pairs per spin
+  float rmA, rmB, rnB, rpA, rpB;  // 1/mA, 1/mB, 1/nB, 1/pA, 1/pB (unused where the divisor is 0)
 };
+
+// a / d and a % d for a < 2^22 and 1 <= d < 2^10, with rd = 1/d correctly
+// rounded to float: a * rd is within a/d * 2^-23 < 1/2 of a/d, so it
+// truncates to the true quotient or one off, and one remainder test corrects
+// it.  Full-rate instructions only (the integer divider's sequence uses
+// quarter-rate ones).
+__device__ __forceinline__ unsigned int udiv_small(unsigned int a, unsigned int d, float rd, unsigned int* rem) {
+  unsigned int q = static_cast<unsigned int>(static_cast<float>(a) * rd);
+  int r = static_cast<int>(a) - static_cast<int>(__umul24(q, d));
+  if (r < 0) {
+    --q;
+    r += static_cast<int>(d);
+  } else if (r >= static_cast<int>(d)) {
+    ++q;
+    r -= static_cast<int>(d);
+  }
+  *rem = static_cast<unsigned int>(r);
+  return q;
+}
 
 // Excitation number e (0 <= e < total) of I: alpha singles, beta singles,
 // alpha-alpha doubles, beta-beta doubles, alpha-beta doubles, each a flat
-// range.  Returns J and sets *rank to 2 (single) or 4 (double).
-__device__ __forceinline__ uint64_t excite(uint64_t I, int e, const Lists& L, const uint16_t* tri, int* rank) {
-  if (e < L.sA) {
-    const int x = e / L.mA;
+// range.  Returns J; *mv holds the moved spin-orbitals, one per byte: a
+// single p -> q as p | q << 16, a double p1 < p2 -> q1 < q2 as
+// p1 | p2 << 8 | q1 << 16 | q2 << 24; *rank is 2 (single) or 4 (double).
+__device__ __forceinline__ uint64_t excite(uint64_t I, int e, const Lists& L, const uint16_t* tri, int* rank,
+                                           unsigned int* mv) {
+  unsigned int r;
+  if (e < L.sA + L.sB) {
+    const bool beta = e >= L.sA;
+    if (beta) e -= L.sA;
+    const unsigned int x = beta ? udiv_small(e, L.mB, L.rmB, &r) : udiv_small(e, L.mA, L.rmA, &r);
+    const unsigned int p = beta ? L.ob[x] : L.oa[x], q = beta ? L.vb[r] : L.va[r];
     *rank = 2;
-    return I ^ (1ull << L.oa[x]) ^ (1ull << L.va[e - x * L.mA]);
+    *mv = p | q << 16;
+    return I ^ (1ull << p) ^ (1ull << q);
   }
-  e -= L.sA;
-  if (e < L.sB) {
-    const int x = e / L.mB;
-    *rank = 2;
-    return I ^ (1ull << L.ob[x]) ^ (1ull << L.vb[e - x * L.mB]);
-  }
-  e -= L.sB;
+  e -= L.sA + L.sB;
   *rank = 4;
+  unsigned int p1, p2, q1, q2;
   if (e < L.dAA + L.dBB) {
     const bool beta = e >= L.dAA;
     if (beta) e -= L.dAA;
     const uint8_t* oc = beta ? L.ob : L.oa;
     const uint8_t* vi = beta ? L.vb : L.va;
-    const int nv = beta ? L.mB : L.mA;
-    const int npv = nv * (nv - 1) / 2;
-    const int x = e / npv;
-    const uint16_t po = tri[x], pv = tri[e - x * npv];
-    return I ^ (1ull << oc[po & 255]) ^ (1ull << oc[po >> 8]) ^ (1ull << vi[pv & 255]) ^ (1ull << vi[pv >> 8]);
+    const unsigned int x = udiv_small(e, beta ? L.pB : L.pA, beta ? L.rpB : L.rpA, &r);
+    const uint16_t po = tri[x], pv = tri[r];
+    // the lists ascend and tri pairs ascend: p1 < p2, q1 < q2
+    p1 = oc[po & 255];
+    p2 = oc[po >> 8];
+    q1 = vi[pv & 255];
+    q2 = vi[pv >> 8];
+  } else {
+    e -= L.dAA + L.dBB;
+    unsigned int xa, xb, jb;
+    const unsigned int ea = udiv_small(e, L.mA, L.rmA, &xa);
+    const unsigned int eb = udiv_small(ea, L.mB, L.rmB, &xb);
+    const unsigned int ia = udiv_small(eb, L.nB, L.rnB, &jb);
+    const unsigned int oA = L.oa[ia], oB = L.ob[jb], vA = L.va[xa], vB = L.vb[xb];
+    p1 = oA < oB ? oA : oB;
+    p2 = oA < oB ? oB : oA;
+    q1 = vA < vB ? vA : vB;
+    q2 = vA < vB ? vB : vA;
   }
-  e -= L.dAA + L.dBB;
-  const int xa = e % L.mA;
-  e /= L.mA;
-  const int xb = e % L.mB;
-  e /= L.mB;
-  const int jb = e % L.nB;
-  const int ia = e / L.nB;
-  return I ^ (1ull << L.oa[ia]) ^ (1ull << L.ob[jb]) ^ (1ull << L.va[xa]) ^ (1ull << L.vb[xb]);
+  *mv = p1 | p2 << 8 | q1 << 16 | q2 << 24;
+  return I ^ (1ull << p1) ^ (1ull << p2) ^ (1ull << q1) ^ (1ull << q2);
 }
 
 // sigma_I = sum_J <I|H|J> c_J over the single and double excitations J of I
@@ -1835,20 +1879,28 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
     L.vb = row + 96;
     L.sA = L.nA * L.mA;
     L.sB = L.nB * L.mB;
-    L.dAA = L.nA * (L.nA - 1) / 2 * (L.mA * (L.mA - 1) / 2);
-    L.dBB = L.nB * (L.nB - 1) / 2 * (L.mB * (L.mB - 1) / 2);
+    L.pA = L.mA * (L.mA - 1) / 2;
+    L.pB = L.mB * (L.mB - 1) / 2;
+    L.dAA = L.nA * (L.nA - 1) / 2 * L.pA;
+    L.dBB = L.nB * (L.nB - 1) / 2 * L.pB;
     L.dAB = L.nA * L.nB * L.mA * L.mB;
+    L.rmA = __frcp_rn(static_cast<float>(L.mA));
+    L.rmB = __frcp_rn(static_cast<float>(L.mB));
+    L.rnB = __frcp_rn(static_cast<float>(L.nB));
+    L.rpA = __frcp_rn(static_cast<float>(L.pA));
+    L.rpB = __frcp_rn(static_cast<float>(L.pB));
     const int total = singles_only ? L.sA + L.sB : L.sA + L.sB + L.dAA + L.dBB + L.dAB;
     double acc = 0.0;
     for (int e0 = g; e0 < total; e0 += SG * SGU) {
       uint64_t J[SGU], home[SGU];
       int rank[SGU];
+      unsigned int mv[SGU];
       Slot<T> hv[SGU];
 #pragma unroll
       for (int u = 0; u < SGU; ++u) {
         const int e = e0 + u * SG;
         if (e < total) {
-          J[u] = excite(I, e, L, tri, &rank[u]);
+          J[u] = excite(I, e, L, tri, &rank[u], &mv[u]);
           home[u] = mix64(J[u]) & (H - 1);
           hv[u] = v.sl[home[u]];
         }
@@ -1859,7 +1911,13 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
         uint64_t ff;
         Slot<T> pv;
         const int64_t sj = find_slot_from(v.sl, H, J[u], home[u], hv[u], &ff, &pv);
-        if (sj >= 0 && !(pv.meta & DEAD)) acc += h_offdiag(I, J[u], rank[u], h1, h2, n) * static_cast<double>(pv.amp);
+        if (sj >= 0 && !(pv.meta & DEAD)) {
+          const uint64_t C = I & J[u];
+          const unsigned int m = mv[u];
+          const double h = rank[u] == 2 ? h_single(C, m & 255, (m >> 16) & 255, h1, h2, n)
+                                        : h_double(C, m & 255, (m >> 8) & 255, (m >> 16) & 255, m >> 24, h2, n);
+          acc += h * static_cast<double>(pv.amp);
+        }
       }
     }
 #pragma unroll
