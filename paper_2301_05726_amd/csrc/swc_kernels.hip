@@ -139,21 +139,67 @@ __device__ __forceinline__ Fx fx3_value(const Fx3& a) {
 
 __device__ __forceinline__ Fx3 fx3_zero() { return Fx3{{0ull, 0ull, 0ull}}; }
 
+// Wave sums through DPP lane moves (no LDS round trips).  Six steps, each
+// adding a moved copy: quad_perm [1,0,3,2] and [2,3,0,1] (quad sums),
+// row_half_mirror and row_mirror (row sums, every lane of a row), row_bcast
+// 15 into rows 1 and 3, row_bcast 31 into rows 2 and 3: lane 63 then holds
+// the total, read back as a wave-uniform value.  Lanes of rows a step leaves
+// out receive 0.  The sums are integer (exact), so the grouping does not
+// matter; every lane of the wave must be active.
+constexpr int DPP_QUAD_1032 = 0xb1, DPP_QUAD_2301 = 0x4e, DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141,
+              DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned int dpp_u32(unsigned int v) {
+  return static_cast<unsigned int>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROWS, 0xf, false));
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const unsigned int lo = dpp_u32<CTRL, ROWS>(static_cast<unsigned int>(v));
+  const unsigned int hi = dpp_u32<CTRL, ROWS>(static_cast<unsigned int>(v >> 32));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long lane63_u64(unsigned long long v) {
+  const unsigned int lo = static_cast<unsigned int>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
+  const unsigned int hi = static_cast<unsigned int>(__builtin_amdgcn_readlane(static_cast<int>(v >> 32), 63));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ Fx dpp_fx(Fx v) {
+  return Fx{dpp_u64<CTRL, ROWS>(v.lo), dpp_u64<CTRL, ROWS>(v.hi)};
+}
+
 __device__ __forceinline__ Fx wave_fx(Fx v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    Fx t;
-    t.lo = __shfl_xor(v.lo, o, 64);
-    t.hi = __shfl_xor(v.hi, o, 64);
-    v = fx_add(v, t);
-  }
-  return v;
+  v = fx_add(v, dpp_fx<DPP_QUAD_1032, 0xf>(v));
+  v = fx_add(v, dpp_fx<DPP_QUAD_2301, 0xf>(v));
+  v = fx_add(v, dpp_fx<DPP_ROW_HALF_MIRROR, 0xf>(v));
+  v = fx_add(v, dpp_fx<DPP_ROW_MIRROR, 0xf>(v));
+  v = fx_add(v, dpp_fx<DPP_ROW_BCAST15, 0xa>(v));
+  v = fx_add(v, dpp_fx<DPP_ROW_BCAST31, 0xc>(v));
+  return Fx{lane63_u64(v.lo), lane63_u64(v.hi)};
+}
+
+__device__ __forceinline__ unsigned int wave_u32(unsigned int v) {
+  v += dpp_u32<DPP_QUAD_1032, 0xf>(v);
+  v += dpp_u32<DPP_QUAD_2301, 0xf>(v);
+  v += dpp_u32<DPP_ROW_HALF_MIRROR, 0xf>(v);
+  v += dpp_u32<DPP_ROW_MIRROR, 0xf>(v);
+  v += dpp_u32<DPP_ROW_BCAST15, 0xa>(v);
+  v += dpp_u32<DPP_ROW_BCAST31, 0xc>(v);
+  return static_cast<unsigned int>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
 }
 
 __device__ __forceinline__ unsigned long long wave_u64(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_u64<DPP_QUAD_1032, 0xf>(v);
+  v += dpp_u64<DPP_QUAD_2301, 0xf>(v);
+  v += dpp_u64<DPP_ROW_HALF_MIRROR, 0xf>(v);
+  v += dpp_u64<DPP_ROW_MIRROR, 0xf>(v);
+  v += dpp_u64<DPP_ROW_BCAST15, 0xa>(v);
+  v += dpp_u64<DPP_ROW_BCAST31, 0xc>(v);
+  return lane63_u64(v);
 }
 
 // block-wide sums of one Fx and up to 7 counters (32-bit: per-launch counts
@@ -167,10 +213,7 @@ __device__ __forceinline__ Red block_reduce(Red r) {
   __shared__ Red part[BLK / 64];
   r.f = wave_fx(r.f);
 #pragma unroll
-  for (int i = 0; i < 7; ++i) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) r.c[i] += __shfl_xor(r.c[i], o, 64);
-  }
+  for (int i = 0; i < 7; ++i) r.c[i] = wave_u32(r.c[i]);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) part[w] = r;
   __syncthreads();
@@ -348,12 +391,6 @@ __device__ __forceinline__ double wave_scale(const StepArr& sa, int b, int k) {
     }
   }
   return S;
-}
-
-__device__ __forceinline__ unsigned int wave_u32(unsigned int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
 }
 
 // global wave index within state b's launch (per-wave statistics slot)
