@@ -512,13 +512,23 @@ __global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy
   const double S = fold_only ? 0.0 : wave_scale(sa, b, static_cast<int>(M) + 1);
   unsigned long long tot[WSTAT];
   for (int i = 0; i < WSTAT; ++i) tot[i] = 0;
-  for (int64_t w = threadIdx.x; w < sa.nws; w += 64)
+  for (int64_t w = threadIdx.x; w < sa.nws; w += blockDim.x)
+#pragma unroll
     for (int i = 0; i < WSTAT; ++i) {
       tot[i] += sa.ws[(b * sa.nws + w) * WSTAT + i];
       sa.ws[(b * sa.nws + w) * WSTAT + i] = 0ull;  // folded: a later chunk starts from zero
     }
+  // block totals: wave sums, then wave 0 adds the other waves' (LDS)
+  __shared__ unsigned long long part[BLK / 64][WSTAT];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
   for (int i = 0; i < WSTAT; ++i) tot[i] = wave_u64(tot[i]);
-  // live count over the shards, before this fold (one wave: threads 0..63)
+  if (lane == 0)
+    for (int i = 0; i < WSTAT; ++i) part[wv][i] = tot[i];
+  __syncthreads();
+  for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w)
+    for (int i = 0; i < WSTAT; ++i) tot[i] += part[w][i];
+  // live count over the shards, before this fold (wave 0's lanes < CSH)
   unsigned long long live = threadIdx.x < CSH ? cnt[b].sh[threadIdx.x].v[C_LIVE] : 0ull;
   live = wave_u64(live);
   if (threadIdx.x == 0) {
@@ -1765,17 +1775,21 @@ __device__ double h_offdiag(uint64_t I, uint64_t J, int pc, const double* __rest
                   __ffsll(static_cast<long long>(dJ)) - 1, 63 - __clzll(static_cast<long long>(dJ)), h2, n);
 }
 
-__device__ double h_diag(uint64_t I, const double* __restrict__ h1, const double* __restrict__ h2, int n) {
+// <I|H|I> from the one-electron diagonal d1[P] = h_PP and the Coulomb and
+// exchange tables J[P][Q] = (PP|QQ), K[P][Q] = (PQ|QP) staged in LDS (the
+// same terms, added in the same order, as the n^4 integrals give them).
+__device__ double h_diag(uint64_t I, const double* d1, const double* J, const double* K, int n) {
   double v = 0.0;
   for (uint64_t a = I; a; a &= a - 1ull) {
     const int p = __ffsll(static_cast<long long>(a)) - 1;
     const int P = p >> 1;
-    v += h1[__umul24(static_cast<unsigned int>(P), static_cast<unsigned int>(n)) + P];
+    const unsigned int row = __umul24(static_cast<unsigned int>(P), static_cast<unsigned int>(n));
+    v += d1[P];
     for (uint64_t bb = a & (a - 1ull); bb; bb &= bb - 1ull) {
       const int q = __ffsll(static_cast<long long>(bb)) - 1;
       const int Q = q >> 1;
-      v += eri(h2, n, P, P, Q, Q);
-      if (((p ^ q) & 1) == 0) v -= eri(h2, n, P, Q, Q, P);
+      v += J[row + Q];
+      if (((p ^ q) & 1) == 0) v -= K[row + Q];
     }
   }
   return v;
@@ -1967,12 +1981,20 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
 __global__ __launch_bounds__(BLK) void k_energy_reduce(Compact cp, Counters* cnt, uint64_t H,
                                                        const double* __restrict__ h1, const double* __restrict__ h2,
                                                        int n) {
+  __shared__ double d1[32], Jt[32 * 32], Kt[32 * 32];  // n <= 32 spatial orbitals
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int P = e / n, Q = e - P * n;
+    Jt[e] = eri(h2, n, P, P, Q, Q);
+    Kt[e] = eri(h2, n, P, Q, Q, P);
+  }
+  for (int P = threadIdx.x; P < n; P += blockDim.x) d1[P] = h1[P * n + P];
+  __syncthreads();
   const int b = blockIdx.y;
   const int64_t N = static_cast<int64_t>(cnt[b].ncompact);
   Fx num = fx_zero(), den = fx_zero();
   for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     const double c = cp.amp[b * H + i];
-    const double sig = cp.sig[b * H + i] + h_diag(cp.key[b * H + i], h1, h2, n) * c;
+    const double sig = cp.sig[b * H + i] + h_diag(cp.key[b * H + i], d1, Jt, Kt, n) * c;
     cp.sig[b * H + i] = sig;
     num = fx_add(num, fx_from(c * sig));
     den = fx_add(den, fx_from(c * c));
@@ -2099,6 +2121,7 @@ __global__ void k_grad_final(StepArr sa, const Counters* cnt, double* grad, int6
   const double den = fx_to_d(cnt[b].den);
   for (int64_t k = blockIdx.x * blockDim.x + threadIdx.x; k < M; k += gridDim.x * blockDim.x) {
     Fx g = fx_zero();
+#pragma unroll 16
     for (int q = 0; q < SH; ++q) g = fx_add(g, fx3_value(sa.gacc[sidx(sa, b, q, k + 1)]));
     grad[b * M + k] = 2.0 * fx_to_d(g) / den;
   }
@@ -2139,7 +2162,7 @@ void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t 
 
 void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, int fold_only,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_sweep_end, dim3(B), dim3(64), 0, st, sa, cnt, M, sy, fold_only);
+  hipLaunchKernelGGL(k_sweep_end, dim3(B), dim3(BLK), 0, st, sa, cnt, M, sy, fold_only);
 }
 
 void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st) {
