@@ -74,6 +74,14 @@ struct alignas(128) CShard {
   unsigned long long v[16];
 };
 
+// Shards of the energy sums sum c sigma and sum c^2 (exact, 3 limbs each):
+// a block of the energy reduction adds to shard (blockIdx.x % ESH) with
+// non-returning atomics; the final kernel adds the shards.
+constexpr int ESH = 16;
+struct alignas(128) ESum {
+  Fx3 num, den;
+};
+
 // per-state device counters
 struct Counters {
   CShard sh[CSH];
@@ -86,6 +94,7 @@ struct Counters {
   Fx den;                       // sum c^2
   double E;
   double pad2;
+  ESum es[ESH];
 };
 
 inline unsigned long long counter_total(const Counters& c, int which) {

@@ -108,12 +108,6 @@ __device__ __forceinline__ double fx_to_d(Fx a) {
 
 __device__ __forceinline__ bool fx_nonzero(Fx a) { return (a.lo | a.hi) != 0ull; }
 
-__device__ __forceinline__ void fx_atomic_add(Fx* dst, Fx v) {
-  const unsigned long long old = atomicAdd(&dst->lo, v.lo);
-  const unsigned long long carry = (old + v.lo < old) ? 1ull : 0ull;
-  atomicAdd(&dst->hi, v.hi + carry);
-}
-
 __device__ __forceinline__ void fx3_atomic_add(Fx3* dst, Fx v) {
   constexpr unsigned long long M42 = (1ull << 42) - 1ull;
   const unsigned long long l0 = v.lo & M42;
@@ -2003,11 +1997,12 @@ __global__ __launch_bounds__(BLK) void k_energy_reduce(Compact cp, Counters* cnt
   r.f = num;
   for (int q = 0; q < 7; ++q) r.c[q] = 0;
   r = block_reduce(r);
-  if (threadIdx.x == 0 && fx_nonzero(r.f)) fx_atomic_add(&cnt[b].num, r.f);
+  ESum& es = cnt[b].es[blockIdx.x & (ESH - 1)];
+  if (threadIdx.x == 0 && fx_nonzero(r.f)) fx3_atomic_add(&es.num, r.f);
   __syncthreads();
   r.f = den;
   r = block_reduce(r);
-  if (threadIdx.x == 0 && fx_nonzero(r.f)) fx_atomic_add(&cnt[b].den, r.f);
+  if (threadIdx.x == 0 && fx_nonzero(r.f)) fx3_atomic_add(&es.den, r.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -2092,12 +2087,23 @@ __global__ void k_energy_begin(Counters* cnt, int B) {
   cnt[b].ncompact = 0;
   cnt[b].num = fx_zero();
   cnt[b].den = fx_zero();
+  for (int q = 0; q < ESH; ++q) {
+    cnt[b].es[q].num = fx3_zero();
+    cnt[b].es[q].den = fx3_zero();
+  }
 }
 
 __global__ void k_energy_final(Counters* cnt, double* E, int B) {
   const int b = threadIdx.x;
   if (b >= B) return;
-  const double e = fx_to_d(cnt[b].num) / fx_to_d(cnt[b].den);
+  Fx num = fx_zero(), den = fx_zero();
+  for (int q = 0; q < ESH; ++q) {
+    num = fx_add(num, fx3_value(cnt[b].es[q].num));
+    den = fx_add(den, fx3_value(cnt[b].es[q].den));
+  }
+  cnt[b].num = num;
+  cnt[b].den = den;
+  const double e = fx_to_d(num) / fx_to_d(den);
   cnt[b].E = e;
   if (E) E[b] = e;
 }
@@ -2116,15 +2122,16 @@ __global__ void k_lambda(Tab t, Compact cp, const Counters* cnt) {
   }
 }
 
+// dE/dtheta_k = 2 <w|A_k psi> / <psi|psi>: one wave per step, lane q adding
+// shard q (exact sums, so the grouping changes nothing)
+static_assert(SH == 64, "one lane per gradient shard");
 __global__ void k_grad_final(StepArr sa, const Counters* cnt, double* grad, int64_t M) {
   const int b = blockIdx.y;
-  const double den = fx_to_d(cnt[b].den);
-  for (int64_t k = blockIdx.x * blockDim.x + threadIdx.x; k < M; k += gridDim.x * blockDim.x) {
-    Fx g = fx_zero();
-#pragma unroll 16
-    for (int q = 0; q < SH; ++q) g = fx_add(g, fx3_value(sa.gacc[sidx(sa, b, q, k + 1)]));
-    grad[b * M + k] = 2.0 * fx_to_d(g) / den;
-  }
+  const int lane = threadIdx.x & 63;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * (BLK / 64) + (threadIdx.x >> 6);  // uniform in a wave
+  const Fx v = k < M ? fx3_value(sa.gacc[sidx(sa, b, lane, k + 1)]) : fx_zero();
+  const Fx g = wave_fx(v);
+  if (lane == 0 && k < M) grad[b * M + k] = 2.0 * fx_to_d(g) / fx_to_d(cnt[b].den);
 }
 
 // ---------------------------------------------------------------------------
@@ -2349,7 +2356,8 @@ void launch_lambda(const Tab& t, const Compact& cp, const Counters* cnt, int64_t
 
 void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int64_t M, int B, hipStream_t st) {
   if (M <= 0) return;
-  hipLaunchKernelGGL(k_grad_final, dim3(grid_for(M, BLK, 1024), B), dim3(BLK), 0, st, sa, cnt, grad, M);
+  hipLaunchKernelGGL(k_grad_final, dim3(static_cast<unsigned int>((M + BLK / 64 - 1) / (BLK / 64)), B), dim3(BLK), 0, st,
+                     sa, cnt, grad, M);
 }
 
 // ---------------------------------------------------------------------------
