@@ -138,6 +138,28 @@ def canonical_excitations(n_orb: int, n_occ: int):
     return singles, doubles
 
 
+def open_shell_det(n_alpha: int, n_beta: int) -> int:
+    """Aufbau determinant with n_alpha alpha (2p) and n_beta beta (2p+1)
+    electrons in the lowest spatial orbitals."""
+    return sum(1 << (2 * p) for p in range(n_alpha)) | sum(1 << (2 * p + 1) for p in range(n_beta))
+
+
+def open_shell_excitations(n_orb: int, n_alpha: int, n_beta: int) -> np.ndarray:
+    """Spin-conserving singles, then doubles, relative to
+    open_shell_det(n_alpha, n_beta), as an int8 array of (i, j, a, b) rows."""
+    ref = open_shell_det(n_alpha, n_beta)
+    occ = [q for q in range(2 * n_orb) if ref >> q & 1]
+    vir = [q for q in range(2 * n_orb) if not ref >> q & 1]
+    rows = [(i, -1, a, -1) for i in occ for a in vir if spin(i) == spin(a)]
+    for ii, i in enumerate(occ):
+        for j in occ[ii + 1:]:
+            for aa, a in enumerate(vir):
+                for b in vir[aa + 1:]:
+                    if spin(i) + spin(j) == spin(a) + spin(b):
+                        rows.append((i, j, a, b))
+    return np.array(rows, dtype=np.int8).reshape(-1, 4)
+
+
 def uccsd_count(n_orb: int, n_occ: int) -> int:
     """Closed form 2ov + 2 C(o,2) C(v,2) + o^2 v^2 for o occupied and v
     virtual spatial orbitals per spin."""

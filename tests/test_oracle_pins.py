@@ -96,6 +96,32 @@ def test_forward_matches_dense_statevector(orc, n_orb, n_occ, sigma, seed):
         assert abs(psi @ (H @ psi) - e_dense) < 1e-11
 
 
+@pytest.mark.parametrize("n_orb,n_alpha,n_beta,sigma,seed", [(5, 3, 1, 0.3, 61), (6, 3, 2, 0.2, 62)])
+def test_open_shell_matches_dense_statevector(orc, n_orb, n_alpha, n_beta, sigma, seed):
+    """Different alpha and beta electron counts: state, energy and gradient
+    against the dense Jordan-Wigner statevector and central differences."""
+    h1, h2 = synth.make_hamiltonian(n_orb, seed)
+    exc = synth.open_shell_excitations(n_orb, n_alpha, n_beta)
+    theta = synth.make_theta(exc.shape[0], sigma, seed + 1)
+    ref = synth.open_shell_det(n_alpha, n_beta)
+    nq = 2 * n_orb
+    d, a, _, _ = orc.apply_ucc(nq, [ref], [1.0], exc, theta, 0.0)
+    jw = DenseJW(nq)
+    psi = jw.apply_factors(jw.basis([ref]), exc, theta)
+    dense = np.zeros(1 << nq)
+    dense[d.astype(np.int64)] = a
+    assert np.max(np.abs(dense - psi)) < 1e-12
+    # every determinant keeps the electron count of each spin
+    assert all(bin(int(x) & 0x5555555555555555).count("1") == n_alpha for x in d)
+    e_dense = jw.energy_epq(h1, h2, psi)
+    assert abs(orc.energy(n_orb, h1, h2, d, a, mode=1) - e_dense) < 1e-11
+    E, g, _ = orc.energy_and_grad(nq, [ref], [1.0], exc, theta, 0.0, h1, h2)
+    assert abs(E - e_dense) < 1e-11
+    idx = synth.fd_subset(exc.shape[0], 16, 3000 + seed)
+    fd = orc.fd_grad(nq, [ref], [1.0], exc, theta, 0.0, h1, h2, idx, h=1e-5)
+    assert np.max(np.abs(fd - g[idx])) < 2e-9
+
+
 @pytest.mark.slow
 def test_forward_matches_dense_16_qubits(orc):
     h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 14)
