@@ -266,6 +266,7 @@ struct swc_ctx {
   // res_fwd / res_rev: resident blocks of k_fwd / k_rev on the whole device.
   int grid_fs = 1, grid_rs = 1;
   int res_fwd = 0, res_rev = 0, res_fwd5 = 0;
+  int res_f2w = 0, res_r2w = 0;  // resident blocks (all members) of the wide two-factor kernels
   // forward steps use the five-wave build of k_fwd when the table takes more
   // than one pass of the resident lanes (a latency-bound one-pass table runs
   // faster without its register spills)
@@ -336,6 +337,13 @@ void set_table(swc_ctx* c, int r, uint64_t Hn) {
   const int rf = c->fwd_wide ? c->res_fwd5 : c->res_fwd;
   c->grid_fs = rf > 0 ? std::min(g, rf) : g;
   c->grid_rs = c->res_rev > 0 ? std::min(g, c->res_rev) : g;
+}
+
+// Two-factor launches load several slots per probe up front when one launch
+// covers the current table in one pass and all its blocks are resident at once.
+int wide2(const swc_ctx* c, int resident) {
+  return static_cast<uint64_t>(c->grid) * 256 >= c->tab.H &&  // 256-thread blocks, one slot per lane
+         static_cast<int64_t>(c->grid) * c->B <= static_cast<int64_t>(resident);
 }
 
 // Occupancy above which a forward step stops the sweep for a growth: with at
@@ -491,7 +499,8 @@ template <class T>
 void issue_fwd(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint64_t lim, hipStream_t st) {
   for (int64_t k = k0; k <= k1;) {
     if (k < k1 && fusable(c, k, thr, lim)) {
-      launch_fwd2<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid, st);
+      launch_fwd2<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid,
+                     wide2(c, c->res_f2w), st);
       k += 2;
     } else {
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
@@ -510,7 +519,8 @@ int64_t issue_rev(swc_ctx* c, int64_t hi, int64_t lo, bool fuse, hipStream_t st)
   int64_t n = 0;
   for (int64_t k = hi; k >= lo; ++n) {
     if (fuse && k > lo && c->hmask[k - 2] != c->hmask[k - 1]) {
-      launch_rev2<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k - 1), c->B, c->grid, st);
+      launch_rev2<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k - 1), c->B, c->grid,
+                     wide2(c, c->res_r2w), st);
       k -= 2;
     } else {
       launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid_rs, st);
@@ -1108,6 +1118,8 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     c->res_fwd = std::max(1, sf * ncu / batch);
     c->res_rev = std::max(1, sr * ncu / batch);
     c->res_fwd5 = std::max(1, s5 * ncu / batch);
+    c->res_f2w = (prec == SWC_FP32 ? resident_blocks_per_cu<float>(5) : resident_blocks_per_cu<double>(5)) * ncu;
+    c->res_r2w = (prec == SWC_FP32 ? resident_blocks_per_cu<float>(6) : resident_blocks_per_cu<double>(6)) * ncu;
     set_table(c, 0, c->H);  // step grids with the resident limits
   }
   if (const char* e = std::getenv("SWC_KERNEL_TIMING")) c->ktiming = std::atoi(e) != 0;

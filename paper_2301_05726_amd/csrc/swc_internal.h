@@ -257,12 +257,14 @@ void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, 
                 int k, int B, int grid, hipStream_t st);
 // steps k and k+1 in one launch (threshold 0, factors with different XOR
 // masks; the table cannot grow during it), and their reverse (no truncation log)
+// (wide: several slots from every home loaded up front; for launches that
+// cover the table in one pass with all blocks resident)
 template <class T>
 void launch_fwd2(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                 int k, int B, int grid, hipStream_t st);
+                 int k, int B, int grid, int wide, hipStream_t st);
 template <class T>
 void launch_rev2(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                 int k, int B, int grid, hipStream_t st);
+                 int k, int B, int grid, int wide, hipStream_t st);
 template <class T>
 void launch_log_restore(const Tab& t, const LogArr& lg, const StepArr& sa, int k, int B, uint32_t maxcnt,
                         hipStream_t st);

@@ -250,21 +250,18 @@ __device__ __forceinline__ int64_t find_slot(const Slot<T>* __restrict__ sl, uin
 // long probe sequence costs one round trip per PG slots rather than per slot;
 // the longest sequence in a launch sets the launch's duration.
 constexpr int PG = 4;
+// slots from the home loaded up front by the two-factor sweep kernels when
+// one launch covers the table in one pass (4: most probes end inside them;
+// 8 measured slower, fewer resident waves)
+constexpr int PH2 = 4;
 
+// The probe's continuation after slot s, the slots already checked counting
+// i0: PG slots per round trip.
 template <class T>
-__device__ __forceinline__ int64_t find_slot_from(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key,
-                                                  uint64_t home, Slot<T> v, uint64_t* first_free, Slot<T>* out) {
+__device__ __forceinline__ int64_t probe_past(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key, uint64_t s,
+                                              uint64_t i0, uint64_t* first_free, Slot<T>* out) {
   const uint64_t mask = H - 1;
-  if (v.key == key) {
-    *out = v;
-    return static_cast<int64_t>(home);
-  }
-  if (v.key == EMPTY_KEY) {
-    *first_free = home;
-    return -1;
-  }
-  uint64_t s = home;
-  for (uint64_t i = 1; i < H; i += PG) {
+  for (uint64_t i = i0; i < H; i += PG) {
     Slot<T> w[PG];
 #pragma unroll
     for (int j = 0; j < PG; ++j) w[j] = sl[(s + 1 + j) & mask];
@@ -284,6 +281,42 @@ __device__ __forceinline__ int64_t find_slot_from(const Slot<T>* __restrict__ sl
   }
   *first_free = H;
   return -1;
+}
+
+template <class T>
+__device__ __forceinline__ int64_t find_slot_from(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key,
+                                                  uint64_t home, Slot<T> v, uint64_t* first_free, Slot<T>* out) {
+  if (v.key == key) {
+    *out = v;
+    return static_cast<int64_t>(home);
+  }
+  if (v.key == EMPTY_KEY) {
+    *first_free = home;
+    return -1;
+  }
+  return probe_past<T>(sl, H, key, home, 1, first_free, out);
+}
+
+// find_slot_from with the first PH slots from home already loaded
+// (pre[j] = sl[home + j]): an answer within them costs no further round trip.
+template <class T, int PH>
+__device__ __forceinline__ int64_t find_slot_pre(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key,
+                                                 uint64_t home, const Slot<T> (&pre)[PH], uint64_t* first_free,
+                                                 Slot<T>* out) {
+  const uint64_t mask = H - 1;
+#pragma unroll
+  for (int j = 0; j < PH; ++j) {
+    const uint64_t t = (home + j) & mask;
+    if (pre[j].key == key) {
+      *out = pre[j];
+      return static_cast<int64_t>(t);
+    }
+    if (pre[j].key == EMPTY_KEY) {
+      *first_free = t;
+      return -1;
+    }
+  }
+  return probe_past<T>(sl, H, key, (home + PH - 1) & mask, PH, first_free, out);
 }
 
 // Claim an EMPTY slot for `key` (known to be absent), starting the linear
@@ -1018,7 +1051,7 @@ __device__ __forceinline__ Quad make_quad(uint64_t X, uint64_t m1, uint64_t m2, 
   return Q;
 }
 
-template <class T>
+template <class T, int PH>
 __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
                                               int64_t ld, StepArr sa, Counters* cnt, int k) {
   const int b = blockIdx.y;
@@ -1059,13 +1092,17 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
     pres[0] = true;
     a[0] = me.amp;
     bool owner = true;
-    // home slots of the other members, loaded together
+    // the first PH slots from the home of every other member, loaded
+    // together: most probes end inside them, so a launch rarely waits for a
+    // third dependent round trip
     uint64_t home[4];
-    Slot<T> hv[4];
+    Slot<T> hv[4][PH];
 #pragma unroll
     for (int j = 1; j < 4; ++j) {
       home[j] = mix64(Q.q[j]) & (H - 1);
-      if (Q.comp & (1u << j)) hv[j] = v.sl[home[j]];
+      if (Q.comp & (1u << j))
+#pragma unroll
+        for (int i = 0; i < PH; ++i) hv[j][i] = v.sl[(home[j] + i) & (H - 1)];
     }
 #pragma unroll
     for (int j = 1; j < 4; ++j) {
@@ -1077,7 +1114,7 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
       Slot<T> pv;
       pv.meta = 0u;
       pv.amp = T(0);
-      slot[j] = find_slot_from(v.sl, H, Q.q[j], home[j], hv[j], &ff[j], &pv);
+      slot[j] = find_slot_pre<T, PH>(v.sl, H, Q.q[j], home[j], hv[j], &ff[j], &pv);
       if (slot[j] >= 0) {
         const uint32_t pt = pv.meta & TAG;
         // present when the launch started: alive and not created by it
@@ -1166,7 +1203,7 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
 // Reverse of steps k+1 then k (threshold 0: nothing was truncated, so the
 // members present after the forward step are the alive ones; members created
 // by a step are removed when it is undone).
-template <class T>
+template <class T, int PH>
 __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
                                               int64_t ld, StepArr sa, Counters* cnt, int k) {
   const int b = blockIdx.y;
@@ -1198,16 +1235,20 @@ __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__
     l[0] = v.lam_fin(me, lam_me);
     born[0] = me.meta & TAG;
     bool owner = true;
-    // home slots (and adjoint values there) of the other members, loaded together
+    // the first PH slots from the home of every other member (and the
+    // adjoint values there), loaded together
     uint64_t home[4];
-    Slot<T> hv[4];
-    T hl[4];
+    Slot<T> hv[4][PH];
+    T hl[4][PH];
 #pragma unroll
     for (int j = 1; j < 4; ++j) {
       home[j] = mix64(Q.q[j]) & (H - 1);
       if (Q.comp & (1u << j)) {
-        hv[j] = v.sl[home[j]];
-        hl[j] = v.lam_pre(home[j]);
+#pragma unroll
+        for (int i = 0; i < PH; ++i) {
+          hv[j][i] = v.sl[(home[j] + i) & (H - 1)];
+          hl[j][i] = v.lam_pre((home[j] + i) & (H - 1));
+        }
       }
     }
 #pragma unroll
@@ -1222,7 +1263,7 @@ __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__
       Slot<T> pv;
       pv.meta = 0u;
       pv.amp = T(0);
-      slot[j] = find_slot_from(v.sl, H, Q.q[j], home[j], hv[j], &ff, &pv);
+      slot[j] = find_slot_pre<T, PH>(v.sl, H, Q.q[j], home[j], hv[j], &ff, &pv);
       if (slot[j] < 0) continue;
       const uint32_t pt = pv.meta & TAG;
       // present when the launch started: alive, or removed by this launch
@@ -1230,8 +1271,12 @@ __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__
       if (!pres[j]) continue;
       if (Q.q[j] < Q.q[0]) owner = false;
       a[j] = pv.amp;
-      l[j] = static_cast<uint64_t>(slot[j]) == home[j] ? v.lam_fin(pv, hl[j])
-                                                       : v.lam_of(pv, static_cast<uint64_t>(slot[j]));
+      const uint64_t off = (static_cast<uint64_t>(slot[j]) - home[j]) & (H - 1);
+      T lp = T(0);
+#pragma unroll
+      for (int i = 0; i < PH; ++i)
+        if (off == static_cast<uint64_t>(i)) lp = hl[j][i];
+      l[j] = off < PH ? v.lam_fin(pv, lp) : v.lam_of(pv, static_cast<uint64_t>(slot[j]));
       born[j] = (pv.meta & DEAD) ? v.born(static_cast<uint64_t>(slot[j])) : pt;
     }
     if (!owner) continue;
@@ -2186,6 +2231,8 @@ int resident_blocks_per_cu(int which) {
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd<T, false, 1>, BLK, 0); break;
     case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev<T>, BLK, 0); break;
     case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd<T, false, 5>, BLK, 0); break;
+    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd2<T, PH2>, BLK, 0); break;
+    case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev2<T, PH2>, BLK, 0); break;
     default: break;
   }
   return e == hipSuccess ? nb : 0;
@@ -2251,14 +2298,23 @@ void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, 
 
 template <class T>
 void launch_fwd2(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                 int k, int B, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_fwd2<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
+                 int k, int B, int grid, int wide, hipStream_t st) {
+  // wide: PH2 slots from every home loaded up front (the caller chooses it
+  // when the launch covers the table in one pass with all its blocks
+  // resident); otherwise the home slot only, keeping more waves resident
+  if (wide)
+    hipLaunchKernelGGL((k_fwd2<T, PH2>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
+  else
+    hipLaunchKernelGGL((k_fwd2<T, 1>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
 }
 
 template <class T>
 void launch_rev2(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                 int k, int B, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_rev2<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
+                 int k, int B, int grid, int wide, hipStream_t st) {
+  if (wide)
+    hipLaunchKernelGGL((k_rev2<T, PH2>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
+  else
+    hipLaunchKernelGGL((k_rev2<T, 1>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
 }
 
 template <class T>
@@ -2692,9 +2748,9 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
   template void launch_rehash<T>(const Tab&, const Tab&, Counters*, int, uint32_t, hipStream_t);                \
   template void launch_count_keep<T>(const Tab&, Counters*, int, uint32_t, hipStream_t);                        \
   template void launch_fwd2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \
-                               int, int, hipStream_t);                                                             \
+                               int, int, int, hipStream_t);                                                        \
   template void launch_rev2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \
-                               int, int, hipStream_t);                                                             \
+                               int, int, int, hipStream_t);                                                        \
   template void launch_snapshot<T>(const Tab&, const Snap&, int, int, hipStream_t);                              \
   template void launch_entropy_scan<T>(const Tab&, const StepArr&, int, int, int, hipStream_t);                   \
   template void launch_topk<T>(const Tab&, const StepArr&, Counters*, TopK*, int, uint64_t, uint64_t, int, int,   \

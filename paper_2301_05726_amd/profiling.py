@@ -90,6 +90,23 @@ def peaks(gib: float, reps: int) -> None:
     torch.cuda.synchronize()
     print(f"graph of {nodes} one-element kernels: {t / nodes * 1e6:.2f} us per node "
           f"(x = {x.item():.0f}, expected {1 + (1 + reps) * nodes}: every node ran)", flush=True)
+    # the same chain of launches, each node reading and writing a whole
+    # table-sized buffer once (2 MiB: the 20-qubit table; 8 MiB: 64 qubits)
+    for mib in (2, 8):
+        y = torch.zeros(mib * (1 << 20) // 4, device=dev)
+        with torch.cuda.stream(side):
+            y.add_(1.0)
+        torch.cuda.current_stream(dev).wait_stream(side)
+        gy = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gy):
+            for _ in range(nodes):
+                y.add_(1.0)
+        t = timed(gy.replay)
+        torch.cuda.synchronize()
+        ok = float(y[0].item()) == 1 + (1 + reps) * nodes
+        print(f"graph of {nodes} kernels each streaming {mib} MiB (read + write): {t / nodes * 1e6:.2f} us per node, "
+              f"{2 * mib * (1 << 20) / (t / nodes) / 1e9:.0f} GB/s (every node ran: {ok})", flush=True)
+        del gy, y
 
 
 def _short(name: str) -> str:
