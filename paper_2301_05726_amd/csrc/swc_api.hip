@@ -255,6 +255,7 @@ struct swc_ctx {
   std::vector<double> h_init_a;
   double S0 = 1.0;
   bool built = false;
+  bool fresh = false;  // the table holds |Psi_0> exactly as a reset leaves it (no call since)
   std::vector<swc_exc> exc_cache;
   hipEvent_t ev[8] = {};
   double fwd_ms = 0, energy_ms = 0, rev_ms = 0;
@@ -409,6 +410,7 @@ int reset_state(swc_ctx* c) {
   });
   if (r) return r;
   SWC_HIP(hipGetLastError());
+  c->fresh = true;
   return SWC_OK;
 }
 
@@ -1188,6 +1190,7 @@ int swc_build_state(swc_ctx* c, const uint64_t* dets, const double* amps, int64_
 
 int swc_apply_ucc(swc_ctx* c, const double* theta, const swc_exc* exc, int64_t M, double threshold) {
   if (!c) return fail(SWC_EINVAL, "null context");
+  c->fresh = false;
   if (!c->built) return fail(SWC_ESTATE, "no state built");
   if (M < 0 || M > c->Mmax) return fail(SWC_EINVAL, "factor count above max_factors");
   if (!(threshold >= 0.0) || !std::isfinite(threshold)) return fail(SWC_EINVAL, "threshold must be finite and >= 0");
@@ -1209,6 +1212,7 @@ int swc_apply_ucc(swc_ctx* c, const double* theta, const swc_exc* exc, int64_t M
 
 int swc_energy(swc_ctx* c, const double* h1, const double* h2, double* E) {
   if (!c) return fail(SWC_EINVAL, "null context");
+  c->fresh = false;
   if (!c->built) return fail(SWC_ESTATE, "no state built");
   if (!E) return fail(SWC_EINVAL, "null output");
   int r = energy_impl(c, h1, h2, E, false);
@@ -1229,7 +1233,10 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   int r = check_exc(c->nq, exc, M);
   if (r) return r;
   if ((r = upload_masks(c, exc, M))) return r;
-  if ((r = reset_state(c))) return r;
+  // a call that follows a reset (the end of the previous gradient call, or
+  // build_state) with nothing in between starts from that table as it is
+  if (!c->fresh && (r = reset_state(c))) return r;
+  c->fresh = false;
   // the angle check's flag is read with the forward sweep's status below
   if ((r = check_theta(c, theta, M, false))) return r;
   if ((r = forward_sweep(c, M, threshold, 1))) return r;
@@ -1342,6 +1349,7 @@ size_t swc_checkpoint_bytes(int prec, int batch, int64_t max_factors, int64_t in
 
 int swc_set_checkpoints(swc_ctx* c, int64_t interval, uint64_t max_entries, void* buffer, size_t bytes) {
   if (!c) return fail(SWC_EINVAL, "null context");
+  c->fresh = false;
   if (interval <= 0) {
     c->ck_interval = 0;
     c->ck_n = 0;
@@ -1368,6 +1376,7 @@ int swc_set_checkpoints(swc_ctx* c, int64_t interval, uint64_t max_entries, void
 
 int swc_set_sigma_scratch(swc_ctx* c, void* buffer, size_t bytes, int mode) {
   if (!c) return fail(SWC_EINVAL, "null context");
+  c->fresh = false;
   if (mode < 0 || mode > 2) return fail(SWC_EINVAL, "mode must be 0 (auto), 1 (always) or 2 (never)");
   if (buffer && reinterpret_cast<uintptr_t>(buffer) % ALIGN) return fail(SWC_EINVAL, "scratch not 256-byte aligned");
   c->sig_buf = static_cast<char*>(buffer);
@@ -1380,6 +1389,7 @@ int swc_set_sigma_scratch(swc_ctx* c, void* buffer, size_t bytes, int mode) {
 
 int swc_set_topk(swc_ctx* c, uint64_t n_max, uint64_t n_cut) {
   if (!c) return fail(SWC_EINVAL, "null context");
+  c->fresh = false;
   if (n_max == 0 && n_cut == 0) {
     c->tk_max = c->tk_cut = 0;
     return SWC_OK;
@@ -1392,12 +1402,14 @@ int swc_set_topk(swc_ctx* c, uint64_t n_max, uint64_t n_cut) {
 
 int swc_track_entropy(swc_ctx* c, int on) {
   if (!c) return fail(SWC_EINVAL, "null context");
+  c->fresh = false;
   c->entropy = on != 0;
   return SWC_OK;
 }
 
 int swc_track_live(swc_ctx* c, int on) {
   if (!c) return fail(SWC_EINVAL, "null context");
+  c->fresh = false;
   c->live = on != 0;
   return SWC_OK;
 }
@@ -1440,6 +1452,7 @@ int swc_get_live_counts(swc_ctx* c, int b, int64_t* n, int64_t len) {
 
 int swc_get_state(swc_ctx* c, int b, uint64_t* dets, double* amps, int64_t cap, int64_t* n_out) {
   if (!c) return fail(SWC_EINVAL, "null context");
+  c->fresh = false;
   if (!c->built) return fail(SWC_ESTATE, "no state built");
   if (b < 0 || b >= c->B || !n_out) return fail(SWC_EINVAL, "bad batch index or output");
   launch_energy_begin(c->cnt, c->B, c->st);

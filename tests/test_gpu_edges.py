@@ -97,3 +97,40 @@ def test_initial_zero_amplitude_kept(swc, orc, prec):
     assert abs(E.item() - E_ref) <= TOL[prec]["E"]
     assert np.max(np.abs(g.cpu().numpy()[0] - g_ref)) <= TOL[prec]["g"]
     s.close()
+
+
+@pytest.mark.parametrize("thr", [0.0, 1e-4], ids=["thr0", "thr"])
+def test_gradient_calls_around_other_calls(swc, orc, thr):
+    """A gradient call that follows another starts from the table the first
+    one left; every call that changes the state or the settings in between
+    makes the next one rebuild |Psi_0>. All results are bit-identical."""
+    say(f"[case] gradient calls around other calls thr={thr}")
+    h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 162)  # no amplitude within 1e-5 of the cut
+    s = swc.Solver(16, 4, 4, capacity_for(8, 4), prec=1, batch=1, max_factors=exc.shape[0])
+    s.build_state()
+    E0, g0 = (x.cpu().numpy() for x in s.energy_and_grad(theta, exc, thr, h1, h2))
+    orc.set_nearcut_window(1e-5)
+    E_ref, g_ref, nc = orc.energy_and_grad(16, [hf], [1.0], exc, theta[0], thr, h1, h2)
+    assert nc == 0
+    assert abs(E0[0] - E_ref) <= TOL[1]["E"] and np.max(np.abs(g0[0] - g_ref)) <= TOL[1]["g"]
+
+    def again():
+        E, g = (x.cpu().numpy() for x in s.energy_and_grad(theta, exc, thr, h1, h2))
+        assert np.array_equal(E, E0) and np.array_equal(g, g0)
+
+    again()                           # right after a gradient call
+    s.apply_ucc(theta, exc, thr)      # the table now holds the circuit's output
+    again()
+    s.energy(h1, h2)
+    again()
+    s.get_state(0)
+    again()
+    s.set_topk(0, 0)
+    again()
+    s.track_live(True)
+    again()
+    s.build_state()
+    again()
+    d, a = s.get_state(0)
+    assert list(d) == [hf] and a.tolist() == [1.0]
+    s.close()
