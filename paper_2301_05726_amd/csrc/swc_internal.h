@@ -187,14 +187,21 @@ constexpr int ES = 16;
 // (|amp| bits, ~key): larger rank = larger |c|, then smaller determinant.
 constexpr int TK_BITS = 12;              // digit width of one selection pass
 constexpr int TK_BINS = 1 << TK_BITS;
-struct alignas(256) TopK {
-  unsigned int hist[TK_BINS];
+struct TKState {
   unsigned long long pre_hi, pre_lo;  // selected leading digits (right-aligned 128-bit)
   unsigned long long remaining;       // entries still to keep among those matching the prefix
   int depth;                          // digits selected
   int done;                           // selection finished
   int nokill;                         // at most N_MAX live entries: nothing to remove
   int pad;
+};
+// Pass p histograms into hist[p % 3]; the pass after it (or the kill) makes
+// the selection of pass p from it in every block, and the state after the
+// selection of pass p is kept in st[p & 1] (rotating, so that no launch
+// writes what its own blocks read).
+struct alignas(256) TopK {
+  unsigned int hist[3][TK_BINS];
+  TKState st[2];
 };
 
 // one checkpoint: snapshot of the live (key, raw amplitude) pairs of every

@@ -1622,13 +1622,90 @@ __device__ __forceinline__ unsigned digit_of(R128 r, int nbits, int pass) {
   return static_cast<unsigned>(shr128(r, low).lo) & ((1u << (top - low)) - 1u);
 }
 
+// The selection of pass `pass` from its histogram, made by a whole block
+// (every block of the launch that follows the pass computes the same result):
+// in = the state after the previous pass's selection (unused for pass 0).
 template <class T>
-__global__ __launch_bounds__(BLK) void k_topk_hist(Tab t, TopK* tk, const Counters* cnt, int k, int pass) {
+__device__ TKState tk_select(const unsigned int* __restrict__ hist, const TKState* in, int pass,
+                             unsigned long long n_max, unsigned long long n_cut) {
+  constexpr int nbits = rank_bits<T>();
+  constexpr int PER = TK_BINS / BLK;
+  __shared__ unsigned long long part[BLK];
+  __shared__ TKState out;
+  unsigned long long my = 0;
+  for (int j = 0; j < PER; ++j) my += hist[TK_BINS - 1 - (threadIdx.x * PER + j)];
+  part[threadIdx.x] = my;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    TKState o;
+    bool go = true;
+    if (pass == 0) {
+      unsigned long long total = 0;
+      for (int i = 0; i < BLK; ++i) total += part[i];
+      o.pre_hi = o.pre_lo = 0ull;
+      o.depth = 0;
+      o.done = 0;
+      o.nokill = 0;
+      o.pad = 0;
+      o.remaining = n_cut;
+      if (total <= n_max) {
+        o.done = 1;
+        o.nokill = 1;
+        go = false;
+      }
+    } else {
+      o = *in;
+      if (o.done) go = false;
+    }
+    if (go) {
+      const unsigned long long rem = o.remaining;
+      unsigned long long cum = 0;  // entries of higher digits
+      int i = 0;
+      while (i < BLK - 1 && cum + part[i] < rem) cum += part[i++];
+      int d = TK_BINS - 1 - i * PER;
+      for (int j = 0; j < PER; ++j) {
+        d = TK_BINS - 1 - (i * PER + j);
+        const unsigned long long hd = hist[d];
+        if (cum + hd >= rem) break;
+        cum += hd;
+      }
+      const unsigned long long need = rem - cum;  // to keep inside digit d
+      const int top = nbits - TK_BITS * pass;
+      const int w = top > TK_BITS ? TK_BITS : top;
+      // prefix = (prefix << w) | d
+      R128 pre{o.pre_hi, o.pre_lo};
+      pre = R128{(pre.hi << w) | (pre.lo >> (64 - w)), (pre.lo << w) | static_cast<unsigned long long>(d)};
+      o.pre_hi = pre.hi;
+      o.pre_lo = pre.lo;
+      o.depth = pass + 1;
+      o.remaining = need;
+      if (hist[d] == need || top <= TK_BITS) o.done = 1;
+    }
+    out = o;
+  }
+  __syncthreads();
+  return out;
+}
+
+// Pass `pass` of the selection: the previous pass's selection (every block),
+// then, unless it finished, the histogram of this pass's digit over the
+// entries that match the digits chosen so far.  Also clears the histogram
+// buffer the next pass fills.
+template <class T>
+__global__ __launch_bounds__(BLK) void k_topk_pass(Tab t, TopK* tk, const Counters* cnt, int k, int pass,
+                                                    unsigned long long n_max, unsigned long long n_cut) {
   const int b = blockIdx.y;
   if (static_cast<uint32_t>(k) >= cnt[0].stop) return;
-  TopK& st = tk[b];
-  if (pass > 0 && st.done) return;
+  TopK& tb = tk[b];
   constexpr int nbits = rank_bits<T>();
+  TKState st{};
+  if (pass > 0) {
+    st = tk_select<T>(tb.hist[(pass - 1) % 3], &tb.st[pass & 1], pass - 1, n_max, n_cut);
+    if (blockIdx.x == 0 && threadIdx.x == 0) tb.st[(pass - 1) & 1] = st;
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < TK_BINS; i += gridDim.x * blockDim.x)
+    tb.hist[(pass + 1) % 3][i] = 0u;
+  if (pass > 0 && st.done) return;
   __shared__ unsigned int h[TK_BINS];
   for (int i = threadIdx.x; i < TK_BINS; i += blockDim.x) h[i] = 0u;
   __syncthreads();
@@ -1647,76 +1724,24 @@ __global__ __launch_bounds__(BLK) void k_topk_hist(Tab t, TopK* tk, const Counte
   }
   __syncthreads();
   for (int i = threadIdx.x; i < TK_BINS; i += blockDim.x)
-    if (h[i]) atomicAdd(&st.hist[i], h[i]);
+    if (h[i]) atomicAdd(&tb.hist[pass % 3][i], h[i]);
 }
 
-// one block per member: choose the digit of pass `pass`, then clear the histogram
 template <class T>
-__global__ __launch_bounds__(BLK) void k_topk_select(TopK* tk, const Counters* cnt, int k, int pass,
-                                                     unsigned long long n_max, unsigned long long n_cut) {
+__global__ __launch_bounds__(BLK) void k_topk_kill(Tab t, StepArr sa, Counters* cnt, TopK* tk, int k,
+                                                    unsigned long long n_max, unsigned long long n_cut) {
   const int b = blockIdx.y;
   if (static_cast<uint32_t>(k) >= cnt[0].stop) return;
-  TopK& st = tk[b];
-  if (pass > 0 && st.done) return;
   constexpr int nbits = rank_bits<T>();
-  constexpr int PER = TK_BINS / BLK;
-  __shared__ unsigned long long part[BLK];
-  unsigned long long my = 0;
-  for (int j = 0; j < PER; ++j) my += st.hist[TK_BINS - 1 - (threadIdx.x * PER + j)];
-  part[threadIdx.x] = my;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    bool go = true;
-    if (pass == 0) {
-      unsigned long long total = 0;
-      for (int i = 0; i < BLK; ++i) total += part[i];
-      st.pre_hi = st.pre_lo = 0ull;
-      st.depth = 0;
-      st.done = 0;
-      st.nokill = 0;
-      st.remaining = n_cut;
-      if (total <= n_max) {
-        st.done = 1;
-        st.nokill = 1;
-        go = false;
-      }
-    }
-    if (go) {
-      const unsigned long long rem = st.remaining;
-      unsigned long long cum = 0;  // entries of higher digits
-      int i = 0;
-      while (i < BLK - 1 && cum + part[i] < rem) cum += part[i++];
-      int d = TK_BINS - 1 - i * PER;
-      for (int j = 0; j < PER; ++j) {
-        d = TK_BINS - 1 - (i * PER + j);
-        const unsigned long long hd = st.hist[d];
-        if (cum + hd >= rem) break;
-        cum += hd;
-      }
-      const unsigned long long need = rem - cum;  // to keep inside digit d
-      const int top = nbits - TK_BITS * pass;
-      const int w = top > TK_BITS ? TK_BITS : top;
-      // prefix = (prefix << w) | d
-      R128 pre{st.pre_hi, st.pre_lo};
-      pre = R128{(pre.hi << w) | (pre.lo >> (64 - w)), (pre.lo << w) | static_cast<unsigned long long>(d)};
-      st.pre_hi = pre.hi;
-      st.pre_lo = pre.lo;
-      st.depth = pass + 1;
-      st.remaining = need;
-      if (st.hist[d] == need || top <= TK_BITS) st.done = 1;
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < TK_BINS; i += blockDim.x) st.hist[i] = 0u;
-}
-
-template <class T>
-__global__ __launch_bounds__(BLK) void k_topk_kill(Tab t, StepArr sa, Counters* cnt, const TopK* tk, int k) {
-  const int b = blockIdx.y;
-  if (static_cast<uint32_t>(k) >= cnt[0].stop) return;
-  const TopK& st = tk[b];
+  constexpr int npass = (nbits + TK_BITS - 1) / TK_BITS;
+  // the first pass of the next selection fills hist[0]: the one this
+  // selection filled at pass npass - 2 is cleared here
+  static_assert(npass % 3 == 2, "the histogram buffers rotate back to hist[0]");
+  TopK& tb = tk[b];
+  const TKState st = tk_select<T>(tb.hist[(npass - 1) % 3], &tb.st[npass & 1], npass - 1, n_max, n_cut);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < TK_BINS; i += gridDim.x * blockDim.x)
+    tb.hist[(npass - 2) % 3][i] = 0u;
   if (st.nokill || st.depth == 0) return;
-  constexpr int nbits = rank_bits<T>();
   const int sel = TK_BITS * st.depth < nbits ? TK_BITS * st.depth : nbits;
   const R128 pre{st.pre_hi, st.pre_lo};
   const View<T> v = view<T>(t, b);
@@ -2353,12 +2378,10 @@ template <class T>
 void launch_topk(const Tab& t, const StepArr& sa, Counters* cnt, TopK* tk, int k, uint64_t n_max, uint64_t n_cut,
                  int B, int grid, hipStream_t st) {
   constexpr int npass = (rank_bits<T>() + TK_BITS - 1) / TK_BITS;
-  for (int pass = 0; pass < npass; ++pass) {
-    hipLaunchKernelGGL(k_topk_hist<T>, dim3(grid, B), dim3(BLK), 0, st, t, tk, cnt, k, pass);
-    hipLaunchKernelGGL(k_topk_select<T>, dim3(1, B), dim3(BLK), 0, st, tk, cnt, k, pass,
-                       static_cast<unsigned long long>(n_max), static_cast<unsigned long long>(n_cut));
-  }
-  hipLaunchKernelGGL(k_topk_kill<T>, dim3(grid, B), dim3(BLK), 0, st, t, sa, cnt, tk, k);
+  const unsigned long long nm = n_max, nc = n_cut;
+  for (int pass = 0; pass < npass; ++pass)
+    hipLaunchKernelGGL(k_topk_pass<T>, dim3(grid, B), dim3(BLK), 0, st, t, tk, cnt, k, pass, nm, nc);
+  hipLaunchKernelGGL(k_topk_kill<T>, dim3(grid, B), dim3(BLK), 0, st, t, sa, cnt, tk, k, nm, nc);
 }
 
 void launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t st) {
