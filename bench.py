@@ -5,13 +5,20 @@ One step = one energy_and_grad call: forward sweep of all UCC factors with
 truncation, sigma = H psi and E, and the adjoint sweep giving dE/dtheta,
 for one theta vector of the workload, inputs already resident in HBM.
 
-    python bench.py [--steps K] [--warmup W] [--workload q20] [--prec fp32]
+    python bench.py [--steps K] [--warmup W] [--workload q64] [--prec fp64]
+
+The default workload is the 64-qubit one (32 electrons, all 94,848 factors of
+spin-conserving UCCSD, threshold 1e-4, hash capacity 2^28, checkpoints every
+4096 factors) with FP64 amplitudes: the largest configuration, whose energy
+the FP64 path gives within 1e-6 Ha.
 
 Prints one JSON line.  Besides the step rate it reports the forward
 det-update rate, the same-GPU FP64 forward + central finite-difference
 gradient rate (extrapolated from sampled parameters), the roofline figures
-of the dominant kernel from HIP events, and the CPU oracle timed on the
-host.
+of the dominant kernel from HIP events, the FP32-amplitude path's rate and
+its difference from the timed path, parity against the CPU oracle (the whole
+circuit up to 20 qubits, a prefix of it above), and the CPU oracle timed on
+the host.
 """
 from __future__ import annotations
 
@@ -44,8 +51,8 @@ def measured_traffic(workload: str, prec: str) -> dict:
     summary (calibrated against a copy kernel), only while the kernel sources
     are the ones that were profiled; otherwise empty (traffic reported null)."""
     from paper_2301_05726_amd.profiling import sources_sha
-    path = os.path.join(ROOT, "profiles", f"sweep_kernels_{workload}_traffic.txt")
-    if prec != "fp32" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", f"sweep_kernels_{workload}_{prec}_traffic.txt")
+    if not os.path.exists(path):
         return {}
     vals, sha = {}, None
     for line in open(path):
@@ -82,16 +89,19 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="q20")
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--workload", default="q64")
+    ap.add_argument("--prec", default="fp64", choices=["fp32", "fp64"])
     ap.add_argument("--fd-params", type=int, default=32)
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--fd-full-max-s", type=float, default=60.0,
                     help="run the finite differences over every parameter when the sampled estimate is below this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--factors", type=int, default=0, help="keep only the first K factors (0: all)")
-    ap.add_argument("--cpu-factors", type=int, default=600,
-                    help="prefix the CPU oracle sample runs beyond 20 qubits")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="beyond 20 qubits the CPU oracle evaluates E+grad on ever longer prefixes of the circuit "
+                         "(x2 factors each) until one takes at least this long; the GPU is compared with it there")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32-amplitude rate and accuracy reported beside an FP64 run")
     ap.add_argument("--batch", type=int, default=1, help="theta vectors per call")
     ap.add_argument("--capacity-log2", type=int, default=0, help="hash capacity 2^c (0: the workload's)")
     ap.add_argument("--log-capacity-log2", type=int, default=0, help="truncation-log records 2^c (0: capacity)")
@@ -102,8 +112,9 @@ def main() -> int:
     ap.add_argument("--sigma-mode", type=int, default=0, help="pairing: 0 auto, 1 always, 2 never")
     ap.add_argument("--fp64-check", action="store_true",
                     help="also run one FP64 energy_and_grad and report its differences from the timed path")
-    ap.add_argument("--checkpoint-interval", type=int, default=0,
-                    help="snapshot psi every K factors of the gradient sweep (0: off)")
+    ap.add_argument("--checkpoint-interval", type=int, default=-1,
+                    help="snapshot psi every K factors of the gradient sweep (0: off; -1: 4096 at 64 qubits, "
+                         "else off)")
     ap.add_argument("--checkpoint-entries-log2", type=int, default=24,
                     help="live determinants per snapshot the checkpoint buffer holds, 2^c")
     args = ap.parse_args()
@@ -118,6 +129,8 @@ def main() -> int:
     from paper_2301_05726_amd import swc, synth
 
     wl = synth.WORKLOADS[args.workload]
+    if args.checkpoint_interval < 0:
+        args.checkpoint_interval = 4096 if wl.name == "q64" else 0
     p = synth.make_problem(wl, batch=args.batch, n_factors=args.factors or None)
     B = args.batch
     cap = (1 << args.capacity_log2) if args.capacity_log2 else wl.capacity
@@ -343,6 +356,33 @@ def main() -> int:
         }
         sf.close()
 
+    if prec == swc.FP64 and not args.no_fp32:
+        # the FP32-amplitude path (FP64 reductions) on the same workload: its
+        # rate and its distance from the FP64 result timed above
+        s32 = swc.Solver(nq, wl.n_occ, wl.n_occ, cap, prec=swc.FP32, batch=B, max_factors=M, log_capacity=logcap,
+                         device=dev)
+        if args.sigma_scratch_gib > 0:
+            s32.set_sigma_scratch(int(args.sigma_scratch_gib * (1 << 30)), mode=args.sigma_mode)
+        if args.checkpoint_interval > 0:
+            s32.set_checkpoints(args.checkpoint_interval, 1 << args.checkpoint_entries_log2)
+        s32.build_state()
+        s32.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
+        torch.cuda.synchronize()
+        n32 = 2
+        c0 = time.perf_counter()
+        for _ in range(n32):
+            E32, g32 = s32.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
+        torch.cuda.synchronize()
+        c1 = time.perf_counter()
+        s32.close()
+        progress("FP32 evaluations done")
+        out["fp32"] = {
+            "what": "FP32 amplitudes and rotations, FP64 reductions; same workload, same theta",
+            "evals_per_s": round(n32 * B / (c1 - c0), 4),
+            "abs_dE_vs_fp64": float(np.max(np.abs(E32.cpu().numpy() - E.cpu().numpy()))),
+            "max_abs_dg_vs_fp64": float(np.max(np.abs(g32.cpu().numpy() - g.cpu().numpy()))),
+        }
+
     if not args.no_cpu_baseline:
         import oracle
         if topk:
@@ -364,19 +404,50 @@ def main() -> int:
             }
             out["parity_vs_oracle"] = {"abs_dE": abs(E0 - E_ref), "max_abs_dg": float(np.max(np.abs(g0 - g_ref)))}
         else:
-            # bounded sample: the forward sweep over a prefix of the circuit
-            Kc = min(M, args.cpu_factors)
+            # The oracle's E+grad over prefixes of the circuit twice as long
+            # each time, until one takes cpu-seconds; that evaluation is the
+            # CPU sample and the parity reference of the GPU on the prefix.
+            K = 256
+            while True:
+                K = min(M, 2 * K)
+                c0 = time.perf_counter()
+                E_ref, g_ref, nc = oracle.energy_and_grad(nq, [p.hf], [1.0], p.exc[:K], p.theta[0, :K], wl.threshold,
+                                                          p.h1, p.h2)
+                t_eg = time.perf_counter() - c0
+                if t_eg >= args.cpu_seconds or K == M:
+                    break
+            progress(f"oracle E+grad of the first {K} factors: {t_eg:.1f} s")
+            par = {"factors": K, "oracle_near_cut_events": nc}
+            for name, pr in (("fp64", swc.FP64), ("fp32", swc.FP32)):
+                sp_ = swc.Solver(nq, wl.n_occ, wl.n_occ, 1 << 20, prec=pr, batch=1, max_factors=K, device=dev)
+                sp_.build_state()
+                Ep, gp = sp_.energy_and_grad(theta[0:1, :K], p.exc[:K], wl.threshold, h1, h2)
+                par[f"abs_dE_{name}"] = abs(float(Ep[0].item()) - E_ref)
+                par[f"max_abs_dg_{name}"] = float(np.max(np.abs(gp.cpu().numpy()[0] - g_ref)))
+                sp_.close()
+            out["parity_vs_oracle"] = par
+            # Scaled to the whole circuit: the sweeps' time grows with the
+            # determinants visited (det-updates), the energy's with the final
+            # determinants (each probes the same number of connections).
+            dK, aK, _, _ = oracle.apply_ucc(nq, [p.hf], [1.0], p.exc[:K], p.theta[0, :K], wl.threshold)
             c0 = time.perf_counter()
-            _, _, _, du_c = oracle.apply_ucc(nq, [p.hf], [1.0], p.exc[:Kc], p.theta[0, :Kc], wl.threshold)
-            c1 = time.perf_counter()
+            oracle.energy(nq // 2, p.h1, p.h2, dK, aK)
+            t_E = time.perf_counter() - c0
+            du_c = int(np.sum(oracle.live_trajectory(nq, [p.hf], [1.0], p.exc[:K], p.theta[0, :K],
+                                                     wl.threshold)[:-1]))
+            t_sw = max(t_eg - t_E, 0.0)
+            t_full_cpu = t_sw * det_updates / max(du_c, 1) + t_E * n_live / len(dK)
             out["cpu_baseline"] = {
-                "value": round(du_c / (c1 - c0), 1),
-                "unit": "det-updates/s (forward)",
+                "value": round(1.0 / t_full_cpu, 9),
+                "unit": "E+grad evals/s",
                 "cores": 1,
                 "kind": "oracle",
-                "sample": f"forward sweep of the first {Kc} factors of {wl.name} ({du_c} det-updates), "
-                          "single-threaded std::map FP64",
-                "seconds": round(c1 - c0, 3),
+                "sample": f"one E+grad evaluation of the first {K} factors of {wl.name} ({t_eg:.1f} s: sweeps "
+                          f"{t_sw:.1f} s over {du_c} det-updates, energy {t_E:.1f} s over {len(dK)} determinants), "
+                          "single-threaded std::map FP64; scaled to the whole circuit (sweeps by its "
+                          f"{det_updates} det-updates, energy by its {n_live} final determinants)",
+                "extrapolated": K < M,
+                "seconds": round(t_eg + t_E, 3),
                 "host_cpus": os.cpu_count(),
                 "host_cpu_model": cpu_model(),
             }

@@ -50,6 +50,8 @@ def lib():
         L.orc_entropy_trajectory.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, D, P]
         L.orc_live_trajectory.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, D, P]
         L.orc_set_topk.argtypes = [I64, I64]
+        L.orc_uncertainty.argtypes = [ctypes.c_int, P, P, I64, P, P, I64, D, D, P, P, I64, P, P, P, I64, P,
+                                      P, P, I64, P, P]
         _lib = L
     return _lib
 
@@ -207,3 +209,39 @@ def apply_inverse(nq, dets0, amps0, exc, theta, cap=None):
     _chk(lib().orc_apply_inverse(nq, _p(d), _p(a), len(d), _p(e), _p(t), e.shape[0], _p(do), _p(ao), cap,
                                  ctypes.byref(n)))
     return do[: n.value].copy(), ao[: n.value].copy()
+
+
+def uncertainty(nq, dets0, amps0, exc, theta, thr, window=1e-3):
+    """Which truncation decisions of the forward circuit may legitimately
+    differ in another evaluation whose rounding differs (oracle.cpp,
+    orc_uncertainty): a dict with
+      nearcut    [(determinant, step)] with ||phi| - thr| <= window * thr
+      uncertain  dict determinant -> last step whose decision was uncertain
+      delta      dict determinant -> bound on the amplitude difference
+      eps        bound on the relative difference of the common scale
+    (another run's amplitudes c' satisfy |c'_D - c_D| <= delta[D] + eps |c_D|)."""
+    d, a = _init(dets0, amps0)
+    e = np.ascontiguousarray(exc, dtype=np.int8)
+    t = np.ascontiguousarray(theta, dtype=np.float64)
+    M = e.shape[0]
+    cap = 1 << 12
+    while True:
+        nck, ncs = np.empty(cap, np.uint64), np.empty(cap, np.int64)
+        unk, uns = np.empty(cap, np.uint64), np.empty(cap, np.int64)
+        dlk, dlv = np.empty(cap, np.uint64), np.empty(cap, np.float64)
+        nn, un, dn = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        eps = ctypes.c_double(0)
+        r = lib().orc_uncertainty(nq, _p(d), _p(a), len(d), _p(e), _p(t), M, float(thr), float(window), _p(nck),
+                                  _p(ncs), cap, ctypes.byref(nn), _p(unk), _p(uns), cap, ctypes.byref(un), _p(dlk),
+                                  _p(dlv), cap, ctypes.byref(dn), ctypes.byref(eps))
+        if r == ECAPACITY:
+            cap = max(nn.value, un.value, dn.value)
+            continue
+        _chk(r)
+        return {
+            "nearcut": [(int(k), int(st)) for k, st in zip(nck[: nn.value], ncs[: nn.value])],
+            "nearcut_keys": {int(k) for k in nck[: nn.value]},
+            "uncertain": {int(k): int(s) for k, s in zip(unk[: un.value], uns[: un.value])},
+            "delta": {int(k): float(v) for k, v in zip(dlk[: dn.value], dlv[: dn.value])},
+            "eps": eps.value,
+        }

@@ -33,6 +33,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <set>
 #include <utility>
 #include <vector>
 
@@ -415,6 +416,104 @@ int write_state(const State& psi, uint64_t* dets, double* amps, int64_t cap, int
   return OK;
 }
 
+// ---------------------------------------------------------------------------
+// which truncation decisions may legitimately differ between two evaluations
+// ---------------------------------------------------------------------------
+// The cut after every factor (Methods section) compares each amplitude with
+// the threshold.  Another evaluation of the same circuit, whose rounding
+// differs (another summation order, FP32 amplitudes), may decide differently
+// for an amplitude within the near-cut window w*thr of the cut.  Its
+// amplitudes then differ from the ones here by up to that amplitude, and
+// later factors carry the difference to the pair partners (the descendants
+// of the flipped determinant).  This tracks, in exact arithmetic:
+//   delta[D]  a bound on |c'_D - c_D| over every such evaluation (c_D = 0 for
+//             determinants not held here), apart from a common scale;
+//   eps       a bound on the relative difference of that common scale (the
+//             runs remove different weights, so they renormalise differently);
+// so |c'_D - c_D| <= delta[D] + eps |c_D|.  A decision is uncertain when
+// | |phi_D| - thr | <= w thr + delta[D] + eps |phi_D|, phi the state of the
+// step before its cut.  Every other decision is the same in both runs, so two
+// runs hold the same determinants except those whose decision was uncertain
+// at some step.
+struct Uncertainty {
+  double window = 1e-3;
+  std::map<uint64_t, double> delta;
+  double eps = 0.0;
+  std::vector<std::pair<uint64_t, int64_t>> nearcut;  // (determinant, step): | |phi| - thr | <= w thr
+  std::map<uint64_t, int64_t> uncertain;             // determinant -> last step its decision was uncertain
+};
+
+double delta_of(const std::map<uint64_t, double>& d, uint64_t key) {
+  auto it = d.find(key);
+  return it == d.end() ? 0.0 : it->second;
+}
+
+// Differences through one factor: on a pair (L, U) the rotation gives
+// |dx'| <= |cos| |dx| + |sin| |dy| and |dy'| <= |cos| |dy| + |sin| |dx|, the
+// pairs taken whether or not their members are held here.
+void propagate_delta(const Exc& e, double c, double sn, std::map<uint64_t, double>& delta) {
+  std::map<uint64_t, double> out;
+  std::set<uint64_t> lowers;
+  for (const auto& kv : delta) {
+    uint64_t P = 0;
+    if (apply_tau(e, kv.first, P))
+      lowers.insert(kv.first);
+    else if (apply_tau_dag(e, kv.first, P))
+      lowers.insert(P);
+    else
+      out[kv.first] = kv.second;  // in no pair of this factor
+  }
+  for (uint64_t L : lowers) {
+    uint64_t U = 0;
+    apply_tau(e, L, U);
+    const double dL = delta_of(delta, L), dU = delta_of(delta, U);
+    out[L] = std::fabs(c) * dL + std::fabs(sn) * dU;
+    out[U] = std::fabs(c) * dU + std::fabs(sn) * dL;
+  }
+  delta.swap(out);
+}
+
+// The decisions of step `step` on phi (before its cut) and the renormalisation
+// that follows; the cut itself is prune_renorm's.
+void decide_step(const State& phi, double thr, int64_t step, Uncertainty& u) {
+  const double w = u.window * thr;
+  std::set<uint64_t> keys;
+  for (const auto& kv : phi) keys.insert(kv.first);
+  for (const auto& kv : u.delta) keys.insert(kv.first);
+  double removed = 0.0;  // weight this run removes
+  double rho = 0.0;      // bound on |removed' - removed|
+  std::map<uint64_t, double> out;
+  for (uint64_t D : keys) {
+    auto it = phi.find(D);
+    const double v = (it == phi.end()) ? 0.0 : std::fabs(it->second);
+    const double dl = delta_of(u.delta, D);
+    const double d = dl + u.eps * v;  // bound on the other run's difference here
+    if (it != phi.end() && std::fabs(v - thr) <= w) u.nearcut.emplace_back(D, step);
+    if (v < thr) removed += v * v;
+    double nd;
+    if (std::fabs(v - thr) <= w + d) {  // either decision possible
+      u.uncertain[D] = step;
+      nd = (v >= thr) ? std::max(v, d) : v + d;  // kept here: 0 or within d; cut here: up to v + d there
+      rho += (v + d) * (v + d);
+    } else if (v < thr) {  // both runs cut
+      nd = 0.0;
+      rho += 4.0 * (v + d) * d;
+    } else {  // both runs keep
+      nd = dl;
+    }
+    if (nd > 0.0) out[D] = nd;
+  }
+  u.delta.swap(out);
+  if (rho > 0.0 || removed > 0.0) {
+    // nu^2 = 1 - removed for both runs (unit-norm states before the step), so
+    // |nu / nu' - 1| <= rho / (1 - removed - rho)
+    const double nu = std::sqrt(1.0 - removed);
+    const double es = rho / (1.0 - removed - rho);
+    for (auto& kv : u.delta) kv.second *= (1.0 + es) / nu;
+    u.eps = u.eps * (1.0 + es) + es;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -459,6 +558,61 @@ int orc_apply_ucc(int nq, const uint64_t* dets0, const double* amps0, int64_t n0
   if (det_updates) *det_updates = du;
   if (r) return r;
   return write_state(psi, dets_out, amps_out, cap, n_out);
+}
+
+// The forward circuit with the analysis above: the near-cut events (every
+// determinant and step with | |phi| - thr | <= window thr), the determinants
+// whose decision was uncertain at some step (with the last such step), and
+// the final bounds delta (determinant, bound) and eps.  The final state is
+// orc_apply_ucc's.  Not defined with N_MAX / N_CUT on (EINVAL).  Each list
+// is written up to its capacity; ECAPACITY (with the counts set) when one is
+// longer.
+int orc_uncertainty(int nq, const uint64_t* dets0, const double* amps0, int64_t n0, const int8_t* exc,
+                    const double* theta, int64_t M, double thr, double window, uint64_t* nc_key, int64_t* nc_step,
+                    int64_t nc_cap, int64_t* nc_n, uint64_t* un_key, int64_t* un_step, int64_t un_cap,
+                    int64_t* un_n, uint64_t* dl_key, double* dl_val, int64_t dl_cap, int64_t* dl_n,
+                    double* eps_out) {
+  int r = check_common(nq, theta, M, thr);
+  if (r) return r;
+  if (g_nmax > 0 || !(window >= 0.0)) return EINVAL_;
+  std::vector<Exc> ex;
+  if ((r = parse_excitations(exc, M, nq, ex))) return r;
+  State psi;
+  if ((r = load_state(nq, dets0, amps0, n0, psi))) return r;
+  Uncertainty u;
+  u.window = window;
+  State phi;
+  for (int64_t k = 0; k < M; ++k) {
+    const double c = std::cos(theta[k]), sn = std::sin(theta[k]);
+    apply_factor(ex[static_cast<size_t>(k)], c, sn, psi, phi);
+    if (thr > 0.0) {
+      propagate_delta(ex[static_cast<size_t>(k)], c, sn, u.delta);
+      decide_step(phi, thr, k + 1, u);
+    }
+    double nu = 1.0;
+    if ((r = prune_renorm(phi, thr, &nu, nullptr)) < 0) return r;
+    psi.swap(phi);
+  }
+  *nc_n = static_cast<int64_t>(u.nearcut.size());
+  *un_n = static_cast<int64_t>(u.uncertain.size());
+  *dl_n = static_cast<int64_t>(u.delta.size());
+  *eps_out = u.eps;
+  if (*nc_n > nc_cap || *un_n > un_cap || *dl_n > dl_cap) return ECAPACITY_;
+  for (size_t i = 0; i < u.nearcut.size(); ++i) {
+    nc_key[i] = u.nearcut[i].first;
+    nc_step[i] = u.nearcut[i].second;
+  }
+  int64_t i = 0;
+  for (const auto& kv : u.uncertain) {
+    un_key[i] = kv.first;
+    un_step[i++] = kv.second;
+  }
+  i = 0;
+  for (const auto& kv : u.delta) {
+    dl_key[i] = kv.first;
+    dl_val[i++] = kv.second;
+  }
+  return OK;
 }
 
 // Wavefunction entropy (Eq. 6): S = -sum_I p_I ln p_I with p_I = c_I^2 / sum c^2

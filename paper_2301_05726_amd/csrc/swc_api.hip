@@ -149,8 +149,9 @@ FacMask factor_mask(const swc_exc& e) {
 }
 
 // A captured run of per-step kernels: direction (0 forward, 1 reverse),
-// steps k0..k1, threshold, log flag, table and occupancy limit are baked
-// into the kernel arguments.
+// steps k0..k1, threshold, log flag, table, occupancy limit and the optional
+// per-step arrays are baked into the kernel arguments; the choice of fused
+// factor pairs depends on the excitation list, whose upload clears the cache.
 struct GraphKey {
   int dir;
   int64_t k0, k1;
@@ -160,9 +161,10 @@ struct GraphKey {
   uint64_t H, lim;
   int ent = 0;
   uint64_t tk_max = 0, tk_cut = 0;
+  int live = 0;  // the live-count array is passed to the kernels (swc_track_live)
   bool operator==(const GraphKey& o) const {
     return dir == o.dir && k0 == o.k0 && k1 == o.k1 && thr == o.thr && log_on == o.log_on && slots == o.slots &&
-           H == o.H && lim == o.lim && ent == o.ent && tk_max == o.tk_max && tk_cut == o.tk_cut;
+           H == o.H && lim == o.lim && ent == o.ent && tk_max == o.tk_max && tk_cut == o.tk_cut && live == o.live;
   }
 };
 constexpr int64_t GRAPH_CHUNK = 2048;
@@ -323,6 +325,11 @@ int upload_masks(swc_ctx* c, const swc_exc* exc, int64_t M) {
   SWC_HIP(hipMemcpyAsync(c->fac, f.data(), sizeof(FacMask) * M, hipMemcpyHostToDevice, c->st));
   SWC_HIP(hipStreamSynchronize(c->st));
   c->exc_cache.assign(exc, exc + M);
+  // Captured sweeps bake in which neighbouring factors share a launch (a
+  // choice made from the XOR masks): graphs recorded for another list are
+  // dropped (the stream has just been synchronized, so none is running).
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+  c->graphs.clear();
   return SWC_OK;
 }
 
@@ -540,7 +547,8 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
   return dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
     if (c->use_graph && !c->ktiming && graph_ok) {
-      const GraphKey key{0, k0, k1, thr, log_on, c->tab.slots, c->tab.H, lim, c->entropy ? 1 : 0, c->tk_max, c->tk_cut};
+      const GraphKey key{0, k0, k1, thr, log_on, c->tab.slots, c->tab.H, lim, c->entropy ? 1 : 0,
+                         c->tk_max, c->tk_cut, c->live ? 1 : 0};
       hipGraphExec_t ex = nullptr;
       const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { issue_fwd<T>(c, k0, k1, thr, log_on, lim, cs); });
       if (rr) return rr;

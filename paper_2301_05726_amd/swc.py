@@ -7,8 +7,11 @@ present, the calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 import torch
@@ -54,6 +57,17 @@ class Stats(ctypes.Structure):
 
 
 _lib = None
+
+# Contexts not yet closed.  They are destroyed by an exit hook that runs
+# before the interpreter finalises (torch and the HIP runtime still intact),
+# so no HIP call is left for object finalisers during interpreter shutdown.
+_open_solvers: "weakref.WeakSet[Solver]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_solvers():
+    for s in list(_open_solvers):
+        s.close()
 
 
 def lib():
@@ -149,6 +163,7 @@ class Solver:
         _chk(L.swc_create(ctypes.byref(self._ctx), n_qubits, n_alpha, n_beta, capacity, prec, batch, max_factors,
                           log_capacity, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                           ctypes.c_void_p(self.stream.cuda_stream)))
+        _open_solvers.add(self)
 
     # -- helpers ----------------------------------------------------------
     def _dev(self, t, shape=None) -> torch.Tensor:
@@ -283,11 +298,30 @@ class Solver:
         return {f: getattr(s, f) for f, _ in Stats._fields_}
 
     def close(self):
+        """Destroy the context (its graphs, events and capture stream) while
+        the HIP runtime is up; the workspace tensor is released with the
+        object.  Idempotent."""
         if getattr(self, "_ctx", None) and self._ctx.value:
+            # the library's work on its stream must finish before the graphs
+            # and events it uses are destroyed
+            self.stream.synchronize()
             lib().swc_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+        _open_solvers.discard(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
+        # During interpreter shutdown the HIP runtime may already be torn
+        # down: make no device call then (the exit hook has closed every
+        # context that was still open before finalisation began).
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -96,6 +96,40 @@ def test_forward_matches_dense_statevector(orc, n_orb, n_occ, sigma, seed):
         assert abs(psi @ (H @ psi) - e_dense) < 1e-11
 
 
+def test_multi_determinant_start_matches_dense_statevector(orc):
+    """A non-normalised initial state of several determinants (Eq. 1 with a
+    general |Psi_0>): the oracle normalises it and then applies the circuit;
+    the dense statevector does the same with its own normalisation and matrix
+    exponentials, with and without a threshold (dense truncate and
+    renormalise after every factor)."""
+    h1, h2, exc, theta, hf = small_problem(5, 2, 0.3, 71)
+    nq = 10
+    jw = DenseJW(nq)
+    sector = jw.sector(2, 2)
+    rng = np.random.default_rng(72)
+    dets = rng.choice(sector, size=7, replace=False)
+    amps = rng.normal(size=7) * 3.0  # norm far from 1
+    amps[2] = 0.0                    # an exact zero is kept as a member
+    d, a, _, _ = orc.apply_ucc(nq, dets, amps, exc, theta, 0.0)
+    v = np.zeros(1 << nq)
+    v[dets.astype(np.int64)] = amps
+    psi = jw.apply_factors(v / np.linalg.norm(v), exc, theta)
+    dense = np.zeros(1 << nq)
+    dense[d.astype(np.int64)] = a
+    assert np.max(np.abs(dense - psi)) < 1e-12
+    thr = 0.01
+    d, a, _, _ = orc.apply_ucc(nq, dets, amps, exc, theta, thr)
+    psi = v / np.linalg.norm(v)
+    for k in range(exc.shape[0]):
+        psi = jw.apply_factors(psi, exc[k:k + 1], theta[k:k + 1])
+        cut = (np.abs(psi) < thr) & (psi != 0)
+        if np.any(cut):
+            psi[cut] = 0.0
+            psi /= np.linalg.norm(psi)
+    assert sorted(d.tolist()) == np.flatnonzero(psi).tolist()
+    assert np.max(np.abs(a - psi[d.astype(np.int64)])) < 1e-12
+
+
 @pytest.mark.parametrize("n_orb,n_alpha,n_beta,sigma,seed", [(5, 3, 1, 0.3, 61), (6, 3, 2, 0.2, 62)])
 def test_open_shell_matches_dense_statevector(orc, n_orb, n_alpha, n_beta, sigma, seed):
     """Different alpha and beta electron counts: state, energy and gradient
@@ -462,3 +496,68 @@ def test_topk_gradient_vs_fd(topk):
     orc.set_topk(0, 0)
     _, g0, _ = orc.energy_and_grad(10, [hf], [1.0], exc, theta, 0.0, h1, h2)
     assert np.max(np.abs(g0 - g)) > 1e-6
+
+
+# ---------------------------------------------------------------- near-cut decisions (Methods: cut after every factor)
+
+
+def test_nearcut_events_match_dense_truncation(orc):
+    """The near-cut events the oracle names -- (determinant, step) whose
+    amplitude before the cut of that step lies within window*thr of the
+    threshold -- equal those of a dense Jordan-Wigner run truncated and
+    renormalised after every factor (the rule written on the dense vector)."""
+    h1, h2, exc, theta, hf = small_problem(4, 2, 0.3, 32)
+    jw = DenseJW(8)
+    thr, w = 0.02, 0.25
+    u = orc.uncertainty(8, [hf], [1.0], exc, theta, thr, w)
+    dense = []
+    psi = jw.basis([hf])
+    for k in range(exc.shape[0]):
+        psi = jw.apply_factors(psi, exc[k:k + 1], theta[k:k + 1])
+        for D in np.flatnonzero(np.abs(np.abs(psi) - thr) <= w * thr):
+            dense.append((int(D), k + 1))
+        cut = (np.abs(psi) < thr) & (psi != 0)
+        if np.any(cut):
+            psi[cut] = 0.0
+            psi /= np.linalg.norm(psi)
+    assert len(dense) > 0
+    assert sorted(u["nearcut"]) == sorted(dense)
+    # threshold 0 never cuts: nothing is near the cut or uncertain
+    u0 = orc.uncertainty(8, [hf], [1.0], exc, theta, 0.0, w)
+    assert u0["nearcut"] == [] and u0["uncertain"] == {} and u0["delta"] == {} and u0["eps"] == 0.0
+
+
+UNC_CASES = [(6, 3, 0.2, 201, 1e-3), (6, 3, 0.2, 203, 1e-3), (6, 3, 0.2, 214, 3e-4), (6, 3, 0.2, 208, 1e-3)]
+
+
+@pytest.mark.parametrize("case", UNC_CASES, ids=[f"s{c[3]}_thr{c[4]:g}" for c in UNC_CASES])
+def test_uncertainty_bounds_other_valid_runs(orc, case):
+    """Brute force over other valid evaluations: runs whose thresholds differ
+    by less than the window decide differently exactly where an amplitude lies
+    within the window of the cut.  Every such run must hold the same
+    determinants except uncertain ones, and its amplitudes must lie within
+    delta + eps |c| of the oracle's.  Some runs do flip a decision, and their
+    differences reach determinants that were never near the cut themselves
+    (the descendants), so the propagation of the bounds is exercised."""
+    n_orb, n_occ, sigma, seed, thr = case
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed)
+    nq, w = 2 * n_orb, 1e-3
+    u = orc.uncertainty(nq, [hf], [1.0], exc, theta, thr, w)
+    assert len(u["nearcut"]) > 0
+    d0, a0, _, _ = orc.apply_ucc(nq, [hf], [1.0], exc, theta, thr)
+    ref = dict(zip(d0.tolist(), a0.tolist()))
+    flipped = descendant = 0
+    for f in (1 - 0.99 * w, 1 - 0.5 * w, 1 + 0.5 * w, 1 + 0.99 * w):
+        d1, a1, _, _ = orc.apply_ucc(nq, [hf], [1.0], exc, theta, thr * f)
+        oth = dict(zip(d1.tolist(), a1.tolist()))
+        diff = set(ref) ^ set(oth)
+        assert diff <= set(u["uncertain"]), diff - set(u["uncertain"])
+        flipped += len(diff) > 0 or any(abs(oth.get(k, 0.0) - v) > 1e-9 for k, v in ref.items())
+        for k in set(ref) | set(oth):
+            dv = abs(ref.get(k, 0.0) - oth.get(k, 0.0))
+            bound = u["delta"].get(k, 0.0) + u["eps"] * abs(ref.get(k, 0.0)) + 1e-13
+            assert dv <= bound, (k, dv, bound)
+            if dv > 1e-9 and u["delta"].get(k, 0.0) > 0.0 and k not in u["nearcut_keys"]:
+                descendant += 1
+    assert flipped > 0, "no perturbed run changed a decision: the case does not exercise the bound"
+    assert descendant > 0
