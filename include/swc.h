@@ -54,11 +54,11 @@
  * setting): SWC_SWEEP=persistent runs each sweep as cooperative launches with
  * grid barriers instead of one launch per step; SWC_GRAPH=0 launches steps
  * directly instead of replaying captured graphs; SWC_FUSE=0 applies one
- * factor per launch at threshold 0; SWC_TABLE_MIN=n sets the smallest table
- * (default 2^18 slots); SWC_SHRINK=0 keeps the table size in the adjoint
- * sweep; SWC_PROGRESS=1 waits after each range of steps and reports it on
- * stderr; SWC_KERNEL_TIMING=1 times every step launch (one step per launch);
- * SWC_GRID=n caps the sweep launches at n blocks (tuning).
+ * factor per launch at threshold 0; SWC_TABLE_MIN=n sets the smallest hash
+ * index (default 2^18 slots); SWC_PROGRESS=1 waits after each range of steps
+ * and reports it on stderr; SWC_KERNEL_TIMING=1 times every step launch (one
+ * step per launch); SWC_GRID=n caps the sweep launches at about n blocks
+ * (at least one per arena of entries; tuning).
  */
 #ifndef SWC_H
 #define SWC_H
@@ -75,7 +75,7 @@ enum {
   SWC_EINVAL = -1,    /* bad argument: sizes, indices, overlapping excitation
                          index sets, non-finite theta, threshold < 0, bad
                          determinant, workspace too small, batch index */
-  SWC_ECAPACITY = -2, /* hash table or truncation log full */
+  SWC_ECAPACITY = -2, /* index, entry arenas or truncation log full */
   SWC_EEMPTY = -3,    /* truncation removed every determinant */
   SWC_EDEVICE = -4,   /* a HIP runtime error (text via swc_last_error) */
   SWC_ESTATE = -5     /* call order: no state built yet */
@@ -98,8 +98,8 @@ typedef struct {
   int64_t inserts;       /* determinants created (last forward sweep) */
   int64_t pruned;        /* amplitudes removed by truncation (last forward sweep) */
   int64_t log_records;   /* truncation-log records of the last gradient sweep */
-  int64_t table_slots;   /* current hash-table size per batch member (grows up to the capacity) */
-  int64_t slots_used;    /* occupied slots incl. tombstones (batch member 0) */
+  int64_t table_slots;   /* current hash-index size per batch member (grows up to the capacity) */
+  int64_t slots_used;    /* entries, alive and dead (= occupied index slots; batch member 0) */
   double fwd_ms;         /* device time of the last forward sweep */
   double energy_ms;      /* device time of the last energy evaluation */
   double rev_ms;         /* device time of the last reverse (adjoint) sweep */
@@ -113,14 +113,16 @@ typedef struct {
   int64_t reverse_launches;  /* reverse launches of the last adjoint sweep (one or two factors each) */
   double sigma_kernel_ms;    /* duration of the sigma kernel (always filled) */
   int64_t partner_hits;      /* pairs whose partner existed (last forward sweep) */
-  int64_t rehashes;          /* table growths during the last forward sweep */
-  int64_t compactions;       /* rehashes at its start that dropped tombstones of
-                                earlier sweeps (over 1/4 of the occupied slots) */
+  int64_t rehashes;          /* index growths during the last forward sweep */
+  int64_t compactions;       /* rebuilds at its start that dropped the dead entries
+                                of earlier sweeps (over 1/4 of the entries) */
   int64_t checkpoints;       /* snapshots taken by the last gradient sweep */
   int64_t sigma_partitions;  /* partitions of the last pairing sigma (0: hash probes were used) */
-  int64_t shrinks;           /* rehashes into a smaller table during the last reverse sweep */
-  int64_t fwd_slots_scanned; /* sum over the last forward sweep's launches of the table size */
-  int64_t rev_slots_scanned; /* the same for the last reverse sweep */
+  int64_t shrinks;           /* always 0: the reverse sweep scans fewer entries as it goes
+                                back without rebuilding anything */
+  int64_t fwd_slots_scanned; /* entries (alive and dead) the last forward sweep's launches scanned */
+  int64_t rev_slots_scanned; /* entries the reverse sweep scans to undo each factor, summed
+                                over the factors (a two-factor launch scans its pair's once) */
   /* Totals over every swc_energy_and_grad call that completed since
      swc_create (a caller reads them before and after a series of calls
      instead of after each one): */
@@ -128,20 +130,37 @@ typedef struct {
   double fwd_ms_total;          /* fwd_ms summed over those calls */
   double rev_ms_total;          /* rev_ms summed over those calls */
   double sigma_kernel_ms_total; /* sigma_kernel_ms summed over those calls */
+  int64_t kernel_builds;        /* SWC_BUILD_* bits: the sweep kernel builds the last
+                                   forward sweep and the reverse sweep after it launched */
 } swc_stats;
 
+/* Sweep kernel builds (swc_stats.kernel_builds). */
+enum {
+  SWC_BUILD_FWD = 1,          /* one factor per launch, forward */
+  SWC_BUILD_FWD_WIDE = 2,     /* the same, built for five resident waves (states scanned in many passes) */
+  SWC_BUILD_FWD_ENT = 4,      /* the same, with the entropy sums */
+  SWC_BUILD_FWD2 = 8,         /* two factors per launch (threshold 0), forward, home index slot preloaded */
+  SWC_BUILD_FWD2_PRE = 16,    /* the same, four index slots per probe preloaded (one-pass states) */
+  SWC_BUILD_REV = 32,         /* one factor per launch, reverse */
+  SWC_BUILD_REV2 = 64,        /* two factors per launch, reverse, home slot preloaded */
+  SWC_BUILD_REV2_PRE = 128,   /* the same, four index slots preloaded */
+  SWC_BUILD_PERSISTENT = 256  /* persistent cooperative sweeps (SWC_SWEEP=persistent) */
+};
+
 /*
- * Bytes of device workspace needed for a context whose hash table may grow
- * to `capacity` slots per state (a power of two, >= 64; determinants plus
- * tombstones of the current sweep must stay below 0.9 * capacity), `batch`
- * independent states, circuits of up to `max_factors` factors, and
- * `log_capacity` truncation-log records per state (0 selects capacity; a
- * record, 20 bytes in FP32, saves a tombstone of the current sweep that a
- * later factor revives, for the adjoint sweep).
- * The table starts small after every reset to |Psi_0> and is rehashed into a
- * larger one (x2 or more) during a forward sweep when its occupancy nears a
- * growth limit, so the per-factor scan covers the current table, not the
- * capacity; the workspace holds two capacity-sized table regions for this.
+ * Bytes of device workspace needed for a context whose hash index may grow
+ * to `capacity` slots per state (a power of two, >= 64; the determinants a
+ * state holds, alive plus those removed during the current sweep, must stay
+ * below 0.9 * capacity), `batch` independent states, circuits of up to
+ * `max_factors` factors, and `log_capacity` truncation-log records per state
+ * (0 selects capacity; a record, 20 bytes in FP32, saves the state of a
+ * determinant removed earlier in the sweep that a later factor revives, for
+ * the adjoint sweep).
+ * The determinants of a state are dense arrays of entries (64 arenas with
+ * room for 1.125 * capacity entries in all); the per-factor scans read the
+ * entries only.  The index maps a determinant to its entry; it starts small
+ * after every reset to |Psi_0> and is rebuilt larger (x2 or more) during a
+ * forward sweep when the entries near a growth limit (45% of its slots).
  * Returns 0 for invalid arguments.
  */
 size_t swc_workspace_bytes(int n_qubits, uint64_t capacity, int prec, int batch, int64_t max_factors,
@@ -173,15 +192,22 @@ int swc_build_state(swc_ctx* ctx, const uint64_t* dets, const double* amps, int6
 int swc_apply_ucc(swc_ctx* ctx, const double* theta, const swc_exc* exc, int64_t M, double threshold);
 
 /*
- * E[b] = <psi_b|H|psi_b> / <psi_b|psi_b> of the current states.
+ * E[b] = <psi_b|H|psi_b> / <psi_b|psi_b> of the current states: the
+ * energy objective the paper evaluates on the final state of the circuit
+ * (Results section), as a Rayleigh quotient of the second-quantized H above.
  * h1: device double [n][n]; h2: device double [n][n][n][n]; E: device double [batch].
  */
 int swc_energy(swc_ctx* ctx, const double* h1, const double* h2, double* E);
 
 /*
  * E(theta) and dE/dtheta for every batch member, starting from |Psi_0>
- * (forward sweep with truncation, energy, adjoint sweep).  Arguments as in
- * swc_apply_ucc and swc_energy; grad: device double [batch][M].  On return
+ * (forward sweep with truncation, energy, adjoint sweep).  The paper does not
+ * say how its optimizer (SLSQP, Methods section) obtains gradients; this is
+ * the exact derivative of E with the truncation decisions of the forward
+ * sweep held fixed (the limit of central differences whenever no amplitude
+ * crosses the cut; the true gradient at threshold 0), computed by running the
+ * factors backwards on the state and on lambda = P (H - E) psi.  Arguments as
+ * in swc_apply_ucc and swc_energy; grad: device double [batch][M].  On return
  * the current state is |Psi_0> again.
  */
 int swc_energy_and_grad(swc_ctx* ctx, const double* theta, const swc_exc* exc, int64_t M, double threshold,

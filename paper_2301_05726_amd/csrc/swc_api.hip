@@ -39,9 +39,9 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of every workspace region.
 struct Layout {
-  size_t slots[2], aux[2];
+  size_t ent, aux, idx, ac;
   size_t lkey, lmeta, lborn, lamp;
-  size_t scale, pw, pcnt, gacc, logn, logoff, rmax, ws, ea, eb, ent, pvis;
+  size_t scale, pw, pcnt, gacc, logn, logoff, rmax, ws, ea, eb, entr, pvis, nb, app;
   size_t ckey, camp, cslot, csig;
   size_t cnt, fac, trig, init_d, init_a, sync, topk;
   size_t total;
@@ -49,12 +49,20 @@ struct Layout {
 
 bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
-// Sweep kernels use at most this many 256-thread blocks per state; each of
-// their waves owns a statistics slot.
+// Sweep kernels use at most this many 256-thread blocks per state (NA-way
+// interleaved over the arenas); each of their waves owns a statistics slot.
 constexpr int MAX_SWEEP_BLOCKS = 2048;
-size_t max_waves(uint64_t H) { return static_cast<size_t>(grid_for(H, 256, MAX_SWEEP_BLOCKS)) * 4; }
+constexpr int MAX_ARENA_BLOCKS = MAX_SWEEP_BLOCKS / NA;
+size_t max_waves() { return static_cast<size_t>(MAX_SWEEP_BLOCKS) * 4; }
 
-Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
+// Entries per arena for an index of Hcap slots: the index holds at most 90%
+// of Hcap entries, and the arenas 25% more than an even share of them.
+uint64_t arena_size(uint64_t Hcap) {
+  const uint64_t a = (Hcap / 10 * 9 / NA) * 5 / 4 + 64;
+  return std::min<uint64_t>(a, 1ull << ID_POS_BITS);
+}
+
+Layout make_layout(uint64_t Hcap, int tsz, int B, int64_t Mmax, uint64_t L) {
   Layout l{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -62,14 +70,14 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
     off = align_up(off + bytes);
     return o;
   };
-  const size_t BH = static_cast<size_t>(B) * H;
+  const size_t BE = static_cast<size_t>(B) * NA * arena_size(Hcap);
+  const size_t BH = static_cast<size_t>(B) * Hcap;
   const size_t BL = static_cast<size_t>(B) * L;
   const size_t BS = static_cast<size_t>(B) * static_cast<size_t>(Mmax + 1);
-  // two table regions: the table ping-pongs between them when it grows
-  for (int r = 0; r < 2; ++r) {
-    l.slots[r] = take(BH * (tsz == 4 ? sizeof(Slot<float>) : sizeof(Slot<double>)));
-    l.aux[r] = take(tsz == 4 ? BH * sizeof(AuxF) : 0);
-  }
+  l.ent = take(BE * (tsz == 4 ? sizeof(Slot<float>) : sizeof(Slot<double>)));
+  l.aux = take(tsz == 4 ? BE * sizeof(AuxF) : 0);
+  l.idx = take(BH * sizeof(Idx));
+  l.ac = take(static_cast<size_t>(B) * NA * 4);
   l.lkey = take(BL * 8);
   l.lmeta = take(BL * 4);
   l.lborn = take(BL * 4);
@@ -81,20 +89,22 @@ Layout make_layout(uint64_t H, int tsz, int B, int64_t Mmax, uint64_t L) {
   l.logn = take(BS * 4);
   l.logoff = take(BS * 4);
   l.rmax = take(static_cast<size_t>(Mmax + 1) * 4);
-  l.ws = take(static_cast<size_t>(B) * max_waves(H) * WSTAT * 8);
+  l.ws = take(static_cast<size_t>(B) * max_waves() * WSTAT * 8);
   l.ea = take(BS * ES * sizeof(Fx3));
   l.eb = take(BS * ES * sizeof(Fx3));
-  l.ent = take(BS * 8);
+  l.entr = take(BS * 8);
   l.pvis = take(BS * SH * 4);
-  l.ckey = take(BH * 8);
-  l.camp = take(BH * 8);
-  l.cslot = take(BH * 4);
-  l.csig = take(BH * 8);
+  l.nb = take(static_cast<size_t>(B) * static_cast<size_t>(Mmax + 3) * NA * 4);
+  l.app = take(static_cast<size_t>(B) * static_cast<size_t>(Mmax + 3) * NA * 4);
+  l.ckey = take(BE * 8);
+  l.camp = take(BE * 8);
+  l.cslot = take(BE * 4);
+  l.csig = take(BE * 8);
   l.cnt = take(static_cast<size_t>(B) * sizeof(Counters));
   l.fac = take(static_cast<size_t>(Mmax + 1) * sizeof(FacMask));
   l.trig = take(static_cast<size_t>(B) * static_cast<size_t>(Mmax + 1) * sizeof(Trig));
-  l.init_d = take(H / 2 * 8);
-  l.init_a = take(H / 2 * 8);
+  l.init_d = take(Hcap / 2 * 8);
+  l.init_a = take(Hcap / 2 * 8);
   l.sync = take(sizeof(Sync));
   l.topk = take(static_cast<size_t>(B) * sizeof(TopK));
   l.total = off;
@@ -149,7 +159,7 @@ FacMask factor_mask(const swc_exc& e) {
 }
 
 // A captured run of per-step kernels: direction (0 forward, 1 reverse),
-// steps k0..k1, threshold, log flag, table, occupancy limit and the optional
+// steps k0..k1, threshold, log flag, index size, occupancy limit and the optional
 // per-step arrays are baked into the kernel arguments; the choice of fused
 // factor pairs depends on the excitation list, whose upload clears the cache.
 struct GraphKey {
@@ -157,13 +167,12 @@ struct GraphKey {
   int64_t k0, k1;
   double thr;
   int log_on;
-  const void* slots;
   uint64_t H, lim;
   int ent = 0;
   uint64_t tk_max = 0, tk_cut = 0;
   int live = 0;  // the live-count array is passed to the kernels (swc_track_live)
   bool operator==(const GraphKey& o) const {
-    return dir == o.dir && k0 == o.k0 && k1 == o.k1 && thr == o.thr && log_on == o.log_on && slots == o.slots &&
+    return dir == o.dir && k0 == o.k0 && k1 == o.k1 && thr == o.thr && log_on == o.log_on &&
            H == o.H && lim == o.lim && ent == o.ent && tk_max == o.tk_max && tk_cut == o.tk_cut && live == o.live;
   }
 };
@@ -180,29 +189,20 @@ int64_t chunk_end(int64_t k) {
   while (p < k) p *= 2;
   return p;
 }
-int64_t chunk_begin(int64_t k) {
-  if (k > GRAPH_CHUNK) return (k - 1) / GRAPH_CHUNK * GRAPH_CHUNK + 1;
-  const int64_t p = chunk_end(k);
-  return p == 1 ? 1 : p / 2 + 1;
-}
 
 }  // namespace
 
 struct swc_ctx {
   int nq = 0, na = 0, nb = 0, prec = 0, B = 1;
-  uint64_t H = 0, L = 0;  // H: capacity (largest table), L: log records per state
-  // The table starts small and grows by rehashing into the other of two
-  // workspace regions (each sized for the capacity) between chunks of steps.
-  int region = 0;              // region holding the current table (tab.H slots)
-  // smallest table after a reset (SWC_TABLE_MIN): 2^18 slots (4-8 MB) scan in
-  // well under a launch latency, so growing below that only adds host round trips
+  uint64_t H = 0, L = 0;  // H: capacity (largest index), L: log records per state
+  // The index starts small and is rebuilt larger from the entries (which never
+  // move) between chunks of steps.  Smallest index after a reset
+  // (SWC_TABLE_MIN): 2^18 slots, so that growing below that adds no host
+  // round trips.
   uint64_t table_min = 1ull << 18;
   int grid_override = 0;       // SWC_GRID
   // two factors per launch at threshold 0 (SWC_FUSE=0 turns it off)
   bool fuse = true;
-  // the reverse sweep rehashes into a smaller table as its support shrinks
-  // (SWC_SHRINK=0 turns it off)
-  bool shrink = true;
   // entropy of every forward step (swc_track_entropy); sa.ea/eb are set
   // while it is on; ent_M: factors of the last tracked sweep (-1: none)
   bool entropy = false;
@@ -235,11 +235,11 @@ struct swc_ctx {
   int64_t ck_taken = 0;
   std::vector<uint64_t> ck_nmax;  // per checkpoint: most entries over the batch (last sweep)
   int64_t fwd_launches = 0, rev_launches = 0;  // launches of the last sweeps (per-launch timing)
-  int64_t rehashes = 0;        // table growths in the last forward sweep
-  int64_t compactions = 0;     // tombstone-dropping rehashes at its start
-  int64_t shrinks = 0;         // rehashes into smaller tables in the last reverse sweep
-  // slots the sweep launches scanned (sum over launches of the table size)
-  int64_t fwd_slots = 0, rev_slots = 0;
+  int64_t rehashes = 0;        // index growths in the last forward sweep
+  int64_t compactions = 0;     // rebuilds without the dead entries of earlier sweeps at its start
+  int64_t last_M = 0;          // factors of the last forward sweep (entry-scan totals of swc_get_stats)
+  bool rev_fused = false;      // the last reverse sweep undid two factors per launch
+  int64_t builds = 0;          // SWC_BUILD_* bits of the kernels the last sweeps launched
   int64_t Mmax = 0;
   hipStream_t st = nullptr;
   char* ws = nullptr;
@@ -262,18 +262,22 @@ struct swc_ctx {
   hipEvent_t ev[8] = {};
   double fwd_ms = 0, energy_ms = 0, rev_ms = 0;
   int64_t log_records = 0;
-  int grid = 1;  // blocks of a sweep launch: one per 256 slots, up to MAX_SWEEP_BLOCKS
-  // The one-factor step kernels are latency-bound while the table is small:
-  // they run fastest with as many lanes as can be resident at once (one wave
-  // round, the SCAN_U slots of a lane loaded together), and no more.
+  // Launches that scan the entries take NA * r blocks (r per arena).  grid:
+  // one entry per lane for the entries the current index may hold at its
+  // growth limit (the two-factor kernels and the one-pass kernels).  The
+  // one-factor step kernels are latency-bound while the state is small: they
+  // run fastest with as many lanes as can be resident at once (one wave
+  // round, the SCAN_U entries of a lane loaded together), and no more.
   // res_fwd / res_rev: resident blocks of k_fwd / k_rev on the whole device.
-  int grid_fs = 1, grid_rs = 1;
+  int grid = NA;
+  int grid_fs = NA, grid_rs = NA;
   int res_fwd = 0, res_rev = 0, res_fwd5 = 0;
   int res_f2w = 0, res_r2w = 0;  // resident blocks (all members) of the wide two-factor kernels
-  // forward steps use the five-wave build of k_fwd when the table takes more
-  // than one pass of the resident lanes (a latency-bound one-pass table runs
+  // forward steps use the five-wave build of k_fwd when the state takes more
+  // than one pass of the resident lanes (a latency-bound one-pass state runs
   // faster without its register spills)
   int fwd_wide = 0;
+  uint64_t per_arena = 0;  // entries per arena the grids are sized for
   // persistent (cooperative) sweeps, one launch per sweep: opt-in with
   // SWC_SWEEP=persistent (per-step launches are faster on MI355X: a
   // device-wide barrier needs agent-scope fences in every block)
@@ -333,33 +337,43 @@ int upload_masks(swc_ctx* c, const swc_exc* exc, int64_t M) {
   return SWC_OK;
 }
 
-// Make table `Hn` in workspace region `r` the current one.
-void set_table(swc_ctx* c, int r, uint64_t Hn) {
-  c->region = r;
-  c->tab = Tab{c->ws + c->lay.slots[r], c->ws + c->lay.aux[r], Hn};
-  int g = grid_for(Hn, 256, MAX_SWEEP_BLOCKS);
-  if (c->grid_override > 0) g = std::min(c->grid_override, g);
-  c->grid = g;
-  c->fwd_wide = (c->res_fwd > 0 && c->res_fwd5 > 0 &&
-                 Hn > static_cast<uint64_t>(c->res_fwd) * 256 * SCAN_U) ? 1 : 0;
-  const int rf = c->fwd_wide ? c->res_fwd5 : c->res_fwd;
-  c->grid_fs = rf > 0 ? std::min(g, rf) : g;
-  c->grid_rs = c->res_rev > 0 ? std::min(g, c->res_rev) : g;
+// A grid of NA * r blocks, r blocks of 256 lanes per arena covering `per`
+// entries of an arena `items` per lane, at least 1 and at most rmax blocks
+// per arena.
+int arena_grid(uint64_t per, int items, int rmax) {
+  uint64_t r = (per + 256 * items - 1) / (256 * items);
+  r = std::max<uint64_t>(1, std::min<uint64_t>(r, static_cast<uint64_t>(std::max(1, rmax))));
+  return static_cast<int>(r) * NA;
 }
 
-// Two-factor launches load several slots per probe up front when one launch
-// covers the current table in one pass and all its blocks are resident at once.
+// Make an index of Hn slots the current one (the grids follow its size).
+void set_table(swc_ctx* c, uint64_t Hn) {
+  c->tab.H = Hn;
+  // the entries an index of Hn slots holds at its growth limit (45%), per arena
+  c->per_arena = (Hn / 20 * 9 + NA - 1) / NA;
+  int rmax = MAX_ARENA_BLOCKS;
+  if (c->grid_override > 0) rmax = std::max(1, c->grid_override / NA);
+  c->grid = arena_grid(c->per_arena, 1, rmax);
+  c->fwd_wide = (c->res_fwd > 0 && c->res_fwd5 > 0 &&
+                 c->per_arena > static_cast<uint64_t>(c->res_fwd / NA) * 256 * SCAN_U) ? 1 : 0;
+  const int rf = c->fwd_wide ? c->res_fwd5 : c->res_fwd;
+  c->grid_fs = arena_grid(c->per_arena, SCAN_U, std::min(rmax, rf > 0 ? rf / NA : rmax));
+  c->grid_rs = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_rev > 0 ? c->res_rev / NA : rmax));
+}
+
+// Two-factor launches load several index slots per probe up front when one
+// launch covers the state in one pass and all its blocks are resident at once.
 int wide2(const swc_ctx* c, int resident) {
-  return static_cast<uint64_t>(c->grid) * 256 >= c->tab.H &&  // 256-thread blocks, one slot per lane
+  return static_cast<uint64_t>(c->grid / NA) * 256 >= c->per_arena &&
          static_cast<int64_t>(c->grid) * c->B <= static_cast<int64_t>(resident);
 }
 
-// Occupancy above which a forward step stops the sweep for a growth: with at
-// most a doubling per step and a stop that takes effect two steps later, the
-// table never passes 4 x 0.225 = 90% occupancy.
-uint64_t occ_limit(const swc_ctx* c) { return c->tab.H < c->H ? c->tab.H / 40 * 9 : NO_LIMIT; }
+// Entries above which a forward step does not run and stops the sweep for a
+// growth of the index: a step that runs at most doubles the entries, so the
+// index never passes 2 x 0.45 = 90% occupancy.
+uint64_t occ_limit(const swc_ctx* c) { return c->tab.H < c->H ? c->tab.H / 20 * 9 : NO_LIMIT; }
 
-// Smallest table, at least Hmin, that holds `need` occupied slots at <= 10% load.
+// Smallest index, at least Hmin, that holds `need` entries at <= 10% load.
 uint64_t table_size_for(const swc_ctx* c, uint64_t need, uint64_t Hmin) {
   if (c->persistent) return c->H;  // a persistent sweep cannot stop for a growth
   uint64_t h = std::min(Hmin, c->H);
@@ -367,38 +381,32 @@ uint64_t table_size_for(const swc_ctx* c, uint64_t need, uint64_t Hmin) {
   return h;
 }
 
-// Rehash the current table into the other region, `Hn` slots, keeping the
-// alive entries and the tombstones tagged 1..tag_max.
-int rehash_to(swc_ctx* c, uint64_t Hn, uint32_t tag_max = ~0u) {
-  const int r = 1 - c->region;
-  const Tab to{c->ws + c->lay.slots[r], c->ws + c->lay.aux[r], Hn};
-  const Tab from = c->tab;
+// Rebuild the index with Hn slots from the entries (the arena counts are
+// current: the sweep's runs end with a fold that sets them).
+int reindex_to(swc_ctx* c, uint64_t Hn) {
+  set_table(c, Hn);
   dispatch(c, [&](auto* tp) -> int {
-    launch_rehash<std::remove_pointer_t<decltype(tp)>>(from, to, c->cnt, c->B, tag_max, c->st);
+    launch_reindex<std::remove_pointer_t<decltype(tp)>>(c->tab, c->cnt, c->B, c->grid, c->st);
     return SWC_OK;
   });
   SWC_HIP(hipGetLastError());
-  set_table(c, r, Hn);
   ++c->rehashes;
   return SWC_OK;
 }
 
-// Grow the table (x2 at least) so that `need` occupied slots stay under the
-// growth limit of the new size.
+// Grow the index (x2 at least) so that `need` entries stay under the growth
+// limit of the new size.
 int grow_table(swc_ctx* c, uint64_t need) {
   if (c->persistent || c->tab.H >= c->H) return SWC_OK;
   uint64_t Hn = 2 * c->tab.H;
-  while (Hn < c->H && need > Hn / 40 * 9) Hn <<= 1;
-  return rehash_to(c, std::min(Hn, c->H));
+  while (Hn < c->H && need > Hn / 20 * 9) Hn <<= 1;
+  return reindex_to(c, std::min(Hn, c->H));
 }
 
-// Reset every batch member to |Psi_0> in a table sized for it.
+// Reset every batch member to |Psi_0> with an index sized for it.
 int reset_state(swc_ctx* c) {
-  set_table(c, 0, table_size_for(c, c->h_init_d.size(), c->table_min));
-  dispatch(c, [&](auto* tp) -> int {
-    launch_fill<std::remove_pointer_t<decltype(tp)>>(c->tab, c->B, c->st);
-    return SWC_OK;
-  });
+  set_table(c, table_size_for(c, c->h_init_d.size(), c->table_min));
+  launch_fill(c->tab, c->B, c->st);
   for (int b = 0; b < c->B; ++b) {
     Counters z{};
     z.S = c->S0;
@@ -412,12 +420,36 @@ int reset_state(swc_ctx* c) {
   const int64_t n = static_cast<int64_t>(c->h_init_d.size());
   int r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
-    launch_insert_init<T>(c->tab, c->cnt, c->init_d, c->init_a, n, c->B, c->st);
+    launch_insert_list<T>(c->tab, c->cnt, c->init_d, c->init_a, n, 0, n, c->B, c->st);
     return SWC_OK;
   });
   if (r) return r;
   SWC_HIP(hipGetLastError());
   c->fresh = true;
+  return SWC_OK;
+}
+
+// Drop the dead entries of earlier sweeps: the live entries are copied out
+// (the compact arrays), the state is emptied and they are inserted again.
+// Every live entry is tagged 0 at a sweep's start anyway.
+int compact_state(swc_ctx* c, uint64_t live) {
+  launch_energy_begin(c->cnt, c->B, c->st);
+  int r = dispatch(c, [&](auto* tp) -> int {
+    launch_compact<std::remove_pointer_t<decltype(tp)>>(c->tab, c->cp, c->cnt, c->B, c->grid, c->st);
+    return SWC_OK;
+  });
+  if (r) return r;
+  set_table(c, table_size_for(c, live, c->table_min));
+  launch_fill(c->tab, c->B, c->st);
+  launch_counters_live_reset(c->cnt, c->B, c->st);
+  r = dispatch(c, [&](auto* tp) -> int {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    launch_insert_list<T>(c->tab, c->cnt, c->cp.key, c->cp.amp, -1, c->cp.cs, static_cast<int64_t>(live), c->B,
+                          c->st);
+    return SWC_OK;
+  });
+  if (r) return r;
+  SWC_HIP(hipGetLastError());
   return SWC_OK;
 }
 
@@ -498,9 +530,34 @@ bool fusable(const swc_ctx* c, int64_t k, double thr, uint64_t lim) {
   return c->fuse && !c->entropy && c->tk_max == 0 && thr == 0.0 && lim == NO_LIMIT && c->hmask[k - 1] != c->hmask[k];
 }
 
-int64_t fwd_launch_count(const swc_ctx* c, int64_t k0, int64_t k1, double thr, uint64_t lim) {
+// The launches a forward range issues (issue_fwd): their number, and the
+// kernel builds they use added to *builds (SWC_BUILD_* bits).
+int64_t fwd_plan(const swc_ctx* c, int64_t k0, int64_t k1, double thr, uint64_t lim, int64_t* builds) {
   int64_t n = 0;
-  for (int64_t k = k0; k <= k1; ++n) k += (k < k1 && fusable(c, k, thr, lim)) ? 2 : 1;
+  for (int64_t k = k0; k <= k1; ++n) {
+    if (k < k1 && fusable(c, k, thr, lim)) {
+      *builds |= wide2(c, c->res_f2w) ? SWC_BUILD_FWD2_PRE : SWC_BUILD_FWD2;
+      k += 2;
+    } else {
+      *builds |= c->entropy ? SWC_BUILD_FWD_ENT : c->fwd_wide ? SWC_BUILD_FWD_WIDE : SWC_BUILD_FWD;
+      k += 1;
+    }
+  }
+  return n;
+}
+
+// The same for a reverse range (issue_rev).
+int64_t rev_plan(const swc_ctx* c, int64_t hi, int64_t lo, bool fuse, int64_t* builds) {
+  int64_t n = 0;
+  for (int64_t k = hi; k >= lo; ++n) {
+    if (fuse && k > lo && c->hmask[k - 2] != c->hmask[k - 1]) {
+      *builds |= wide2(c, c->res_r2w) ? SWC_BUILD_REV2_PRE : SWC_BUILD_REV2;
+      k -= 2;
+    } else {
+      *builds |= SWC_BUILD_REV;
+      k -= 1;
+    }
+  }
   return n;
 }
 
@@ -547,24 +604,21 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
   return dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
     if (c->use_graph && !c->ktiming && graph_ok) {
-      const GraphKey key{0, k0, k1, thr, log_on, c->tab.slots, c->tab.H, lim, c->entropy ? 1 : 0,
-                         c->tk_max, c->tk_cut, c->live ? 1 : 0};
+      const GraphKey key{0, k0, k1, thr, log_on, c->tab.H, lim, c->entropy ? 1 : 0, c->tk_max, c->tk_cut,
+                         c->live ? 1 : 0};
       hipGraphExec_t ex = nullptr;
       const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { issue_fwd<T>(c, k0, k1, thr, log_on, lim, cs); });
       if (rr) return rr;
       SWC_HIP(hipGraphLaunch(ex, c->st));
-      const int64_t n = fwd_launch_count(c, k0, k1, thr, lim);
-      c->fwd_launches += n;
-      c->fwd_slots += n * static_cast<int64_t>(c->tab.H);
+      c->fwd_launches += fwd_plan(c, k0, k1, thr, lim, &c->builds);
       return SWC_OK;
     }
     if (!c->ktiming) {
       issue_fwd<T>(c, k0, k1, thr, log_on, lim, c->st);
-      const int64_t n = fwd_launch_count(c, k0, k1, thr, lim);
-      c->fwd_launches += n;
-      c->fwd_slots += n * static_cast<int64_t>(c->tab.H);
+      c->fwd_launches += fwd_plan(c, k0, k1, thr, lim, &c->builds);
       return SWC_OK;
     }
+    c->builds |= c->entropy ? SWC_BUILD_FWD_ENT : c->fwd_wide ? SWC_BUILD_FWD_WIDE : SWC_BUILD_FWD;
     for (int64_t k = k0; k <= k1; ++k) {  // every launch timed: one step per launch
       (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
@@ -575,7 +629,6 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
                        c->st);
     }
     c->fwd_launches += k1 - k0 + 1;
-    c->fwd_slots += (k1 - k0 + 1) * static_cast<int64_t>(c->tab.H);
     return SWC_OK;
   });
 }
@@ -614,7 +667,8 @@ int take_checkpoint(swc_ctx* c, int64_t k, int64_t M, int log_on) {
   const int64_t j = ckpt_index(c, k, M);
   if (j < 0) return SWC_OK;
   dispatch(c, [&](auto* tp) -> int {
-    launch_snapshot<std::remove_pointer_t<decltype(tp)>>(c->tab, ckpt_snap(c, j), c->B, c->grid, c->st);
+    launch_snapshot<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, ckpt_snap(c, j), static_cast<int>(k), c->B,
+                                                         c->grid, c->st);
     return SWC_OK;
   });
   ++c->ck_taken;
@@ -650,20 +704,16 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   }
   c->rehashes = 0;
   c->compactions = 0;
+  c->builds = 0;
   c->sa.ea = c->entropy ? c->ent_ea : nullptr;
   c->sa.eb = c->entropy ? c->ent_eb : nullptr;
   c->ent_M = -1;
   c->live_M = -1;
   c->sa.pvis = c->live ? c->live_pvis : nullptr;
-  dispatch(c, [&](auto* tp) -> int {
-    launch_sweep_begin<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, c->cnt, M, c->B, c->st);
-    return SWC_OK;
-  });
-  SWC_HIP(hipEventRecord(c->ev[0], c->st));
   {
-    // Tombstones of earlier sweeps (tag 0 after the sweep start) are dropped
-    // by a rehash; compact when they are over a quarter of the occupied slots.
-    // The counters are current: the theta check has just read them.
+    // Dead entries of earlier sweeps are dropped when they are over a quarter
+    // of the entries.  The counters are current: they were read after the
+    // call that left this state.
     uint64_t live = 0;
     bool compact = false;
     for (int b = 0; b < c->B; ++b) {
@@ -672,12 +722,16 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       compact = compact || (ob >= 1024 && 4 * (ob - std::min(ob, lb)) > ob);
     }
     if (M > 0 && compact) {
-      const int r = rehash_to(c, table_size_for(c, live, c->table_min));
-      if (r) return r;
-      --c->rehashes;
+      if (int r = compact_state(c, live)) return r;
       ++c->compactions;
     }
   }
+  dispatch(c, [&](auto* tp) -> int {
+    launch_sweep_begin<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, c->cnt, M, c->B, c->grid, c->st);
+    return SWC_OK;
+  });
+  c->last_M = M;
+  SWC_HIP(hipEventRecord(c->ev[0], c->st));
   if (c->entropy) {  // entropy of the state the sweep starts from
     dispatch(c, [&](auto* tp) -> int {
       launch_entropy_scan<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, 0, c->B, c->grid, c->st);
@@ -687,7 +741,6 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   c->ck_taken = 0;
   if (log_on && c->ck_n > 0) launch_zero_u64(c->ck_count, static_cast<uint64_t>(c->ck_n) * c->B, c->st);
   c->fwd_launches = 0;
-  c->fwd_slots = 0;
   if (c->persistent && c->tk_max == 0) {
     // one cooperative launch per range between checkpoints (the N_MAX / N_CUT
     // selection needs launches of its own after every step: per-step path)
@@ -698,6 +751,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
         if (ckpt_index(c, nxt, M) >= 0) k1 = nxt;
       }
       launch_sync_reset(c->sy, k == 1, c->st);
+      c->builds |= SWC_BUILD_PERSISTENT;
       const int r = dispatch(c, [&](auto* tp) -> int {
         using T = std::remove_pointer_t<decltype(tp)>;
         const int64_t i = c->fwd_launches;
@@ -709,7 +763,6 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       });
       if (r) return r;
       ++c->fwd_launches;
-      c->fwd_slots += (k1 - k + 1) * static_cast<int64_t>(c->tab.H);
       if (int rr = take_checkpoint(c, k1, M, log_on)) return rr;
       k = k1 + 1;
     }
@@ -729,13 +782,12 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
         k = k1 + 1;
         continue;
       }
-      launch_sweep_end(c->sa, c->cnt, k1, c->B, nullptr, 1, c->st);
+      launch_sweep_end(c->tab, c->sa, c->cnt, k1, k1, c->B, nullptr, 1, c->st);
       if ((r = read_counters(c))) return r;
       // a step that stopped the sweep (stop = first step not run) asks for a growth
       const uint32_t stop = c->hcnt[0].stop;
       const bool stopped = stop != ~0u;
       const int64_t next = stopped ? std::min<int64_t>(static_cast<int64_t>(stop), k1 + 1) : k1 + 1;
-      c->fwd_slots -= (k1 + 1 - next) * static_cast<int64_t>(c->tab.H);  // stopped steps scanned nothing
       bool full = false;
       for (int b = 0; b < c->B; ++b) full = full || (c->hcnt[b].flags & F_TABLE_FULL);
       if (full) break;  // reported by the caller's status check
@@ -760,7 +812,7 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       k = next;
     }
   }
-  launch_sweep_end(c->sa, c->cnt, M, c->B, (c->persistent && M > 0) ? c->sy : nullptr, 0, c->st);
+  launch_sweep_end(c->tab, c->sa, c->cnt, M, M, c->B, (c->persistent && M > 0) ? c->sy : nullptr, 0, c->st);
   SWC_HIP(hipEventRecord(c->ev[1], c->st));
   if (c->entropy) {
     launch_entropy_final(c->sa, M, c->B, c->st);
@@ -771,52 +823,23 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   return SWC_OK;
 }
 
-// Before the reverse sweep undoes steps hi, hi-1, ...: the entries it still
-// needs are the alive ones and the tombstones of steps <= hi (members that
-// undoing a later step removed, and tombstones of earlier sweeps, are dead
-// weight).  The reverse sweep never adds a slot, so when those fit a table of
-// at most half the size at <= 45% occupancy, they move into one: every later
-// step scans fewer slots.  The truncation log and the checkpoints locate
-// entries by determinant, so they stay valid.
-int shrink_table(swc_ctx* c, int64_t hi) {
-  if (!c->shrink || c->persistent || c->tab.H <= c->table_min) return SWC_OK;
-  const uint32_t tag_max = static_cast<uint32_t>(hi);
-  dispatch(c, [&](auto* tp) -> int {
-    launch_count_keep<std::remove_pointer_t<decltype(tp)>>(c->tab, c->cnt, c->B, tag_max, c->st);
-    return SWC_OK;
-  });
-  if (int r = read_counters(c)) return r;
-  uint64_t keep = 0;
-  for (int b = 0; b < c->B; ++b) keep = std::max<uint64_t>(keep, counter_total(c->hcnt[b], C_COPY));
-  uint64_t Hn = c->table_min;
-  while (Hn < c->tab.H && keep > Hn / 20 * 9) Hn <<= 1;
-  if (Hn > c->tab.H / 2) return SWC_OK;
-  const int64_t g = c->rehashes;
-  if (int r = rehash_to(c, Hn, tag_max)) return r;
-  c->rehashes = g;  // growths are counted for the forward sweep only
-  ++c->shrinks;
-  return SWC_OK;
-}
-
 // The adjoint sweep, steps M..1, in ranges that end where a chunk or a
 // checkpoint interval ends; after the range that reconstructs the state of a
 // checkpoint, the checkpoint's amplitudes are written back over it.
 // maxn[k]: largest number of truncation-log records of step k over the batch.
 int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>& maxn) {
   c->rev_launches = 0;
-  c->rev_slots = 0;
-  c->shrinks = 0;
-  // ranges between the shrink checks; a table at the minimum size cannot
-  // shrink, so its ranges only stop at multiples of GRAPH_CHUNK
-  const bool wide = !c->shrink || c->persistent || c->tab.H <= c->table_min;
+  c->rev_fused = c->fuse && thr == 0.0 && !c->persistent && !c->ktiming && c->log_records == 0;
+  // Each step scans only the entries that existed after it in the forward
+  // sweep, so the scans shrink as the sweep goes back without any rebuild;
+  // ranges stop at multiples of GRAPH_CHUNK and at checkpoints.
   for (int64_t hi = M; hi >= 1;) {
-    int64_t lo = wide ? (hi - 1) / GRAPH_CHUNK * GRAPH_CHUNK + 1 : chunk_begin(hi);
+    int64_t lo = (hi - 1) / GRAPH_CHUNK * GRAPH_CHUNK + 1;
     if (c->ck_interval > 0) lo = std::max(lo, (hi - 1) / c->ck_interval * c->ck_interval + 1);
-    if (int rr = shrink_table(c, hi)) return rr;
-    const int64_t launches0 = c->rev_launches;
     const int r = dispatch(c, [&](auto* tp) -> int {
       using T = std::remove_pointer_t<decltype(tp)>;
       if (c->persistent) {
+        c->builds |= SWC_BUILD_PERSISTENT;
         launch_sync_reset(c->sy, hi == M, c->st);
         const int64_t i = c->rev_launches++;
         if (c->ktiming) (void)hipEventRecord(c->kev[2 * i], c->st);
@@ -829,22 +852,19 @@ int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>
         // no log restores interleaved: one or two steps per launch, from a
         // cached graph of the range
         const bool fz = c->fuse && thr == 0.0;
+        c->rev_launches += rev_plan(c, hi, lo, fz, &c->builds);
         if (!c->use_graph) {
-          c->rev_launches += issue_rev<T>(c, hi, lo, fz, c->st);
+          issue_rev<T>(c, hi, lo, fz, c->st);
           return SWC_OK;
         }
-        const GraphKey key{1, lo, hi, fz ? 0.0 : 1.0, 0, c->tab.slots, c->tab.H, 0};
+        const GraphKey key{1, lo, hi, fz ? 0.0 : 1.0, 0, c->tab.H, 0};
         hipGraphExec_t ex = nullptr;
-        int64_t n = 0;
-        const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { n = issue_rev<T>(c, hi, lo, fz, cs); });
+        const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { issue_rev<T>(c, hi, lo, fz, cs); });
         if (rr) return rr;
         SWC_HIP(hipGraphLaunch(ex, c->st));
-        if (n == 0) {  // graph from the cache: count its launches the same way
-          for (int64_t k = hi; k >= lo; ++n) k -= (fz && k > lo && c->hmask[k - 2] != c->hmask[k - 1]) ? 2 : 1;
-        }
-        c->rev_launches += n;
         return SWC_OK;
       }
+      c->builds |= SWC_BUILD_REV;
       for (int64_t k = hi; k >= lo; --k) {
         if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
         launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid_rs,
@@ -856,7 +876,6 @@ int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>
       return SWC_OK;
     });
     if (r) return r;
-    c->rev_slots += (c->rev_launches - launches0) * static_cast<int64_t>(c->tab.H);
     if (int rr = report_progress(c, "reverse", M - lo + 1, M)) return rr;
     const int64_t j = ckpt_index(c, lo - 1, M);
     if (j >= 0) {
@@ -940,7 +959,7 @@ int pair_sigma(swc_ctx* c, const double* h1, const double* h2, int64_t nmax) {
   PairScratch ps;
   if (!pair_scratch(c, static_cast<uint64_t>(nmax), &ps)) return fail(SWC_EINVAL, "sigma scratch too small");
   const uint64_t P = static_cast<uint64_t>(electrons(c)) * (electrons(c) - 1) / 2;
-  const uint64_t H = c->tab.H;
+  const uint64_t H = c->cp.cs;  // stride of the compact arrays
   for (int b = 0; b < c->B; ++b) {
     const uint64_t N = c->hcnt[b].ncompact;
     if (N == 0) continue;
@@ -1007,7 +1026,7 @@ int energy_run(swc_ctx* c, const double* h1, const double* h2, double* E, bool w
   c->sig_parts = 0;
   if (pairs && (r = pair_sigma(c, h1, h2, nmax))) return r;
   SWC_HIP(hipEventRecord(c->ev[7], c->st));
-  launch_energy_reduce(c->cp, c->cnt, c->tab.H, h1, h2, n, nmax, c->B, c->st);
+  launch_energy_reduce(c->cp, c->cnt, h1, h2, n, nmax, c->B, c->st);
   launch_energy_final(c->cnt, E, c->B, c->st);
   if (want_lambda) {
     r = dispatch(c, [&](auto* tp) -> int {
@@ -1076,7 +1095,9 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   c->lay = make_layout(c->H, tsz, c->B, c->Mmax, c->L);
   const Layout& l = c->lay;
   char* w = c->ws;
-  c->tab = Tab{w + l.slots[0], w + l.aux[0], c->H};
+  const uint64_t A = arena_size(c->H);
+  c->tab = Tab{w + l.ent, w + l.aux, reinterpret_cast<Idx*>(w + l.idx), reinterpret_cast<uint32_t*>(w + l.ac), c->H,
+               c->H, A};
   c->lg = LogArr{reinterpret_cast<uint64_t*>(w + l.lkey), reinterpret_cast<uint32_t*>(w + l.lmeta),
                  reinterpret_cast<uint32_t*>(w + l.lborn), w + l.lamp, c->L};
   c->sa = StepArr{reinterpret_cast<double*>(w + l.scale),   reinterpret_cast<Fx3*>(w + l.pw),
@@ -1084,14 +1105,17 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
                   reinterpret_cast<uint32_t*>(w + l.logn),  reinterpret_cast<uint32_t*>(w + l.logoff),
                   reinterpret_cast<uint32_t*>(w + l.rmax),
                   reinterpret_cast<unsigned long long*>(w + l.ws),
-                  static_cast<int64_t>(max_waves(c->H)),
+                  static_cast<int64_t>(max_waves()),
                   c->Mmax + 1,
-                  nullptr, nullptr, reinterpret_cast<double*>(w + l.ent), nullptr};
+                  nullptr, nullptr, reinterpret_cast<double*>(w + l.entr), nullptr,
+                  reinterpret_cast<uint32_t*>(w + l.nb), reinterpret_cast<uint32_t*>(w + l.app),
+                  c->Mmax + 3};
   c->live_pvis = reinterpret_cast<uint32_t*>(w + l.pvis);
   c->ent_ea = reinterpret_cast<Fx3*>(w + l.ea);
   c->ent_eb = reinterpret_cast<Fx3*>(w + l.eb);
   c->cp = Compact{reinterpret_cast<uint64_t*>(w + l.ckey), reinterpret_cast<double*>(w + l.camp),
-                  reinterpret_cast<uint32_t*>(w + l.cslot), reinterpret_cast<double*>(w + l.csig)};
+                  reinterpret_cast<uint32_t*>(w + l.cslot), reinterpret_cast<double*>(w + l.csig),
+                  static_cast<uint64_t>(NA) * A};
   c->cnt = reinterpret_cast<Counters*>(w + l.cnt);
   c->fac = reinterpret_cast<FacMask*>(w + l.fac);
   c->trig = reinterpret_cast<Trig*>(w + l.trig);
@@ -1103,7 +1127,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     const long long v = std::atoll(e);
     if (v >= 64 && pow2(static_cast<uint64_t>(v))) c->table_min = static_cast<uint64_t>(v);
   }
-  set_table(c, 0, c->H);
+  set_table(c, c->H);
   const int g = c->grid;
   c->sy = reinterpret_cast<Sync*>(w + l.sync);
   c->tk = reinterpret_cast<TopK*>(w + l.topk);
@@ -1118,8 +1142,8 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     const int bf = prec == SWC_FP32 ? resident_blocks_per_cu<float>(0) : resident_blocks_per_cu<double>(0);
     const int br = prec == SWC_FP32 ? resident_blocks_per_cu<float>(1) : resident_blocks_per_cu<double>(1);
     // co-resident blocks shared by the batch members (grid.y = batch)
-    c->grid_fwd = std::min(g, bf * ncu / batch);
-    c->grid_rev = std::min(g, br * ncu / batch);
+    c->grid_fwd = std::min(g, bf * ncu / batch) / NA * NA;
+    c->grid_rev = std::min(g, br * ncu / batch) / NA * NA;
     if (c->grid_fwd < 1 || c->grid_rev < 1) c->persistent = false;
     // resident step blocks, shared by the batch members (grid.y = batch)
     const int sf = prec == SWC_FP32 ? resident_blocks_per_cu<float>(2) : resident_blocks_per_cu<double>(2);
@@ -1130,13 +1154,12 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     c->res_fwd5 = std::max(1, s5 * ncu / batch);
     c->res_f2w = (prec == SWC_FP32 ? resident_blocks_per_cu<float>(5) : resident_blocks_per_cu<double>(5)) * ncu;
     c->res_r2w = (prec == SWC_FP32 ? resident_blocks_per_cu<float>(6) : resident_blocks_per_cu<double>(6)) * ncu;
-    set_table(c, 0, c->H);  // step grids with the resident limits
+    set_table(c, c->H);  // step grids with the resident limits
   }
   if (const char* e = std::getenv("SWC_KERNEL_TIMING")) c->ktiming = std::atoi(e) != 0;
   if (const char* e = std::getenv("SWC_GRAPH")) c->use_graph = std::atoi(e) != 0;
   if (const char* e = std::getenv("SWC_PROGRESS")) c->progress = std::atoi(e) != 0;
   if (const char* e = std::getenv("SWC_FUSE")) c->fuse = std::atoi(e) != 0;
-  if (const char* e = std::getenv("SWC_SHRINK")) c->shrink = std::atoi(e) != 0;
   for (auto& e : c->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
       swc_destroy(c);
@@ -1315,7 +1338,7 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
   if ((r = reverse_sweep(c, M, threshold, maxn))) return r;
   launch_grad_final(c->sa, c->cnt, grad, M, c->B, c->st);
   SWC_HIP(hipEventRecord(c->ev[5], c->st));
-  if (c->persistent && M > 0) launch_sweep_end(c->sa, c->cnt, 0, c->B, c->sy, 0, c->st);  // barrier status only
+  if (c->persistent && M > 0) launch_sweep_end(c->tab, c->sa, c->cnt, 0, 0, c->B, c->sy, 0, c->st);  // barrier status only
   SWC_HIP(hipGetLastError());
   // One host wait for the adjoint sweep's status and the counters of the
   // state it leaves (|Psi_0> again, rebuilt right away).
@@ -1477,8 +1500,8 @@ int swc_get_state(swc_ctx* c, int b, uint64_t* dets, double* amps, int64_t cap, 
   if (n > cap) return fail(SWC_ECAPACITY, "output arrays too small");
   std::vector<uint64_t> k(static_cast<size_t>(n));
   std::vector<double> a(static_cast<size_t>(n));
-  SWC_HIP(hipMemcpyAsync(k.data(), c->cp.key + b * c->tab.H, 8 * n, hipMemcpyDeviceToHost, c->st));
-  SWC_HIP(hipMemcpyAsync(a.data(), c->cp.amp + b * c->tab.H, 8 * n, hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipMemcpyAsync(k.data(), c->cp.key + b * c->cp.cs, 8 * n, hipMemcpyDeviceToHost, c->st));
+  SWC_HIP(hipMemcpyAsync(a.data(), c->cp.amp + b * c->cp.cs, 8 * n, hipMemcpyDeviceToHost, c->st));
   SWC_HIP(hipStreamSynchronize(c->st));
   std::vector<int64_t> idx(static_cast<size_t>(n));
   for (int64_t i = 0; i < n; ++i) idx[i] = i;
@@ -1495,6 +1518,7 @@ int swc_get_state(swc_ctx* c, int b, uint64_t* dets, double* amps, int64_t cap, 
 
 int swc_get_stats(swc_ctx* c, swc_stats* out) {
   if (!c || !out) return fail(SWC_EINVAL, "null argument");
+  if (c->last_M > 0) launch_scan_totals(c->sa, c->cnt, c->last_M, c->B, c->st);
   int r = read_counters(c);
   if (r) return r;
   swc_stats s{};
@@ -1511,9 +1535,12 @@ int swc_get_stats(swc_ctx* c, swc_stats* out) {
   s.table_slots = static_cast<int64_t>(c->tab.H);
   s.rehashes = c->rehashes;
   s.compactions = c->compactions;
-  s.shrinks = c->shrinks;
-  s.fwd_slots_scanned = c->fwd_slots;
-  s.rev_slots_scanned = c->rev_slots;
+  s.shrinks = 0;
+  s.kernel_builds = c->builds;
+  for (int b = 0; b < c->B; ++b) {
+    s.fwd_slots_scanned += static_cast<int64_t>(c->hcnt[b].sh[0].v[C_FSCAN]);
+    s.rev_slots_scanned += static_cast<int64_t>(c->hcnt[b].sh[0].v[C_RSCAN]);
+  }
   s.checkpoints = c->ck_taken;
   s.sigma_partitions = c->sig_parts;
   s.fwd_ms = c->fwd_ms;

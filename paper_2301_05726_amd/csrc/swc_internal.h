@@ -9,20 +9,32 @@
 namespace swc {
 
 // ---------------------------------------------------------------------------
-// hash-table slot encoding
+// state layout: dense entry arrays + a hash index
 // ---------------------------------------------------------------------------
-// keys[s] == EMPTY_KEY: never used.  Otherwise meta[s] holds a state bit and
-// a step tag (1-based factor index within the current sweep, 0 = before it):
+// The determinants of a state are entries of dense arrays (Slot<T>, plus the
+// AuxF side array for float states), split into NA arenas: a launch appends
+// the entries it creates to the arena of the creating wave, so the entries of
+// an arena are in creation order.  The sweeps scan the entries, never the
+// empty slots of a hash table.  A separate open-addressed index (linear
+// probing on a 64-bit mixer) maps a determinant to its entry.
+//
+// An entry's meta holds a state bit and a step tag (1-based factor index
+// within the current sweep, 0 = before it):
 //   alive:  meta = born tag          (step that created the entry)
 //   dead:   meta = DEAD | death tag   (step whose truncation removed it)
-// born[s] keeps the creation tag of dead entries (needed when the reverse
-// sweep resurrects them).  A dead entry keeps its key (tombstone) and, for a
-// death during the current sweep, the pre-truncation amplitude.
+// born keeps the creation tag of dead entries (needed when the reverse sweep
+// resurrects them).  A dead entry keeps its key (it stays in the index) and,
+// for a death during the current sweep, its pre-truncation amplitude.
 constexpr uint64_t EMPTY_KEY = ~0ull;
-constexpr uint64_t NO_LIMIT = ~0ull;  // occupancy limit of a table that cannot grow
+constexpr uint64_t NO_LIMIT = ~0ull;  // index occupancy limit of an index that cannot grow
 constexpr int SH = 64;  // shards of each per-step accumulator
 constexpr uint32_t DEAD = 0x80000000u;
 constexpr uint32_t TAG = 0x7fffffffu;
+constexpr int NA = 64;                   // arenas per state
+constexpr int ID_POS_BITS = 26;          // entry id = arena << 26 | position in the arena
+constexpr uint32_t ID_POS_MASK = (1u << ID_POS_BITS) - 1u;
+constexpr uint32_t NO_ID = ~0u;          // an index slot whose entry id is not written yet
+constexpr uint32_t NB_UNSET = ~0u;       // no forward launch began at this step
 
 // status flags (Counters::flags)
 enum : uint32_t {
@@ -61,15 +73,16 @@ struct Fx3 {
 constexpr int CSH = 32;
 enum : int {
   C_LIVE = 0,  // alive entries
-  C_OCC,       // slots holding a key (alive + tombstones)
+  C_OCC,       // entries (alive + dead) = occupied index slots
   C_DU,        // det visits (forward)
   C_PAIRS,     // rotated pairs (forward)
   C_INS,       // created entries (forward)
   C_PRUNED,    // truncated amplitudes (forward)
   C_HITS,      // rotated pairs whose partner existed (forward)
-  C_COPY,      // slots copied by the last rehash
   C_NCNT
 };
+// shard 0 only: entry positions scanned by the last forward / reverse sweep
+constexpr int C_FSCAN = 14, C_RSCAN = 15;
 struct alignas(128) CShard {
   unsigned long long v[16];
 };
@@ -111,9 +124,9 @@ struct Trig {
   double c, s, cm1;  // cos, sin, cos - 1 (= -2 sin^2(theta/2))
 };
 
-// Hash-table slots.  float states: 16-byte {key, amp, meta} plus an 8-byte
-// side array {lam, born}; double states: one 32-byte slot.  lam is the
-// adjoint amplitude of the reverse sweep, born the creation tag.
+// Entries.  float states: 16-byte {key, amp, meta} plus an 8-byte side
+// array {lam, born}; double states: one 32-byte entry.  lam is the adjoint
+// amplitude of the reverse sweep, born the creation tag.
 template <class T>
 struct Slot;
 template <>
@@ -135,11 +148,23 @@ struct alignas(8) AuxF {
   uint32_t born;
 };
 
-// per-state tables; member b's slots start at b*H
+// index slot: determinant and its entry id (EMPTY_KEY: free)
+struct alignas(16) Idx {
+  uint64_t key;
+  uint32_t id;
+  uint32_t pad;
+};
+
+// The state of every batch member: member b's entries at b*E (E = NA*A; arena
+// s at s*A), its index slots at b*Hcap (H of them in use).
 struct Tab {
-  void* slots;  // Slot<T>[B*H]
-  void* aux;    // AuxF[B*H] for float states, unused for double
-  uint64_t H;   // slots per state, power of two
+  void* ent;     // Slot<T>[B*E]
+  void* aux;     // AuxF[B*E] for float states, unused for double
+  Idx* idx;      // Idx[B*Hcap]
+  uint32_t* ac;  // entries per arena [B*NA] between sweeps (a sweep keeps its counts per step)
+  uint64_t H;    // index slots in use per member (power of two)
+  uint64_t Hcap; // index slots reserved per member
+  uint64_t A;    // entries per arena (<= 2^ID_POS_BITS)
 };
 
 // truncation log: states of tombstones overwritten by a resurrection
@@ -176,6 +201,14 @@ struct StepArr {
   // sharded like pcnt; shard 0 at k = 0 holds the live count after the sweep
   // (null unless tracked)
   uint32_t* pvis;
+  // entries per arena when the forward launch at step k began (NB_UNSET where
+  // no launch began: the second step of a two-factor launch, or not run yet),
+  // and the entries that launch appended: [(b*nstride + k)*NA + arena]; the
+  // counts of a launch are those of the one before it plus its appends, and
+  // nb[M + 1] holds the counts at the end of the sweep
+  uint32_t* nb;
+  uint32_t* app;
+  int64_t nstride;  // max_factors + 3
 };
 constexpr int WSTAT = 8;
 // table slots each lane of a one-factor sweep step loads per pass
@@ -214,33 +247,39 @@ struct Snap {
   uint64_t cap;
 };
 
-// compact copies of the live entries (energy / state export), member b at b*H
+// compact copies of the live entries (energy / state export), member b at b*cs
 struct Compact {
   uint64_t* key;
   double* amp;
-  uint32_t* slot;
+  uint32_t* slot;  // entry id
   double* sig;
+  uint64_t cs;     // stride per member (>= its entries)
 };
 
 // ---------------------------------------------------------------------------
-// kernel launchers (swc_kernels.hip); all asynchronous on `st`
+// kernel launchers (swc_kernels.hip); all asynchronous on `st`.  Launches
+// that scan the entries take a grid of NA * r blocks (r blocks per arena).
 // ---------------------------------------------------------------------------
-template <class T>
+// an empty state: index cleared (t.H slots), arenas empty
 void launch_fill(const Tab& t, int B, hipStream_t st);
+// insert n determinants (member b's at b * stride; n_fixed < 0: member b's
+// count is cnt[b].ncompact) into an empty state; nmax bounds the counts
 template <class T>
-void launch_insert_init(const Tab& t, Counters* cnt, const uint64_t* dets, const double* amps, int64_t n, int B,
-                        hipStream_t st);
+void launch_insert_list(const Tab& t, Counters* cnt, const uint64_t* keys, const double* amps, int64_t n_fixed,
+                        uint64_t stride, int64_t nmax, int B, hipStream_t st);
 void launch_trig(const double* theta, Trig* trig, int64_t M, int64_t ld, int B, Counters* cnt, hipStream_t st);
 template <class T>
-void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st);
-// fold the per-wave statistics into the counters; unless fold_only, also the
-// final scale S_M
-void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, int fold_only,
-                      hipStream_t st);
+void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int B, int grid, hipStream_t st);
+// fold the per-wave statistics into the counters and set the arena counts
+// after the last step that ran (fold_only: a run of steps up to k_last, cut
+// short where a growth check stopped it); unless fold_only, also the final
+// scale S_M and the counts the reverse sweep starts from
+void launch_sweep_end(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int64_t k_last, int B,
+                      const Sync* sy, int fold_only, hipStream_t st);
 void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st);
 // co-resident blocks per CU of the persistent forward (which=0) / reverse (1)
-// sweep, and of the one-factor forward (2; 4: the five-wave build) / reverse
-// (3) step kernels
+// sweep, of the one-factor forward (2; 4: the five-wave build) / reverse (3)
+// step kernels, and of the wide two-factor forward (5) / reverse (6) kernels
 template <class T>
 int resident_blocks_per_cu(int which);
 template <class T>
@@ -251,10 +290,10 @@ template <class T>
 hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa,
                             Counters* cnt, const LogArr& lg, int k_hi, int k_lo, Sync* sy, int B, int grid,
                             hipStream_t st);
-// occ_lim: a step that sees a member's occupancy above it stops the steps
-// after the next one (Counters::stop) so the host can grow the table;
-// NO_LIMIT for a table at full capacity.  wide: the kernel built for five
-// resident waves per SIMD (tables scanned in many passes)
+// occ_lim: a step whose start finds a member's entries above it does not run
+// and stops the sweep (Counters::stop) so the host can grow the index;
+// NO_LIMIT for an index at full capacity.  wide: the kernel built for five
+// resident waves per SIMD (states scanned in many passes)
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
@@ -263,9 +302,9 @@ template <class T>
 void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 int k, int B, int grid, hipStream_t st);
 // steps k and k+1 in one launch (threshold 0, factors with different XOR
-// masks; the table cannot grow during it), and their reverse (no truncation log)
-// (wide: several slots from every home loaded up front; for launches that
-// cover the table in one pass with all blocks resident)
+// masks; the index cannot grow during it), and their reverse (no truncation
+// log) (wide: several index slots from every home loaded up front; for
+// launches that cover the state in one pass with all blocks resident)
 template <class T>
 void launch_fwd2(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                  int k, int B, int grid, int wide, hipStream_t st);
@@ -281,7 +320,8 @@ template <class T>
 void launch_sigma(const Tab& t, const Compact& cp, const Counters* cnt, const double* h1, const double* h2, int nq,
                   int64_t nmax, int B, int singles_only, hipStream_t st);
 // sigma of double excitations by pairing determinants on two-electron-removed
-// keys (records (K, i) of one hash partition, radix-sorted by K)
+// keys (records (K, i) of one hash partition, radix-sorted by K); H is the
+// stride of the compact arrays
 void launch_pair_emit(const Compact& cp, uint64_t H, int b, uint64_t N, int part, int nparts, uint64_t* rk,
                       uint32_t* ri, unsigned long long* count, uint64_t cap, hipStream_t st);
 int launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t n, int bits, uint32_t* hist,
@@ -291,27 +331,25 @@ void launch_pair_groups(const Compact& cp, uint64_t H, int b, const uint64_t* K,
                         hipStream_t st);
 void launch_pair_finish(const Compact& cp, uint64_t H, int b, uint64_t N, Fx3* acc, hipStream_t st);
 void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st);
-void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
-                          int64_t nmax, int B, hipStream_t st);
+void launch_energy_reduce(const Compact& cp, Counters* cnt, const double* h1, const double* h2, int n, int64_t nmax,
+                          int B, hipStream_t st);
 void launch_energy_final(Counters* cnt, double* E, int B, hipStream_t st);
 template <class T>
 void launch_lambda(const Tab& t, const Compact& cp, const Counters* cnt, int64_t nmax, int B, hipStream_t st);
 void launch_counters_reset(Counters* cnt, int B, double S0, hipStream_t st);
 void launch_energy_begin(Counters* cnt, int B, hipStream_t st);
-// rehash every slot of `from` that is alive or a tombstone with a step tag in
-// [1, tag_max] into the table `to` (cleared first; larger when the forward
-// sweep grows, smaller when the reverse sweep shrinks); the occupancy counter
-// becomes the number of slots copied
+// zero the live and entry counts (before a state is refilled)
+void launch_counters_live_reset(Counters* cnt, int B, hipStream_t st);
+// entry positions the last sweeps of M factors scanned, into C_FSCAN / C_RSCAN
+void launch_scan_totals(const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st);
+// rebuild the index (t.H slots) from the entries; the growth stop is lifted
 template <class T>
-void launch_rehash(const Tab& from, const Tab& to, Counters* cnt, int B, uint32_t tag_max, hipStream_t st);
-// number of slots such a rehash would copy, into the C_COPY counters
-template <class T>
-void launch_count_keep(const Tab& t, Counters* cnt, int B, uint32_t tag_max, hipStream_t st);
+void launch_reindex(const Tab& t, Counters* cnt, int B, int grid, hipStream_t st);
 void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int64_t M, int B, hipStream_t st);
-// checkpoints: write the live entries into `sn` (count must be zero), and
-// write a snapshot's amplitudes back over the entries of the same keys
+// checkpoints: write the live entries after step k into `sn` (count must be
+// zero), and write a snapshot's amplitudes back over the entries of the same keys
 template <class T>
-void launch_snapshot(const Tab& t, const Snap& sn, int B, int grid, hipStream_t st);
+void launch_snapshot(const Tab& t, const StepArr& sa, const Snap& sn, int k, int B, int grid, hipStream_t st);
 template <class T>
 void launch_snap_restore(const Tab& t, const Snap& sn, Counters* cnt, uint64_t nmax, int B, hipStream_t st);
 void launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t st);
@@ -320,7 +358,7 @@ void launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t st);
 template <class T>
 void launch_topk(const Tab& t, const StepArr& sa, Counters* cnt, TopK* tk, int k, uint64_t n_max, uint64_t n_cut,
                  int B, int grid, hipStream_t st);
-// entropy tracking: add the live entries of the table to step k's sums;
+// entropy tracking: add the live entries of the state to step k's sums;
 // turn the sums of steps 0..M into entropies
 template <class T>
 void launch_entropy_scan(const Tab& t, const StepArr& sa, int k, int B, int grid, hipStream_t st);

@@ -1,18 +1,24 @@
 // HIP kernels of the sparse wavefunction circuit (gfx950).
 //
-// State layout (per batch member): an open-addressed hash table in HBM,
-// linear probing on a 64-bit mixer of the determinant, array-of-structs
-// slots so that one load returns key, state word and amplitude:
-//   float  states: 16-byte slot {key, amp, meta} + 8-byte side slot {lam, born}
-//   double states: 32-byte slot {key, amp, lam, meta, born}
-// One lane owns one slot per sweep step; a determinant pair touched by a
-// factor is updated by exactly one lane (the lower member if it is present,
-// else the upper one), so no amplitude is ever written by two lanes.
+// State layout (per batch member): the determinants are entries of dense
+// arrays, split into NA arenas that grow by appending; an open-addressed hash
+// index (linear probing on a 64-bit mixer of the determinant) maps a
+// determinant to its entry id.  Entry arrays are array-of-structs, so one
+// load returns key, state word and amplitude:
+//   float  states: 16-byte entry {key, amp, meta} + 8-byte side entry {lam, born}
+//   double states: 32-byte entry {key, amp, lam, meta, born}
+// Sweep steps scan the entries (a block takes one arena), not the slots of a
+// hash table; a determinant pair touched by a factor is updated by exactly one
+// lane (the lower member if it is present, else the upper one), so no
+// amplitude is ever written by two lanes.
 //
 // Cross-lane rules inside one step kernel:
-//  * new entries are placed with atomicCAS on an EMPTY key, so two inserts
-//    never share a slot; lookups of entries that existed before the step
-//    are unaffected by concurrent inserts;
+//  * new entries are appended to the creating wave's arena (one returning
+//    atomic per wave) and indexed with atomicCAS on an EMPTY index key, so two
+//    inserts never share an entry or an index slot;
+//  * the entries an arena held when the launch began are known to every lane
+//    (the counts of the previous launch plus its appends), so an entry created
+//    by the launch itself is recognised from its id alone, without reading it;
 //  * "present at the start of step k" is read from meta as
 //    alive-and-not-born-in-k, or dead-with-tag-k (killed in this step); every
 //    write a lane makes during step k keeps that predicate unchanged, so a
@@ -30,7 +36,7 @@ namespace swc {
 constexpr int BLK = 256;
 
 // ---------------------------------------------------------------------------
-// table views
+// state views
 // ---------------------------------------------------------------------------
 
 template <class T>
@@ -38,35 +44,48 @@ struct View;
 
 template <>
 struct View<float> {
-  Slot<float>* sl;
+  Slot<float>* sl;  // entries of the member
   AuxF* aux;
-  __device__ float& lam(uint64_t s) const { return aux[s].lam; }
-  __device__ uint32_t& born(uint64_t s) const { return aux[s].born; }
-  __device__ float lam_of(const Slot<float>&, uint64_t s) const { return aux[s].lam; }
-  // split load: issue lam_pre(s) early, combine with the slot later
-  __device__ float lam_pre(uint64_t s) const { return aux[s].lam; }
+  Idx* ix;          // index of the member
+  uint64_t H, A;
+  __device__ float& lam(uint64_t e) const { return aux[e].lam; }
+  __device__ uint32_t& born(uint64_t e) const { return aux[e].born; }
+  __device__ float lam_of(const Slot<float>&, uint64_t e) const { return aux[e].lam; }
+  // split load: issue lam_pre(e) early, combine with the entry later
+  __device__ float lam_pre(uint64_t e) const { return aux[e].lam; }
   __device__ float lam_fin(const Slot<float>&, float pre) const { return pre; }
+  __device__ uint64_t off(uint32_t id) const { return (id >> ID_POS_BITS) * A + (id & ID_POS_MASK); }
 };
 
 template <>
 struct View<double> {
   Slot<double>* sl;
-  __device__ double& lam(uint64_t s) const { return sl[s].lam; }
-  __device__ uint32_t& born(uint64_t s) const { return sl[s].born; }
+  Idx* ix;
+  uint64_t H, A;
+  __device__ double& lam(uint64_t e) const { return sl[e].lam; }
+  __device__ uint32_t& born(uint64_t e) const { return sl[e].born; }
   __device__ double lam_of(const Slot<double>& v, uint64_t) const { return v.lam; }
   __device__ double lam_pre(uint64_t) const { return 0.0; }
   __device__ double lam_fin(const Slot<double>& v, double) const { return v.lam; }
+  __device__ uint64_t off(uint32_t id) const { return (id >> ID_POS_BITS) * A + (id & ID_POS_MASK); }
 };
 
 template <class T>
 __device__ __forceinline__ View<T> view(const Tab& t, int b);
 template <>
 __device__ __forceinline__ View<float> view<float>(const Tab& t, int b) {
-  return View<float>{static_cast<Slot<float>*>(t.slots) + b * t.H, static_cast<AuxF*>(t.aux) + b * t.H};
+  const uint64_t E = static_cast<uint64_t>(NA) * t.A;
+  return View<float>{static_cast<Slot<float>*>(t.ent) + b * E, static_cast<AuxF*>(t.aux) + b * E,
+                     t.idx + b * t.Hcap, t.H, t.A};
 }
 template <>
 __device__ __forceinline__ View<double> view<double>(const Tab& t, int b) {
-  return View<double>{static_cast<Slot<double>*>(t.slots) + b * t.H};
+  const uint64_t E = static_cast<uint64_t>(NA) * t.A;
+  return View<double>{static_cast<Slot<double>*>(t.ent) + b * E, t.idx + b * t.Hcap, t.H, t.A};
+}
+
+__device__ __forceinline__ uint32_t entry_id(int arena, uint64_t pos) {
+  return (static_cast<uint32_t>(arena) << ID_POS_BITS) | static_cast<uint32_t>(pos);
 }
 
 // ---------------------------------------------------------------------------
@@ -221,15 +240,19 @@ __device__ __forceinline__ Red block_reduce(Red r) {
   return r;
 }
 
-// Linear probe for `key`; on a hit returns the slot and its contents (one
-// whole-slot load per probe step), else -1 and the first EMPTY slot seen.
-template <class T>
-__device__ __forceinline__ int64_t find_slot(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key,
-                                             uint64_t* first_free, Slot<T>* out) {
+
+// ---------------------------------------------------------------------------
+// index probes
+// ---------------------------------------------------------------------------
+
+// Linear probe for `key`; on a hit returns the index slot and its contents
+// (one whole-slot load per probe step), else -1 and the first EMPTY slot seen.
+__device__ __forceinline__ int64_t find_slot(const Idx* __restrict__ ix, uint64_t H, uint64_t key,
+                                             uint64_t* first_free, Idx* out) {
   const uint64_t mask = H - 1;
   uint64_t s = mix64(key) & mask;
   for (uint64_t i = 0; i < H; ++i, s = (s + 1) & mask) {
-    const Slot<T> v = sl[s];
+    const Idx v = ix[s];
     if (v.key == key) {
       *out = v;
       return static_cast<int64_t>(s);
@@ -243,28 +266,23 @@ __device__ __forceinline__ int64_t find_slot(const Slot<T>* __restrict__ sl, uin
   return -1;
 }
 
-// find_slot with the home slot already loaded (`v` = sl[home]), so several
+// find_slot with the home slot already loaded (`v` = ix[home]), so several
 // probes can have their first loads in flight together.  Past the home slot
 // the probe loads PG slots at a time and checks them in order (the same
 // answer as one slot at a time: the loads are only issued together), so a
-// long probe sequence costs one round trip per PG slots rather than per slot;
-// the longest sequence in a launch sets the launch's duration.
+// long probe sequence costs one round trip per PG slots rather than per slot.
 constexpr int PG = 4;
 // slots from the home loaded up front by the two-factor sweep kernels when
-// one launch covers the table in one pass (4: most probes end inside them;
-// 8 measured slower, fewer resident waves)
+// one launch covers the state in one pass
 constexpr int PH2 = 4;
 
-// The probe's continuation after slot s, the slots already checked counting
-// i0: PG slots per round trip.
-template <class T>
-__device__ __forceinline__ int64_t probe_past(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key, uint64_t s,
-                                              uint64_t i0, uint64_t* first_free, Slot<T>* out) {
+__device__ __forceinline__ int64_t probe_past(const Idx* __restrict__ ix, uint64_t H, uint64_t key, uint64_t s,
+                                              uint64_t i0, uint64_t* first_free, Idx* out) {
   const uint64_t mask = H - 1;
   for (uint64_t i = i0; i < H; i += PG) {
-    Slot<T> w[PG];
+    Idx w[PG];
 #pragma unroll
-    for (int j = 0; j < PG; ++j) w[j] = sl[(s + 1 + j) & mask];
+    for (int j = 0; j < PG; ++j) w[j] = ix[(s + 1 + j) & mask];
 #pragma unroll
     for (int j = 0; j < PG; ++j) {
       const uint64_t t = (s + 1 + j) & mask;
@@ -283,9 +301,8 @@ __device__ __forceinline__ int64_t probe_past(const Slot<T>* __restrict__ sl, ui
   return -1;
 }
 
-template <class T>
-__device__ __forceinline__ int64_t find_slot_from(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key,
-                                                  uint64_t home, Slot<T> v, uint64_t* first_free, Slot<T>* out) {
+__device__ __forceinline__ int64_t find_slot_from(const Idx* __restrict__ ix, uint64_t H, uint64_t key, uint64_t home,
+                                                  Idx v, uint64_t* first_free, Idx* out) {
   if (v.key == key) {
     *out = v;
     return static_cast<int64_t>(home);
@@ -294,15 +311,14 @@ __device__ __forceinline__ int64_t find_slot_from(const Slot<T>* __restrict__ sl
     *first_free = home;
     return -1;
   }
-  return probe_past<T>(sl, H, key, home, 1, first_free, out);
+  return probe_past(ix, H, key, home, 1, first_free, out);
 }
 
 // find_slot_from with the first PH slots from home already loaded
-// (pre[j] = sl[home + j]): an answer within them costs no further round trip.
-template <class T, int PH>
-__device__ __forceinline__ int64_t find_slot_pre(const Slot<T>* __restrict__ sl, uint64_t H, uint64_t key,
-                                                 uint64_t home, const Slot<T> (&pre)[PH], uint64_t* first_free,
-                                                 Slot<T>* out) {
+// (pre[j] = ix[home + j]): an answer within them costs no further round trip.
+template <int PH>
+__device__ __forceinline__ int64_t find_slot_pre(const Idx* __restrict__ ix, uint64_t H, uint64_t key, uint64_t home,
+                                                 const Idx (&pre)[PH], uint64_t* first_free, Idx* out) {
   const uint64_t mask = H - 1;
 #pragma unroll
   for (int j = 0; j < PH; ++j) {
@@ -316,25 +332,72 @@ __device__ __forceinline__ int64_t find_slot_pre(const Slot<T>* __restrict__ sl,
       return -1;
     }
   }
-  return probe_past<T>(sl, H, key, (home + PH - 1) & mask, PH, first_free, out);
+  return probe_past(ix, H, key, (home + PH - 1) & mask, PH, first_free, out);
 }
 
-// Claim an EMPTY slot for `key` (known to be absent), starting the linear
-// probe at `start`.  Returns the slot or -1 when the table is full.
-template <class T>
-__device__ __forceinline__ int64_t claim_slot(Slot<T>* sl, uint64_t H, uint64_t key, uint64_t start) {
-  if (start >= H) return -1;
+// Index `key` (known to be absent) under entry id `id`, starting the linear
+// probe at `start`: the key is claimed with a compare-and-swap on an EMPTY
+// slot, then the id is written.  Returns false when the index is full.
+__device__ __forceinline__ bool index_insert(Idx* ix, uint64_t H, uint64_t key, uint64_t start, uint32_t id) {
+  if (start >= H) return false;
   const uint64_t mask = H - 1;
   uint64_t s = start;
   for (uint64_t i = 0; i < H; ++i, s = (s + 1) & mask) {
-    if (sl[s].key != EMPTY_KEY) continue;
-    const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&sl[s].key),
+    if (ix[s].key != EMPTY_KEY) continue;
+    const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&ix[s].key),
                                              static_cast<unsigned long long>(EMPTY_KEY),
                                              static_cast<unsigned long long>(key));
-    if (old == EMPTY_KEY) return static_cast<int64_t>(s);
+    if (old == EMPTY_KEY) {
+      ix[s].id = id;
+      return true;
+    }
   }
-  return -1;
+  return false;
 }
+
+// Entries of every arena of member b when the forward launch that runs step
+// k began (lane a holds arena a): the counts of the launch before it plus its
+// appends.  That launch began at step k-1, or at k-2 when it applied steps
+// k-2 and k-1 together (no launch began at k-1 then).  For k = 1 the counts
+// of the sweep's start.  Appends past an arena's capacity A were refused (the
+// table-full flag fails the call), so counts are cut at A: no scan leaves its
+// arena.
+__device__ __forceinline__ uint32_t counts_before(const StepArr& sa, int b, int k, uint64_t A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = static_cast<int64_t>(b) * sa.nstride;
+  const uint32_t n1 = sa.nb[(row + k - 1) * NA + lane], a1 = sa.app[(row + k - 1) * NA + lane];
+  uint64_t n;
+  if (k < 2) {
+    n = static_cast<uint64_t>(n1) + a1;
+  } else {
+    const uint32_t n2 = sa.nb[(row + k - 2) * NA + lane], a2 = sa.app[(row + k - 2) * NA + lane];
+    n = n1 != NB_UNSET ? static_cast<uint64_t>(n1) + a1 : static_cast<uint64_t>(n2) + a2;
+  }
+  return static_cast<uint32_t>(n < A ? n : A);
+}
+
+// Entries of every arena of member b after forward step k (lane a: arena a).
+__device__ __forceinline__ uint32_t counts_after(const StepArr& sa, int b, int k, uint64_t A) {
+  return counts_before(sa, b, k + 1, A);
+}
+
+// Entries the reverse sweep must scan to undo step k: those created by the
+// forward launches up to the one that applied step k, i.e. the counts when the
+// next forward launch began (at k + 1, or k + 2 when k + 1 began no launch);
+// nb[M + 1] holds the counts at the end of the forward sweep.
+__device__ __forceinline__ uint32_t counts_reverse(const StepArr& sa, int b, int k, uint64_t A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = static_cast<int64_t>(b) * sa.nstride;
+  const uint32_t n1 = sa.nb[(row + k + 1) * NA + lane], n2 = sa.nb[(row + k + 2) * NA + lane];
+  const uint64_t n = n1 != NB_UNSET ? n1 : n2;
+  return static_cast<uint32_t>(n < A ? n : A);
+}
+
+// Arena of a block of an entry scan (blocks are NA-way interleaved over the
+// arenas), the block's rank among those of its arena, and their number.
+__device__ __forceinline__ int scan_arena() { return static_cast<int>(blockIdx.x & (NA - 1)); }
+__device__ __forceinline__ uint64_t scan_rank() { return blockIdx.x / NA; }
+__device__ __forceinline__ uint64_t scan_blocks() { return gridDim.x / NA; }
 
 __device__ __forceinline__ uint32_t shard() { return blockIdx.x & (SH - 1); }
 __device__ __forceinline__ uint32_t cshard() { return blockIdx.x & (CSH - 1); }
@@ -380,14 +443,17 @@ __device__ __forceinline__ void ent_flush(const StepArr& sa, int b, int k, Fx a,
 
 // The SCAN_U slots s0, s0 + stride, ... of one pass of a sweep step (slots
 // past the table read as empty).
+
+// The SCAN_U entries j0, j0 + stride, ... of one pass of a sweep step in arena
+// s, n of them valid (positions past n read as empty).
 template <class T>
-__device__ __forceinline__ void load_pass(const View<T>& v, uint64_t H, uint64_t s0, uint64_t stride,
+__device__ __forceinline__ void load_pass(const View<T>& v, uint64_t base, uint64_t n, uint64_t j0, uint64_t stride,
                                           Slot<T>* out) {
 #pragma unroll
   for (int u = 0; u < SCAN_U; ++u) {
-    const uint64_t s = s0 + u * stride;
-    if (s < H) {
-      out[u] = v.sl[s];
+    const uint64_t j = j0 + u * stride;
+    if (j < n) {
+      out[u] = v.sl[base + j];
     } else {
       out[u].key = EMPTY_KEY;
       out[u].meta = DEAD;
@@ -425,39 +491,57 @@ __device__ __forceinline__ int64_t wave_id() {
   return (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * (BLK / 64) + (threadIdx.x >> 6);
 }
 
+
 // ---------------------------------------------------------------------------
-// table set-up
+// state set-up
 // ---------------------------------------------------------------------------
 
-template <class T>
+// An empty state: every index slot free, every arena empty.
 __global__ void k_fill(Tab t) {
-  const View<T> v = view<T>(t, blockIdx.y);
+  const int b = blockIdx.y;
+  Idx* ix = t.idx + b * t.Hcap;
   for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
-    v.sl[s].key = EMPTY_KEY;
-    v.sl[s].meta = DEAD;
-    v.born(s) = 0u;
+    ix[s].key = EMPTY_KEY;
+    ix[s].id = NO_ID;
   }
+  if (blockIdx.x == 0 && threadIdx.x < NA) t.ac[b * NA + threadIdx.x] = 0u;
 }
 
+// Insert n determinants into an empty state: item i goes to arena i % NA at
+// position i / NA (no counter to contend for), then into the index.  keys and
+// amps of member b at b * stride; n < 0: member b's count is cnt[b].ncompact
+// (the compact copies of its live entries).
 template <class T>
-__global__ void k_insert_init(Tab t, Counters* cnt, const uint64_t* __restrict__ dets,
-                              const double* __restrict__ amps, int64_t n) {
+__global__ void k_insert_list(Tab t, Counters* cnt, const uint64_t* __restrict__ keys,
+                              const double* __restrict__ amps, int64_t n_fixed, uint64_t stride) {
   const int b = blockIdx.y;
-  const uint64_t H = t.H;
   const View<T> v = view<T>(t, b);
+  const int64_t n = n_fixed >= 0 ? n_fixed : static_cast<int64_t>(cnt[b].ncompact);
   unsigned long long ok = 0;
   for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint64_t key = dets[i];
-    const int64_t s = claim_slot(v.sl, H, key, mix64(key) & (H - 1));
-    if (s < 0) {
+    const uint64_t key = keys[b * stride + i];
+    const int a = static_cast<int>(i % NA);
+    const uint64_t pos = static_cast<uint64_t>(i / NA);
+    if (pos >= t.A) {
       atomicOr(&cnt[b].flags, F_TABLE_FULL);
       continue;
     }
-    v.sl[s].amp = static_cast<T>(amps[i]);
-    v.sl[s].meta = 0u;
-    v.born(s) = 0u;
-    v.lam(s) = T(0);
+    const uint64_t e = a * t.A + pos;
+    v.sl[e].key = key;
+    v.sl[e].amp = static_cast<T>(amps[b * stride + i]);
+    v.sl[e].meta = 0u;
+    v.born(e) = 0u;
+    v.lam(e) = T(0);
+    if (!index_insert(v.ix, v.H, key, mix64(key) & (v.H - 1), entry_id(a, pos))) {
+      atomicOr(&cnt[b].flags, F_TABLE_FULL);
+      continue;
+    }
     ++ok;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < NA) {
+    const int64_t a = threadIdx.x;
+    const int64_t m = n > a ? (n - a + NA - 1) / NA : 0;
+    t.ac[b * NA + a] = static_cast<uint32_t>(m < static_cast<int64_t>(t.A) ? m : static_cast<int64_t>(t.A));
   }
   ok = wave_u64(ok);
   if ((threadIdx.x & 63) == 0 && ok) {
@@ -482,18 +566,26 @@ __global__ void k_trig(const double* __restrict__ theta, Trig* __restrict__ trig
 }
 
 // Start of a sweep: every live entry becomes "born before the sweep"
-// (tag 0), tombstones get tag 0, per-step accumulators are cleared.
+
+// Start of a sweep: every live entry becomes "born before the sweep"
+// (tag 0), dead entries get tag 0, per-step accumulators are cleared, and the
+// arena counts of step 0 are the state's.
 template <class T>
 __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
   const int b = blockIdx.y;
   const View<T> v = view<T>(t, b);
+  {
+    const int a = scan_arena();
+    const uint64_t n = t.ac[b * NA + a];
+    for (uint64_t j = scan_rank() * BLK + threadIdx.x; j < n; j += scan_blocks() * BLK) {
+      const uint64_t e = a * t.A + j;
+      const uint32_t m = v.sl[e].meta;
+      v.sl[e].meta = (m & DEAD) ? DEAD : 0u;
+      v.born(e) = 0u;
+    }
+  }
   const uint64_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t gsz = gridDim.x * blockDim.x;
-  for (uint64_t s = gtid; s < t.H; s += gsz) {
-    const uint32_t m = v.sl[s].meta;
-    v.sl[s].meta = (m & DEAD) ? DEAD : 0u;
-    v.born(s) = 0u;
-  }
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
   for (uint64_t i = gtid; i < static_cast<uint64_t>((M + 1) * SH); i += gsz) {
     const int sh = static_cast<int>(i / (M + 1));
@@ -506,6 +598,11 @@ __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
   for (uint64_t i = gtid; i < static_cast<uint64_t>(M + 1); i += gsz) {
     sa.logn[base + i] = 0u;
     sa.scale[base + i] = cnt[b].S;  // steps that remove nothing keep the scale
+  }
+  for (uint64_t i = gtid; i < static_cast<uint64_t>((M + 3) * NA); i += gsz) {
+    const int64_t row = static_cast<int64_t>(b) * sa.nstride * NA;
+    sa.nb[row + i] = i < static_cast<uint64_t>(NA) ? t.ac[b * NA + i] : NB_UNSET;
+    sa.app[row + i] = 0u;
   }
   if (sa.ea) {
     for (uint64_t i = gtid; i < static_cast<uint64_t>((M + 1) * ES); i += gsz) {
@@ -529,10 +626,13 @@ __global__ void k_sweep_begin(Tab t, StepArr sa, Counters* cnt, int64_t M) {
   }
 }
 
-// End of a forward sweep, or of a run of its steps (one wave per state): the
-// per-wave statistics folded into the state's counters, and at the end of
-// the sweep the final scale S_M.
-__global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy, int fold_only) {
+// End of a forward sweep, or of a run of its steps up to k_last (one block
+// per state): the per-wave statistics folded into the state's counters, the
+// arena counts after the last step that ran (a run stops early at the step a
+// growth check stopped), and at the end of the sweep the final scale S_M and
+// the counts the reverse sweep starts from (nb[M + 1]).
+__global__ void k_sweep_end(Tab t, StepArr sa, Counters* cnt, int64_t M, int64_t k_last, const Sync* sy,
+                            int fold_only) {
   const int b = blockIdx.x;
   if (threadIdx.x == 0 && sy && sy->timeout) atomicOr(&cnt[b].flags, F_TIMEOUT);
   if (M == 0) return;
@@ -543,7 +643,7 @@ __global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy
 #pragma unroll
     for (int i = 0; i < WSTAT; ++i) {
       tot[i] += sa.ws[(b * sa.nws + w) * WSTAT + i];
-      sa.ws[(b * sa.nws + w) * WSTAT + i] = 0ull;  // folded: a later chunk starts from zero
+      sa.ws[(b * sa.nws + w) * WSTAT + i] = 0ull;  // folded: a later run starts from zero
     }
   // block totals: wave sums, then wave 0 adds the other waves' (LDS)
   __shared__ unsigned long long part[BLK / 64][WSTAT];
@@ -555,10 +655,26 @@ __global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy
   __syncthreads();
   for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w)
     for (int i = 0; i < WSTAT; ++i) tot[i] += part[w][i];
-  // live count over the shards, before this fold (wave 0's lanes < CSH)
-  unsigned long long live = threadIdx.x < CSH ? cnt[b].sh[threadIdx.x].v[C_LIVE] : 0ull;
+  if (wv != 0) return;
+  // live count over the shards, before this fold
+  unsigned long long live = lane < CSH ? cnt[b].sh[lane].v[C_LIVE] : 0ull;
   live = wave_u64(live);
-  if (threadIdx.x == 0) {
+  // arena counts after the last step that ran
+  int64_t ke = M;
+  if (fold_only) {
+    const int64_t stop = static_cast<int64_t>(cnt[0].stop);
+    ke = stop - 1 < k_last ? stop - 1 : k_last;
+  }
+  const uint32_t na = counts_after(sa, b, static_cast<int>(ke), t.A);
+  t.ac[b * NA + lane] = na;
+  if (!fold_only) {
+    const int64_t row = (static_cast<int64_t>(b) * sa.nstride + M + 1) * NA;
+    sa.nb[row + lane] = na;
+    sa.app[row + lane] = 0u;
+  }
+  const unsigned long long nent = wave_u64(na);
+  if (lane < CSH) cnt[b].sh[lane].v[C_OCC] = lane == 0 ? nent : 0ull;
+  if (lane == 0) {
     if (!fold_only) {
       sa.scale[static_cast<int64_t>(b) * sa.stride + M] = S;
       cnt[b].S = S;
@@ -574,6 +690,7 @@ __global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy
   }
 }
 
+
 // ---------------------------------------------------------------------------
 // forward step k: pair rotation exp(theta_k A_k) + truncation
 // ---------------------------------------------------------------------------
@@ -581,47 +698,98 @@ __global__ void k_sweep_end(StepArr sa, Counters* cnt, int64_t M, const Sync* sy
 //   x' = x cos - s sin y,  y' = y cos + s sin x       (closed form, Eqs. 4-5)
 // written as x' = x + (x (cos-1) - s sin y) for accuracy at small theta.
 // Truncation (Methods section): a member whose |S x'| < thr is removed; its
-// tombstone keeps x' for the reverse sweep.  The removed weight feeds the
+// entry keeps x' for the reverse sweep.  The removed weight feeds the
 // renormalisation scale of the next step.
+//
+// Arena for the entries a wave creates in step k: a hash of the wave and the
+// step, so that the creations of any step spread over all arenas whatever
+// arena the creating wave scans (a state that starts in one arena and doubles
+// in a few steps would otherwise pile into a few arenas).
+__device__ __forceinline__ int create_arena(int k) {
+  const uint64_t w = static_cast<uint64_t>(blockIdx.x) * (BLK / 64) + (threadIdx.x >> 6);
+  return static_cast<int>(mix64((static_cast<uint64_t>(k) << 32) | w) & (NA - 1));
+}
+
+// Positions for the new entries a wave creates in one round: lanes with
+// want[u] get consecutive positions of the wave's arena after those taken
+// before (one returning atomic per wave and round).  Every lane of the wave
+// must be active.  Returns the arena; pos[u] is set for the lanes that want.
+template <int U>
+__device__ __forceinline__ int claim_positions(const StepArr& sa, int b, int k, uint32_t nk, const bool (&want)[U],
+                                               uint64_t (&pos)[U]) {
+  const int lane = threadIdx.x & 63;
+  const int a = create_arena(k);
+  unsigned long long m[U];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    m[u] = __ballot(want[u]);
+    tot += static_cast<uint32_t>(__popcll(m[u]));
+  }
+  if (tot == 0) return a;
+  uint32_t basep = 0;
+  if (lane == 0) basep = atomicAdd(&sa.app[(static_cast<int64_t>(b) * sa.nstride + k) * NA + a], tot);
+  basep = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(basep)));
+  const uint32_t arena_start = static_cast<uint32_t>(__shfl(static_cast<int>(nk), a, 64));
+  const unsigned long long below = lane ? ((1ull << lane) - 1ull) : 0ull;
+  uint32_t run = arena_start + basep;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    pos[u] = run + static_cast<uint32_t>(__popcll(m[u] & below));
+    run += static_cast<uint32_t>(__popcll(m[u]));
+  }
+  return a;
+}
+
 template <class T, bool ENT>
 __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict__ fac,
                                          const Trig* __restrict__ trig, int64_t ld, const StepArr& sa, Counters* cnt,
                                          const LogArr& lg, int k, double thr, int prune_all, int log_on,
                                          uint64_t occ_lim) {
   const int b = blockIdx.y;
-  const uint64_t H = t.H;
   const View<T> v = view<T>(t, b);
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
   const int lane = threadIdx.x & 63;
   const uint32_t K = static_cast<uint32_t>(k);
+  const int s = scan_arena();
+  if (occ_lim != NO_LIMIT && K >= cnt[0].stop) return;  // a growth check stopped the sweep
+  // entries of every arena when the launch began (lane a: arena a)
+  const uint32_t nk = counts_before(sa, b, k, v.A);
   if (occ_lim != NO_LIMIT) {
-    // Growth guard.  A step adds at most one slot per live entry, so the
-    // occupancy at most doubles per step.  Wave 0 of block 0 compares the
-    // occupancy it sees (>= that after step k-1) with the limit and, above
-    // it, stops every step from k+1 on: a step that runs saw occupancy
-    // <= limit two steps earlier, so it ends at <= 4 x limit.
-    if (K >= cnt[0].stop) return;
-    if (blockIdx.x == 0 && threadIdx.x < 64) {
-      unsigned long long o = lane < CSH ? cnt[b].sh[lane].v[C_OCC] : 0ull;
-      o = wave_u64(o);
-      if (lane == 0 && o > occ_lim) atomicMin(&cnt[0].stop, K + 1u);
+    // Growth check: every block of every member sees the same exact counts,
+    // so all return together when a member's index holds more than the limit
+    // (the host grows the index and runs the step again); a step that runs
+    // at most doubles the entries, so the index stays below twice the limit.
+    unsigned long long most = 0;
+    for (int bb = 0; bb < static_cast<int>(gridDim.y); ++bb) {
+      const unsigned long long n = wave_u64(bb == b ? nk : counts_before(sa, bb, k, v.A));
+      most = n > most ? n : most;
+    }
+    if (most > occ_lim) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicMin(&cnt[0].stop, K);
+      return;
     }
   }
+  const uint64_t ns = static_cast<uint32_t>(__shfl(static_cast<int>(nk), s, 64));  // this block's arena
+  if (scan_rank() == 0 && threadIdx.x == 0) sa.nb[(static_cast<int64_t>(b) * sa.nstride + k) * NA + s] = static_cast<uint32_t>(ns);
   // this wave's statistics slot (read now, written back at the end)
   unsigned long long* wst = sa.ws + (static_cast<int64_t>(b) * sa.nws + (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6))) * WSTAT;
   const unsigned long long wold = lane < WSTAT ? wst[lane] : 0ull;
 
-  // SCAN_U slots per lane per pass.  The first pass's slots are requested
-  // before the scale is reduced, and each pass requests the next pass's slots
-  // before it probes partners, so a lane keeps two passes of loads in flight.
-  // (A slot read early is safe for the same reason a partner's is: whatever
-  // other lanes write during the step keeps its presence at the start of
-  // the step, and the owner of its pair, unchanged.)
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  // SCAN_U entries per lane per pass.  The first pass's entries are requested
+  // before the scale is reduced, and each pass requests the next pass's before
+  // it probes partners, so a lane keeps two passes of loads in flight.  (An
+  // entry read early is safe for the same reason a partner's is: whatever
+  // other lanes write during the step keeps its presence at the start of the
+  // step, and the owner of its pair, unchanged.)  The pass loop runs the same
+  // number of times for every lane of a wave.
+  const uint64_t ebase = s * v.A;
+  const uint64_t stride = scan_blocks() * BLK;
   const uint64_t pass = SCAN_U * stride;
-  uint64_t s0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t j0w = scan_rank() * BLK + (threadIdx.x & ~63u);  // the wave's first position
+  uint64_t j0 = scan_rank() * BLK + threadIdx.x;
   Slot<T> nxt[SCAN_U];
-  load_pass<T>(v, H, s0, stride, nxt);
+  load_pass<T>(v, ebase, ns, j0, stride, nxt);
 
   // threshold 0 never truncates, so the scale is not needed
   const bool trunc = thr > 0.0;
@@ -636,13 +804,13 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   Red r;
   r.f = fx_zero();
   for (int i = 0; i < 7; ++i) r.c[i] = 0;
-  // c[0] removed count, c[1] visits, c[2] pairs, c[3] creates, c[4] kills, c[5] new slots,
+  // c[0] removed count, c[1] visits, c[2] pairs, c[3] creates, c[4] kills, c[5] new entries,
   // c[6] pairs whose partner existed
   unsigned int flags = 0;
 
-  auto kill = [&](uint64_t s, T x) {
-    v.sl[s].amp = x;
-    v.sl[s].meta = DEAD | K;
+  auto kill = [&](uint64_t e, T x) {
+    v.sl[e].amp = x;
+    v.sl[e].meta = DEAD | K;
     const double dv = static_cast<double>(x);
     r.f = fx_add(r.f, fx_from(dv * dv));
     r.c[0] += 1;
@@ -653,46 +821,36 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     r.f = fx_add(r.f, fx_from(dv * dv));
     r.c[0] += 1;
   };
-  // create `key` with value x: revive the tombstone `old` at `hint`, or claim a slot
-  auto create = [&](uint64_t key, T x, int64_t hint, const Slot<T>& old, uint64_t free_start) {
-    int64_t s = hint;
-    if (s >= 0) {
-      if ((old.meta & TAG) != 0u && log_on) {  // tombstone from this sweep: remember it
-        const unsigned long long pos = atomicAdd(&cnt[b].logcnt, 1ull);
-        if (pos < lg.cap) {
-          const uint64_t li = b * lg.cap + pos;
-          lg.key[li] = key;
-          lg.meta[li] = old.meta;
-          lg.born[li] = v.born(s);
-          static_cast<T*>(lg.amp)[li] = old.amp;
-          atomicAdd(&sa.logn[base + k], 1u);
-        } else {
-          flags |= F_LOG_FULL;
-        }
+  // revive the dead entry e (`old` its contents) of determinant `key` with value x
+  auto revive = [&](uint64_t key, T x, uint64_t e, const Slot<T>& old) {
+    if ((old.meta & TAG) != 0u && log_on) {  // dead entry of this sweep: remember it
+      const unsigned long long p = atomicAdd(&cnt[b].logcnt, 1ull);
+      if (p < lg.cap) {
+        const uint64_t li = b * lg.cap + p;
+        lg.key[li] = key;
+        lg.meta[li] = old.meta;
+        lg.born[li] = v.born(e);
+        static_cast<T*>(lg.amp)[li] = old.amp;
+        atomicAdd(&sa.logn[base + k], 1u);
+      } else {
+        flags |= F_LOG_FULL;
       }
-    } else {
-      s = claim_slot(v.sl, H, key, free_start);
-      if (s < 0) {
-        flags |= F_TABLE_FULL;
-        return;
-      }
-      r.c[5] += 1;
     }
-    v.sl[s].amp = x;
-    v.born(s) = K;
-    v.sl[s].meta = K;
+    v.sl[e].amp = x;
+    v.born(e) = K;
+    v.sl[e].meta = K;
     r.c[3] += 1;
   };
 
   Fx ent_a = fx_zero(), ent_b = fx_zero();  // entropy sums (when tracked)
-  for (; s0 < H; s0 += pass) {
+  for (uint64_t jw = j0w; jw < ns; jw += pass, j0 += pass) {
     Slot<T> mes[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) mes[u] = nxt[u];
-    if (s0 + pass < H) load_pass<T>(v, H, s0 + pass, stride, nxt);
-    // the home slots of this pass's partners are then loaded together
+    if (jw + pass < ns) load_pass<T>(v, ebase, ns, j0 + pass, stride, nxt);
+    // the home index slots of this pass's partners are then loaded together
     uint64_t home[SCAN_U];
-    Slot<T> hv[SCAN_U];
+    Idx hv[SCAN_U];
     bool act[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
@@ -706,46 +864,68 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
         if ((m & TAG) == K) r.c[1] += 1;
         continue;
       }
-      if ((m & TAG) == K) continue;  // created in this step
+      if ((m & TAG) == K) continue;  // revived in this step
       r.c[1] += 1;
       const bool lower = ((me.key & f.occ) == f.occ) && !(me.key & f.vir);
       const bool upper = ((me.key & f.vir) == f.vir) && !(me.key & f.occ);
       if (!lower && !upper) {
         if (prune_all && !(fabs(S * static_cast<double>(me.amp)) >= thr)) {
-          kill(s0 + u * stride, me.amp);
+          kill(ebase + j0 + u * stride, me.amp);
         } else if (ENT) {
           ent_add(ent_a, ent_b, static_cast<double>(me.amp));
         }
         continue;
       }
       act[u] = true;
-      home[u] = mix64(me.key ^ pm) & (H - 1);
-      hv[u] = v.sl[home[u]];
+      home[u] = mix64(me.key ^ pm) & (v.H - 1);
+      hv[u] = v.ix[home[u]];
     }
+    // resolve the probes, then load the partners' entries together
+    uint64_t free_start[SCAN_U], pe[SCAN_U];
+    bool found[SCAN_U];
+    Slot<T> pv[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
+      found[u] = false;
+      free_start[u] = v.H;
+      if (!act[u]) continue;
+      Idx iv;
+      found[u] = find_slot_from(v.ix, v.H, mes[u].key ^ pm, home[u], hv[u], &free_start[u], &iv) >= 0;
+      if (found[u]) {
+        if (iv.id == NO_ID) {  // cannot happen: only this lane creates its partner
+          flags |= F_INCONSISTENT;
+          found[u] = false;
+        } else {
+          pe[u] = v.off(iv.id);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u)
+      if (found[u]) pv[u] = v.sl[pe[u]];
+    bool want[SCAN_U];
+    uint64_t wkey[SCAN_U], wfree[SCAN_U];
+    T wamp[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      want[u] = false;
       if (!act[u]) continue;
       const Slot<T>& me = mes[u];
-      const uint64_t s = s0 + u * stride;
+      const uint64_t e = ebase + j0 + u * stride;
       const uint64_t key = me.key;
       const bool lower = ((key & f.occ) == f.occ) && !(key & f.vir);
       const uint64_t pk = key ^ pm;
-      uint64_t free_start = H;
-      Slot<T> pv;
-      pv.meta = 0u;
-      pv.amp = T(0);
-      const int64_t ps = find_slot_from(v.sl, H, pk, home[u], hv[u], &free_start, &pv);
       bool p_alive = false, p_start = false;
-      if (ps >= 0) {
-        p_alive = !(pv.meta & DEAD);
-        p_start = p_alive || ((pv.meta & TAG) == K);
+      if (found[u]) {
+        p_alive = !(pv[u].meta & DEAD);
+        p_start = p_alive || ((pv[u].meta & TAG) == K);
       }
       if (!lower && p_start) continue;  // the lower member owns the pair
       r.c[2] += 1;
       if (lower && p_alive) r.c[6] += 1;
       const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
       const T x = lower ? me.amp : T(0);
-      const T y = lower ? (p_alive ? pv.amp : T(0)) : me.amp;
+      const T y = lower ? (p_alive ? pv[u].amp : T(0)) : me.amp;
       const T xn = x + fmaT<T>(x, cm1, -ss * y);
       const T yn = y + fmaT<T>(y, cm1, ss * x);
       const bool keepx = fabs(S * static_cast<double>(xn)) >= thr;
@@ -754,19 +934,62 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
         if (keepx) ent_add(ent_a, ent_b, static_cast<double>(xn));
         if (keepy) ent_add(ent_a, ent_b, static_cast<double>(yn));
       }
+      // the partner's new value, when it is created (kept, and not present)
+      bool make = false;
+      T pnew = T(0);
       if (lower) {
-        if (keepx) v.sl[s].amp = xn; else kill(s, xn);
+        if (keepx) v.sl[e].amp = xn; else kill(e, xn);
         if (p_alive) {
-          if (keepy) v.sl[ps].amp = yn; else kill(static_cast<uint64_t>(ps), yn);
+          if (keepy) v.sl[pe[u]].amp = yn; else kill(pe[u], yn);
         } else if (keepy) {
-          create(pk, yn, ps, pv, free_start);
+          make = true;
+          pnew = yn;
         } else {
           drop_new(yn);
         }
       } else {
-        if (keepy) v.sl[s].amp = yn; else kill(s, yn);
-        if (keepx) create(pk, xn, ps, pv, free_start); else drop_new(xn);
+        if (keepy) v.sl[e].amp = yn; else kill(e, yn);
+        if (keepx) {
+          make = true;
+          pnew = xn;
+        } else {
+          drop_new(xn);
+        }
       }
+      if (make) {
+        if (found[u]) {
+          revive(pk, pnew, pe[u], pv[u]);  // its dead entry comes back
+        } else {
+          want[u] = true;                   // a new entry (positions below)
+          wkey[u] = pk;
+          wamp[u] = pnew;
+          wfree[u] = free_start[u];
+        }
+      }
+    }
+    // new entries: positions in the wave's arena, then the entries and the
+    // index slots
+    uint64_t pos[SCAN_U];
+    const int a = claim_positions<SCAN_U>(sa, b, k, nk, want, pos);
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      if (!want[u]) continue;
+      if (pos[u] >= v.A) {
+        flags |= F_TABLE_FULL;
+        continue;
+      }
+      const uint64_t e = a * v.A + pos[u];
+      v.sl[e].key = wkey[u];
+      v.sl[e].amp = wamp[u];
+      v.sl[e].meta = K;
+      v.born(e) = K;
+      v.lam(e) = T(0);
+      if (!index_insert(v.ix, v.H, wkey[u], wfree[u], entry_id(a, pos[u]))) {
+        flags |= F_TABLE_FULL;
+        continue;
+      }
+      r.c[3] += 1;
+      r.c[5] += 1;
     }
   }
 
@@ -786,14 +1009,13 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     }
   }
   if (sa.pvis && c[1] && lane == 0) atomicAdd(&sa.pvis[sidx(sa, b, wsh, k)], c[1]);
-  // occupancy is live: the growth guard of later steps reads it
-  if (c[5] && lane == 0) atomicAdd(&cnt[b].sh[wsh & (CSH - 1)].v[C_OCC], static_cast<unsigned long long>(c[5]));
   if (lane < 7) {
     const unsigned int mine = lane == 0 ? c[0] : lane == 1 ? c[1] : lane == 2 ? c[2] : lane == 3 ? c[3]
                               : lane == 4 ? c[4] : lane == 5 ? c[5] : c[6];
     wst[lane] = wold + mine;
   }
 }
+
 
 // ---------------------------------------------------------------------------
 // reverse step k: exact inverse of the truncated forward step on psi, and
@@ -802,19 +1024,22 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
 // renormalisation constants cancel in the Rayleigh quotient).
 // ---------------------------------------------------------------------------
 // "Present after step k": alive, or dead with tag k (removed by the
-// truncation of step k; its tombstone holds the pre-truncation value and its
+// truncation of step k; its entry holds the pre-truncation value and its
 // adjoint component is 0).  Pair inversion:
 //   both present            (x, y) = U^T (x', y')
 //   only one present        the other was created and truncated in step k:
 //                           x = x' / cos (or y = y' / cos)
-// Members born in step k are removed; tombstones of step k are revived.
+// Members born in step k are removed; entries that died in step k are
+// revived.  Only the entries that existed after step k are scanned (those
+// created by later steps lie beyond the counts of the next forward launch).
 template <class T>
 __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict__ fac,
                                          const Trig* __restrict__ trig, int64_t ld, const StepArr& sa, Counters* cnt,
                                          int k) {
   const int b = blockIdx.y;
-  const uint64_t H = t.H;
   const View<T> v = view<T>(t, b);
+  const int s = scan_arena();
+  const uint64_t ns = static_cast<uint32_t>(__shfl(static_cast<int>(counts_reverse(sa, b, k, v.A)), s, 64));
 
   const FacMask f = fac[k - 1];
   const Trig tr = trig[b * ld + k - 1];
@@ -827,19 +1052,20 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
   for (int i = 0; i < 7; ++i) r.c[i] = 0;
   unsigned int flags = 0;
 
-  // SCAN_U slots per lane per pass, the next pass's slots requested before
-  // this pass probes partners (as in the forward step)
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  // SCAN_U entries per lane per pass, the next pass's requested before this
+  // pass probes partners (as in the forward step)
+  const uint64_t ebase = s * v.A;
+  const uint64_t stride = scan_blocks() * BLK;
   const uint64_t pass = SCAN_U * stride;
   Slot<T> nxt[SCAN_U];
-  load_pass<T>(v, H, blockIdx.x * blockDim.x + threadIdx.x, stride, nxt);
-  for (uint64_t s0 = blockIdx.x * blockDim.x + threadIdx.x; s0 < H; s0 += pass) {
+  load_pass<T>(v, ebase, ns, scan_rank() * BLK + threadIdx.x, stride, nxt);
+  for (uint64_t j0 = scan_rank() * BLK + threadIdx.x; j0 < ns; j0 += pass) {
     Slot<T> mes[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) mes[u] = nxt[u];
-    if (s0 + pass < H) load_pass<T>(v, H, s0 + pass, stride, nxt);
+    if (j0 + pass < ns) load_pass<T>(v, ebase, ns, j0 + pass, stride, nxt);
     uint64_t home[SCAN_U];
-    Slot<T> hv[SCAN_U];
+    Idx hv[SCAN_U];
     T lms[SCAN_U];
     bool act[SCAN_U];
 #pragma unroll
@@ -852,57 +1078,73 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
       if (dead && (m & TAG) != K) continue;
       const bool lower = ((me.key & f.occ) == f.occ) && !(me.key & f.vir);
       const bool upper = ((me.key & f.vir) == f.vir) && !(me.key & f.occ);
+      const uint64_t e = ebase + j0 + u * stride;
       if (!lower && !upper) {
         if (dead) {  // truncated at step k without being rotated (first step of a sweep)
-          const uint64_t s = s0 + u * stride;
-          v.sl[s].meta = v.born(s);
-          v.lam(s) = T(0);
+          v.sl[e].meta = v.born(e);
+          v.lam(e) = T(0);
         }
         continue;
       }
       act[u] = true;
       // the adjoint value of this member (only members of a pair need it)
-      // and the partner's home slot; the partner's adjoint value is loaded
-      // only by the pair's owner once the partner is found (a speculative
-      // load there cost more traffic than the round trip it saved)
-      lms[u] = v.lam_pre(s0 + u * stride);
-      home[u] = mix64(me.key ^ pm) & (H - 1);
-      hv[u] = v.sl[home[u]];
+      // and the partner's home index slot; the partner's adjoint value is
+      // loaded only by the pair's owner once the partner is found
+      lms[u] = v.lam_pre(e);
+      home[u] = mix64(me.key ^ pm) & (v.H - 1);
+      hv[u] = v.ix[home[u]];
     }
+    // resolve the probes, then load the partners' entries together
+    bool found[SCAN_U];
+    uint64_t pe[SCAN_U];
+    Slot<T> pv[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      found[u] = false;
+      if (!act[u]) continue;
+      uint64_t ff = v.H;
+      Idx iv;
+      found[u] = find_slot_from(v.ix, v.H, mes[u].key ^ pm, home[u], hv[u], &ff, &iv) >= 0;
+      if (found[u]) {
+        if (iv.id == NO_ID) {
+          flags |= F_INCONSISTENT;
+          found[u] = false;
+        } else {
+          pe[u] = v.off(iv.id);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u)
+      if (found[u]) pv[u] = v.sl[pe[u]];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
       if (!act[u]) continue;
       const Slot<T>& me = mes[u];
-      const uint64_t s = s0 + u * stride;
+      const uint64_t e = ebase + j0 + u * stride;
       const uint32_t m = me.meta;
       const bool dead = (m & DEAD) != 0u;
       const uint64_t key = me.key;
       const bool lower = ((key & f.occ) == f.occ) && !(key & f.vir);
-      const uint64_t pk = key ^ pm;
-      uint64_t free_start = H;
-      Slot<T> pv;
-      pv.meta = 0u;
-      pv.amp = T(0);
-      const int64_t ps = find_slot_from(v.sl, H, pk, home[u], hv[u], &free_start, &pv);
       bool p_pres = false;
-      if (ps >= 0) p_pres = !(pv.meta & DEAD) || ((pv.meta & TAG) == K);
+      if (found[u]) p_pres = !(pv[u].meta & DEAD) || ((pv[u].meta & TAG) == K);
       if (!lower && p_pres) continue;  // the lower member owns the pair
       const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
 
-      int64_t sL, sU;
-      uint32_t mL, mU;
+      uint64_t eL = 0, eU = 0;
+      uint32_t mL = 0, mU = 0;
       bool hL, hU;
       T xp, yp, lL, lU;
       if (lower) {
-        sL = static_cast<int64_t>(s); mL = m; hL = true;
-        sU = ps; mU = pv.meta; hU = p_pres;
+        eL = e; mL = m; hL = true;
+        eU = pe[u]; mU = pv[u].meta; hU = p_pres;
         xp = me.amp;
-        yp = hU ? pv.amp : T(0);
+        yp = hU ? pv[u].amp : T(0);
         lL = dead ? T(0) : v.lam_fin(me, lms[u]);
-        lU = (hU && !(mU & DEAD)) ? v.lam_of(pv, static_cast<uint64_t>(ps)) : T(0);
+        lU = (hU && !(mU & DEAD)) ? v.lam_of(pv[u], eU) : T(0);
       } else {
-        sU = static_cast<int64_t>(s); mU = m; hU = true;
-        sL = ps; mL = pv.meta; hL = false;
+        eU = e; mU = m; hU = true;
+        hL = false;
         xp = T(0);
         yp = me.amp;
         lL = T(0);
@@ -927,27 +1169,27 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
       r.f = fx_add(r.f, fx_from(term));
       r.c[2] += 1;
       if (hL) {
-        const uint32_t bL = (mL & DEAD) ? v.born(sL) : (mL & TAG);
+        const uint32_t bL = (mL & DEAD) ? v.born(eL) : (mL & TAG);
         if (bL == K) {
           if (!hU) flags |= F_INCONSISTENT;
-          v.sl[sL].meta = DEAD | K;
+          v.sl[eL].meta = DEAD | K;
           r.c[4] += 1;
         } else {
-          v.sl[sL].amp = x;
-          v.lam(sL) = wL;
-          v.sl[sL].meta = bL;
+          v.sl[eL].amp = x;
+          v.lam(eL) = wL;
+          v.sl[eL].meta = bL;
         }
       }
       if (hU) {
-        const uint32_t bU = (mU & DEAD) ? v.born(sU) : (mU & TAG);
+        const uint32_t bU = (mU & DEAD) ? v.born(eU) : (mU & TAG);
         if (bU == K) {
           if (!hL) flags |= F_INCONSISTENT;
-          v.sl[sU].meta = DEAD | K;
+          v.sl[eU].meta = DEAD | K;
           r.c[4] += 1;
         } else {
-          v.sl[sU].amp = y;
-          v.lam(sU) = wU;
-          v.sl[sU].meta = bU;
+          v.sl[eU].amp = y;
+          v.lam(eU) = wU;
+          v.sl[eU].meta = bU;
         }
       }
     }
@@ -959,7 +1201,7 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
   if ((threadIdx.x & 63) == 0 && fx_nonzero(g)) fx3_atomic_add(&sa.gacc[sidx(sa, b, wsh, k)], g);
 }
 
-// Tombstones overwritten by a resurrection in forward step k get their old
+// Entries whose dead state a revival in forward step k overwrote get that
 // state back once the reverse sweep has undone step k.
 template <class T>
 __device__ __forceinline__ void restore_step(const Tab& t, const LogArr& lg, const StepArr& sa, int k) {
@@ -970,23 +1212,23 @@ __device__ __forceinline__ void restore_step(const Tab& t, const LogArr& lg, con
   const uint32_t off = sa.logoff[base + k];
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint64_t li = b * lg.cap + off + i;
-    // the determinant is still in the table (removed by the reverse step, so
-    // a tombstone); locate its slot by key
+    // the determinant is still in the state (removed by the reverse step, so
+    // dead); locate its entry by key
     uint64_t ff;
-    Slot<T> cur;
-    const int64_t s = find_slot(v.sl, t.H, lg.key[li], &ff, &cur);
-    if (s < 0) continue;
-    v.sl[s].meta = lg.meta[li];
-    v.born(s) = lg.born[li];
-    v.sl[s].amp = static_cast<const T*>(lg.amp)[li];
+    Idx iv;
+    if (find_slot(v.ix, v.H, lg.key[li], &ff, &iv) < 0 || iv.id == NO_ID) continue;
+    const uint64_t e = v.off(iv.id);
+    v.sl[e].meta = lg.meta[li];
+    v.born(e) = lg.born[li];
+    v.sl[e].amp = static_cast<const T*>(lg.amp)[li];
   }
 }
 
 // one launch per step.  ENT: the entropy sums are tracked (a separate
 // instantiation keeps their registers out of the common case).  MINW: waves
 // per SIMD the register allocation must allow; 5 (a few registers spill) for
-// tables scanned in many passes, where more resident waves hide more memory
-// latency, 1 (no constraint) for tables one resident wave round covers,
+// states scanned in many passes, where more resident waves hide more memory
+// latency, 1 (no constraint) for states one resident wave round covers,
 // where each wave's own latency counts.
 template <class T, bool ENT, int MINW>
 __global__ __launch_bounds__(BLK, MINW) void k_fwd(Tab t, const FacMask* __restrict__ fac,
@@ -1002,6 +1244,7 @@ __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ 
   rev_step<T>(t, fac, trig, ld, sa, cnt, k);
 }
 
+
 // ---------------------------------------------------------------------------
 // two factors per launch (threshold 0)
 // ---------------------------------------------------------------------------
@@ -1011,10 +1254,13 @@ __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ 
 // Which pairs act follows from the keys alone: factor 1 pairs (0,1) and
 // (2,3), factor 2 pairs (0,2) and (1,3), each when its members are lower/
 // upper for that factor.  A lane whose determinant lies in a connected set
-// of acting pairs probes the other members of the set; the member with the
+// of acting pairs looks up the other members of the set; the member with the
 // smallest key among those present when the launch starts applies step k,
 // then step k+1, to the whole set, with the same per-pair arithmetic, in the
-// same order, as two single-step launches (results are bit-identical).
+// same order, as two single-step launches (results are bit-identical).  A
+// member whose entry this launch created is recognised from its id (a
+// position at or past its arena's count when the launch began), so no lane
+// reads an entry another lane may still be writing.
 
 __device__ __forceinline__ int side(uint64_t x, const FacMask& f) {
   if ((x & f.occ) == f.occ && !(x & f.vir)) return 1;   // lower
@@ -1051,13 +1297,27 @@ __device__ __forceinline__ Quad make_quad(uint64_t X, uint64_t m1, uint64_t m2, 
   return Q;
 }
 
+// An entry id created by the current launch: its position is at or past its
+// arena's count when the launch began (arena_n: the block's LDS copy of the
+// counts; a lane shuffle would read other lanes' registers, which is not
+// defined for lanes that branched away).
+__device__ __forceinline__ bool created_here(uint32_t id, const uint32_t* arena_n) {
+  return (id & ID_POS_MASK) >= arena_n[id >> ID_POS_BITS];
+}
+
 template <class T, int PH>
 __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
                                               int64_t ld, StepArr sa, Counters* cnt, int k) {
   const int b = blockIdx.y;
-  const uint64_t H = t.H;
   const View<T> v = view<T>(t, b);
   const int lane = threadIdx.x & 63;
+  const int s = scan_arena();
+  const uint32_t nk = counts_before(sa, b, k, v.A);
+  const uint64_t ns = static_cast<uint32_t>(__shfl(static_cast<int>(nk), s, 64));
+  if (scan_rank() == 0 && threadIdx.x == 0) sa.nb[(static_cast<int64_t>(b) * sa.nstride + k) * NA + s] = static_cast<uint32_t>(ns);
+  __shared__ uint32_t arena_n[NA];
+  if (threadIdx.x < NA) arena_n[threadIdx.x] = nk;
+  __syncthreads();
   unsigned long long* wst =
       sa.ws + (static_cast<int64_t>(b) * sa.nws + (blockIdx.x * (BLK / 64) + (threadIdx.x >> 6))) * WSTAT;
   const unsigned long long wold = lane < WSTAT ? wst[lane] : 0ull;
@@ -1067,120 +1327,166 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
   const T sn2 = static_cast<T>(t2.s), cm1b = static_cast<T>(t2.cm1);
   const uint64_t m1 = f1.occ | f1.vir, m2 = f2.occ | f2.vir;
   const uint32_t K1 = static_cast<uint32_t>(k), K2 = K1 + 1u;
-  // c[1] visits, c[2] pairs, c[3] creates, c[5] new slots, c[6] pairs whose partner existed
+  const uint64_t mask = v.H - 1;
+  // c[1] visits, c[2] pairs, c[3] creates, c[5] new entries, c[6] pairs whose partner existed
   // c1a / c1b: visits of step k / k+1 (c1 of the statistics is their sum)
   unsigned long long c1a = 0, c1b = 0, c2 = 0, c3 = 0, c5 = 0, c6 = 0;
   unsigned int flags = 0;
 
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
-    const Slot<T> me = v.sl[s];
-    if (me.key == EMPTY_KEY) continue;
-    const uint32_t m = me.meta;
-    if ((m & DEAD) || (m & TAG) == K1 || (m & TAG) == K2) continue;  // dead, or created by this launch
-    const Quad Q = make_quad(me.key, m1, m2, f1, f2);
-    if (Q.comp == 1u) {  // acted on by neither factor
-      c1a += 1;
-      c1b += 1;
-      continue;
-    }
-    int64_t slot[4];
-    uint64_t ff[4];
-    bool pres[4];
-    T a[4];
-    slot[0] = static_cast<int64_t>(s);
-    pres[0] = true;
-    a[0] = me.amp;
-    bool owner = true;
-    // the first PH slots from the home of every other member, loaded
-    // together: most probes end inside them, so a launch rarely waits for a
-    // third dependent round trip
-    uint64_t home[4];
-    Slot<T> hv[4][PH];
-#pragma unroll
-    for (int j = 1; j < 4; ++j) {
-      home[j] = mix64(Q.q[j]) & (H - 1);
-      if (Q.comp & (1u << j))
-#pragma unroll
-        for (int i = 0; i < PH; ++i) hv[j][i] = v.sl[(home[j] + i) & (H - 1)];
-    }
-#pragma unroll
-    for (int j = 1; j < 4; ++j) {
-      slot[j] = -1;
-      ff[j] = H;
-      pres[j] = false;
-      a[j] = T(0);
-      if (!(Q.comp & (1u << j))) continue;
-      Slot<T> pv;
-      pv.meta = 0u;
-      pv.amp = T(0);
-      slot[j] = find_slot_pre<T, PH>(v.sl, H, Q.q[j], home[j], hv[j], &ff[j], &pv);
-      if (slot[j] >= 0) {
-        const uint32_t pt = pv.meta & TAG;
-        // present when the launch started: alive and not created by it
-        pres[j] = !(pv.meta & DEAD) && pt != K1 && pt != K2;
-        a[j] = pv.amp;
-        if (pres[j] && Q.q[j] < Q.q[0]) owner = false;
+  const uint64_t ebase = s * v.A;
+  const uint64_t stride = scan_blocks() * BLK;
+  uint64_t j = scan_rank() * BLK + threadIdx.x;
+  for (uint64_t jw = scan_rank() * BLK + (threadIdx.x & ~63u); jw < ns; jw += stride, j += stride) {
+    // this lane's work for the round; new entries are claimed by the whole
+    // wave at its end
+    bool want[4] = {false, false, false, false};
+    uint64_t wfree[4] = {0, 0, 0, 0};
+    T wamp[4];
+    uint32_t wborn[4] = {0, 0, 0, 0};
+    Quad Q;
+    Q.q[0] = Q.q[1] = Q.q[2] = Q.q[3] = 0;
+    do {
+      if (j >= ns) break;
+      const Slot<T> me = v.sl[ebase + j];
+      const uint32_t m = me.meta;
+      if ((m & DEAD) || (m & TAG) == K1 || (m & TAG) == K2) break;  // dead, or revived by this launch
+      Q = make_quad(me.key, m1, m2, f1, f2);
+      if (Q.comp == 1u) {  // acted on by neither factor
+        c1a += 1;
+        c1b += 1;
+        break;
       }
-    }
-    if (!owner) continue;
-    bool exist[4];
-    uint32_t born[4];
+      uint64_t ent[4], ff[4];
+      bool pres[4], found[4];
+      T a[4];
+      ent[0] = ebase + j;
+      pres[0] = found[0] = true;
+      a[0] = me.amp;
+      bool owner = true;
+      // the first PH index slots from the home of every other member, loaded
+      // together: most probes end inside them
+      uint64_t home[4];
+      Idx hv[4][PH];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      exist[j] = pres[j];
-      born[j] = 0u;
-      if (!pres[j]) a[j] = T(0);
-    }
-    // one pair rotation of factor f on members u, w (absent members count as 0)
-    auto rot = [&](int u, int w, const FacMask& f, T sn, T cm1, uint32_t Kt) {
-      if (!pres[u] && !pres[w]) return;
-      const int L = side(Q.q[u], f) == 1 ? u : w;
-      const int U = L == u ? w : u;
-      c2 += 1;
-      if (pres[L] && pres[U]) c6 += 1;
-      const T ss = (__popcll(Q.q[L] & f.sgn) & 1) ? -sn : sn;
-      const T x = a[L], y = a[U];
-      const T xn = x + fmaT<T>(x, cm1, -ss * y);
-      const T yn = y + fmaT<T>(y, cm1, ss * x);
-      a[L] = xn;
-      a[U] = yn;
-      if (!pres[L]) {
-        pres[L] = true;
-        born[L] = Kt;
-        c3 += 1;
-      }
-      if (!pres[U]) {
-        pres[U] = true;
-        born[U] = Kt;
-        c3 += 1;
-      }
-    };
-    c1a += static_cast<unsigned long long>(pres[0]) + pres[1] + pres[2] + pres[3];
-    if (Q.e1a) rot(0, 1, f1, sn1, cm1a, K1);
-    if (Q.e1b && (Q.comp & 4u)) rot(2, 3, f1, sn1, cm1a, K1);
-    c1b += static_cast<unsigned long long>(pres[0]) + pres[1] + pres[2] + pres[3];
-    if (Q.e2a) rot(0, 2, f2, sn2, cm1b, K2);
-    if (Q.e2b && (Q.comp & 2u)) rot(1, 3, f2, sn2, cm1b, K2);
+      for (int q = 1; q < 4; ++q) {
+        home[q] = mix64(Q.q[q]) & mask;
+        if (Q.comp & (1u << q))
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (!pres[j]) continue;
-      if (exist[j]) {
-        v.sl[slot[j]].amp = a[j];
-        continue;
+          for (int i = 0; i < PH; ++i) hv[q][i] = v.ix[(home[q] + i) & mask];
       }
-      int64_t d = slot[j];  // a tombstone of an earlier sweep is revived in place
-      if (d < 0) {
-        d = claim_slot(v.sl, H, Q.q[j], ff[j]);
-        if (d < 0) {
-          flags |= F_TABLE_FULL;
+      uint32_t pid[4];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        ent[q] = 0;
+        ff[q] = v.H;
+        pres[q] = found[q] = false;
+        a[q] = T(0);
+        pid[q] = NO_ID;
+        if (!(Q.comp & (1u << q))) continue;
+        Idx iv;
+        if (find_slot_pre<PH>(v.ix, v.H, Q.q[q], home[q], hv[q], &ff[q], &iv) < 0) continue;
+        found[q] = true;
+        pid[q] = iv.id;
+      }
+      // entries of the members that existed when the launch began, loaded together
+      Slot<T> pv[4];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        if (!found[q]) continue;
+        if (pid[q] == NO_ID || created_here(pid[q], arena_n)) {  // created by this launch: not present
+          found[q] = false;
           continue;
         }
-        c5 += 1;
+        ent[q] = v.off(pid[q]);
+        pv[q] = v.sl[ent[q]];
       }
-      v.sl[d].amp = a[j];
-      v.born(d) = born[j];
-      v.sl[d].meta = born[j];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        if (!found[q]) continue;
+        const uint32_t pt = pv[q].meta & TAG;
+        // present when the launch started: alive and not revived by it
+        pres[q] = !(pv[q].meta & DEAD) && pt != K1 && pt != K2;
+        a[q] = pv[q].amp;
+        if (pres[q] && Q.q[q] < Q.q[0]) owner = false;
+      }
+      if (!owner) break;
+      bool exist[4];
+      uint32_t born[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        exist[q] = pres[q];
+        born[q] = 0u;
+        if (!pres[q]) a[q] = T(0);
+      }
+      // one pair rotation of factor f on members u, w (absent members count as 0)
+      auto rot = [&](int u, int w, const FacMask& f, T sn, T cm1, uint32_t Kt) {
+        if (!pres[u] && !pres[w]) return;
+        const int L = side(Q.q[u], f) == 1 ? u : w;
+        const int U = L == u ? w : u;
+        c2 += 1;
+        if (pres[L] && pres[U]) c6 += 1;
+        const T ss = (__popcll(Q.q[L] & f.sgn) & 1) ? -sn : sn;
+        const T x = a[L], y = a[U];
+        const T xn = x + fmaT<T>(x, cm1, -ss * y);
+        const T yn = y + fmaT<T>(y, cm1, ss * x);
+        a[L] = xn;
+        a[U] = yn;
+        if (!pres[L]) {
+          pres[L] = true;
+          born[L] = Kt;
+          c3 += 1;
+        }
+        if (!pres[U]) {
+          pres[U] = true;
+          born[U] = Kt;
+          c3 += 1;
+        }
+      };
+      c1a += static_cast<unsigned long long>(pres[0]) + pres[1] + pres[2] + pres[3];
+      if (Q.e1a) rot(0, 1, f1, sn1, cm1a, K1);
+      if (Q.e1b && (Q.comp & 4u)) rot(2, 3, f1, sn1, cm1a, K1);
+      c1b += static_cast<unsigned long long>(pres[0]) + pres[1] + pres[2] + pres[3];
+      if (Q.e2a) rot(0, 2, f2, sn2, cm1b, K2);
+      if (Q.e2b && (Q.comp & 2u)) rot(1, 3, f2, sn2, cm1b, K2);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!pres[q]) continue;
+        if (exist[q]) {
+          v.sl[ent[q]].amp = a[q];
+          continue;
+        }
+        if (found[q]) {  // a dead entry of an earlier sweep is revived in place
+          v.sl[ent[q]].amp = a[q];
+          v.born(ent[q]) = born[q];
+          v.sl[ent[q]].meta = born[q];
+          continue;
+        }
+        want[q] = true;
+        wamp[q] = a[q];
+        wborn[q] = born[q];
+        wfree[q] = ff[q];
+      }
+    } while (false);
+    uint64_t pos[4];
+    const int ar = claim_positions<4>(sa, b, k, nk, want, pos);
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      if (!want[q]) continue;
+      if (pos[q] >= v.A) {
+        flags |= F_TABLE_FULL;
+        continue;
+      }
+      const uint64_t e = ar * v.A + pos[q];
+      v.sl[e].key = Q.q[q];
+      v.sl[e].amp = wamp[q];
+      v.sl[e].meta = wborn[q];
+      v.born(e) = wborn[q];
+      v.lam(e) = T(0);
+      if (!index_insert(v.ix, v.H, Q.q[q], wfree[q], entry_id(ar, pos[q]))) {
+        flags |= F_TABLE_FULL;
+        continue;
+      }
+      c5 += 1;
     }
   }
   if (flags) atomicOr(&cnt[b].flags, flags);
@@ -1193,7 +1499,6 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
     if (w1a) atomicAdd(&sa.pvis[sidx(sa, b, wsh, k)], w1a);
     if (w1b) atomicAdd(&sa.pvis[sidx(sa, b, wsh, k + 1)], w1b);
   }
-  if (w5 && lane == 0) atomicAdd(&cnt[b].sh[wsh & (CSH - 1)].v[C_OCC], static_cast<unsigned long long>(w5));
   if (lane < 7) {
     const unsigned int mine = lane == 1 ? w1 : lane == 2 ? w2 : lane == 3 ? w3 : lane == 5 ? w5 : lane == 6 ? w6 : 0u;
     wst[lane] = wold + mine;
@@ -1207,85 +1512,93 @@ template <class T, int PH>
 __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
                                               int64_t ld, StepArr sa, Counters* cnt, int k) {
   const int b = blockIdx.y;
-  const uint64_t H = t.H;
   const View<T> v = view<T>(t, b);
+  const int s = scan_arena();
+  const uint64_t ns = static_cast<uint32_t>(__shfl(static_cast<int>(counts_reverse(sa, b, k + 1, v.A)), s, 64));
   const FacMask f1 = fac[k - 1], f2 = fac[k];
   const Trig t1 = trig[b * ld + k - 1], t2 = trig[b * ld + k];
   const T c1 = static_cast<T>(t1.c), sn1 = static_cast<T>(t1.s), cm1a = static_cast<T>(t1.cm1);
   const T c2 = static_cast<T>(t2.c), sn2 = static_cast<T>(t2.s), cm1b = static_cast<T>(t2.cm1);
   const uint64_t m1 = f1.occ | f1.vir, m2 = f2.occ | f2.vir;
   const uint32_t K1 = static_cast<uint32_t>(k), K2 = K1 + 1u;
+  const uint64_t mask = v.H - 1;
   Fx g1 = fx_zero(), g2 = fx_zero();
   unsigned int flags = 0;
 
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < H; s += stride) {
-    const Slot<T> me = v.sl[s];
-    const T lam_me = v.lam_pre(s);
-    if (me.key == EMPTY_KEY || (me.meta & DEAD)) continue;
+  const uint64_t ebase = s * v.A;
+  const uint64_t stride = scan_blocks() * BLK;
+  for (uint64_t j = scan_rank() * BLK + threadIdx.x; j < ns; j += stride) {
+    const Slot<T> me = v.sl[ebase + j];
+    const T lam_me = v.lam_pre(ebase + j);
+    if (me.meta & DEAD) continue;
     const Quad Q = make_quad(me.key, m1, m2, f1, f2);
     if (Q.comp == 1u) continue;
-    int64_t slot[4];
-    bool pres[4];
+    uint64_t ent[4];
+    bool pres[4], found[4];
     uint32_t born[4];
     T a[4], l[4];
-    slot[0] = static_cast<int64_t>(s);
-    pres[0] = true;
+    ent[0] = ebase + j;
+    pres[0] = found[0] = true;
     a[0] = me.amp;
     l[0] = v.lam_fin(me, lam_me);
     born[0] = me.meta & TAG;
     bool owner = true;
-    // the first PH slots from the home of every other member (and the
-    // adjoint values there), loaded together
+    // the first PH index slots from the home of every other member, loaded together
     uint64_t home[4];
-    Slot<T> hv[4][PH];
-    T hl[4][PH];
+    Idx hv[4][PH];
 #pragma unroll
-    for (int j = 1; j < 4; ++j) {
-      home[j] = mix64(Q.q[j]) & (H - 1);
-      if (Q.comp & (1u << j)) {
+    for (int q = 1; q < 4; ++q) {
+      home[q] = mix64(Q.q[q]) & mask;
+      if (Q.comp & (1u << q))
 #pragma unroll
-        for (int i = 0; i < PH; ++i) {
-          hv[j][i] = v.sl[(home[j] + i) & (H - 1)];
-          hl[j][i] = v.lam_pre((home[j] + i) & (H - 1));
-        }
-      }
+        for (int i = 0; i < PH; ++i) hv[q][i] = v.ix[(home[q] + i) & mask];
     }
 #pragma unroll
-    for (int j = 1; j < 4; ++j) {
-      slot[j] = -1;
-      pres[j] = false;
-      a[j] = T(0);
-      l[j] = T(0);
-      born[j] = 0u;
-      if (!(Q.comp & (1u << j))) continue;
-      uint64_t ff = H;
-      Slot<T> pv;
-      pv.meta = 0u;
-      pv.amp = T(0);
-      slot[j] = find_slot_pre<T, PH>(v.sl, H, Q.q[j], home[j], hv[j], &ff, &pv);
-      if (slot[j] < 0) continue;
-      const uint32_t pt = pv.meta & TAG;
-      // present when the launch started: alive, or removed by this launch
-      pres[j] = !(pv.meta & DEAD) || pt == K1 || pt == K2;
-      if (!pres[j]) continue;
-      if (Q.q[j] < Q.q[0]) owner = false;
-      a[j] = pv.amp;
-      const uint64_t off = (static_cast<uint64_t>(slot[j]) - home[j]) & (H - 1);
-      T lp = T(0);
+    for (int q = 1; q < 4; ++q) {
+      ent[q] = 0;
+      pres[q] = found[q] = false;
+      a[q] = T(0);
+      l[q] = T(0);
+      born[q] = 0u;
+      if (!(Q.comp & (1u << q))) continue;
+      uint64_t ff = v.H;
+      Idx iv;
+      if (find_slot_pre<PH>(v.ix, v.H, Q.q[q], home[q], hv[q], &ff, &iv) < 0) continue;
+      if (iv.id == NO_ID) {
+        flags |= F_INCONSISTENT;
+        continue;
+      }
+      found[q] = true;
+      ent[q] = v.off(iv.id);
+    }
+    // the members' entries (and adjoint values), loaded together
+    Slot<T> pv[4];
+    T pl[4];
 #pragma unroll
-      for (int i = 0; i < PH; ++i)
-        if (off == static_cast<uint64_t>(i)) lp = hl[j][i];
-      l[j] = off < PH ? v.lam_fin(pv, lp) : v.lam_of(pv, static_cast<uint64_t>(slot[j]));
-      born[j] = (pv.meta & DEAD) ? v.born(static_cast<uint64_t>(slot[j])) : pt;
+    for (int q = 1; q < 4; ++q) {
+      if (!found[q]) continue;
+      pv[q] = v.sl[ent[q]];
+      pl[q] = v.lam_pre(ent[q]);
+    }
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      if (!found[q]) continue;
+      const uint32_t pt = pv[q].meta & TAG;
+      // present when the launch started: alive, or removed by this launch
+      pres[q] = !(pv[q].meta & DEAD) || pt == K1 || pt == K2;
+      if (!pres[q]) continue;
+      if (Q.q[q] < Q.q[0]) owner = false;
+      a[q] = pv[q].amp;
+      l[q] = v.lam_fin(pv[q], pl[q]);
+      born[q] = (pv[q].meta & DEAD) ? v.born(ent[q]) : pt;
     }
     if (!owner) continue;
     bool exist[4];
     uint32_t gone[4];  // step whose undo removed the member (0: kept)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      exist[j] = pres[j];
-      gone[j] = 0u;
+    for (int q = 0; q < 4; ++q) {
+      exist[q] = pres[q];
+      gone[q] = 0u;
     }
     auto unrot = [&](int u, int w, const FacMask& f, T c, T sn, T cm1, uint32_t Kt, Fx& g) {
       if (!pres[u] && !pres[w]) return;
@@ -1337,15 +1650,15 @@ __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__
     if (Q.e1a) unrot(0, 1, f1, c1, sn1, cm1a, K1, g1);
     if (Q.e1b && (Q.comp & 4u)) unrot(2, 3, f1, c1, sn1, cm1a, K1, g1);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (!exist[j]) continue;
-      const uint64_t d = static_cast<uint64_t>(slot[j]);
-      if (gone[j]) {
-        v.sl[d].meta = DEAD | gone[j];
+    for (int q = 0; q < 4; ++q) {
+      if (!exist[q]) continue;
+      const uint64_t d = ent[q];
+      if (gone[q]) {
+        v.sl[d].meta = DEAD | gone[q];
       } else {
-        v.sl[d].amp = a[j];
-        v.lam(d) = l[j];
-        v.sl[d].meta = born[j];
+        v.sl[d].amp = a[q];
+        v.lam(d) = l[q];
+        v.sl[d].meta = born[q];
       }
     }
   }
@@ -1438,6 +1751,7 @@ __global__ __launch_bounds__(BLK) void k_rev_sweep(Tab t, const FacMask* __restr
   }
 }
 
+
 // ---------------------------------------------------------------------------
 // energy: compact live entries, sigma = H psi on the support, E
 // ---------------------------------------------------------------------------
@@ -1449,19 +1763,20 @@ __global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cn
   __shared__ unsigned int wcount[BLK / 64];
   __shared__ unsigned long long wbase[BLK / 64];
   const int b = blockIdx.y;
-  const uint64_t H = t.H;
   const View<T> v = view<T>(t, b);
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const int a = scan_arena();
+  const uint64_t n = t.ac[b * NA + a];
+  const uint64_t stride = scan_blocks() * BLK;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (uint64_t s0 = blockIdx.x * blockDim.x; s0 < H; s0 += stride) {  // the same passes for the whole block
-    const uint64_t s = s0 + threadIdx.x;
+  for (uint64_t j0 = scan_rank() * BLK; j0 < n; j0 += stride) {  // the same passes for the whole block
+    const uint64_t j = j0 + threadIdx.x;
     bool live = false;
     Slot<T> me;
     me.key = 0;
     me.amp = T(0);
-    if (s < H) {
-      me = v.sl[s];
-      live = me.key != EMPTY_KEY && !(me.meta & DEAD);
+    if (j < n) {
+      me = v.sl[a * v.A + j];
+      live = !(me.meta & DEAD);
     }
     const unsigned long long mask = __ballot(live);
     if (lane == 0) wcount[w] = static_cast<unsigned int>(__popcll(mask));
@@ -1469,10 +1784,10 @@ __global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cn
     if (threadIdx.x == 0) {
       unsigned long long tot = 0;
       for (int i = 0; i < BLK / 64; ++i) tot += wcount[i];
-      unsigned long long base = tot ? atomicAdd(&cnt[b].ncompact, tot) : 0ull;
+      unsigned long long basep = tot ? atomicAdd(&cnt[b].ncompact, tot) : 0ull;
       for (int i = 0; i < BLK / 64; ++i) {
-        wbase[i] = base;
-        base += wcount[i];
+        wbase[i] = basep;
+        basep += wcount[i];
       }
     }
     __syncthreads();
@@ -1481,10 +1796,10 @@ __global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cn
     if (live) {
       const unsigned long long below = lane ? (mask & ((1ull << lane) - 1ull)) : 0ull;
       const uint64_t pos = basep + __popcll(below);
-      cp.key[b * H + pos] = me.key;
-      cp.amp[b * H + pos] = static_cast<double>(me.amp);
-      cp.slot[b * H + pos] = static_cast<uint32_t>(s);
-      cp.sig[b * H + pos] = 0.0;
+      cp.key[b * cp.cs + pos] = me.key;
+      cp.amp[b * cp.cs + pos] = static_cast<double>(me.amp);
+      cp.slot[b * cp.cs + pos] = entry_id(a, j);
+      cp.sig[b * cp.cs + pos] = 0.0;
     }
   }
 }
@@ -1497,22 +1812,23 @@ __global__ __launch_bounds__(BLK) void k_compact(Tab t, Compact cp, Counters* cn
 // exactly, so every snapshot key is alive at that point.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(BLK) void k_snapshot(Tab t, Snap sn) {
+__global__ __launch_bounds__(BLK) void k_snapshot(Tab t, StepArr sa, Snap sn, int k) {
   const int b = blockIdx.y;
-  const uint64_t H = t.H;
   const View<T> v = view<T>(t, b);
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const int a = scan_arena();
+  const uint64_t n = static_cast<uint32_t>(__shfl(static_cast<int>(counts_after(sa, b, k, v.A)), a, 64));
+  const uint64_t stride = scan_blocks() * BLK;
   const int lane = threadIdx.x & 63;
   T* amp = static_cast<T*>(sn.amp);
-  for (uint64_t s0 = blockIdx.x * blockDim.x; s0 < H; s0 += stride) {
-    const uint64_t s = s0 + threadIdx.x;
+  for (uint64_t j0 = scan_rank() * BLK + (threadIdx.x & ~63u); j0 < n; j0 += stride) {  // uniform per wave
+    const uint64_t j = j0 + lane;
     bool live = false;
     Slot<T> me;
     me.key = 0;
     me.amp = T(0);
-    if (s < H) {
-      me = v.sl[s];
-      live = me.key != EMPTY_KEY && !(me.meta & DEAD);
+    if (j < n) {
+      me = v.sl[a * v.A + j];
+      live = !(me.meta & DEAD);
     }
     const unsigned long long mask = __ballot(live);
     if (!mask) continue;
@@ -1538,28 +1854,30 @@ __global__ __launch_bounds__(BLK) void k_snap_restore(Tab t, Snap sn, Counters* 
   const uint64_t n = sn.count[b] < sn.cap ? sn.count[b] : sn.cap;
   const T* amp = static_cast<const T*>(sn.amp);
   for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    uint64_t ff = t.H;
-    Slot<T> cur;
-    const int64_t s = find_slot(v.sl, t.H, sn.key[b * sn.cap + i], &ff, &cur);
-    if (s < 0 || (cur.meta & DEAD)) {
+    uint64_t ff = v.H;
+    Idx iv;
+    if (find_slot(v.ix, v.H, sn.key[b * sn.cap + i], &ff, &iv) < 0 || iv.id == NO_ID ||
+        (v.sl[v.off(iv.id)].meta & DEAD)) {
       atomicOr(&cnt[b].flags, F_INCONSISTENT);
       continue;
     }
-    v.sl[s].amp = amp[b * sn.cap + i];
+    v.sl[v.off(iv.id)].amp = amp[b * sn.cap + i];
   }
 }
 
-// entropy of the state in the table (alive entries) into step k's sums
+// entropy of the state (alive entries) into step k's sums
 template <class T>
 __global__ __launch_bounds__(BLK) void k_entropy_scan(Tab t, StepArr sa, int k) {
   const int b = blockIdx.y;
   const View<T> v = view<T>(t, b);
-  Fx a = fx_zero(), e = fx_zero();
-  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
-    const Slot<T> x = v.sl[s];
-    if (x.key != EMPTY_KEY && !(x.meta & DEAD)) ent_add(a, e, static_cast<double>(x.amp));
+  const int a = scan_arena();
+  const uint64_t n = t.ac[b * NA + a];
+  Fx ea = fx_zero(), eb = fx_zero();
+  for (uint64_t j = scan_rank() * BLK + threadIdx.x; j < n; j += scan_blocks() * BLK) {
+    const Slot<T> x = v.sl[a * v.A + j];
+    if (!(x.meta & DEAD)) ent_add(ea, eb, static_cast<double>(x.amp));
   }
-  ent_flush(sa, b, k, a, e);
+  ent_flush(sa, b, k, ea, eb);
 }
 
 // Entropy (Eq. 6) after step k from the exact sums A = sum r^2 ln r^2 and
@@ -1692,7 +2010,7 @@ __device__ TKState tk_select(const unsigned int* __restrict__ hist, const TKStat
 // entries that match the digits chosen so far.  Also clears the histogram
 // buffer the next pass fills.
 template <class T>
-__global__ __launch_bounds__(BLK) void k_topk_pass(Tab t, TopK* tk, const Counters* cnt, int k, int pass,
+__global__ __launch_bounds__(BLK) void k_topk_pass(Tab t, StepArr sa, TopK* tk, const Counters* cnt, int k, int pass,
                                                     unsigned long long n_max, unsigned long long n_cut) {
   const int b = blockIdx.y;
   if (static_cast<uint32_t>(k) >= cnt[0].stop) return;
@@ -1712,9 +2030,11 @@ __global__ __launch_bounds__(BLK) void k_topk_pass(Tab t, TopK* tk, const Counte
   const R128 pre{st.pre_hi, st.pre_lo};
   const int shift = nbits - TK_BITS * pass;
   const View<T> v = view<T>(t, b);
-  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
-    const Slot<T> x = v.sl[s];
-    if (x.key == EMPTY_KEY || (x.meta & DEAD)) continue;
+  const int a = scan_arena();
+  const uint64_t n = static_cast<uint32_t>(__shfl(static_cast<int>(counts_after(sa, b, k, v.A)), a, 64));
+  for (uint64_t j = scan_rank() * BLK + threadIdx.x; j < n; j += scan_blocks() * BLK) {
+    const Slot<T> x = v.sl[a * v.A + j];
+    if (x.meta & DEAD) continue;
     const R128 r = rank_of<T>(x.key, x.amp);
     if (pass > 0) {
       const R128 top = shr128(r, shift);
@@ -1746,19 +2066,22 @@ __global__ __launch_bounds__(BLK) void k_topk_kill(Tab t, StepArr sa, Counters* 
   const R128 pre{st.pre_hi, st.pre_lo};
   const View<T> v = view<T>(t, b);
   const uint32_t K = static_cast<uint32_t>(k);
+  const int a = scan_arena();
+  const uint64_t n = static_cast<uint32_t>(__shfl(static_cast<int>(counts_after(sa, b, k, v.A)), a, 64));
   Fx w = fx_zero(), ea = fx_zero(), eb = fx_zero();
-  unsigned int n = 0;
-  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
-    const Slot<T> x = v.sl[s];
-    if (x.key == EMPTY_KEY || (x.meta & DEAD)) continue;
+  unsigned int nk = 0;
+  for (uint64_t j = scan_rank() * BLK + threadIdx.x; j < n; j += scan_blocks() * BLK) {
+    const uint64_t e = a * v.A + j;
+    const Slot<T> x = v.sl[e];
+    if (x.meta & DEAD) continue;
     if (!lt128(shr128(rank_of<T>(x.key, x.amp), nbits - sel), pre)) continue;
-    v.sl[s].meta = DEAD | K;  // tombstone keeps the pre-truncation amplitude
+    v.sl[e].meta = DEAD | K;  // the entry keeps the pre-truncation amplitude
     const double r = static_cast<double>(x.amp);
     w = fx_add(w, fx_from(r * r));
-    ++n;
+    ++nk;
     if (sa.ea) ent_add(ea, eb, r);
   }
-  const unsigned int c = wave_u32(n);
+  const unsigned int c = wave_u32(nk);
   const int lane = threadIdx.x & 63;
   const int wv = blockIdx.x * (BLK / 64) + (threadIdx.x >> 6);
   if (c) {
@@ -1945,7 +2268,7 @@ __device__ __forceinline__ uint64_t excite(uint64_t I, int e, const Lists& L, co
 }
 
 // sigma_I = sum_J <I|H|J> c_J over the single and double excitations J of I
-// that are alive in the table (off-diagonal part; the diagonal is added in
+// that are alive in the state (off-diagonal part; the diagonal is added in
 // k_energy_reduce).  SG lanes of one wave share I and its orbital lists (one
 // LDS row per group, written identically by all its lanes before any of them
 // reads it: a wave executes its LDS instructions in order).  The excitations
@@ -1982,7 +2305,7 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
     return c;
   };
   for (int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / SG; i < N; i += gstride) {
-    const uint64_t I = cp.key[b * H + i];
+    const uint64_t I = cp.key[b * cp.cs + i];
     Lists L;
     L.nA = fill(row, I & ALPHA);
     L.nB = fill(row + 32, I & BETA);
@@ -2010,41 +2333,54 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
       uint64_t J[SGU], home[SGU];
       int rank[SGU];
       unsigned int mv[SGU];
-      Slot<T> hv[SGU];
+      Idx hv[SGU];
 #pragma unroll
       for (int u = 0; u < SGU; ++u) {
         const int e = e0 + u * SG;
         if (e < total) {
           J[u] = excite(I, e, L, tri, &rank[u], &mv[u]);
           home[u] = mix64(J[u]) & (H - 1);
-          hv[u] = v.sl[home[u]];
+          hv[u] = v.ix[home[u]];
         }
       }
+      // resolve the index probes, then load the entries found together
+      uint64_t pe[SGU];
+      bool hit[SGU];
 #pragma unroll
       for (int u = 0; u < SGU; ++u) {
-        if (e0 + u * SG >= total) break;
+        hit[u] = false;
+        if (e0 + u * SG >= total) continue;
         uint64_t ff;
-        Slot<T> pv;
-        const int64_t sj = find_slot_from(v.sl, H, J[u], home[u], hv[u], &ff, &pv);
-        if (sj >= 0 && !(pv.meta & DEAD)) {
-          const uint64_t C = I & J[u];
-          const unsigned int m = mv[u];
-          const double h = rank[u] == 2 ? h_single(C, m & 255, (m >> 16) & 255, h1, h2, n)
-                                        : h_double(C, m & 255, (m >> 8) & 255, (m >> 16) & 255, m >> 24, h2, n);
-          acc += h * static_cast<double>(pv.amp);
+        Idx iv;
+        if (find_slot_from(v.ix, H, J[u], home[u], hv[u], &ff, &iv) >= 0 && iv.id != NO_ID) {
+          hit[u] = true;
+          pe[u] = v.off(iv.id);
         }
+      }
+      Slot<T> pv[SGU];
+#pragma unroll
+      for (int u = 0; u < SGU; ++u)
+        if (hit[u]) pv[u] = v.sl[pe[u]];
+#pragma unroll
+      for (int u = 0; u < SGU; ++u) {
+        if (!hit[u] || (pv[u].meta & DEAD)) continue;
+        const uint64_t C = I & J[u];
+        const unsigned int m = mv[u];
+        const double h = rank[u] == 2 ? h_single(C, m & 255, (m >> 16) & 255, h1, h2, n)
+                                      : h_double(C, m & 255, (m >> 8) & 255, (m >> 16) & 255, m >> 24, h2, n);
+        acc += h * static_cast<double>(pv[u].amp);
       }
     }
 #pragma unroll
     for (int o = SG / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, SG);
-    if (g == 0) cp.sig[b * H + i] = acc;
+    if (g == 0) cp.sig[b * cp.cs + i] = acc;
   }
 }
 
 // adds the diagonal, then sum c*sigma and sum c^2 (exact) per state
-__global__ __launch_bounds__(BLK) void k_energy_reduce(Compact cp, Counters* cnt, uint64_t H,
-                                                       const double* __restrict__ h1, const double* __restrict__ h2,
-                                                       int n) {
+__global__ __launch_bounds__(BLK) void k_energy_reduce(Compact cp, Counters* cnt, const double* __restrict__ h1,
+                                                       const double* __restrict__ h2, int n) {
+  const uint64_t H = cp.cs;
   __shared__ double d1[32], Jt[32 * 32], Kt[32 * 32];  // n <= 32 spatial orbitals
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int P = e / n, Q = e - P * n;
@@ -2075,66 +2411,67 @@ __global__ __launch_bounds__(BLK) void k_energy_reduce(Compact cp, Counters* cnt
   if (threadIdx.x == 0 && fx_nonzero(r.f)) fx3_atomic_add(&es.den, r.f);
 }
 
-// ---------------------------------------------------------------------------
-// table growth: rehash into a larger, empty table
-// ---------------------------------------------------------------------------
-__global__ void k_rehash_begin(Counters* cnt) {
-  for (int i = threadIdx.x; i < CSH; i += blockDim.x) cnt[blockIdx.x].sh[i].v[C_COPY] = 0ull;
-}
 
-// Which entries a rehash keeps: alive ones, and tombstones with a step tag in
-// [1, tag_max] (the reverse sweep still needs their values).  Tombstones of
-// earlier sweeps (tag 0) are dropped; so, in the reverse sweep, are the
-// members that undoing a step above tag_max has removed (tag > tag_max).
-__device__ __forceinline__ bool keep_entry(uint64_t key, uint32_t meta, uint32_t tag_max) {
-  if (key == EMPTY_KEY) return false;
-  if (!(meta & DEAD)) return true;
-  const uint32_t tag = meta & TAG;
-  return tag != 0u && tag <= tag_max;
-}
 
-// Keys are unique, so every copy claims its own slot.
-template <class T>
-__global__ void k_rehash(Tab from, Tab to, Counters* cnt, uint32_t tag_max) {
-  const int b = blockIdx.y;
-  const View<T> vf = view<T>(from, b), vt = view<T>(to, b);
-  unsigned long long n = 0;
-  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < from.H; s += gridDim.x * blockDim.x) {
-    const Slot<T> x = vf.sl[s];
-    if (!keep_entry(x.key, x.meta, tag_max)) continue;
-    const int64_t d = claim_slot(vt.sl, to.H, x.key, mix64(x.key) & (to.H - 1));
-    if (d < 0) {
-      atomicOr(&cnt[b].flags, F_TABLE_FULL);
-      continue;
-    }
-    vt.sl[d].amp = x.amp;
-    vt.sl[d].meta = x.meta;
-    vt.born(d) = vf.born(s);
-    vt.lam(d) = vf.lam(s);
-    ++n;
+// ---------------------------------------------------------------------------
+// index growth: a larger index, rebuilt from the entries (which do not move)
+// ---------------------------------------------------------------------------
+__global__ void k_idx_clear(Tab t) {
+  Idx* ix = t.idx + blockIdx.y * t.Hcap;
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
+    ix[s].key = EMPTY_KEY;
+    ix[s].id = NO_ID;
   }
-  n = wave_u64(n);
-  if ((threadIdx.x & 63) == 0 && n) atomicAdd(&cnt[b].sh[cshard()].v[C_COPY], n);
 }
 
-// entries a rehash with this tag_max would keep, into the C_COPY counters
+// Every entry, alive or dead, is indexed (keys are unique, so every insert
+// claims its own slot); the growth check stopped no step any more.
 template <class T>
-__global__ void k_count_keep(Tab t, Counters* cnt, uint32_t tag_max) {
+__global__ void k_reindex(Tab t, Counters* cnt) {
   const int b = blockIdx.y;
   const View<T> v = view<T>(t, b);
-  unsigned long long n = 0;
-  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
-    const Slot<T> x = v.sl[s];
-    n += keep_entry(x.key, x.meta, tag_max) ? 1ull : 0ull;
+  const int a = scan_arena();
+  const uint64_t n = t.ac[b * NA + a];
+  for (uint64_t j = scan_rank() * BLK + threadIdx.x; j < n; j += scan_blocks() * BLK) {
+    const uint64_t key = v.sl[a * v.A + j].key;
+    if (!index_insert(v.ix, v.H, key, mix64(key) & (v.H - 1), entry_id(a, j))) atomicOr(&cnt[b].flags, F_TABLE_FULL);
   }
-  n = wave_u64(n);
-  if ((threadIdx.x & 63) == 0 && n) atomicAdd(&cnt[b].sh[cshard()].v[C_COPY], n);
+  if (b == 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[0].stop = ~0u;
 }
 
-// the occupancy of the new table is the number of slots copied
-__global__ void k_rehash_end(Counters* cnt) {
-  for (int i = threadIdx.x; i < CSH; i += blockDim.x) cnt[blockIdx.x].sh[i].v[C_OCC] = cnt[blockIdx.x].sh[i].v[C_COPY];
-  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[0].stop = ~0u;  // the grown table lets the stopped steps run
+// Entry positions the last sweeps scanned (statistics): the forward
+// launches' counts at their start (every arena of a launch is written
+// together), and what undoing each factor scans; into C_FSCAN / C_RSCAN of
+// shard 0.
+__global__ void k_scan_totals(StepArr sa, Counters* cnt, int64_t M) {
+  const int b = blockIdx.x;
+  unsigned long long f = 0, r = 0;
+  for (int64_t k = 1 + threadIdx.x; k <= M; k += blockDim.x) {
+    const int64_t row = (static_cast<int64_t>(b) * sa.nstride + k) * NA;
+    if (sa.nb[row] != NB_UNSET)
+      for (int a = 0; a < NA; ++a) f += sa.nb[row + a];
+    for (int a = 0; a < NA; ++a) {
+      const uint32_t n1 = sa.nb[row + NA + a];
+      r += n1 != NB_UNSET ? n1 : sa.nb[row + 2 * NA + a];
+    }
+  }
+  __shared__ unsigned long long part[2][BLK / 64];
+  f = wave_u64(f);
+  r = wave_u64(r);
+  if ((threadIdx.x & 63) == 0) {
+    part[0][threadIdx.x >> 6] = f;
+    part[1][threadIdx.x >> 6] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tf = 0, tr = 0;
+    for (int w = 0; w < BLK / 64; ++w) {
+      tf += part[0][w];
+      tr += part[1][w];
+    }
+    cnt[b].sh[0].v[C_FSCAN] = tf;
+    cnt[b].sh[0].v[C_RSCAN] = tr;
+  }
 }
 
 // Counters of a fresh state: everything zero, the scale S0, no stop step.
@@ -2149,6 +2486,14 @@ __global__ void k_counters_reset(Counters* cnt, double S0) {
   for (unsigned int i = threadIdx.x; i < nw; i += blockDim.x)
     w[i] = i == w_stop ? (0xffffffffull << 32) : i == w_s ? static_cast<unsigned long long>(__double_as_longlong(S0))
                                                             : 0ull;
+}
+
+// The live and entry counts of a state about to be refilled.
+__global__ void k_counters_live_reset(Counters* cnt) {
+  if (threadIdx.x < CSH) {
+    cnt[blockIdx.x].sh[threadIdx.x].v[C_LIVE] = 0ull;
+    cnt[blockIdx.x].sh[threadIdx.x].v[C_OCC] = 0ull;
+  }
 }
 
 __global__ void k_energy_begin(Counters* cnt, int B) {
@@ -2182,13 +2527,12 @@ __global__ void k_energy_final(Counters* cnt, double* E, int B) {
 template <class T>
 __global__ void k_lambda(Tab t, Compact cp, const Counters* cnt) {
   const int b = blockIdx.y;
-  const uint64_t H = t.H;
   const View<T> v = view<T>(t, b);
   const int64_t N = static_cast<int64_t>(cnt[b].ncompact);
   const double E = cnt[b].E;
   for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
-    const double x = cp.sig[b * H + i] - E * cp.amp[b * H + i];
-    v.lam(cp.slot[b * H + i]) = static_cast<T>(x);
+    const double x = cp.sig[b * cp.cs + i] - E * cp.amp[b * cp.cs + i];
+    v.lam(v.off(cp.slot[b * cp.cs + i])) = static_cast<T>(x);
   }
 }
 
@@ -2204,6 +2548,7 @@ __global__ void k_grad_final(StepArr sa, const Counters* cnt, double* grad, int6
   if (lane == 0 && k < M) grad[b * M + k] = 2.0 * fx_to_d(g) / fx_to_d(cnt[b].den);
 }
 
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -2215,16 +2560,15 @@ int grid_for(uint64_t work, int block, int cap) {
   return static_cast<int>(g);
 }
 
-template <class T>
 void launch_fill(const Tab& t, int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t);
 }
 
 template <class T>
-void launch_insert_init(const Tab& t, Counters* cnt, const uint64_t* dets, const double* amps, int64_t n, int B,
-                        hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_insert_init<T>, dim3(grid_for(n, BLK, 4096), B), dim3(BLK), 0, st, t, cnt, dets, amps, n);
+void launch_insert_list(const Tab& t, Counters* cnt, const uint64_t* keys, const double* amps, int64_t n_fixed,
+                        uint64_t stride, int64_t nmax, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_insert_list<T>, dim3(grid_for(nmax > 0 ? nmax : 1, BLK, 4096), B), dim3(BLK), 0, st, t, cnt,
+                     keys, amps, n_fixed, stride);
 }
 
 void launch_trig(const double* theta, Trig* trig, int64_t M, int64_t ld, int B, Counters* cnt, hipStream_t st) {
@@ -2233,13 +2577,13 @@ void launch_trig(const double* theta, Trig* trig, int64_t M, int64_t ld, int B, 
 }
 
 template <class T>
-void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_sweep_begin<T>, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t, sa, cnt, M);
+void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_sweep_begin<T>, dim3(grid, B), dim3(BLK), 0, st, t, sa, cnt, M);
 }
 
-void launch_sweep_end(const StepArr& sa, Counters* cnt, int64_t M, int B, const Sync* sy, int fold_only,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_sweep_end, dim3(B), dim3(BLK), 0, st, sa, cnt, M, sy, fold_only);
+void launch_sweep_end(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int64_t k_last, int B,
+                      const Sync* sy, int fold_only, hipStream_t st) {
+  hipLaunchKernelGGL(k_sweep_end, dim3(B), dim3(BLK), 0, st, t, sa, cnt, M, k_last, sy, fold_only);
 }
 
 void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st) {
@@ -2324,8 +2668,8 @@ void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, 
 template <class T>
 void launch_fwd2(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                  int k, int B, int grid, int wide, hipStream_t st) {
-  // wide: PH2 slots from every home loaded up front (the caller chooses it
-  // when the launch covers the table in one pass with all its blocks
+  // wide: PH2 index slots from every home loaded up front (the caller chooses
+  // it when the launch covers the state in one pass with all its blocks
   // resident); otherwise the home slot only, keeping more waves resident
   if (wide)
     hipLaunchKernelGGL((k_fwd2<T, PH2>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
@@ -2354,8 +2698,8 @@ void launch_compact(const Tab& t, const Compact& cp, Counters* cnt, int B, int g
 }
 
 template <class T>
-void launch_snapshot(const Tab& t, const Snap& sn, int B, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_snapshot<T>, dim3(grid, B), dim3(BLK), 0, st, t, sn);
+void launch_snapshot(const Tab& t, const StepArr& sa, const Snap& sn, int k, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_snapshot<T>, dim3(grid, B), dim3(BLK), 0, st, t, sa, sn, k);
 }
 
 template <class T>
@@ -2380,7 +2724,7 @@ void launch_topk(const Tab& t, const StepArr& sa, Counters* cnt, TopK* tk, int k
   constexpr int npass = (rank_bits<T>() + TK_BITS - 1) / TK_BITS;
   const unsigned long long nm = n_max, nc = n_cut;
   for (int pass = 0; pass < npass; ++pass)
-    hipLaunchKernelGGL(k_topk_pass<T>, dim3(grid, B), dim3(BLK), 0, st, t, tk, cnt, k, pass, nm, nc);
+    hipLaunchKernelGGL(k_topk_pass<T>, dim3(grid, B), dim3(BLK), 0, st, t, sa, tk, cnt, k, pass, nm, nc);
   hipLaunchKernelGGL(k_topk_kill<T>, dim3(grid, B), dim3(BLK), 0, st, t, sa, cnt, tk, k, nm, nc);
 }
 
@@ -2397,13 +2741,21 @@ void launch_sigma(const Tab& t, const Compact& cp, const Counters* cnt, const do
                      t, cp, cnt, h1, h2, nq, singles_only);
 }
 
-void launch_energy_reduce(const Compact& cp, Counters* cnt, uint64_t H, const double* h1, const double* h2, int n,
-                          int64_t nmax, int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_energy_reduce, dim3(grid_for(nmax, BLK, 2048), B), dim3(BLK), 0, st, cp, cnt, H, h1, h2, n);
+void launch_energy_reduce(const Compact& cp, Counters* cnt, const double* h1, const double* h2, int n, int64_t nmax,
+                          int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_reduce, dim3(grid_for(nmax, BLK, 2048), B), dim3(BLK), 0, st, cp, cnt, h1, h2, n);
 }
 
 void launch_counters_reset(Counters* cnt, int B, double S0, hipStream_t st) {
   hipLaunchKernelGGL(k_counters_reset, dim3(B), dim3(BLK), 0, st, cnt, S0);
+}
+
+void launch_scan_totals(const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_totals, dim3(B), dim3(BLK), 0, st, sa, cnt, M);
+}
+
+void launch_counters_live_reset(Counters* cnt, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_counters_live_reset, dim3(B), dim3(64), 0, st, cnt);
 }
 
 void launch_energy_begin(Counters* cnt, int B, hipStream_t st) {
@@ -2411,17 +2763,9 @@ void launch_energy_begin(Counters* cnt, int B, hipStream_t st) {
 }
 
 template <class T>
-void launch_rehash(const Tab& from, const Tab& to, Counters* cnt, int B, uint32_t tag_max, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(to.H, BLK, 8192), B), dim3(BLK), 0, st, to);
-  hipLaunchKernelGGL(k_rehash_begin, dim3(B), dim3(64), 0, st, cnt);
-  hipLaunchKernelGGL(k_rehash<T>, dim3(grid_for(from.H, BLK, 8192), B), dim3(BLK), 0, st, from, to, cnt, tag_max);
-  hipLaunchKernelGGL(k_rehash_end, dim3(B), dim3(64), 0, st, cnt);
-}
-
-template <class T>
-void launch_count_keep(const Tab& t, Counters* cnt, int B, uint32_t tag_max, hipStream_t st) {
-  hipLaunchKernelGGL(k_rehash_begin, dim3(B), dim3(64), 0, st, cnt);
-  hipLaunchKernelGGL(k_count_keep<T>, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t, cnt, tag_max);
+void launch_reindex(const Tab& t, Counters* cnt, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_idx_clear, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t);
+  hipLaunchKernelGGL(k_reindex<T>, dim3(grid, B), dim3(BLK), 0, st, t, cnt);
 }
 
 void launch_energy_final(Counters* cnt, double* E, int B, hipStream_t st) {
@@ -2748,10 +3092,9 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
 }
 
 #define SWC_INST(T)                                                                                                \
-  template void launch_fill<T>(const Tab&, int, hipStream_t);                                                      \
-  template void launch_insert_init<T>(const Tab&, Counters*, const uint64_t*, const double*, int64_t, int,         \
-                                      hipStream_t);                                                                \
-  template void launch_sweep_begin<T>(const Tab&, const StepArr&, Counters*, int64_t, int, hipStream_t);          \
+  template void launch_insert_list<T>(const Tab&, Counters*, const uint64_t*, const double*, int64_t, uint64_t,   \
+                                      int64_t, int, hipStream_t);                                                  \
+  template void launch_sweep_begin<T>(const Tab&, const StepArr&, Counters*, int64_t, int, int, hipStream_t);     \
   template void launch_fwd<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*,        \
                               const LogArr&, int, double, int, int, uint64_t, int, int, int, hipStream_t);         \
   template void launch_rev<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,   \
@@ -2768,13 +3111,12 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
                                           hipStream_t);                                                            \
   template hipError_t launch_rev_sweep<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&,       \
                                           Counters*, const LogArr&, int, int, Sync*, int, int, hipStream_t);      \
-  template void launch_rehash<T>(const Tab&, const Tab&, Counters*, int, uint32_t, hipStream_t);                \
-  template void launch_count_keep<T>(const Tab&, Counters*, int, uint32_t, hipStream_t);                        \
+  template void launch_reindex<T>(const Tab&, Counters*, int, int, hipStream_t);                                 \
   template void launch_fwd2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \
                                int, int, int, hipStream_t);                                                        \
   template void launch_rev2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \
                                int, int, int, hipStream_t);                                                        \
-  template void launch_snapshot<T>(const Tab&, const Snap&, int, int, hipStream_t);                              \
+  template void launch_snapshot<T>(const Tab&, const StepArr&, const Snap&, int, int, int, hipStream_t);          \
   template void launch_entropy_scan<T>(const Tab&, const StepArr&, int, int, int, hipStream_t);                   \
   template void launch_topk<T>(const Tab&, const StepArr&, Counters*, TopK*, int, uint64_t, uint64_t, int, int,   \
                                hipStream_t);                                                                       \

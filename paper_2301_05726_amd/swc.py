@@ -53,7 +53,13 @@ class Stats(ctypes.Structure):
         ("rev_slots_scanned", ctypes.c_int64),
         ("grad_calls", ctypes.c_int64), ("fwd_ms_total", ctypes.c_double), ("rev_ms_total", ctypes.c_double),
         ("sigma_kernel_ms_total", ctypes.c_double),
+        ("kernel_builds", ctypes.c_int64),
     ]
+
+
+# sweep kernel builds (Stats.kernel_builds bits)
+BUILD_FWD, BUILD_FWD_WIDE, BUILD_FWD_ENT, BUILD_FWD2, BUILD_FWD2_PRE = 1, 2, 4, 8, 16
+BUILD_REV, BUILD_REV2, BUILD_REV2_PRE, BUILD_PERSISTENT = 32, 64, 128, 256
 
 
 _lib = None

@@ -257,8 +257,14 @@ def test_table_growth_exact(swc, orc, monkeypatch, case, prec):
     say(f"  grown: rehashes={grown[0]['rehashes']}/{grown[1]['rehashes']} table={grown[0]['table_slots']} "
         f"fixed: rehashes={fixed[0]['rehashes']} table={fixed[0]['table_slots']}")
     assert grown[0]["rehashes"] >= 2 and grown[1]["rehashes"] >= 2
-    assert grown[1]["shrinks"] >= 1  # the reverse sweep moved into smaller tables
-    assert fixed[0]["rehashes"] == 0 and fixed[0]["table_slots"] == cap and fixed[1]["shrinks"] == 0
+    assert fixed[0]["rehashes"] == 0 and fixed[0]["table_slots"] == cap
+    # the entries never move: with one factor per launch (a threshold, or an
+    # index that may still grow) the sweeps scan the same entries whatever
+    # the index size; at threshold 0 the full-size index fuses factor pairs
+    if thr > 0.0:
+        for i in (0, 1):
+            assert grown[i]["fwd_slots_scanned"] == fixed[i]["fwd_slots_scanned"] > 0
+            assert grown[i]["rev_slots_scanned"] == fixed[i]["rev_slots_scanned"]
     assert grown[0]["n_live"] == fixed[0]["n_live"]
     assert grown[1]["live_counts"] == fixed[1]["live_counts"]
     for x, y in zip(grown[2][0], fixed[2][0]):
@@ -297,8 +303,9 @@ def test_table_growth_batch(swc, orc, monkeypatch):
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 def test_launch_grid_bitwise(swc, monkeypatch, prec):
-    """The number of blocks of the sweep launches (resident-sized by default,
-    capped at 16 or 3 here, so every lane takes many passes) changes no bit
+    """The number of blocks of the sweep launches (resident-sized by default;
+    SWC_GRID caps them at one block per arena of entries here, so every lane
+    takes many passes) changes no bit
     of the state, energy or gradient: every sum is an exact fixed-point sum
     and every pair has one owner, wherever it sits in the launch."""
     say(f"[case] grid caps q16_thr prec={prec}")
@@ -323,7 +330,7 @@ def test_launch_grid_bitwise(swc, monkeypatch, prec):
     assert out[0] == out[1] == out[2]
 
 
-SHRINK_CASES = [
+SCAN_CASES = [
     ("q16", 8, 4, 0.1, 104, None, 0.0, 0),
     ("q16_thr_ckpt", 8, 4, 0.1, 105, None, 1e-4, 16),
     ("q20_pre_thr", 10, 5, 0.05, 107, 300, 1e-5, 0),
@@ -332,48 +339,50 @@ SHRINK_CASES = [
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("case", SHRINK_CASES, ids=[c[0] for c in SHRINK_CASES])
-def test_reverse_sweep_shrink_bitwise(swc, orc, monkeypatch, case, prec):
-    """The adjoint sweep rehashes into smaller tables as undoing steps removes
-    members (tombstones of later steps dropped, log records and checkpoints
-    found by determinant): energy and gradient are bit-identical to a sweep
-    that keeps its table, fewer slots are scanned, and both match the oracle."""
+@pytest.mark.parametrize("case", SCAN_CASES, ids=[c[0] for c in SCAN_CASES])
+def test_reverse_sweep_scans_shrink(swc, orc, monkeypatch, case, prec):
+    """Undoing factor k scans only the entries that existed after forward
+    step k (those created later lie past the arena counts of the next forward
+    launch): the reverse sweep scans fewer entries than M times the largest
+    state, gradient calls repeat bit for bit (the log records and checkpoints
+    are found by determinant), the state after the call is |Psi_0>, and the
+    results match the oracle."""
     name, n_orb, n_occ, sigma, seed, nf, thr, ck = case
-    say(f"[case] shrink {name} prec={prec} thr={thr} ckpt={ck}")
+    say(f"[case] reverse scans {name} prec={prec} thr={thr} ckpt={ck}")
     h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed, nf)
     nq = 2 * n_orb
     cap = capacity_for(n_orb, n_occ)
-    out = {}
-    for shrink in ("0", "1"):
-        monkeypatch.setenv("SWC_TABLE_MIN", "64")
-        monkeypatch.setenv("SWC_SHRINK", shrink)
-        s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=1, max_factors=exc.shape[0])
-        if ck:
-            s.set_checkpoints(ck, cap)
-        s.build_state()
-        reps = []
-        for _ in range(2):
-            E, g = s.energy_and_grad(theta, exc, thr, h1, h2)
-            reps.append((E.cpu().numpy().tobytes(), g.cpu().numpy().tobytes()))
-            st = s.stats()
-        assert reps[0] == reps[1]
-        # the state after the call is |Psi_0> again
-        d, a = s.get_state(0)
-        assert d.tolist() == [hf] and a.tolist() == [1.0]
-        out[shrink] = (reps[0], st)
-        s.close()
-    st0, st1 = out["0"][1], out["1"][1]
-    say(f"  shrinks {st1['shrinks']}, reverse slots scanned {st0['rev_slots_scanned']} -> "
-        f"{st1['rev_slots_scanned']}, log records {st1['log_records']}")
-    assert st0["shrinks"] == 0 and st1["shrinks"] >= 1
-    assert st1["rev_slots_scanned"] < st0["rev_slots_scanned"]
-    assert st0["fwd_slots_scanned"] == st1["fwd_slots_scanned"] > 0
-    assert out["0"][0] == out["1"][0]
+    M = exc.shape[0]
+    monkeypatch.setenv("SWC_TABLE_MIN", "64")
+    s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=1, max_factors=M)
+    if ck:
+        s.set_checkpoints(ck, cap)
+    s.track_live(True)
+    s.build_state()
+    reps = []
+    for _ in range(2):
+        E, g = s.energy_and_grad(theta, exc, thr, h1, h2)
+        reps.append((E.cpu().numpy().tobytes(), g.cpu().numpy().tobytes()))
+    st = s.stats()
+    assert reps[0] == reps[1]
+    d, a = s.get_state(0)
+    assert d.tolist() == [hf] and a.tolist() == [1.0]
+    s.apply_ucc(theta, exc, thr)  # the entries a forward sweep ends with, and its visits
+    st_f = s.stats()
+    n_end = st_f["slots_used"]
+    s.close()
+    say(f"  forward entries scanned {st['fwd_slots_scanned']}, reverse {st['rev_slots_scanned']}, "
+        f"entries at the end {n_end}, log records {st['log_records']}")
+    # a two-factor launch scans each entry once for two steps of visits
+    assert st_f["fwd_slots_scanned"] == st["fwd_slots_scanned"]
+    assert 2 * st["fwd_slots_scanned"] >= st_f["det_updates"] > 0
+    assert st["fwd_slots_scanned"] <= st["rev_slots_scanned"] < M * n_end
+    assert st["shrinks"] == 0
     orc.set_nearcut_window(1e-5)
     E_ref, g_ref, nc = orc.energy_and_grad(nq, [hf], [1.0], exc, theta[0], thr, h1, h2)
     assert nc == 0
-    E = np.frombuffer(out["1"][0][0], dtype=np.float64)[0]
-    g = np.frombuffer(out["1"][0][1], dtype=np.float64)
+    E = np.frombuffer(reps[0][0], dtype=np.float64)[0]
+    g = np.frombuffer(reps[0][1], dtype=np.float64)
     assert abs(E - E_ref) <= TOL[prec]["E"]
     assert np.max(np.abs(g - g_ref)) <= TOL[prec]["g"]
 
@@ -584,4 +593,58 @@ def test_topk_truncation_vs_oracle(swc, orc, monkeypatch, case, prec, mode):
     assert s.stats()["n_live"] > len(d_ref)  # the truncation was active
     with pytest.raises(swc.SwcError):
         s.set_topk(10, 11)
+    s.close()
+
+
+# ---------------------------------------------------------------- kernel builds used at full size
+BUILD_CASES = [
+    # (name, n_orb, n_occ, sigma, seed, n_factors, threshold, capacity, table_min, grid cap, builds expected)
+    # an index of 2^23 slots: the five-wave forward build (many passes per lane)
+    ("fwd_wide_q16_thr", 8, 4, 0.1, 105, None, 1e-4, 1 << 23, 1 << 23, None, ("BUILD_FWD_WIDE", "BUILD_REV")),
+    # threshold 0, one block per arena over an index of 2^16 slots: the
+    # two-factor kernels that preload one index slot per probe
+    ("fused_ph1_q16", 8, 4, 0.1, 104, None, 0.0, 1 << 16, 1 << 16, "64", ("BUILD_FWD2", "BUILD_REV2")),
+    ("fused_ph1_q20_pre", 10, 5, 0.05, 106, 160, 0.0, 1 << 17, 1 << 17, "64", ("BUILD_FWD2", "BUILD_REV2")),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", BUILD_CASES, ids=[c[0] for c in BUILD_CASES])
+def test_full_size_builds_vs_oracle(swc, orc, monkeypatch, case, prec):
+    """The kernel builds the large workloads run (the five-wave forward build
+    for states scanned in many passes; the two-factor kernels that preload one
+    index slot per probe) forced on small instances and checked against the
+    oracle: the state, the live count of every step, E and the gradient.  The
+    builds that ran are read back from the statistics."""
+    name, n_orb, n_occ, sigma, seed, nf, thr, cap, tmin, grid, builds = case
+    say(f"[case] builds {name} prec={prec}")
+    h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed, nf)
+    nq = 2 * n_orb
+    monkeypatch.setenv("SWC_TABLE_MIN", str(tmin))
+    if grid:
+        monkeypatch.setenv("SWC_GRID", grid)
+    else:
+        monkeypatch.delenv("SWC_GRID", raising=False)
+    s = swc.Solver(nq, n_occ, n_occ, cap, prec=prec, batch=1, max_factors=exc.shape[0])
+    s.track_live(True)
+    s.build_state()
+    tol = TOL[prec]
+    orc.set_nearcut_window(1e-5)
+    d_ref, a_ref, nc, du_ref = orc.apply_ucc(nq, [hf], [1.0], exc, theta[0], thr)
+    E_ref, g_ref, _ = orc.energy_and_grad(nq, [hf], [1.0], exc, theta[0], thr, h1, h2)
+    assert nc == 0
+    n_ref = orc.live_trajectory(nq, [hf], [1.0], exc, theta[0], thr)
+    E, g = s.energy_and_grad(theta, exc, thr, h1, h2)
+    st = s.stats()
+    got = st["kernel_builds"]
+    say(f"  builds {got:#x}")
+    for bname in builds:
+        assert got & getattr(swc, bname), (bname, hex(got))
+    assert abs(E.cpu().numpy()[0] - E_ref) <= tol["E"]
+    assert np.max(np.abs(g.cpu().numpy()[0] - g_ref)) <= tol["g"]
+    assert np.array_equal(s.live_counts(0), n_ref)
+    s.apply_ucc(theta, exc, thr)
+    assert s.stats()["det_updates"] == du_ref
+    d, a = s.get_state(0)
+    compare_states(d, a, d_ref, a_ref, tol["amp"])
     s.close()
