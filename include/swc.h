@@ -137,7 +137,6 @@ typedef struct {
 /* Sweep kernel builds (swc_stats.kernel_builds). */
 enum {
   SWC_BUILD_FWD = 1,          /* one factor per launch, forward */
-  SWC_BUILD_FWD_WIDE = 2,     /* the same, built for five resident waves (states scanned in many passes) */
   SWC_BUILD_FWD_ENT = 4,      /* the same, with the entropy sums */
   SWC_BUILD_FWD2 = 8,         /* two factors per launch (threshold 0), forward, home index slot preloaded */
   SWC_BUILD_FWD2_PRE = 16,    /* the same, four index slots per probe preloaded (one-pass states) */

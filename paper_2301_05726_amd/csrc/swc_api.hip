@@ -271,12 +271,8 @@ struct swc_ctx {
   // res_fwd / res_rev: resident blocks of k_fwd / k_rev on the whole device.
   int grid = NA;
   int grid_fs = NA, grid_rs = NA;
-  int res_fwd = 0, res_rev = 0, res_fwd5 = 0;
+  int res_fwd = 0, res_rev = 0;
   int res_f2w = 0, res_r2w = 0;  // resident blocks (all members) of the wide two-factor kernels
-  // forward steps use the five-wave build of k_fwd when the state takes more
-  // than one pass of the resident lanes (a latency-bound one-pass state runs
-  // faster without its register spills)
-  int fwd_wide = 0;
   uint64_t per_arena = 0;  // entries per arena the grids are sized for
   // persistent (cooperative) sweeps, one launch per sweep: opt-in with
   // SWC_SWEEP=persistent (per-step launches are faster on MI355X: a
@@ -354,10 +350,7 @@ void set_table(swc_ctx* c, uint64_t Hn) {
   int rmax = MAX_ARENA_BLOCKS;
   if (c->grid_override > 0) rmax = std::max(1, c->grid_override / NA);
   c->grid = arena_grid(c->per_arena, 1, rmax);
-  c->fwd_wide = (c->res_fwd > 0 && c->res_fwd5 > 0 &&
-                 c->per_arena > static_cast<uint64_t>(c->res_fwd / NA) * 256 * SCAN_U) ? 1 : 0;
-  const int rf = c->fwd_wide ? c->res_fwd5 : c->res_fwd;
-  c->grid_fs = arena_grid(c->per_arena, SCAN_U, std::min(rmax, rf > 0 ? rf / NA : rmax));
+  c->grid_fs = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_fwd > 0 ? c->res_fwd / NA : rmax));
   c->grid_rs = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_rev > 0 ? c->res_rev / NA : rmax));
 }
 
@@ -539,7 +532,7 @@ int64_t fwd_plan(const swc_ctx* c, int64_t k0, int64_t k1, double thr, uint64_t 
       *builds |= wide2(c, c->res_f2w) ? SWC_BUILD_FWD2_PRE : SWC_BUILD_FWD2;
       k += 2;
     } else {
-      *builds |= c->entropy ? SWC_BUILD_FWD_ENT : c->fwd_wide ? SWC_BUILD_FWD_WIDE : SWC_BUILD_FWD;
+      *builds |= c->entropy ? SWC_BUILD_FWD_ENT : SWC_BUILD_FWD;
       k += 1;
     }
   }
@@ -570,7 +563,7 @@ void issue_fwd(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint6
       k += 2;
     } else {
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, c->grid_fs, c->fwd_wide, st);
+                    log_on, lim, c->B, c->grid_fs, st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid, st);
       k += 1;
@@ -618,11 +611,11 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
       c->fwd_launches += fwd_plan(c, k0, k1, thr, lim, &c->builds);
       return SWC_OK;
     }
-    c->builds |= c->entropy ? SWC_BUILD_FWD_ENT : c->fwd_wide ? SWC_BUILD_FWD_WIDE : SWC_BUILD_FWD;
+    c->builds |= c->entropy ? SWC_BUILD_FWD_ENT : SWC_BUILD_FWD;
     for (int64_t k = k0; k <= k1; ++k) {  // every launch timed: one step per launch
       (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, c->grid_fs, c->fwd_wide, c->st);
+                    log_on, lim, c->B, c->grid_fs, c->st);
       (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid,
@@ -1148,10 +1141,8 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     // resident step blocks, shared by the batch members (grid.y = batch)
     const int sf = prec == SWC_FP32 ? resident_blocks_per_cu<float>(2) : resident_blocks_per_cu<double>(2);
     const int sr = prec == SWC_FP32 ? resident_blocks_per_cu<float>(3) : resident_blocks_per_cu<double>(3);
-    const int s5 = prec == SWC_FP32 ? resident_blocks_per_cu<float>(4) : resident_blocks_per_cu<double>(4);
     c->res_fwd = std::max(1, sf * ncu / batch);
     c->res_rev = std::max(1, sr * ncu / batch);
-    c->res_fwd5 = std::max(1, s5 * ncu / batch);
     c->res_f2w = (prec == SWC_FP32 ? resident_blocks_per_cu<float>(5) : resident_blocks_per_cu<double>(5)) * ncu;
     c->res_r2w = (prec == SWC_FP32 ? resident_blocks_per_cu<float>(6) : resident_blocks_per_cu<double>(6)) * ncu;
     set_table(c, c->H);  // step grids with the resident limits

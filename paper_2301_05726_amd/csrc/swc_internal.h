@@ -278,8 +278,8 @@ void launch_sweep_end(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M,
                       const Sync* sy, int fold_only, hipStream_t st);
 void launch_sync_reset(Sync* sy, int clear_timeout, hipStream_t st);
 // co-resident blocks per CU of the persistent forward (which=0) / reverse (1)
-// sweep, of the one-factor forward (2; 4: the five-wave build) / reverse (3)
-// step kernels, and of the wide two-factor forward (5) / reverse (6) kernels
+// sweep, of the one-factor forward (2) / reverse (3) step kernels, and of the
+// wide two-factor forward (5) / reverse (6) kernels
 template <class T>
 int resident_blocks_per_cu(int which);
 template <class T>
@@ -292,12 +292,11 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
                             hipStream_t st);
 // occ_lim: a step whose start finds a member's entries above it does not run
 // and stops the sweep (Counters::stop) so the host can grow the index;
-// NO_LIMIT for an index at full capacity.  wide: the kernel built for five
-// resident waves per SIMD (states scanned in many passes)
+// NO_LIMIT for an index at full capacity
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
-                int wide, hipStream_t st);
+                hipStream_t st);
 template <class T>
 void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 int k, int B, int grid, hipStream_t st);

@@ -1225,13 +1225,9 @@ __device__ __forceinline__ void restore_step(const Tab& t, const LogArr& lg, con
 }
 
 // one launch per step.  ENT: the entropy sums are tracked (a separate
-// instantiation keeps their registers out of the common case).  MINW: waves
-// per SIMD the register allocation must allow; 5 (a few registers spill) for
-// states scanned in many passes, where more resident waves hide more memory
-// latency, 1 (no constraint) for states one resident wave round covers,
-// where each wave's own latency counts.
-template <class T, bool ENT, int MINW>
-__global__ __launch_bounds__(BLK, MINW) void k_fwd(Tab t, const FacMask* __restrict__ fac,
+// instantiation keeps their registers out of the common case).
+template <class T, bool ENT>
+__global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ fac,
                                                    const Trig* __restrict__ trig, int64_t ld, StepArr sa,
                                                    Counters* cnt, LogArr lg, int k, double thr, int prune_all,
                                                    int log_on, uint64_t occ_lim) {
@@ -2597,9 +2593,8 @@ int resident_blocks_per_cu(int which) {
   switch (which) {
     case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_sweep<T>, BLK, 0); break;
     case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev_sweep<T>, BLK, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd<T, false, 1>, BLK, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd<T, false>, BLK, 0); break;
     case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev<T>, BLK, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd<T, false, 5>, BLK, 0); break;
     case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd2<T, PH2>, BLK, 0); break;
     case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev2<T, PH2>, BLK, 0); break;
     default: break;
@@ -2647,15 +2642,12 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
-                int wide, hipStream_t st) {
+                hipStream_t st) {
   if (sa.ea)
-    hipLaunchKernelGGL((k_fwd<T, true, 1>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
-                       prune_all, log_on, occ_lim);
-  else if (wide)
-    hipLaunchKernelGGL((k_fwd<T, false, 5>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
+    hipLaunchKernelGGL((k_fwd<T, true>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
                        prune_all, log_on, occ_lim);
   else
-    hipLaunchKernelGGL((k_fwd<T, false, 1>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
+    hipLaunchKernelGGL((k_fwd<T, false>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
                        prune_all, log_on, occ_lim);
 }
 
@@ -3096,7 +3088,7 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
                                       int64_t, int, hipStream_t);                                                  \
   template void launch_sweep_begin<T>(const Tab&, const StepArr&, Counters*, int64_t, int, int, hipStream_t);     \
   template void launch_fwd<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*,        \
-                              const LogArr&, int, double, int, int, uint64_t, int, int, int, hipStream_t);         \
+                              const LogArr&, int, double, int, int, uint64_t, int, int, hipStream_t);              \
   template void launch_rev<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,   \
                               int, int, hipStream_t);                                                              \
   template void launch_log_restore<T>(const Tab&, const LogArr&, const StepArr&, int, int, uint32_t,              \

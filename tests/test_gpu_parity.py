@@ -599,8 +599,8 @@ def test_topk_truncation_vs_oracle(swc, orc, monkeypatch, case, prec, mode):
 # ---------------------------------------------------------------- kernel builds used at full size
 BUILD_CASES = [
     # (name, n_orb, n_occ, sigma, seed, n_factors, threshold, capacity, table_min, grid cap, builds expected)
-    # an index of 2^23 slots: the five-wave forward build (many passes per lane)
-    ("fwd_wide_q16_thr", 8, 4, 0.1, 105, None, 1e-4, 1 << 23, 1 << 23, None, ("BUILD_FWD_WIDE", "BUILD_REV")),
+    # one block per arena: the one-factor builds take many passes per lane
+    ("fwd_passes_q16_thr", 8, 4, 0.1, 105, None, 1e-4, 1 << 16, 1 << 16, "64", ("BUILD_FWD", "BUILD_REV")),
     # threshold 0, one block per arena over an index of 2^16 slots: the
     # two-factor kernels that preload one index slot per probe
     ("fused_ph1_q16", 8, 4, 0.1, 104, None, 0.0, 1 << 16, 1 << 16, "64", ("BUILD_FWD2", "BUILD_REV2")),
@@ -611,11 +611,11 @@ BUILD_CASES = [
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("case", BUILD_CASES, ids=[c[0] for c in BUILD_CASES])
 def test_full_size_builds_vs_oracle(swc, orc, monkeypatch, case, prec):
-    """The kernel builds the large workloads run (the five-wave forward build
-    for states scanned in many passes; the two-factor kernels that preload one
-    index slot per probe) forced on small instances and checked against the
-    oracle: the state, the live count of every step, E and the gradient.  The
-    builds that ran are read back from the statistics."""
+    """The kernel builds and launch shapes the large workloads run (one-factor
+    steps whose lanes take many passes; the two-factor kernels that preload
+    one index slot per probe) forced on small instances and checked against
+    the oracle: the state, the live count of every step, E and the gradient.
+    The builds that ran are read back from the statistics."""
     name, n_orb, n_occ, sigma, seed, nf, thr, cap, tmin, grid, builds = case
     say(f"[case] builds {name} prec={prec}")
     h1, h2, exc, theta, hf = small_problem(n_orb, n_occ, sigma, seed, nf)
