@@ -159,7 +159,7 @@ enum {
  * room for 1.125 * capacity entries in all); the per-factor scans read the
  * entries only.  The index maps a determinant to its entry; it starts small
  * after every reset to |Psi_0> and is rebuilt larger (x2 or more) during a
- * forward sweep when the entries near a growth limit (45% of its slots).
+ * forward sweep when the entries near a growth limit (22.5% of its slots).
  * Returns 0 for invalid arguments.
  */
 size_t swc_workspace_bytes(int n_qubits, uint64_t capacity, int prec, int batch, int64_t max_factors,

@@ -345,7 +345,7 @@ int arena_grid(uint64_t per, int items, int rmax) {
 // Make an index of Hn slots the current one (the grids follow its size).
 void set_table(swc_ctx* c, uint64_t Hn) {
   c->tab.H = Hn;
-  // the entries an index of Hn slots holds at its growth limit (45%), per arena
+  // the entries an index of Hn slots holds when it runs at 45%, per arena
   c->per_arena = (Hn / 20 * 9 + NA - 1) / NA;
   int rmax = MAX_ARENA_BLOCKS;
   if (c->grid_override > 0) rmax = std::max(1, c->grid_override / NA);
@@ -363,8 +363,10 @@ int wide2(const swc_ctx* c, int resident) {
 
 // Entries above which a forward step does not run and stops the sweep for a
 // growth of the index: a step that runs at most doubles the entries, so the
-// index never passes 2 x 0.45 = 90% occupancy.
-uint64_t occ_limit(const swc_ctx* c) { return c->tab.H < c->H ? c->tab.H / 20 * 9 : NO_LIMIT; }
+// index never passes 2 x 0.225 = 45% occupancy.  (The index is only probed,
+// never scanned: a sparser one costs memory, not scan time, and its probes
+// end in the first slots loaded.)
+uint64_t occ_limit(const swc_ctx* c) { return c->tab.H < c->H ? c->tab.H / 40 * 9 : NO_LIMIT; }
 
 // Smallest index, at least Hmin, that holds `need` entries at <= 10% load.
 uint64_t table_size_for(const swc_ctx* c, uint64_t need, uint64_t Hmin) {
@@ -392,7 +394,7 @@ int reindex_to(swc_ctx* c, uint64_t Hn) {
 int grow_table(swc_ctx* c, uint64_t need) {
   if (c->persistent || c->tab.H >= c->H) return SWC_OK;
   uint64_t Hn = 2 * c->tab.H;
-  while (Hn < c->H && need > Hn / 20 * 9) Hn <<= 1;
+  while (Hn < c->H && need > Hn / 40 * 9) Hn <<= 1;
   return reindex_to(c, std::min(Hn, c->H));
 }
 

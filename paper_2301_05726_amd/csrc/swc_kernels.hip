@@ -316,6 +316,8 @@ __device__ __forceinline__ int64_t find_slot_from(const Idx* __restrict__ ix, ui
 
 // find_slot_from with the first PH slots from home already loaded
 // (pre[j] = ix[home + j]): an answer within them costs no further round trip.
+// The sweep steps load four (64 bytes) per probe: with the index at most 45%
+// full, a probe rarely runs past them, and a wave waits for its slowest lane.
 template <int PH>
 __device__ __forceinline__ int64_t find_slot_pre(const Idx* __restrict__ ix, uint64_t H, uint64_t key, uint64_t home,
                                                  const Idx (&pre)[PH], uint64_t* first_free, Idx* out) {
@@ -850,7 +852,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     if (jw + pass < ns) load_pass<T>(v, ebase, ns, j0 + pass, stride, nxt);
     // the home index slots of this pass's partners are then loaded together
     uint64_t home[SCAN_U];
-    Idx hv[SCAN_U];
+    Idx hv[SCAN_U][4];
     bool act[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
@@ -878,7 +880,8 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       }
       act[u] = true;
       home[u] = mix64(me.key ^ pm) & (v.H - 1);
-      hv[u] = v.ix[home[u]];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hv[u][i] = v.ix[(home[u] + i) & (v.H - 1)];
     }
     // resolve the probes, then load the partners' entries together
     uint64_t free_start[SCAN_U], pe[SCAN_U];
@@ -890,7 +893,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       free_start[u] = v.H;
       if (!act[u]) continue;
       Idx iv;
-      found[u] = find_slot_from(v.ix, v.H, mes[u].key ^ pm, home[u], hv[u], &free_start[u], &iv) >= 0;
+      found[u] = find_slot_pre<4>(v.ix, v.H, mes[u].key ^ pm, home[u], hv[u], &free_start[u], &iv) >= 0;
       if (found[u]) {
         if (iv.id == NO_ID) {  // cannot happen: only this lane creates its partner
           flags |= F_INCONSISTENT;
@@ -1065,7 +1068,7 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
     for (int u = 0; u < SCAN_U; ++u) mes[u] = nxt[u];
     if (j0 + pass < ns) load_pass<T>(v, ebase, ns, j0 + pass, stride, nxt);
     uint64_t home[SCAN_U];
-    Idx hv[SCAN_U];
+    Idx hv[SCAN_U][4];
     T lms[SCAN_U];
     bool act[SCAN_U];
 #pragma unroll
@@ -1092,7 +1095,8 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
       // loaded only by the pair's owner once the partner is found
       lms[u] = v.lam_pre(e);
       home[u] = mix64(me.key ^ pm) & (v.H - 1);
-      hv[u] = v.ix[home[u]];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hv[u][i] = v.ix[(home[u] + i) & (v.H - 1)];
     }
     // resolve the probes, then load the partners' entries together
     bool found[SCAN_U];
@@ -1104,7 +1108,7 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
       if (!act[u]) continue;
       uint64_t ff = v.H;
       Idx iv;
-      found[u] = find_slot_from(v.ix, v.H, mes[u].key ^ pm, home[u], hv[u], &ff, &iv) >= 0;
+      found[u] = find_slot_pre<4>(v.ix, v.H, mes[u].key ^ pm, home[u], hv[u], &ff, &iv) >= 0;
       if (found[u]) {
         if (iv.id == NO_ID) {
           flags |= F_INCONSISTENT;

@@ -16,6 +16,10 @@
         short text table (per-kernel calls, total and mean duration, or mean
         counter value per dispatch).
 
+    python -m paper_2301_05726_amd.profiling reduce <csv> <out.csv>
+        Sum a rocprofv3 counter_collection.csv into one row per kernel and
+        counter (the input of `traffic` may be either form).
+
     python -m paper_2301_05726_amd.profiling traffic --fetch <csv> --write <csv>
             --cal-fetch <csv> --cal-write <csv> --cal-mib M --cal-reps R [--cmd "..."]
         HBM bytes per dispatch of each kernel: FETCH_SIZE and WRITE_SIZE (KiB
@@ -141,15 +145,38 @@ def summarize(path: str, top: int, cmd: str | None) -> None:
 
 
 def _mean_per_kernel(path: str, counter: str) -> dict:
+    """Mean counter value per dispatch of each kernel, from a rocprofv3
+    counter_collection.csv or from its `reduce`d form."""
     acc = defaultdict(lambda: [0.0, 0])
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name", counter) != counter:
             continue
         name = _short(r.get("Kernel_Name", r.get("Kernel-Name", "?")))
         key = name.replace("swc::", "").split("<")[0]
+        if "Counter_Sum" in r:
+            acc[key][0] += float(r["Counter_Sum"])
+            acc[key][1] += int(r["Dispatches"])
+        else:
+            acc[key][0] += float(r.get("Counter_Value", 0.0))
+            acc[key][1] += 1
+    return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
+
+
+def reduce_counters(path: str, out: str) -> None:
+    """Sum a counter_collection.csv (one row per dispatch and counter) into
+    one row per kernel and counter, so a run of many dispatches keeps a
+    small file."""
+    acc = defaultdict(lambda: [0.0, 0])
+    for r in csv.DictReader(open(path)):
+        key = (r.get("Kernel_Name", r.get("Kernel-Name", "?")), r.get("Counter_Name", "?"))
         acc[key][0] += float(r.get("Counter_Value", 0.0))
         acc[key][1] += 1
-    return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
+    with open(out, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Counter_Name", "Counter_Sum", "Dispatches"])
+        for (k, c), (v, n) in sorted(acc.items()):
+            w.writerow([k, c, repr(v), n])
+    print(f"{path}: {sum(n for _, n in acc.values())} rows -> {len(acc)} kernels/counters in {out}")
 
 
 def sources_sha() -> str:
@@ -208,6 +235,9 @@ def main(argv=None) -> int:
         t.add_argument(f, required=True)
     t.add_argument("--cal-mib", type=int, default=512)
     t.add_argument("--cmd", action="append")
+    rd = sub.add_parser("reduce")
+    rd.add_argument("csv")
+    rd.add_argument("out")
     a = ap.parse_args(argv)
     if a.sub == "copy":
         copy_kernel(a.mib, a.reps)
@@ -215,6 +245,8 @@ def main(argv=None) -> int:
         peaks(a.gib, a.reps)
     elif a.sub == "traffic":
         traffic(a)
+    elif a.sub == "reduce":
+        reduce_counters(a.csv, a.out)
     else:
         summarize(a.csv, a.top, a.cmd)
     return 0
