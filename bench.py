@@ -93,6 +93,8 @@ def main() -> int:
     ap.add_argument("--prec", default="fp64", choices=["fp32", "fp64"])
     ap.add_argument("--fd-params", type=int, default=32)
     ap.add_argument("--no-fd", action="store_true")
+    ap.add_argument("--fd-max-s", type=float, default=40.0,
+                    help="time budget of the sampled finite-difference parameters (at least two are timed)")
     ap.add_argument("--fd-full-max-s", type=float, default=60.0,
                     help="run the finite differences over every parameter when the sampled estimate is below this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -303,14 +305,18 @@ def main() -> int:
         if args.sigma_scratch_gib > 0:  # the same sigma method as the adjoint run
             sf.set_sigma_scratch(int(args.sigma_scratch_gib * (1 << 30)), mode=args.sigma_mode)
         sf.build_state()
-        idx = synth.fd_subset(M, args.fd_params, 3000 + wl.cfg)
         h = 1e-5
         tp = theta[0:1].clone()
+        w0 = time.perf_counter()
         sf.apply_ucc(tp, p.exc, wl.threshold)
         sf.energy(h1, h2)
         sf.build_state()
         torch.cuda.synchronize()
-        progress("finite differences: warm-up evaluation done")
+        t_eval = time.perf_counter() - w0
+        # as many sampled parameters as fit the time budget (at least two)
+        n_fd = max(2, min(args.fd_params, int(args.fd_max_s / (2.0 * t_eval))))
+        idx = synth.fd_subset(M, n_fd, 3000 + wl.cfg)
+        progress(f"finite differences: warm-up evaluation done ({t_eval:.2f} s), {n_fd} parameters sampled")
         fd = np.empty(len(idx))
         f0 = time.perf_counter()
         for q, k in enumerate(idx):

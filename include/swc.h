@@ -156,8 +156,9 @@ enum {
  * determinant removed earlier in the sweep that a later factor revives, for
  * the adjoint sweep).
  * The determinants of a state are dense arrays of entries (64 arenas with
- * room for 1.125 * capacity entries in all); the per-factor scans read the
- * entries only.  The index maps a determinant to its entry; it starts small
+ * room for 0.9 * capacity entries in all, so a state that outgrows the
+ * capacity fails with SWC_ECAPACITY while its probes are still short); the
+ * per-factor scans read the entries only.  The index maps a determinant to its entry; it starts small
  * after every reset to |Psi_0> and is rebuilt larger (x2 or more) during a
  * forward sweep when the entries near a growth limit (22.5% of its slots).
  * Returns 0 for invalid arguments.

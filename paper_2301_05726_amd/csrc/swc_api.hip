@@ -55,10 +55,13 @@ constexpr int MAX_SWEEP_BLOCKS = 2048;
 constexpr int MAX_ARENA_BLOCKS = MAX_SWEEP_BLOCKS / NA;
 size_t max_waves() { return static_cast<size_t>(MAX_SWEEP_BLOCKS) * 4; }
 
-// Entries per arena for an index of Hcap slots: the index holds at most 90%
-// of Hcap entries, and the arenas 25% more than an even share of them.
+// Entries per arena for an index of Hcap slots: an even share of 90% of
+// Hcap.  The arenas bound the index's occupancy at full size, where no growth
+// check runs: an entry that finds its arena full fails the sweep with
+// "hash table full" before the index passes about 90% (past that, a linear
+// probe for an absent key grows without bound).
 uint64_t arena_size(uint64_t Hcap) {
-  const uint64_t a = (Hcap / 10 * 9 / NA) * 5 / 4 + 64;
+  const uint64_t a = Hcap / 10 * 9 / NA + 64;
   return std::min<uint64_t>(a, 1ull << ID_POS_BITS);
 }
 

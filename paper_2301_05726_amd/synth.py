@@ -54,7 +54,7 @@ class Workload:
 WORKLOADS = {
     "q8": Workload("q8", 4, 2, 0.05, 0.0, 1 << 8, 1, 1),
     "q20": Workload("q20", 10, 5, 0.02, 0.0, 1 << 17, 1, 2),
-    "q32": Workload("q32", 16, 8, 0.01, 1e-6, 1 << 24, 1, 3),
+    "q32": Workload("q32", 16, 8, 0.01, 1e-6, 1 << 26, 1, 3),
     "q48": Workload("q48", 24, 12, 0.005, 1e-5, 1 << 26, 8, 4),
     "q64": Workload("q64", 32, 16, 0.003, 1e-4, 1 << 28, 1, 5),
 }

@@ -100,3 +100,29 @@ def test_workload_prefix_vs_oracle(swc, orc, case, prec):
         assert dg <= tol["g"]
     assert du_gpu == du_ref
     s.close()
+
+
+def test_state_beyond_capacity_fails_promptly(swc):
+    """The 20-qubit workload reaches 63,504 determinants; with a capacity of
+    2^16 slots (room for 0.9 x 65,536 = 58,982 entries) the forward sweep must
+    end with SWC_ECAPACITY, and soon: the entry arenas fill before the index
+    passes about 90%, so no probe runs the length of a full index."""
+    import time
+    from paper_2301_05726_amd import synth
+    wl = synth.WORKLOADS["q20"]
+    p = synth.make_problem(wl, batch=1)
+    say("[case] q20 full at capacity 2^16 (too small)")
+    s = swc.Solver(wl.n_qubits, wl.n_occ, wl.n_occ, 1 << 16, prec=0, batch=1, max_factors=p.M)
+    s.build_state()
+    t0 = time.perf_counter()
+    with pytest.raises(swc.SwcError) as e:
+        s.apply_ucc(p.theta, p.exc, wl.threshold)
+    dt = time.perf_counter() - t0
+    say(f"  ECAPACITY after {dt:.2f} s: {e.value}")
+    assert e.value.code == swc.ECAPACITY
+    assert dt < 20.0
+    # the context stays usable: a state that fits runs after the failure
+    s.build_state()
+    s.apply_ucc(p.theta[:, :50], p.exc[:50], wl.threshold)
+    assert s.stats()["n_live"] > 1
+    s.close()
