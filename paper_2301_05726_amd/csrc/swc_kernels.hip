@@ -247,10 +247,16 @@ __device__ __forceinline__ Red block_reduce(Red r) {
 
 // Linear probe for `key`; on a hit returns the index slot and its contents
 // (one whole-slot load per probe step), else -1 and the first EMPTY slot seen.
+// The linear probe for `key` starts at the first slot of its 4-slot group
+// (64 bytes, one aligned memory segment), so the first load of a probe brings
+// in the whole group: with the index at most 45% full, nearly every probe
+// ends inside it.  (H is a power of two >= 64.)
+__device__ __forceinline__ uint64_t home_slot(uint64_t key, uint64_t H) { return mix64(key) & (H - 1) & ~3ull; }
+
 __device__ __forceinline__ int64_t find_slot(const Idx* __restrict__ ix, uint64_t H, uint64_t key,
                                              uint64_t* first_free, Idx* out) {
   const uint64_t mask = H - 1;
-  uint64_t s = mix64(key) & mask;
+  uint64_t s = home_slot(key, H);
   for (uint64_t i = 0; i < H; ++i, s = (s + 1) & mask) {
     const Idx v = ix[s];
     if (v.key == key) {
@@ -316,8 +322,8 @@ __device__ __forceinline__ int64_t find_slot_from(const Idx* __restrict__ ix, ui
 
 // find_slot_from with the first PH slots from home already loaded
 // (pre[j] = ix[home + j]): an answer within them costs no further round trip.
-// The sweep steps load four (64 bytes) per probe: with the index at most 45%
-// full, a probe rarely runs past them, and a wave waits for its slowest lane.
+// The sweep steps load the whole 4-slot group of the home: a probe rarely
+// runs past it, and a wave waits for its slowest lane.
 template <int PH>
 __device__ __forceinline__ int64_t find_slot_pre(const Idx* __restrict__ ix, uint64_t H, uint64_t key, uint64_t home,
                                                  const Idx (&pre)[PH], uint64_t* first_free, Idx* out) {
@@ -534,7 +540,7 @@ __global__ void k_insert_list(Tab t, Counters* cnt, const uint64_t* __restrict__
     v.sl[e].meta = 0u;
     v.born(e) = 0u;
     v.lam(e) = T(0);
-    if (!index_insert(v.ix, v.H, key, mix64(key) & (v.H - 1), entry_id(a, pos))) {
+    if (!index_insert(v.ix, v.H, key, home_slot(key, v.H), entry_id(a, pos))) {
       atomicOr(&cnt[b].flags, F_TABLE_FULL);
       continue;
     }
@@ -879,7 +885,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
         continue;
       }
       act[u] = true;
-      home[u] = mix64(me.key ^ pm) & (v.H - 1);
+      home[u] = home_slot(me.key ^ pm, v.H);
 #pragma unroll
       for (int i = 0; i < 4; ++i) hv[u][i] = v.ix[(home[u] + i) & (v.H - 1)];
     }
@@ -1094,7 +1100,7 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
       // and the partner's home index slot; the partner's adjoint value is
       // loaded only by the pair's owner once the partner is found
       lms[u] = v.lam_pre(e);
-      home[u] = mix64(me.key ^ pm) & (v.H - 1);
+      home[u] = home_slot(me.key ^ pm, v.H);
 #pragma unroll
       for (int i = 0; i < 4; ++i) hv[u][i] = v.ix[(home[u] + i) & (v.H - 1)];
     }
@@ -1369,7 +1375,7 @@ __global__ __launch_bounds__(BLK) void k_fwd2(Tab t, const FacMask* __restrict__
       Idx hv[4][PH];
 #pragma unroll
       for (int q = 1; q < 4; ++q) {
-        home[q] = mix64(Q.q[q]) & mask;
+        home[q] = home_slot(Q.q[q], v.H);
         if (Q.comp & (1u << q))
 #pragma unroll
           for (int i = 0; i < PH; ++i) hv[q][i] = v.ix[(home[q] + i) & mask];
@@ -1548,7 +1554,7 @@ __global__ __launch_bounds__(BLK) void k_rev2(Tab t, const FacMask* __restrict__
     Idx hv[4][PH];
 #pragma unroll
     for (int q = 1; q < 4; ++q) {
-      home[q] = mix64(Q.q[q]) & mask;
+      home[q] = home_slot(Q.q[q], v.H);
       if (Q.comp & (1u << q))
 #pragma unroll
         for (int i = 0; i < PH; ++i) hv[q][i] = v.ix[(home[q] + i) & mask];
@@ -2333,14 +2339,15 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
       uint64_t J[SGU], home[SGU];
       int rank[SGU];
       unsigned int mv[SGU];
-      Idx hv[SGU];
+      Idx hv[SGU][4];
 #pragma unroll
       for (int u = 0; u < SGU; ++u) {
         const int e = e0 + u * SG;
         if (e < total) {
           J[u] = excite(I, e, L, tri, &rank[u], &mv[u]);
-          home[u] = mix64(J[u]) & (H - 1);
-          hv[u] = v.ix[home[u]];
+          home[u] = home_slot(J[u], H);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) hv[u][q] = v.ix[home[u] + q];
         }
       }
       // resolve the index probes, then load the entries found together
@@ -2352,7 +2359,7 @@ __global__ __launch_bounds__(BLK) void k_sigma(Tab t, Compact cp, const Counters
         if (e0 + u * SG >= total) continue;
         uint64_t ff;
         Idx iv;
-        if (find_slot_from(v.ix, H, J[u], home[u], hv[u], &ff, &iv) >= 0 && iv.id != NO_ID) {
+        if (find_slot_pre<4>(v.ix, H, J[u], home[u], hv[u], &ff, &iv) >= 0 && iv.id != NO_ID) {
           hit[u] = true;
           pe[u] = v.off(iv.id);
         }
@@ -2434,7 +2441,7 @@ __global__ void k_reindex(Tab t, Counters* cnt) {
   const uint64_t n = t.ac[b * NA + a];
   for (uint64_t j = scan_rank() * BLK + threadIdx.x; j < n; j += scan_blocks() * BLK) {
     const uint64_t key = v.sl[a * v.A + j].key;
-    if (!index_insert(v.ix, v.H, key, mix64(key) & (v.H - 1), entry_id(a, j))) atomicOr(&cnt[b].flags, F_TABLE_FULL);
+    if (!index_insert(v.ix, v.H, key, home_slot(key, v.H), entry_id(a, j))) atomicOr(&cnt[b].flags, F_TABLE_FULL);
   }
   if (b == 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[0].stop = ~0u;
 }
