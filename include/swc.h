@@ -309,6 +309,33 @@ const char* swc_last_error(void);
 void swc_destroy(swc_ctx* ctx);
 
 /*
+ * For callers that cannot allocate device memory (code whose launches are
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc): the energy E = <Psi|H|Psi> / <Psi|Psi> of the state with the n
+ * distinct determinants dets[i] and amplitudes amps[i] (device arrays, FP64),
+ * the value swc_build_state + swc_energy give for it (FP64 amplitudes; equal up
+ * to the rounding of the norm, which this call does not apply), without a
+ * context and with no device allocation: the index, entries, compact arrays
+ * and counters live in one static device array of SWC_NOALLOC_SCRATCH_BYTES
+ * that every device the library runs on holds until the process ends.
+ *   n_qubits  even, 2..64 (spin-orbital q = 2p + spin, as everywhere here)
+ *   n         1..SWC_NOALLOC_MAX_DETS determinants; larger states: SWC_EINVAL
+ *   h1, h2    device, n_qubits/2 spatial orbitals, as for swc_energy
+ *   E         device, one double (written on the stream)
+ *   stream    the HIP stream every kernel of the call runs on
+ * The call waits for the stream at its end, to report what the device checks
+ * found: SWC_EINVAL for a repeated determinant, a bit at or above n_qubits, a
+ * non-finite amplitude or a zero norm (E is then meaningless).  Calls on one
+ * device share its array, which keeps the last call's contents (the call
+ * clears what it reads): calls that overlap on one device, from several host
+ * threads or streams, race.
+ */
+#define SWC_NOALLOC_MAX_DETS 65536
+#define SWC_NOALLOC_SCRATCH_BYTES 8133120 /* 7.8 MiB per device */
+int swc_energy_noalloc(int n_qubits, const uint64_t* dets, const double* amps, int64_t n, const double* h1,
+                       const double* h2, double* E, void* stream);
+
+/*
  * Host-only helpers (no device work; usable on machines without a GPU).
  * swc_validate_excitations: SWC_OK or SWC_EINVAL for an excitation list.
  * swc_factor_masks: per factor k writes masks[3k..3k+2] =

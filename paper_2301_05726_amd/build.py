@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libswc.so")
-SOURCES = ["swc_kernels.hip", "swc_api.hip"]
+SOURCES = ["swc_kernels.hip", "swc_api.hip", "swc_noalloc.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 

@@ -27,6 +27,12 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+int swc::report_error(int code, const char* msg) { return fail(code, msg); }
+
+namespace {
+
 #define SWC_HIP(call)                                                                                    \
   do {                                                                                                   \
     hipError_t e_ = (call);                                                                              \

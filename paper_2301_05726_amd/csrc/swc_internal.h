@@ -43,6 +43,7 @@ enum : uint32_t {
   F_BAD_THETA = 4u,
   F_INCONSISTENT = 8u,
   F_TIMEOUT = 16u,  // a grid barrier of a persistent sweep gave up waiting
+  F_BAD_INPUT = 32u,  // a device-side input list failed its check (k_check_list)
 };
 
 // grid-barrier state of the persistent sweeps (one 256-byte line)
@@ -267,6 +268,14 @@ void launch_fill(const Tab& t, int B, hipStream_t st);
 template <class T>
 void launch_insert_list(const Tab& t, Counters* cnt, const uint64_t* keys, const double* amps, int64_t n_fixed,
                         uint64_t stride, int64_t nmax, int B, hipStream_t st);
+// record `msg` as the calling thread's last error (swc_last_error); returns code
+int report_error(int code, const char* msg);
+
+// member 0 only: flag F_BAD_INPUT unless every key of the list just
+// inserted is a determinant of nq qubits, indexed under its own entry, with a
+// finite amplitude
+void launch_check_list(const Tab& t, Counters* cnt, const uint64_t* keys, const double* amps, int64_t n, int nq,
+                       hipStream_t st);
 void launch_trig(const double* theta, Trig* trig, int64_t M, int64_t ld, int B, Counters* cnt, hipStream_t st);
 template <class T>
 void launch_sweep_begin(const Tab& t, const StepArr& sa, Counters* cnt, int64_t M, int B, int grid, hipStream_t st);

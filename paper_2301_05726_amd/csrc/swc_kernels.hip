@@ -2571,6 +2571,33 @@ void launch_fill(const Tab& t, int B, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t);
 }
 
+// Checks a list that k_insert_list put into member 0: every key a
+// determinant of nq qubits, every amplitude finite, and every key indexed
+// under its own entry (a key given twice is found under one of its entries
+// only, so the other fails the check).
+__global__ void k_check_list(Tab t, Counters* cnt, const uint64_t* __restrict__ keys,
+                             const double* __restrict__ amps, int64_t n, int nq) {
+  const uint64_t high = nq >= 64 ? 0ull : (~0ull << nq);
+  bool bad = false;
+  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint64_t key = keys[i];
+    if (key == EMPTY_KEY || (key & high) || !isfinite(amps[i])) {
+      bad = true;
+      continue;
+    }
+    uint64_t ff;
+    Idx iv;
+    if (find_slot(t.idx, t.H, key, &ff, &iv) < 0 || iv.id != entry_id(static_cast<int>(i % NA), i / NA)) bad = true;
+  }
+  if (bad) atomicOr(&cnt[0].flags, F_BAD_INPUT);
+}
+
+void launch_check_list(const Tab& t, Counters* cnt, const uint64_t* keys, const double* amps, int64_t n, int nq,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_check_list, dim3(grid_for(n > 0 ? n : 1, BLK, 4096)), dim3(BLK), 0, st, t, cnt, keys, amps,
+                     n, nq);
+}
+
 template <class T>
 void launch_insert_list(const Tab& t, Counters* cnt, const uint64_t* keys, const double* amps, int64_t n_fixed,
                         uint64_t stride, int64_t nmax, int B, hipStream_t st) {

@@ -184,7 +184,7 @@ def sources_sha() -> str:
     import os
     h = hashlib.sha256()
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-    for f in ("swc_kernels.hip", "swc_api.hip", "swc_internal.h"):
+    for f in ("swc_kernels.hip", "swc_api.hip", "swc_internal.h", "swc_noalloc.hip"):
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 

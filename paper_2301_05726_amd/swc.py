@@ -27,8 +27,10 @@ EXPORTS = [
     "swc_energy_and_grad", "swc_get_state", "swc_get_stats", "swc_strerror", "swc_last_error",
     "swc_destroy", "swc_validate_excitations", "swc_factor_masks", "swc_checkpoint_bytes",
     "swc_set_checkpoints", "swc_track_entropy", "swc_get_entropy", "swc_set_topk", "swc_set_sigma_scratch",
-    "swc_track_live", "swc_get_live_counts",
+    "swc_track_live", "swc_get_live_counts", "swc_energy_noalloc",
 ]
+
+NOALLOC_MAX_DETS = 65536  # SWC_NOALLOC_MAX_DETS
 
 
 class SwcError(RuntimeError):
@@ -111,6 +113,7 @@ def lib():
         L.swc_track_live.argtypes = [P, I]
         L.swc_set_topk.argtypes = [P, U64, U64]
         L.swc_set_sigma_scratch.argtypes = [P, P, SZ, I]
+        L.swc_energy_noalloc.argtypes = [I, P, P, I64, P, P, P, P]
         _lib = L
     return _lib
 
@@ -141,6 +144,25 @@ def factor_masks(n_qubits: int, exc) -> np.ndarray:
     out = np.zeros((e.shape[0], 3), dtype=np.uint64)
     _chk(lib().swc_factor_masks(n_qubits, _ptr(e), e.shape[0], _ptr(out)))
     return out
+
+
+def energy_noalloc(n_qubits: int, dets: torch.Tensor, amps: torch.Tensor, h1: torch.Tensor, h2: torch.Tensor,
+                   E: torch.Tensor, stream=None) -> None:
+    """swc_energy_noalloc: E[0] = <Psi|H|Psi>/<Psi|Psi> of the state (dets,
+    amps) with no device allocation by the library.  Every argument is a
+    contiguous tensor on the device the call runs on (dets int64 holding the
+    64-bit determinants, amps/h1/h2/E float64); the caller allocates them."""
+    for name, t, dt in (("dets", dets, torch.int64), ("amps", amps, torch.float64), ("h1", h1, torch.float64),
+                        ("h2", h2, torch.float64), ("E", E, torch.float64)):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == dt):
+            raise ValueError(f"{name} must be a contiguous {dt} tensor on the GPU")
+    if dets.numel() != amps.numel():
+        raise ValueError("dets and amps differ in length")
+    with torch.cuda.device(dets.device):  # the library works on the current device
+        st = stream if stream is not None else torch.cuda.current_stream(dets.device)
+        _chk(lib().swc_energy_noalloc(n_qubits, ctypes.c_void_p(dets.data_ptr()), ctypes.c_void_p(amps.data_ptr()),
+                                      dets.numel(), ctypes.c_void_p(h1.data_ptr()), ctypes.c_void_p(h2.data_ptr()),
+                                      ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
 
 
 def workspace_bytes(n_qubits, capacity, prec, batch, max_factors, log_capacity=0) -> int:
