@@ -23,6 +23,7 @@ the host.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -62,6 +63,49 @@ def measured_traffic(workload: str, prec: str) -> dict:
         elif len(parts) == 2 and parts[0] == "sources_sha":
             sha = parts[1]
     return vals if sha == sources_sha() else {}
+
+
+def state_difference(s64, s32, theta, exc, thr, h1, h2) -> dict:
+    """Final states (member 0) of the FP64 and FP32 paths after the same
+    forward sweep: the determinants only one of them kept (truncation
+    decisions that rounding moved across the cut, and their descendants),
+    the amplitude differences on the determinants both kept, and the energy
+    difference split exactly into those two parts.  With X|c the state X
+    restricted to the common determinants, every energy evaluated by the FP64
+    path (build_state + energy):
+        E(32) - E(64) = [E(32) - E(32|c)] - [E(64) - E(64|c)]   (decisions)
+                      + [E(32|c) - E(64|c)]                      (rounding)"""
+    import numpy as np
+    out = {}
+    for name, s in (("fp64", s64), ("fp32", s32)):
+        s.apply_ucc(theta, exc, thr)
+        out[name] = s.get_state(0)
+        s.build_state()
+    (d64, a64), (d32, a32) = out["fp64"], out["fp32"]
+    both, i64, i32 = np.intersect1d(d64, d32, assume_unique=True, return_indices=True)
+    diff = np.abs(a64[i64] - a32[i32])
+    only64 = np.setdiff1d(np.arange(d64.size), i64)
+    only32 = np.setdiff1d(np.arange(d32.size), i32)
+
+    def energy(d, a):
+        s64.build_state(d, a)
+        return float(s64.energy(h1, h2)[0].item())
+
+    E64, E32 = energy(d64, a64), energy(d32, a32)
+    E64c, E32c = energy(both, a64[i64]), energy(both, a32[i32])
+    s64.build_state()
+    return {
+        "dE": E32 - E64,
+        "dE_decisions": (E32 - E32c) - (E64 - E64c),
+        "dE_rounding": E32c - E64c,
+        "n_fp64": int(d64.size), "n_fp32": int(d32.size),
+        "only_fp64": int(only64.size), "only_fp32": int(only32.size),
+        "max_abs_amp_only": float(max(np.max(np.abs(a64[only64]), initial=0.0),
+                                      np.max(np.abs(a32[only32]), initial=0.0))),
+        "weight_only": float(np.sum(a64[only64] ** 2) + np.sum(a32[only32] ** 2)),
+        "max_abs_amp_diff_common": float(np.max(diff, initial=0.0)),
+        "rms_amp_diff_common": float(np.sqrt(np.mean(diff ** 2))) if diff.size else 0.0,
+    }
 
 
 def cpu_model() -> str:
@@ -109,7 +153,9 @@ def main() -> int:
     ap.add_argument("--log-capacity-log2", type=int, default=0, help="truncation-log records 2^c (0: capacity)")
     ap.add_argument("--topk", default="", help="N_MAX,N_CUT truncation after every factor (paper's rule)")
     ap.add_argument("--entropy", action="store_true", help="track the entropy (Eq. 6) after every factor")
-    ap.add_argument("--sigma-scratch-gib", type=float, default=0.0,
+    ap.add_argument("--threshold", type=float, default=-1.0,
+                    help="truncation threshold (default: the workload's)")
+    ap.add_argument("--sigma-scratch-gib", type=float, default=-1.0,
                     help="device scratch for sigma by pairing (0: hash probes)")
     ap.add_argument("--sigma-mode", type=int, default=0, help="pairing: 0 auto, 1 always, 2 never")
     ap.add_argument("--fp64-check", action="store_true",
@@ -131,11 +177,17 @@ def main() -> int:
     from paper_2301_05726_amd import swc, synth
 
     wl = synth.WORKLOADS[args.workload]
+    if args.threshold >= 0.0:
+        wl = dataclasses.replace(wl, threshold=args.threshold)
     if args.checkpoint_interval < 0:
         args.checkpoint_interval = 4096 if wl.name == "q64" else 0
     p = synth.make_problem(wl, batch=args.batch, n_factors=args.factors or None)
     B = args.batch
     cap = (1 << args.capacity_log2) if args.capacity_log2 else wl.capacity
+    if args.sigma_scratch_gib < 0:
+        # large states: the doubles of sigma by pairing (32 GiB of scratch);
+        # small ones: by probes, which cost less there
+        args.sigma_scratch_gib = 32.0 if cap >= (1 << 26) else 0.0
     nq, M = wl.n_qubits, p.M
     prec = swc.FP32 if args.prec == "fp32" else swc.FP64
     tsz = 4 if prec == swc.FP32 else 8
@@ -191,8 +243,7 @@ def main() -> int:
     n_fwd, n_rev = st["rotate_launches"], st["reverse_launches"]
     log_records = st["log_records"]
     ck_taken = st["checkpoints"]
-    scans = {"forward": st["fwd_slots_scanned"], "reverse": st["rev_slots_scanned"],
-             "reverse_shrinks": st["shrinks"], "growths": st["rehashes"]}
+    scans = {"forward": st["fwd_slots_scanned"], "reverse": st["rev_slots_scanned"], "index_growths": st["rehashes"]}
     value = args.steps * B / elapsed  # theta vectors evaluated per second
     E0 = float(E[0].item())
     g0 = g.cpu().numpy()[0]
@@ -269,7 +320,7 @@ def main() -> int:
         "sigma_partitions": st["sigma_partitions"],
         "table_slots_final": st["table_slots"],
         "live_trajectory": live_traj,
-        "slots_scanned_per_step": scans,
+        "entry_positions_scanned_per_step": scans,
         "checkpoints_per_step": ck_taken,
         "det_updates_per_s_forward": round(det_updates / (fwd_ms / args.steps * 1e-3), 1) if fwd_ms else None,
         "energy": E0,
@@ -380,14 +431,15 @@ def main() -> int:
             E32, g32 = s32.energy_and_grad(theta, p.exc, wl.threshold, h1, h2)
         torch.cuda.synchronize()
         c1 = time.perf_counter()
-        s32.close()
-        progress("FP32 evaluations done")
         out["fp32"] = {
             "what": "FP32 amplitudes and rotations, FP64 reductions; same workload, same theta",
             "evals_per_s": round(n32 * B / (c1 - c0), 4),
             "abs_dE_vs_fp64": float(np.max(np.abs(E32.cpu().numpy() - E.cpu().numpy()))),
             "max_abs_dg_vs_fp64": float(np.max(np.abs(g32.cpu().numpy() - g.cpu().numpy()))),
+            "final_states": state_difference(s, s32, theta, p.exc, wl.threshold, h1, h2),
         }
+        s32.close()
+        progress("FP32 evaluations done")
 
     if not args.no_cpu_baseline:
         import oracle

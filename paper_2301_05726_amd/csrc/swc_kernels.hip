@@ -760,7 +760,6 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   const int lane = threadIdx.x & 63;
   const uint32_t K = static_cast<uint32_t>(k);
   const int s = scan_arena();
-  if (occ_lim != NO_LIMIT && K >= cnt[0].stop) return;  // a growth check stopped the sweep
   // entries of every arena when the launch began (lane a: arena a)
   const uint32_t nk = counts_before(sa, b, k, v.A);
   if (occ_lim != NO_LIMIT) {
@@ -768,6 +767,9 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     // so all return together when a member's index holds more than the limit
     // (the host grows the index and runs the step again); a step that runs
     // at most doubles the entries, so the index stays below twice the limit.
+    // The steps after one that returned return too: they see its counts
+    // (counts_before falls back to the step before) or, further on, counts
+    // clamped to the arena size, far above any limit.
     unsigned long long most = 0;
     for (int bb = 0; bb < static_cast<int>(gridDim.y); ++bb) {
       const unsigned long long n = wave_u64(bb == b ? nk : counts_before(sa, bb, k, v.A));
@@ -976,14 +978,27 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
         }
       }
     }
-    // new entries: positions in the wave's arena, then the entries and the
-    // index slots
+    // new entries: each claims the free index slot its probe ended at (a
+    // compare-and-swap of the key) while the wave claims positions in its
+    // arena, so the two returning atomics overlap; then the entries, and the
+    // entry ids into the index slots.  Until its id is written a claimed slot
+    // is seen by no probe of this step but its own: a created key is the
+    // partner of one scanned entry only.
+    bool slot_ok[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      slot_ok[u] = false;
+      if (want[u] && wfree[u] < v.H)
+        slot_ok[u] = atomicCAS(reinterpret_cast<unsigned long long*>(&v.ix[wfree[u]].key),
+                               static_cast<unsigned long long>(EMPTY_KEY),
+                               static_cast<unsigned long long>(wkey[u])) == EMPTY_KEY;
+    }
     uint64_t pos[SCAN_U];
     const int a = claim_positions<SCAN_U>(sa, b, k, nk, want, pos);
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
       if (!want[u]) continue;
-      if (pos[u] >= v.A) {
+      if (pos[u] >= v.A) {  // the sweep fails ("hash table full")
         flags |= F_TABLE_FULL;
         continue;
       }
@@ -993,7 +1008,11 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       v.sl[e].meta = K;
       v.born(e) = K;
       v.lam(e) = T(0);
-      if (!index_insert(v.ix, v.H, wkey[u], wfree[u], entry_id(a, pos[u]))) {
+      // (a slot another new key took first: the probe goes on past it)
+      if (slot_ok[u]) {
+        v.ix[wfree[u]].id = entry_id(a, pos[u]);
+      } else if (!index_insert(v.ix, v.H, wkey[u], wfree[u] < v.H ? (wfree[u] + 1) & (v.H - 1) : v.H,
+                               entry_id(a, pos[u]))) {
         flags |= F_TABLE_FULL;
         continue;
       }
