@@ -210,6 +210,7 @@ struct swc_ctx {
   // round trips.
   uint64_t table_min = 1ull << 18;
   int grid_override = 0;       // SWC_GRID
+  int split_override = -1;     // SWC_SPLIT: 1 members always launched apart, 0 never, unset by index size
   // two factors per launch at threshold 0 (SWC_FUSE=0 turns it off)
   bool fuse = true;
   // entropy of every forward step (swc_track_entropy); sa.ea/eb are set
@@ -281,6 +282,9 @@ struct swc_ctx {
   int grid = NA;
   int grid_fs = NA, grid_rs = NA;
   int res_fwd = 0, res_rev = 0;
+  // the same for launches of one batch member each (split_members)
+  int grid_fs1 = NA, grid_rs1 = NA;
+  int res_fwd1 = 0, res_rev1 = 0;
   int res_f2w = 0, res_r2w = 0;  // resident blocks (all members) of the wide two-factor kernels
   uint64_t per_arena = 0;  // entries per arena the grids are sized for
   // persistent (cooperative) sweeps, one launch per sweep: opt-in with
@@ -361,7 +365,22 @@ void set_table(swc_ctx* c, uint64_t Hn) {
   c->grid = arena_grid(c->per_arena, 1, rmax);
   c->grid_fs = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_fwd > 0 ? c->res_fwd / NA : rmax));
   c->grid_rs = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_rev > 0 ? c->res_rev / NA : rmax));
+  c->grid_fs1 = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_fwd1 > 0 ? c->res_fwd1 / NA : rmax));
+  c->grid_rs1 = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_rev1 > 0 ? c->res_rev1 / NA : rmax));
 }
+
+// Batch members get one-factor step launches of their own once their indexes
+// are large (64 MiB and more each): a launch then works on one member's index
+// and entries instead of all B members' at once, which would share the L2 and
+// Infinity Cache between them.  Small states keep one launch for all members
+// (latency-bound launches, where fewer launches win).
+constexpr uint64_t SPLIT_H = 1ull << 22;
+bool split_members(const swc_ctx* c) {
+  return c->B > 1 && (c->split_override >= 0 ? c->split_override > 0 : c->tab.H >= SPLIT_H);
+}
+int fwd_grid(const swc_ctx* c) { return split_members(c) ? c->grid_fs1 : c->grid_fs; }
+int rev_grid(const swc_ctx* c) { return split_members(c) ? c->grid_rs1 : c->grid_rs; }
+int64_t step_launches(const swc_ctx* c) { return split_members(c) ? c->B : 1; }
 
 // Two-factor launches load several index slots per probe up front when one
 // launch covers the state in one pass and all its blocks are resident at once.
@@ -544,6 +563,7 @@ int64_t fwd_plan(const swc_ctx* c, int64_t k0, int64_t k1, double thr, uint64_t 
       k += 2;
     } else {
       *builds |= c->entropy ? SWC_BUILD_FWD_ENT : SWC_BUILD_FWD;
+      n += step_launches(c) - 1;
       k += 1;
     }
   }
@@ -559,6 +579,7 @@ int64_t rev_plan(const swc_ctx* c, int64_t hi, int64_t lo, bool fuse, int64_t* b
       k -= 2;
     } else {
       *builds |= SWC_BUILD_REV;
+      n += step_launches(c) - 1;
       k -= 1;
     }
   }
@@ -574,7 +595,7 @@ void issue_fwd(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint6
       k += 2;
     } else {
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, c->grid_fs, st);
+                    log_on, lim, c->B, fwd_grid(c), split_members(c), st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid, st);
       k += 1;
@@ -593,7 +614,8 @@ int64_t issue_rev(swc_ctx* c, int64_t hi, int64_t lo, bool fuse, hipStream_t st)
                      wide2(c, c->res_r2w), st);
       k -= 2;
     } else {
-      launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid_rs, st);
+      launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, rev_grid(c),
+                    split_members(c), st);
       k -= 1;
     }
   }
@@ -626,13 +648,13 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
     for (int64_t k = k0; k <= k1; ++k) {  // every launch timed: one step per launch
       (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, c->grid_fs, c->st);
+                    log_on, lim, c->B, fwd_grid(c), split_members(c), c->st);
       (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid,
                        c->st);
     }
-    c->fwd_launches += k1 - k0 + 1;
+    c->fwd_launches += (k1 - k0 + 1) * step_launches(c);
     return SWC_OK;
   });
 }
@@ -871,12 +893,12 @@ int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>
       c->builds |= SWC_BUILD_REV;
       for (int64_t k = hi; k >= lo; --k) {
         if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
-        launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, c->grid_rs,
-                      c->st);
+        launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, rev_grid(c),
+                      split_members(c), c->st);
         if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
         if (maxn[k]) launch_log_restore<T>(c->tab, c->lg, c->sa, static_cast<int>(k), c->B, maxn[k], c->st);
       }
-      c->rev_launches += hi - lo + 1;
+      c->rev_launches += (hi - lo + 1) * step_launches(c);
       return SWC_OK;
     });
     if (r) return r;
@@ -1127,6 +1149,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   c->init_a = reinterpret_cast<double*>(w + l.init_a);
   c->hcnt.assign(static_cast<size_t>(batch), Counters{});
   if (const char* e = std::getenv("SWC_GRID")) c->grid_override = std::max(0, std::atoi(e));  // tuning override
+  if (const char* e = std::getenv("SWC_SPLIT")) c->split_override = std::atoi(e) != 0 ? 1 : 0;  // testing, tuning
   if (const char* e = std::getenv("SWC_TABLE_MIN")) {  // smallest table after a reset (testing and tuning)
     const long long v = std::atoll(e);
     if (v >= 64 && pow2(static_cast<uint64_t>(v))) c->table_min = static_cast<uint64_t>(v);
@@ -1154,6 +1177,8 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     const int sr = prec == SWC_FP32 ? resident_blocks_per_cu<float>(3) : resident_blocks_per_cu<double>(3);
     c->res_fwd = std::max(1, sf * ncu / batch);
     c->res_rev = std::max(1, sr * ncu / batch);
+    c->res_fwd1 = std::max(1, sf * ncu);
+    c->res_rev1 = std::max(1, sr * ncu);
     c->res_f2w = (prec == SWC_FP32 ? resident_blocks_per_cu<float>(5) : resident_blocks_per_cu<double>(5)) * ncu;
     c->res_r2w = (prec == SWC_FP32 ? resident_blocks_per_cu<float>(6) : resident_blocks_per_cu<double>(6)) * ncu;
     set_table(c, c->H);  // step grids with the resident limits

@@ -301,14 +301,16 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
                             hipStream_t st);
 // occ_lim: a step whose start finds a member's entries above it does not run
 // and stops the sweep (Counters::stop) so the host can grow the index;
-// NO_LIMIT for an index at full capacity
+// NO_LIMIT for an index at full capacity.  split: one launch per batch
+// member (grid blocks each, one after the other) instead of one launch with
+// grid.y = B
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
-                hipStream_t st);
+                int split, hipStream_t st);
 template <class T>
 void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                int k, int B, int grid, hipStream_t st);
+                int k, int B, int grid, int split, hipStream_t st);
 // steps k and k+1 in one launch (threshold 0, factors with different XOR
 // masks; the index cannot grow during it), and their reverse (no truncation
 // log) (wide: several index slots from every home loaded up front; for

@@ -753,8 +753,8 @@ template <class T, bool ENT>
 __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict__ fac,
                                          const Trig* __restrict__ trig, int64_t ld, const StepArr& sa, Counters* cnt,
                                          const LogArr& lg, int k, double thr, int prune_all, int log_on,
-                                         uint64_t occ_lim) {
-  const int b = blockIdx.y;
+                                         uint64_t occ_lim, int b0, int nmem) {
+  const int b = blockIdx.y + b0;  // b0: the member of a launch for one member (nmem members in all)
   const View<T> v = view<T>(t, b);
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
   const int lane = threadIdx.x & 63;
@@ -771,7 +771,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     // (counts_before falls back to the step before) or, further on, counts
     // clamped to the arena size, far above any limit.
     unsigned long long most = 0;
-    for (int bb = 0; bb < static_cast<int>(gridDim.y); ++bb) {
+    for (int bb = 0; bb < nmem; ++bb) {
       const unsigned long long n = wave_u64(bb == b ? nk : counts_before(sa, bb, k, v.A));
       most = n > most ? n : most;
     }
@@ -1063,8 +1063,8 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
 template <class T>
 __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict__ fac,
                                          const Trig* __restrict__ trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                                         int k) {
-  const int b = blockIdx.y;
+                                         int k, int b0) {
+  const int b = blockIdx.y + b0;  // b0: the member of a launch for one member
   const View<T> v = view<T>(t, b);
   const int s = scan_arena();
   const uint64_t ns = static_cast<uint32_t>(__shfl(static_cast<int>(counts_reverse(sa, b, k, v.A)), s, 64));
@@ -1259,14 +1259,14 @@ template <class T, bool ENT>
 __global__ __launch_bounds__(BLK) void k_fwd(Tab t, const FacMask* __restrict__ fac,
                                                    const Trig* __restrict__ trig, int64_t ld, StepArr sa,
                                                    Counters* cnt, LogArr lg, int k, double thr, int prune_all,
-                                                   int log_on, uint64_t occ_lim) {
-  fwd_step<T, ENT>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on, occ_lim);
+                                                   int log_on, uint64_t occ_lim, int b0, int nmem) {
+  fwd_step<T, ENT>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on, occ_lim, b0, nmem);
 }
 
 template <class T>
 __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
-                                             int64_t ld, StepArr sa, Counters* cnt, int k) {
-  rev_step<T>(t, fac, trig, ld, sa, cnt, k);
+                                             int64_t ld, StepArr sa, Counters* cnt, int k, int b0) {
+  rev_step<T>(t, fac, trig, ld, sa, cnt, k, b0);
 }
 
 
@@ -1751,9 +1751,11 @@ __global__ __launch_bounds__(BLK) void k_fwd_sweep(Tab t, const FacMask* __restr
   unsigned int epoch = 0;
   for (int k = k0; k <= k1; ++k) {
     if (sa.ea)
-      fwd_step<T, true>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_first && k == k0, log_on, NO_LIMIT);
+      fwd_step<T, true>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_first && k == k0, log_on, NO_LIMIT, 0,
+                        static_cast<int>(gridDim.y));
     else
-      fwd_step<T, false>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_first && k == k0, log_on, NO_LIMIT);
+      fwd_step<T, false>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_first && k == k0, log_on, NO_LIMIT, 0,
+                         static_cast<int>(gridDim.y));
     grid_barrier(sy, ++epoch * nblk);
   }
 }
@@ -1767,7 +1769,7 @@ __global__ __launch_bounds__(BLK) void k_rev_sweep(Tab t, const FacMask* __restr
   const unsigned int nblk = gridDim.x * gridDim.y;
   unsigned int epoch = 0;
   for (int k = k_hi; k >= k_lo; --k) {
-    rev_step<T>(t, fac, trig, ld, sa, cnt, k);
+    rev_step<T>(t, fac, trig, ld, sa, cnt, k, 0);
     grid_barrier(sy, ++epoch * nblk);
     if (sa.rmax[k]) {
       restore_step<T>(t, lg, sa, k);
@@ -2699,19 +2701,26 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
-                hipStream_t st) {
-  if (sa.ea)
-    hipLaunchKernelGGL((k_fwd<T, true>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
-                       prune_all, log_on, occ_lim);
-  else
-    hipLaunchKernelGGL((k_fwd<T, false>), dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
-                       prune_all, log_on, occ_lim);
+                int split, hipStream_t st) {
+  const int nl = split ? B : 1, gy = split ? 1 : B;
+  for (int b0 = 0; b0 < nl; ++b0) {
+    if (sa.ea)
+      hipLaunchKernelGGL((k_fwd<T, true>), dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
+                         prune_all, log_on, occ_lim, b0, B);
+    else
+      hipLaunchKernelGGL((k_fwd<T, false>), dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
+                         prune_all, log_on, occ_lim, b0, B);
+  }
 }
 
 template <class T>
 void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                int k, int B, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_rev<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k);
+                int k, int B, int grid, int split, hipStream_t st) {
+  if (split)
+    for (int b0 = 0; b0 < B; ++b0)
+      hipLaunchKernelGGL(k_rev<T>, dim3(grid, 1), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k, b0);
+  else
+    hipLaunchKernelGGL(k_rev<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k, 0);
 }
 
 template <class T>
@@ -3145,9 +3154,9 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
                                       int64_t, int, hipStream_t);                                                  \
   template void launch_sweep_begin<T>(const Tab&, const StepArr&, Counters*, int64_t, int, int, hipStream_t);     \
   template void launch_fwd<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*,        \
-                              const LogArr&, int, double, int, int, uint64_t, int, int, hipStream_t);              \
+                              const LogArr&, int, double, int, int, uint64_t, int, int, int, hipStream_t);         \
   template void launch_rev<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,   \
-                              int, int, hipStream_t);                                                              \
+                              int, int, int, hipStream_t);                                                         \
   template void launch_log_restore<T>(const Tab&, const LogArr&, const StepArr&, int, int, uint32_t,              \
                                       hipStream_t);                                                                \
   template void launch_compact<T>(const Tab&, const Compact&, Counters*, int, int, hipStream_t);                  \

@@ -89,6 +89,38 @@ def test_batch_members_independent(swc, orc):
         compare_states(d, a, d_ref, a_ref, 1e-12)
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_batch_members_launched_apart(swc, orc, monkeypatch, prec):
+    """One-factor step launches of one batch member each (what large batched
+    states use: SWC_SPLIT=1 forces them at any size) give the bits of one
+    launch for all members, and the oracle's values for every member; the
+    index grows during the forward sweep."""
+    say(f"[case] batch3 q16 members launched apart prec={prec}")
+    h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 181, batch=3)
+    M, thr = exc.shape[0], 1e-4
+    monkeypatch.setenv("SWC_TABLE_MIN", "64")
+    res = {}
+    for split in ("0", "1"):
+        monkeypatch.setenv("SWC_SPLIT", split)
+        s = swc.Solver(16, 4, 4, capacity_for(8, 4), prec=prec, batch=3, max_factors=M)
+        s.build_state()
+        E, g = s.energy_and_grad(theta, exc, thr, h1, h2)
+        st = s.stats()
+        res[split] = (E.cpu().numpy(), g.cpu().numpy(), st["rotate_launches"], st["reverse_launches"],
+                      st["rehashes"])
+        s.close()
+    (E0, g0, f0, r0, h0), (E1, g1, f1, r1, h1_) = res["0"], res["1"]
+    say(f"  launches forward {f0} -> {f1}, reverse {r0} -> {r1}, growths {h0}")
+    assert h0 == h1_ > 0
+    assert f1 == 3 * f0 and r1 == 3 * r0
+    assert E1.tobytes() == E0.tobytes() and g1.tobytes() == g0.tobytes()
+    tol = TOL[prec]
+    for b in range(3):
+        E_ref, g_ref, _ = orc.energy_and_grad(16, [hf], [1.0], exc, theta[b], thr, h1, h2)
+        assert abs(E1[b] - E_ref) <= tol["E"]
+        assert np.max(np.abs(g1[b] - g_ref)) <= tol["g"]
+
+
 def test_bitwise_reproducible(swc):
     say("[case] determinism q16 thr")
     h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 121)
