@@ -756,6 +756,11 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
                                          uint64_t occ_lim, int b0, int nmem) {
   const int b = blockIdx.y + b0;  // b0: the member of a launch for one member (nmem members in all)
   const View<T> v = view<T>(t, b);
+  // the factor first: its loads then overlap everything the step loads next
+  const FacMask f = fac[k - 1];
+  const Trig tr = trig[b * ld + k - 1];
+  const T sn = static_cast<T>(tr.s), cm1 = static_cast<T>(tr.cm1);
+  const uint64_t pm = f.occ | f.vir;
   const int64_t base = static_cast<int64_t>(b) * sa.stride;
   const int lane = threadIdx.x & 63;
   const uint32_t K = static_cast<uint32_t>(k);
@@ -806,10 +811,6 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
   const double S = trunc ? wave_scale(sa, b, k) : 1.0;
   if (trunc && k >= 2 && blockIdx.x == 0 && threadIdx.x == 0) sa.scale[base + k - 1] = S;
 
-  const FacMask f = fac[k - 1];
-  const Trig tr = trig[b * ld + k - 1];
-  const T sn = static_cast<T>(tr.s), cm1 = static_cast<T>(tr.cm1);
-  const uint64_t pm = f.occ | f.vir;
 
   Red r;
   r.f = fx_zero();
