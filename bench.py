@@ -137,7 +137,7 @@ def main() -> int:
     ap.add_argument("--prec", default="fp64", choices=["fp32", "fp64"])
     ap.add_argument("--fd-params", type=int, default=32)
     ap.add_argument("--no-fd", action="store_true")
-    ap.add_argument("--fd-max-s", type=float, default=40.0,
+    ap.add_argument("--fd-max-s", type=float, default=90.0,
                     help="time budget of the sampled finite-difference parameters (at least two are timed)")
     ap.add_argument("--fd-full-max-s", type=float, default=60.0,
                     help="run the finite differences over every parameter when the sampled estimate is below this")

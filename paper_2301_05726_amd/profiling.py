@@ -16,6 +16,10 @@
         short text table (per-kernel calls, total and mean duration, or mean
         counter value per dispatch).
 
+    python -m paper_2301_05726_amd.profiling distribution <kernel_trace.csv> [--kernels k_fwd,k_rev] [--parts 8]
+        Per-launch duration percentiles of the sweep kernels, and their median
+        along the sweep, from a rocprofv3 --kernel-trace CSV.
+
     python -m paper_2301_05726_amd.profiling reduce <csv> <out.csv>
         Sum a rocprofv3 counter_collection.csv into one row per kernel and
         counter (the input of `traffic` may be either form).
@@ -162,6 +166,31 @@ def _mean_per_kernel(path: str, counter: str) -> dict:
     return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
 
 
+def distribution(path: str, kernels: list, parts: int, cmd) -> None:
+    """Per-launch durations of the named kernels from a rocprofv3
+    kernel_trace.csv: percentiles over all launches, then the median of each
+    of `parts` equal runs of consecutive launches (how the duration moves
+    along a sweep as the state grows)."""
+    import numpy as np
+    dur = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        name = _short(r.get("Kernel_Name", "?")).replace("swc::", "").split("<")[0]
+        if name in kernels:
+            dur[name].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    if cmd:
+        for c in cmd:
+            print(f"# command: {c}")
+    for k in kernels:
+        if not dur[k]:
+            continue
+        d = np.array([x[1] for x in sorted(dur[k])], dtype=np.float64) / 1e3  # launch order, us
+        q = np.percentile(d, [1, 10, 50, 90, 99, 99.9])
+        print(f"{k}: {d.size} launches, mean {d.mean():.3f} us; percentiles 1/10/50/90/99/99.9: "
+              + " / ".join(f"{v:.2f}" for v in q) + f"; max {d.max():.2f} us")
+        meds = [np.median(c) for c in np.array_split(d, parts)]
+        print(f"  median per 1/{parts} of the launches in order: " + " ".join(f"{v:.2f}" for v in meds))
+
+
 def reduce_counters(path: str, out: str) -> None:
     """Sum a counter_collection.csv (one row per dispatch and counter) into
     one row per kernel and counter, so a run of many dispatches keeps a
@@ -235,6 +264,11 @@ def main(argv=None) -> int:
         t.add_argument(f, required=True)
     t.add_argument("--cal-mib", type=int, default=512)
     t.add_argument("--cmd", action="append")
+    ds = sub.add_parser("distribution")
+    ds.add_argument("csv")
+    ds.add_argument("--kernels", default="k_fwd,k_rev")
+    ds.add_argument("--parts", type=int, default=8)
+    ds.add_argument("--cmd", action="append")
     rd = sub.add_parser("reduce")
     rd.add_argument("csv")
     rd.add_argument("out")
@@ -247,6 +281,8 @@ def main(argv=None) -> int:
         traffic(a)
     elif a.sub == "reduce":
         reduce_counters(a.csv, a.out)
+    elif a.sub == "distribution":
+        distribution(a.csv, a.kernels.split(","), a.parts, a.cmd)
     else:
         summarize(a.csv, a.top, a.cmd)
     return 0
