@@ -58,7 +58,9 @@
  * index (default 2^18 slots); SWC_PROGRESS=1 waits after each range of steps
  * and reports it on stderr; SWC_KERNEL_TIMING=1 times every step launch (one
  * step per launch); SWC_GRID=n caps the sweep launches at about n blocks
- * (at least one per arena of entries; tuning).
+ * (at least one per arena of entries; tuning); SWC_SPLIT=1 (0) always
+ * (never) gives batch members one-factor step launches of their own, which
+ * by default they get once their indexes reach 2^22 slots.
  */
 #ifndef SWC_H
 #define SWC_H
