@@ -915,13 +915,15 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u)
       if (found[u]) pv[u] = v.sl[pe[u]];
+    // One pair: the new values, the keep decisions, the member updates.  A
+    // lane whose partner is absent needs no partner data, so those lanes go
+    // first, while the partners' entries load: the new entries they create
+    // claim their index slots and arena positions with returning atomics
+    // that are then in flight together with those loads.
     bool want[SCAN_U];
     uint64_t wkey[SCAN_U], wfree[SCAN_U];
     T wamp[SCAN_U];
-#pragma unroll
-    for (int u = 0; u < SCAN_U; ++u) {
-      want[u] = false;
-      if (!act[u]) continue;
+    auto pair_step = [&](int u) {
       const Slot<T>& me = mes[u];
       const uint64_t e = ebase + j0 + u * stride;
       const uint64_t key = me.key;
@@ -932,7 +934,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
         p_alive = !(pv[u].meta & DEAD);
         p_start = p_alive || ((pv[u].meta & TAG) == K);
       }
-      if (!lower && p_start) continue;  // the lower member owns the pair
+      if (!lower && p_start) return;  // the lower member owns the pair
       r.c[2] += 1;
       if (lower && p_alive) r.c[6] += 1;
       const T ss = (__popcll(key & f.sgn) & 1) ? -sn : sn;
@@ -978,6 +980,11 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
           wfree[u] = free_start[u];
         }
       }
+    };
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      want[u] = false;
+      if (act[u] && !found[u]) pair_step(u);
     }
     // new entries: each claims the free index slot its probe ended at (a
     // compare-and-swap of the key) while the wave claims positions in its
@@ -996,6 +1003,10 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     }
     uint64_t pos[SCAN_U];
     const int a = claim_positions<SCAN_U>(sa, b, k, nk, want, pos);
+    // the pairs whose partner is present, once its entry has arrived
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u)
+      if (act[u] && found[u]) pair_step(u);
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
       if (!want[u]) continue;
