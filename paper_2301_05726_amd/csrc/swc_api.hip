@@ -245,7 +245,7 @@ struct swc_ctx {
   int64_t ck_taken = 0;
   std::vector<uint64_t> ck_nmax;  // per checkpoint: most entries over the batch (last sweep)
   int64_t fwd_launches = 0, rev_launches = 0;  // launches of the last sweeps (per-launch timing)
-  int64_t rehashes = 0;        // index growths in the last forward sweep
+  int64_t rehashes = 0;        // index rebuilds (growths) in the last forward sweep
   int64_t compactions = 0;     // rebuilds without the dead entries of earlier sweeps at its start
   int64_t last_M = 0;          // factors of the last forward sweep (entry-scan totals of swc_get_stats)
   bool rev_fused = false;      // the last reverse sweep undid two factors per launch
@@ -718,11 +718,11 @@ uint64_t max_occupancy(const swc_ctx* c) {
   return o;
 }
 
-// The forward sweep (Eq. 3): steps 1..M in order.  While the table can still
-// grow, the host reads the counters after every chunk of steps and rehashes
-// into a larger table when the occupancy approaches the growth limit, or
-// when a step stopped the sweep at that limit (the stopped steps are run
-// again on the grown table).
+// The forward sweep (Eq. 3): steps 1..M in order.  While the index can still
+// grow, the host reads the counters after every range of steps and rebuilds
+// the index larger when the entries approach the growth limit, or when a
+// step stopped the sweep at that limit (the stopped steps then run again on
+// the larger index).
 int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   if (c->ktiming) {
     int r0 = ensure_kev(c, static_cast<size_t>(2 * M + 2));
@@ -1389,7 +1389,7 @@ int swc_energy_and_grad(swc_ctx* c, const double* theta, const swc_exc* exc, int
     if (after[b].flags & (F_INCONSISTENT | F_TIMEOUT))
       return fail(SWC_EDEVICE, (after[b].flags & F_TIMEOUT) ? "grid barrier of a persistent sweep timed out"
                                                             : "inconsistent pair state in the reverse sweep");
-    if (after[b].flags & F_TABLE_FULL)  // a rehash found no free slot (cannot happen at <= 45% occupancy)
+    if (after[b].flags & F_TABLE_FULL)  // no reverse kernel inserts: a guard
       return fail(SWC_ECAPACITY, "hash table full in the reverse sweep");
   }
   return SWC_OK;

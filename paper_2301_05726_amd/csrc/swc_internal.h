@@ -168,10 +168,10 @@ struct Tab {
   uint64_t A;    // entries per arena (<= 2^ID_POS_BITS)
 };
 
-// truncation log: states of tombstones overwritten by a resurrection
-// during the forward sweep; member b at offset b*cap
+// truncation log: states of dead entries overwritten by a revival during the
+// forward sweep; member b at offset b*cap
 struct LogArr {
-  uint64_t* key;  // determinant of the overwritten tombstone (slots move on a rehash)
+  uint64_t* key;  // determinant of the overwritten entry (the restore finds it through the index)
   uint32_t* meta;
   uint32_t* born;
   void* amp;

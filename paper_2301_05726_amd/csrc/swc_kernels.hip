@@ -494,10 +494,6 @@ __device__ __forceinline__ double wave_scale(const StepArr& sa, int b, int k) {
   return S;
 }
 
-// global wave index within state b's launch (per-wave statistics slot)
-__device__ __forceinline__ int64_t wave_id() {
-  return (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * (BLK / 64) + (threadIdx.x >> 6);
-}
 
 
 // ---------------------------------------------------------------------------
@@ -1773,7 +1769,7 @@ __global__ __launch_bounds__(BLK) void k_fwd_sweep(Tab t, const FacMask* __restr
 }
 
 // reverse steps k_hi down to k_lo, with the log restores of the steps whose
-// forward pass overwrote tombstones (rmax[k] > 0)
+// forward pass overwrote dead entries (rmax[k] > 0)
 template <class T>
 __global__ __launch_bounds__(BLK) void k_rev_sweep(Tab t, const FacMask* __restrict__ fac,
                                                    const Trig* __restrict__ trig, int64_t ld, StepArr sa,
