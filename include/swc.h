@@ -110,9 +110,10 @@ typedef struct {
      recorded around every launch of these kernels, one factor per launch;
      the *_launches counts are then the timed launches): */
   double rotate_kernel_ms;   /* summed duration of the forward rotate kernels */
-  int64_t rotate_launches;   /* rotate launches of the last forward sweep (one or two factors each) */
+  int64_t rotate_launches;   /* rotate launches of the last forward sweep (one or two factors each;
+                                one per batch member when members are launched apart) */
   double reverse_kernel_ms;  /* summed duration of the reverse kernels */
-  int64_t reverse_launches;  /* reverse launches of the last adjoint sweep (one or two factors each) */
+  int64_t reverse_launches;  /* reverse launches of the last adjoint sweep (likewise) */
   double sigma_kernel_ms;    /* duration of the sigma kernel (always filled) */
   int64_t partner_hits;      /* pairs whose partner existed (last forward sweep) */
   int64_t rehashes;          /* index growths during the last forward sweep */
