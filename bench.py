@@ -108,6 +108,32 @@ def state_difference(s64, s32, theta, exc, thr, h1, h2) -> dict:
     }
 
 
+def graph_node_floor_us(dev, nodes: int = 1000, reps: int = 5) -> float:
+    """Mean time per node of a captured graph of `nodes` one-element kernels
+    (best of `reps` replays), measured with HIP events."""
+    import torch
+    x = torch.zeros(1, device=dev)
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        x.add_(1.0)  # the kernel loaded before the capture
+    torch.cuda.current_stream(dev).wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(nodes):
+            x.add_(1.0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best = float("inf")
+    for _ in range(reps):
+        ev[0].record()
+        graph.replay()
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]) * 1e3 / nodes)
+    del graph
+    return best
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -286,7 +312,13 @@ def main() -> int:
     dom = max(lines, key=lambda n: kern[n][1])
     roofline = dict(lines[dom])
     roofline["kernel_ms_per_step"] = {k: round(v, 4) for k, v in per_step.items()}
+    # the floor of a chain of dependent launches on this device: a captured
+    # graph of one-element kernels (what a sweep step would cost with no work)
+    floor = graph_node_floor_us(dev)
+    roofline["launch_floor_us"] = round(floor, 3)
     roofline["other"] = {n: l for n, l in lines.items() if n != dom}
+    for l in [roofline] + list(roofline["other"].values()):
+        l["launch_over_floor"] = round(l["avg_launch_us"] / floor, 2)
 
     out = {
         "metric": METRIC,

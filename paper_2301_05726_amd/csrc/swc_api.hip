@@ -979,39 +979,47 @@ bool use_pairs(const swc_ctx* c, int64_t nmax) {
   return static_cast<uint64_t>(nmax) * P >= (1ull << 22);
 }
 
-// Double-excitation part of sigma by pairing, member by member, partition by
-// partition; the singles are already in cp.sig.
+// The off-diagonal part of sigma by pairing, member by member: the doubles
+// from the groups of two-electron-removed keys, then the singles from the
+// groups of one-electron-removed keys, partition by partition, all summed
+// exactly into one accumulator per determinant.
 int pair_sigma(swc_ctx* c, const double* h1, const double* h2, int64_t nmax) {
   PairScratch ps;
   if (!pair_scratch(c, static_cast<uint64_t>(nmax), &ps)) return fail(SWC_EINVAL, "sigma scratch too small");
-  const uint64_t P = static_cast<uint64_t>(electrons(c)) * (electrons(c) - 1) / 2;
+  const uint64_t Ne = static_cast<uint64_t>(electrons(c));
+  const uint64_t P[2] = {Ne * (Ne - 1) / 2, Ne};  // records per determinant: order 2, order 1
   const uint64_t H = c->cp.cs;  // stride of the compact arrays
   for (int b = 0; b < c->B; ++b) {
     const uint64_t N = c->hcnt[b].ncompact;
     if (N == 0) continue;
-    int nparts = static_cast<int>(std::max<uint64_t>(1, (N * P + N * P / 4 + ps.cap - 1) / ps.cap));
+    int nparts[2];
+    for (int o = 0; o < 2; ++o)
+      nparts[o] = static_cast<int>(std::max<uint64_t>(1, (N * P[o] + N * P[o] / 4 + ps.cap - 1) / ps.cap));
     for (int attempt = 0;; ++attempt) {
       launch_fx3_zero(ps.acc, N, c->st);
-      bool overflow = false;
-      for (int part = 0; part < nparts; ++part) {
-        launch_zero_u64(ps.count, 1, c->st);
-        launch_pair_emit(c->cp, H, b, N, part, nparts, ps.k0, ps.v0, ps.count, ps.cap, c->st);
-        unsigned long long n = 0;
-        SWC_HIP(hipMemcpyAsync(&n, ps.count, 8, hipMemcpyDeviceToHost, c->st));
-        SWC_HIP(hipStreamSynchronize(c->st));
-        if (n > ps.cap) {
-          overflow = true;
-          break;
+      int overflow = -1;
+      for (int o = 0; o < 2 && overflow < 0; ++o) {
+        const int order = 2 - o;
+        for (int part = 0; part < nparts[o]; ++part) {
+          launch_zero_u64(ps.count, 1, c->st);
+          launch_pair_emit(c->cp, H, b, N, part, nparts[o], ps.k0, ps.v0, ps.count, ps.cap, order, c->st);
+          unsigned long long n = 0;
+          SWC_HIP(hipMemcpyAsync(&n, ps.count, 8, hipMemcpyDeviceToHost, c->st));
+          SWC_HIP(hipStreamSynchronize(c->st));
+          if (n > ps.cap) {
+            overflow = o;
+            break;
+          }
+          const int flip = launch_radix_sort(ps.k0, ps.v0, ps.k1, ps.v1, n, c->nq, ps.hist, ps.sums, c->st);
+          launch_pair_groups(c->cp, H, b, flip ? ps.k1 : ps.k0, flip ? ps.v1 : ps.v0, n, ps.rI, ps.rc, h1, h2,
+                             c->nq / 2, ps.acc, order, c->st);
         }
-        const int flip = launch_radix_sort(ps.k0, ps.v0, ps.k1, ps.v1, n, c->nq, ps.hist, ps.sums, c->st);
-        launch_pair_groups(c->cp, H, b, flip ? ps.k1 : ps.k0, flip ? ps.v1 : ps.v0, n, ps.rI, ps.rc, h1, h2,
-                           c->nq / 2, ps.acc, c->st);
       }
-      if (!overflow) break;
+      if (overflow < 0) break;
       if (attempt >= 8) return fail(SWC_ECAPACITY, "sigma scratch: a partition exceeds the scratch");
-      nparts *= 2;  // an unlucky partition: split finer and start the member again
+      nparts[overflow] *= 2;  // an unlucky partition: split finer and start the member again
     }
-    c->sig_parts = std::max<int64_t>(c->sig_parts, nparts);
+    c->sig_parts = std::max<int64_t>(c->sig_parts, nparts[0]);
     launch_pair_finish(c->cp, H, b, N, ps.acc, c->st);
   }
   SWC_HIP(hipGetLastError());
@@ -1043,14 +1051,17 @@ int energy_run(swc_ctx* c, const double* h1, const double* h2, double* E, bool w
   const int n = c->nq / 2;
   SWC_HIP(hipEventRecord(c->ev[6], c->st));
   const bool pairs = use_pairs(c, nmax);
-  r = dispatch(c, [&](auto* tp) -> int {
-    using T = std::remove_pointer_t<decltype(tp)>;
-    launch_sigma<T>(c->tab, c->cp, c->cnt, h1, h2, c->nq, nmax, c->B, pairs ? 1 : 0, c->st);
-    return SWC_OK;
-  });
-  if (r) return r;
   c->sig_parts = 0;
-  if (pairs && (r = pair_sigma(c, h1, h2, nmax))) return r;
+  if (pairs) {  // every off-diagonal term by pairing
+    if ((r = pair_sigma(c, h1, h2, nmax))) return r;
+  } else {  // every off-diagonal term by enumeration and index probes
+    r = dispatch(c, [&](auto* tp) -> int {
+      using T = std::remove_pointer_t<decltype(tp)>;
+      launch_sigma<T>(c->tab, c->cp, c->cnt, h1, h2, c->nq, nmax, c->B, 0, c->st);
+      return SWC_OK;
+    });
+    if (r) return r;
+  }
   SWC_HIP(hipEventRecord(c->ev[7], c->st));
   launch_energy_reduce(c->cp, c->cnt, h1, h2, n, nmax, c->B, c->st);
   launch_energy_final(c->cnt, E, c->B, c->st);

@@ -329,16 +329,16 @@ void launch_compact(const Tab& t, const Compact& cp, Counters* cnt, int B, int g
 template <class T>
 void launch_sigma(const Tab& t, const Compact& cp, const Counters* cnt, const double* h1, const double* h2, int nq,
                   int64_t nmax, int B, int singles_only, hipStream_t st);
-// sigma of double excitations by pairing determinants on two-electron-removed
-// keys (records (K, i) of one hash partition, radix-sorted by K); H is the
-// stride of the compact arrays
+// the off-diagonal part of sigma by pairing determinants on keys with `order`
+// electrons removed (2: the doubles, 1: the singles; records (K, i) of one
+// hash partition, radix-sorted by K); H is the stride of the compact arrays
 void launch_pair_emit(const Compact& cp, uint64_t H, int b, uint64_t N, int part, int nparts, uint64_t* rk,
-                      uint32_t* ri, unsigned long long* count, uint64_t cap, hipStream_t st);
+                      uint32_t* ri, unsigned long long* count, uint64_t cap, int order, hipStream_t st);
 int launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t n, int bits, uint32_t* hist,
                       uint32_t* sums, hipStream_t st);
 void launch_pair_groups(const Compact& cp, uint64_t H, int b, const uint64_t* K, const uint32_t* ri, uint64_t n,
                         uint64_t* rI, double* rc, const double* h1, const double* h2, int n_orb, Fx3* acc,
-                        hipStream_t st);
+                        int order, hipStream_t st);
 void launch_pair_finish(const Compact& cp, uint64_t H, int b, uint64_t N, Fx3* acc, hipStream_t st);
 void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st);
 void launch_energy_reduce(const Compact& cp, Counters* cnt, const double* h1, const double* h2, int n, int64_t nmax,

@@ -2991,9 +2991,11 @@ __global__ __launch_bounds__(BLK) void k_rs_scatter(const uint64_t* __restrict__
 }
 
 // records (K, i) of partition `part` for determinants i < N of member b
+// Records (K, i) of determinant i for every K = I with `order` (1 or 2)
+// electrons removed, in the hash partition `part`.
 __global__ __launch_bounds__(BLK) void k_pair_emit(Compact cp, uint64_t H, int b, uint64_t N, int part, int nparts,
                                                    uint64_t* __restrict__ rk, uint32_t* __restrict__ ri,
-                                                   unsigned long long* __restrict__ count, uint64_t cap) {
+                                                   unsigned long long* __restrict__ count, uint64_t cap, int order) {
   const int lane = threadIdx.x & 63;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   // loop bound uniform across the wave so the ballot-free prefix below is safe
@@ -3003,6 +3005,10 @@ __global__ __launch_bounds__(BLK) void k_pair_emit(Compact cp, uint64_t H, int b
     unsigned int c = 0;
     for (uint64_t m1 = I; m1; m1 &= m1 - 1ull) {
       const uint64_t b1 = m1 & (~m1 + 1ull);
+      if (order == 1) {
+        c += pair_part(I ^ b1, nparts) == part;
+        continue;
+      }
       for (uint64_t m2 = m1 & (m1 - 1ull); m2; m2 &= m2 - 1ull)
         c += pair_part(I ^ b1 ^ (m2 & (~m2 + 1ull)), nparts) == part;
     }
@@ -3020,6 +3026,16 @@ __global__ __launch_bounds__(BLK) void k_pair_emit(Compact cp, uint64_t H, int b
     uint64_t pos = basep + incl - c;
     for (uint64_t m1 = I; m1; m1 &= m1 - 1ull) {
       const uint64_t b1 = m1 & (~m1 + 1ull);
+      if (order == 1) {
+        const uint64_t K = I ^ b1;
+        if (pair_part(K, nparts) != part) continue;
+        if (pos < cap) {
+          rk[pos] = K;
+          ri[pos] = static_cast<uint32_t>(i);
+        }
+        ++pos;
+        continue;
+      }
       for (uint64_t m2 = m1 & (m1 - 1ull); m2; m2 &= m2 - 1ull) {
         const uint64_t K = I ^ b1 ^ (m2 & (~m2 + 1ull));
         if (pair_part(K, nparts) != part) continue;
@@ -3044,7 +3060,8 @@ __global__ void k_pair_gather(Compact cp, uint64_t H, int b, const uint32_t* __r
 }
 
 // a record's share of sigma: the other members of its group (same K) whose
-// removed pair is disjoint from its own.  A wave takes 64 consecutive
+// removed electrons are disjoint from its own (order 2: the doubles; order 1:
+// every other member, a single excitation).  A wave takes 64 consecutive
 // records: group bounds come from wave scans of the group heads and tails,
 // with a walk only for the groups that cross the wave's edges; members are
 // read four at a time so their loads are in flight together.
@@ -3052,7 +3069,7 @@ __global__ __launch_bounds__(BLK) void k_pair_sigma(const uint64_t* __restrict__
                                                     const double* __restrict__ rc, const uint32_t* __restrict__ ri,
                                                     uint64_t n, const double* __restrict__ h1,
                                                     const double* __restrict__ h2, int n_orb,
-                                                    Fx3* __restrict__ acc) {
+                                                    Fx3* __restrict__ acc, int order) {
   const int lane = threadIdx.x & 63;
   const uint64_t wstride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t j0 = blockIdx.x * static_cast<uint64_t>(blockDim.x) + (threadIdx.x & ~63u); j0 < n; j0 += wstride) {
@@ -3090,27 +3107,29 @@ __global__ __launch_bounds__(BLK) void k_pair_sigma(const uint64_t* __restrict__
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        // same determinant, or a shared removed orbital (a single): not a double
+        // same determinant, or (order 2) a shared removed orbital: a single,
+        // which the one-electron groups count
         if (J[q] == I || ((J[q] ^ k) & dI)) continue;
-        a = fx_add(a, fx_from(h_offdiag(I, J[q], 4, h1, h2, n_orb) * c[q]));
+        a = fx_add(a, fx_from(h_offdiag(I, J[q], 2 * order, h1, h2, n_orb) * c[q]));
       }
     }
     if (fx_nonzero(a)) fx3_atomic_add(&acc[ri[j]], a);
   }
 }
 
+// sigma of the off-diagonal part, summed exactly over both kinds of groups
 __global__ void k_pair_finish(Compact cp, uint64_t H, int b, uint64_t N, Fx3* __restrict__ acc) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < N;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    cp.sig[b * H + i] += fx_to_d(fx3_value(acc[i]));
+    cp.sig[b * H + i] = fx_to_d(fx3_value(acc[i]));
     acc[i] = fx3_zero();
   }
 }
 
 void launch_pair_emit(const Compact& cp, uint64_t H, int b, uint64_t N, int part, int nparts, uint64_t* rk,
-                      uint32_t* ri, unsigned long long* count, uint64_t cap, hipStream_t st) {
+                      uint32_t* ri, unsigned long long* count, uint64_t cap, int order, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_emit, dim3(grid_for(N, BLK, 8192)), dim3(BLK), 0, st, cp, H, b, N, part, nparts, rk, ri,
-                     count, cap);
+                     count, cap, order);
 }
 
 // LSD radix sort of (key, value) by the low `bits` bits of the key, 8 per
@@ -3140,11 +3159,11 @@ int launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, ui
 
 void launch_pair_groups(const Compact& cp, uint64_t H, int b, const uint64_t* K, const uint32_t* ri, uint64_t n,
                         uint64_t* rI, double* rc, const double* h1, const double* h2, int n_orb, Fx3* acc,
-                        hipStream_t st) {
+                        int order, hipStream_t st) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pair_gather, dim3(grid_for(n, BLK, 8192)), dim3(BLK), 0, st, cp, H, b, ri, n, rI, rc);
   hipLaunchKernelGGL(k_pair_sigma, dim3(grid_for(n, BLK, 16384)), dim3(BLK), 0, st, K, rI, rc, ri, n, h1, h2, n_orb,
-                     acc);
+                     acc, order);
 }
 
 void launch_pair_finish(const Compact& cp, uint64_t H, int b, uint64_t N, Fx3* acc, hipStream_t st) {
