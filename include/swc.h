@@ -266,12 +266,13 @@ int swc_set_topk(swc_ctx* ctx, uint64_t n_max, uint64_t n_cut);
 /*
  * Scratch for sigma = H psi (energy; Results section) by pairing instead of
  * hash probes.  Two determinants differ by a double excitation exactly when
- * removing two electrons from each leaves the same pattern K: every live
- * determinant emits one record (K, index) per pair of its occupied
- * spin-orbitals, the records are radix-sorted by K on the device, and each
- * group sums <I|H|J> c_J over its members (exact fixed-point partial sums).
- * Only connections present in the state are touched; absent ones are never
- * probed.  Singles and the diagonal keep their own paths.  `buffer` (device,
+ * removing two electrons from each leaves the same pattern K, and by a single
+ * one when removing one electron from each does: every live determinant
+ * emits one record (K, index) per pair of its occupied spin-orbitals, then
+ * one per occupied spin-orbital; the records are radix-sorted by K on the
+ * device, and each group sums <I|H|J> c_J over its members (exact
+ * fixed-point sums).  Only connections present in the state are touched;
+ * absent ones are never probed.  The diagonal keeps its own path.  `buffer` (device,
  * 256-byte aligned, caller-owned, kept until the next call or swc_destroy):
  * about 41 bytes per record plus 24 bytes per live determinant; records
  * beyond it are processed in hash partitions of K (pairing is skipped when
