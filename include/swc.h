@@ -120,7 +120,8 @@ typedef struct {
   int64_t compactions;       /* rebuilds at its start that dropped the dead entries
                                 of earlier sweeps (over 1/4 of the entries) */
   int64_t checkpoints;       /* snapshots taken by the last gradient sweep */
-  int64_t sigma_partitions;  /* partitions of the last pairing sigma (0: hash probes were used) */
+  int64_t sigma_partitions;  /* hash partitions of the two-electron-removed keys in the last pairing
+                                sigma (0: hash probes were used) */
   int64_t shrinks;           /* always 0: the reverse sweep scans fewer entries as it goes
                                 back without rebuilding anything */
   int64_t fwd_slots_scanned; /* entries (alive and dead) the last forward sweep's launches scanned */
