@@ -108,6 +108,32 @@ def state_difference(s64, s32, theta, exc, thr, h1, h2) -> dict:
     }
 
 
+def random_read_rate(dev, gib: float = 1.0, reps: int = 3) -> float:
+    """Random reads the device serves per second (G/s): torch's gather of
+    8-byte elements at uniformly random positions of a `gib` GiB buffer (best
+    of `reps`, HIP events).  The index reads and the output writes are
+    streamed, so this is a slightly conservative ceiling for kernels whose
+    accesses land at random places of a table this size."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    src = torch.zeros(n, dtype=torch.int64, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    m = 1 << 24
+    idx = torch.randint(0, n, (m,), dtype=torch.int64, device=dev, generator=g)
+    torch.take(src, idx)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best = float("inf")
+    for _ in range(reps):
+        ev[0].record()
+        torch.take(src, idx)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]) * 1e-3)
+    del src, idx
+    return m / best / 1e9
+
+
 def graph_node_floor_us(dev, nodes: int = 1000, reps: int = 5) -> float:
     """Mean time per node of a captured graph of `nodes` one-element kernels
     (best of `reps` replays), measured with HIP events."""
@@ -302,13 +328,28 @@ def main() -> int:
             f"reverse: exact inverse + adjoint rotation + gradient dot, {M} factors in {n_rev} launches"),
     }
     traffic = measured_traffic(args.workload, args.prec)
+    # index probes: every scanned member of a rotated pair looks its partner
+    # up once (the pair's owner, and the upper member of a pair whose lower
+    # member is present, which owns it), so a sweep makes pairs + partner
+    # hits probes; set against the random reads the device serves
+    probes = st["pair_updates"] + st["partner_hits"]
+    rr = random_read_rate(dev)
     lines = {}
     for name, (bpl, ms, what) in kern.items():
         ach = bpl / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        n_l = n_fwd if name.startswith("k_fwd") else n_rev
+        ppl = probes / n_l
+        prate = ppl / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         lines[name] = {"kernel": name, "what": what, "bound": "hbm", "achieved": round(ach, 2),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
                        "traffic": traffic.get(name), "bytes_per_launch": round(bpl, 1),
-                       "avg_launch_us": round(ms * 1e3, 3)}
+                       "avg_launch_us": round(ms * 1e3, 3),
+                       # (a two-factor launch probes for up to three partners per
+                       # member: its probes are not these)
+                       "probes": None if two else {
+                           "per_launch": round(ppl, 1), "achieved_G_per_s": round(prate, 3),
+                           "device_random_reads_G_per_s": round(rr, 3),
+                           "frac": round(prate / rr, 4) if rr > 0 else None}}
     dom = max(lines, key=lambda n: kern[n][1])
     roofline = dict(lines[dom])
     roofline["kernel_ms_per_step"] = {k: round(v, 4) for k, v in per_step.items()}
@@ -348,6 +389,9 @@ def main() -> int:
         },
         "det_updates_per_step": det_updates,
         "pair_updates_per_step": st["pair_updates"],
+        "partner_hits_per_step": st["partner_hits"],
+        "inserts_per_step": st["inserts"],
+        "pruned_per_step": st["pruned"],
         "truncation_log_records": log_records,
         "sigma_partitions": st["sigma_partitions"],
         "table_slots_final": st["table_slots"],

@@ -147,7 +147,9 @@ enum {
   SWC_BUILD_REV = 32,         /* one factor per launch, reverse */
   SWC_BUILD_REV2 = 64,        /* two factors per launch, reverse, home slot preloaded */
   SWC_BUILD_REV2_PRE = 128,   /* the same, four index slots preloaded */
-  SWC_BUILD_PERSISTENT = 256  /* persistent cooperative sweeps (SWC_SWEEP=persistent) */
+  SWC_BUILD_PERSISTENT = 256, /* persistent cooperative sweeps (SWC_SWEEP=persistent) */
+  SWC_BUILD_FWD_HO = 512      /* one factor per launch, forward, built for three resident waves per SIMD
+                                 (indexes of 2^22 slots and more; SWC_HIOCC=1 always, 0 never) */
 };
 
 /*

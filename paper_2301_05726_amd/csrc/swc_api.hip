@@ -211,6 +211,7 @@ struct swc_ctx {
   uint64_t table_min = 1ull << 18;
   int grid_override = 0;       // SWC_GRID
   int split_override = -1;     // SWC_SPLIT: 1 members always launched apart, 0 never, unset by index size
+  int hiocc_override = -1;     // SWC_HIOCC: 1 forward steps always on their high-occupancy build, 0 never, unset by index size
   // two factors per launch at threshold 0 (SWC_FUSE=0 turns it off)
   bool fuse = true;
   // entropy of every forward step (swc_track_entropy); sa.ea/eb are set
@@ -285,6 +286,10 @@ struct swc_ctx {
   // the same for launches of one batch member each (split_members)
   int grid_fs1 = NA, grid_rs1 = NA;
   int res_fwd1 = 0, res_rev1 = 0;
+  // the same for the forward build with more resident waves (hi_occ), all
+  // members in one launch and one member per launch
+  int grid_fsh = NA, grid_fsh1 = NA;
+  int res_fwdh = 0, res_fwdh1 = 0;
   int res_f2w = 0, res_r2w = 0;  // resident blocks (all members) of the wide two-factor kernels
   uint64_t per_arena = 0;  // entries per arena the grids are sized for
   // persistent (cooperative) sweeps, one launch per sweep: opt-in with
@@ -367,6 +372,8 @@ void set_table(swc_ctx* c, uint64_t Hn) {
   c->grid_rs = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_rev > 0 ? c->res_rev / NA : rmax));
   c->grid_fs1 = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_fwd1 > 0 ? c->res_fwd1 / NA : rmax));
   c->grid_rs1 = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_rev1 > 0 ? c->res_rev1 / NA : rmax));
+  c->grid_fsh = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_fwdh > 0 ? c->res_fwdh / NA : rmax));
+  c->grid_fsh1 = arena_grid(c->per_arena, SCAN_U, std::min(rmax, c->res_fwdh1 > 0 ? c->res_fwdh1 / NA : rmax));
 }
 
 // Batch members get one-factor step launches of their own once their indexes
@@ -378,7 +385,19 @@ constexpr uint64_t SPLIT_H = 1ull << 22;
 bool split_members(const swc_ctx* c) {
   return c->B > 1 && (c->split_override >= 0 ? c->split_override > 0 : c->tab.H >= SPLIT_H);
 }
-int fwd_grid(const swc_ctx* c) { return split_members(c) ? c->grid_fs1 : c->grid_fs; }
+// The one-factor forward steps use their build for more resident waves once
+// the index reaches 2^22 slots (a state of a million entries and more: many
+// passes of the grid per step, where more loads in flight per compute unit
+// pay); below, the launches are short dependent chains and the lighter
+// build is faster.
+constexpr uint64_t HIOCC_H = 1ull << 22;
+bool hi_occ(const swc_ctx* c) {
+  return c->hiocc_override >= 0 ? c->hiocc_override > 0 : c->tab.H >= HIOCC_H;
+}
+int fwd_grid(const swc_ctx* c) {
+  if (hi_occ(c)) return split_members(c) ? c->grid_fsh1 : c->grid_fsh;
+  return split_members(c) ? c->grid_fs1 : c->grid_fs;
+}
 int rev_grid(const swc_ctx* c) { return split_members(c) ? c->grid_rs1 : c->grid_rs; }
 int64_t step_launches(const swc_ctx* c) { return split_members(c) ? c->B : 1; }
 
@@ -562,7 +581,7 @@ int64_t fwd_plan(const swc_ctx* c, int64_t k0, int64_t k1, double thr, uint64_t 
       *builds |= wide2(c, c->res_f2w) ? SWC_BUILD_FWD2_PRE : SWC_BUILD_FWD2;
       k += 2;
     } else {
-      *builds |= c->entropy ? SWC_BUILD_FWD_ENT : SWC_BUILD_FWD;
+      *builds |= c->entropy ? SWC_BUILD_FWD_ENT : hi_occ(c) ? SWC_BUILD_FWD_HO : SWC_BUILD_FWD;
       n += step_launches(c) - 1;
       k += 1;
     }
@@ -595,7 +614,7 @@ void issue_fwd(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint6
       k += 2;
     } else {
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, fwd_grid(c), split_members(c), st);
+                    log_on, lim, c->B, fwd_grid(c), split_members(c), hi_occ(c), st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid, st);
       k += 1;
@@ -644,11 +663,11 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
       c->fwd_launches += fwd_plan(c, k0, k1, thr, lim, &c->builds);
       return SWC_OK;
     }
-    c->builds |= c->entropy ? SWC_BUILD_FWD_ENT : SWC_BUILD_FWD;
+    c->builds |= c->entropy ? SWC_BUILD_FWD_ENT : hi_occ(c) ? SWC_BUILD_FWD_HO : SWC_BUILD_FWD;
     for (int64_t k = k0; k <= k1; ++k) {  // every launch timed: one step per launch
       (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, fwd_grid(c), split_members(c), c->st);
+                    log_on, lim, c->B, fwd_grid(c), split_members(c), hi_occ(c), c->st);
       (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid,
@@ -1161,6 +1180,7 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   c->hcnt.assign(static_cast<size_t>(batch), Counters{});
   if (const char* e = std::getenv("SWC_GRID")) c->grid_override = std::max(0, std::atoi(e));  // tuning override
   if (const char* e = std::getenv("SWC_SPLIT")) c->split_override = std::atoi(e) != 0 ? 1 : 0;  // testing, tuning
+  if (const char* e = std::getenv("SWC_HIOCC")) c->hiocc_override = std::atoi(e) != 0 ? 1 : 0;  // testing, tuning
   if (const char* e = std::getenv("SWC_TABLE_MIN")) {  // smallest table after a reset (testing and tuning)
     const long long v = std::atoll(e);
     if (v >= 64 && pow2(static_cast<uint64_t>(v))) c->table_min = static_cast<uint64_t>(v);
@@ -1190,6 +1210,9 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
     c->res_rev = std::max(1, sr * ncu / batch);
     c->res_fwd1 = std::max(1, sf * ncu);
     c->res_rev1 = std::max(1, sr * ncu);
+    const int hf = prec == SWC_FP32 ? resident_blocks_per_cu<float>(7) : resident_blocks_per_cu<double>(7);
+    c->res_fwdh = std::max(1, hf * ncu / batch);
+    c->res_fwdh1 = std::max(1, hf * ncu);
     c->res_f2w = (prec == SWC_FP32 ? resident_blocks_per_cu<float>(5) : resident_blocks_per_cu<double>(5)) * ncu;
     c->res_r2w = (prec == SWC_FP32 ? resident_blocks_per_cu<float>(6) : resident_blocks_per_cu<double>(6)) * ncu;
     set_table(c, c->H);  // step grids with the resident limits

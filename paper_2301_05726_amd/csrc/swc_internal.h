@@ -303,11 +303,12 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
 // and stops the sweep (Counters::stop) so the host can grow the index;
 // NO_LIMIT for an index at full capacity.  split: one launch per batch
 // member (grid blocks each, one after the other) instead of one launch with
-// grid.y = B
+// grid.y = B.  hiocc: the forward build for more resident waves (large
+// states; the entropy build has none)
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
-                int split, hipStream_t st);
+                int split, int hiocc, hipStream_t st);
 template <class T>
 void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 int k, int B, int grid, int split, hipStream_t st);

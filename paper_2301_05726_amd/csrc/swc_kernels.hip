@@ -1277,6 +1277,19 @@ __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ 
   rev_step<T>(t, fac, trig, ld, sa, cnt, k, b0);
 }
 
+// The forward step built for three resident waves per SIMD instead of two
+// (fewer registers, a few spilled), so that more loads are in flight on each
+// compute unit.  It pays once the state spans many passes of the grid; small
+// states keep the build above, whose launches are chains of dependent loads
+// that the spills would lengthen.  (A reverse build for four waves per SIMD
+// gained at 32 qubits and lost at 48: the reverse keeps one build.)
+template <class T>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(3))) void k_fwd_ho(
+    Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig, int64_t ld, StepArr sa, Counters* cnt,
+    LogArr lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int b0, int nmem) {
+  fwd_step<T, false>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on, occ_lim, b0, nmem);
+}
+
 
 // ---------------------------------------------------------------------------
 // two factors per launch (threshold 0)
@@ -2664,6 +2677,7 @@ int resident_blocks_per_cu(int which) {
     case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev<T>, BLK, 0); break;
     case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd2<T, PH2>, BLK, 0); break;
     case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rev2<T, PH2>, BLK, 0); break;
+    case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_ho<T>, BLK, 0); break;
     default: break;
   }
   return e == hipSuccess ? nb : 0;
@@ -2709,11 +2723,14 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
-                int split, hipStream_t st) {
+                int split, int hiocc, hipStream_t st) {
   const int nl = split ? B : 1, gy = split ? 1 : B;
   for (int b0 = 0; b0 < nl; ++b0) {
     if (sa.ea)
       hipLaunchKernelGGL((k_fwd<T, true>), dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
+                         prune_all, log_on, occ_lim, b0, B);
+    else if (hiocc)
+      hipLaunchKernelGGL(k_fwd_ho<T>, dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
                          prune_all, log_on, occ_lim, b0, B);
     else
       hipLaunchKernelGGL((k_fwd<T, false>), dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
@@ -3181,7 +3198,7 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
                                       int64_t, int, hipStream_t);                                                  \
   template void launch_sweep_begin<T>(const Tab&, const StepArr&, Counters*, int64_t, int, int, hipStream_t);     \
   template void launch_fwd<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*,        \
-                              const LogArr&, int, double, int, int, uint64_t, int, int, int, hipStream_t);         \
+                              const LogArr&, int, double, int, int, uint64_t, int, int, int, int, hipStream_t);    \
   template void launch_rev<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,   \
                               int, int, int, hipStream_t);                                                         \
   template void launch_log_restore<T>(const Tab&, const LogArr&, const StepArr&, int, int, uint32_t,              \

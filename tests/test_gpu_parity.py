@@ -121,6 +121,40 @@ def test_batch_members_launched_apart(swc, orc, monkeypatch, prec):
         assert np.max(np.abs(g1[b] - g_ref)) <= tol["g"]
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("batch", [1, 2], ids=["b1", "b2_apart"])
+def test_forward_high_occupancy_build(swc, orc, monkeypatch, prec, batch):
+    """The forward build for more resident waves per SIMD (what indexes of
+    2^22 slots and more use: SWC_HIOCC=1 forces it at any size; with two
+    members, launched one member each) gives the bits of the lighter build
+    and the oracle's values; the index grows during the forward sweep."""
+    say(f"[case] forward high-occupancy build q16 batch{batch} prec={prec}")
+    h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 187, batch=batch)
+    M, thr = exc.shape[0], 1e-4
+    monkeypatch.setenv("SWC_TABLE_MIN", "64")
+    monkeypatch.setenv("SWC_SPLIT", "1" if batch > 1 else "0")
+    res = {}
+    for ho in ("0", "1"):
+        monkeypatch.setenv("SWC_HIOCC", ho)
+        s = swc.Solver(16, 4, 4, capacity_for(8, 4), prec=prec, batch=batch, max_factors=M)
+        s.build_state()
+        E, g = s.energy_and_grad(theta, exc, thr, h1, h2)
+        st = s.stats()
+        res[ho] = (E.cpu().numpy(), g.cpu().numpy(), st["kernel_builds"], st["rehashes"])
+        s.close()
+    (E0, g0, b0, h0), (E1, g1, b1, h1_) = res["0"], res["1"]
+    say(f"  builds {b0:#x} -> {b1:#x}, growths {h0}")
+    assert h0 == h1_ > 0
+    assert b0 & swc.BUILD_FWD and not b0 & swc.BUILD_FWD_HO
+    assert b1 & swc.BUILD_FWD_HO and not b1 & swc.BUILD_FWD
+    assert E1.tobytes() == E0.tobytes() and g1.tobytes() == g0.tobytes()
+    tol = TOL[prec]
+    for b in range(batch):
+        E_ref, g_ref, _ = orc.energy_and_grad(16, [hf], [1.0], exc, theta[b], thr, h1, h2)
+        assert abs(E1[b] - E_ref) <= tol["E"]
+        assert np.max(np.abs(g1[b] - g_ref)) <= tol["g"]
+
+
 def test_bitwise_reproducible(swc):
     say("[case] determinism q16 thr")
     h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 121)
