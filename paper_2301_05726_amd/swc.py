@@ -345,11 +345,13 @@ class Solver:
         self.close()
         return False
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # During interpreter shutdown the HIP runtime may already be torn
         # down: make no device call then (the exit hook has closed every
-        # context that was still open before finalisation began).
-        if sys.is_finalizing():
+        # context that was still open before finalisation began).  The
+        # check is bound at definition: module globals such as `sys` may
+        # already be cleared when a solver held by a script's globals dies.
+        if _finalizing():
             return
         try:
             self.close()

@@ -139,3 +139,27 @@ def test_mask_sign_rule_random_64_qubits(orc):
             assert (so != 0) == lower
             if lower:
                 assert so == s
+
+
+def test_solver_collected_at_interpreter_exit_is_quiet(tmp_path):
+    """A solver still referenced by a script's globals is collected while the
+    interpreter finalises, when module globals may already be cleared: its
+    destructor makes no device call then and raises nothing."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = tmp_path / "hold.py"
+    script.write_text(
+        "import sys\n"
+        f"sys.path.insert(0, {root!r})\n"
+        "from paper_2301_05726_amd import swc\n"
+        "class Held(swc.Solver):\n"
+        "    def __init__(self):\n"
+        "        pass\n"
+        "    def close(self):\n"
+        "        print('device call at exit', flush=True)\n"
+        "held = Held()\n")
+    r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "Exception ignored" not in r.stderr, r.stderr
+    assert "device call at exit" not in r.stdout
