@@ -60,7 +60,9 @@
  * step per launch); SWC_GRID=n caps the sweep launches at about n blocks
  * (at least one per arena of entries; tuning); SWC_SPLIT=1 (0) always
  * (never) gives batch members one-factor step launches of their own, which
- * by default they get once their indexes reach 2^22 slots.
+ * by default they get once their indexes reach 2^22 slots; SWC_HIOCC=1 (0)
+ * always (never) runs the one-factor forward steps on their build for three
+ * resident waves per SIMD, which by default they use from 2^22 index slots.
  */
 #ifndef SWC_H
 #define SWC_H
