@@ -150,8 +150,10 @@ enum {
   SWC_BUILD_REV2 = 64,        /* two factors per launch, reverse, home slot preloaded */
   SWC_BUILD_REV2_PRE = 128,   /* the same, four index slots preloaded */
   SWC_BUILD_PERSISTENT = 256, /* persistent cooperative sweeps (SWC_SWEEP=persistent) */
-  SWC_BUILD_FWD_HO = 512      /* one factor per launch, forward, built for three resident waves per SIMD
+  SWC_BUILD_FWD_HO = 512,     /* one factor per launch, forward, built for three resident waves per SIMD
                                  (indexes of 2^22 slots and more; SWC_HIOCC=1 always, 0 never) */
+  SWC_BUILD_FWD_PF = 1024,    /* the one-factor forward launches probed through the presence filter */
+  SWC_BUILD_REV_PF = 2048     /* the one-factor reverse launches probed through the presence filter */
 };
 
 /*

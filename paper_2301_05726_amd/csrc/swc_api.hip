@@ -49,7 +49,7 @@ struct Layout {
   size_t lkey, lmeta, lborn, lamp;
   size_t scale, pw, pcnt, gacc, logn, logoff, rmax, ws, ea, eb, entr, pvis, nb, app;
   size_t ckey, camp, cslot, csig;
-  size_t cnt, fac, trig, init_d, init_a, sync, topk;
+  size_t cnt, fac, trig, init_d, init_a, sync, topk, pf;
   size_t total;
 };
 
@@ -116,6 +116,7 @@ Layout make_layout(uint64_t Hcap, int tsz, int B, int64_t Mmax, uint64_t L) {
   l.init_a = take(Hcap / 2 * 8);
   l.sync = take(sizeof(Sync));
   l.topk = take(static_cast<size_t>(B) * sizeof(TopK));
+  l.pf = take(BH);  // presence filter: one 64-bit word per 8 index slots
   l.total = off;
   return l;
 }
@@ -180,9 +181,11 @@ struct GraphKey {
   int ent = 0;
   uint64_t tk_max = 0, tk_cut = 0;
   int live = 0;  // the live-count array is passed to the kernels (swc_track_live)
+  int pf = 0;    // the one-factor steps probe through the presence filter
   bool operator==(const GraphKey& o) const {
     return dir == o.dir && k0 == o.k0 && k1 == o.k1 && thr == o.thr && log_on == o.log_on &&
-           H == o.H && lim == o.lim && ent == o.ent && tk_max == o.tk_max && tk_cut == o.tk_cut && live == o.live;
+           H == o.H && lim == o.lim && ent == o.ent && tk_max == o.tk_max && tk_cut == o.tk_cut && live == o.live &&
+           pf == o.pf;
   }
 };
 constexpr int64_t GRAPH_CHUNK = 2048;
@@ -212,6 +215,17 @@ struct swc_ctx {
   int grid_override = 0;       // SWC_GRID
   int split_override = -1;     // SWC_SPLIT: 1 members always launched apart, 0 never, unset by index size
   int hiocc_override = -1;     // SWC_HIOCC: 1 forward steps always on their high-occupancy build, 0 never, unset by index size
+  // Probes through the index's presence filter (SWC_PFILTER: 1 always, 0
+  // never; unset: unless the last completed forward sweep found the partner
+  // of more than 1 rotated pair in 4, where most probes would read the
+  // filter and then the index anyway).  pf_now: the choice for the current
+  // call's sweeps; pf_fwd / pf_rev: whether the forward range being issued /
+  // the reverse sweep probe through it (forward ranges only on indexes of
+  // PF_FWD_H slots and more).
+  int pf_override = -1;
+  bool pf_auto = true, pf_now = false, pf_fwd = false, pf_rev = false;
+  Pf pf;                  // the filter (one word per 8 index slots of every member)
+  bool pf_valid = false;  // it holds every indexed key (steps without it leave it stale)
   // two factors per launch at threshold 0 (SWC_FUSE=0 turns it off)
   bool fuse = true;
   // entropy of every forward step (swc_track_entropy); sa.ea/eb are set
@@ -363,6 +377,7 @@ int arena_grid(uint64_t per, int items, int rmax) {
 // Make an index of Hn slots the current one (the grids follow its size).
 void set_table(swc_ctx* c, uint64_t Hn) {
   c->tab.H = Hn;
+  c->pf.n = Hn / 8;  // the presence filter follows the index
   // the entries an index of Hn slots holds when it runs at 45%, per arena
   c->per_arena = (Hn / 20 * 9 + NA - 1) / NA;
   int rmax = MAX_ARENA_BLOCKS;
@@ -394,6 +409,32 @@ constexpr uint64_t HIOCC_H = 1ull << 22;
 bool hi_occ(const swc_ctx* c) {
   return c->hiocc_override >= 0 ? c->hiocc_override > 0 : c->tab.H >= HIOCC_H;
 }
+// The filter the one-factor step launches probe through (none: plain
+// probes).  Forward steps use it from PF_FWD_H index slots on: on smaller
+// indexes a forward launch is a short chain of dependent loads that the
+// filter's second round trip (for the few partners it may hold, and for the
+// pairs that create their partner) lengthens, while the reverse, which
+// creates nothing, gains at every size.
+constexpr uint64_t PF_FWD_H = 1ull << 22;
+Pf fwd_pf(const swc_ctx* c) { return c->pf_fwd ? c->pf : Pf{}; }
+Pf rev_pf(const swc_ctx* c) { return c->pf_rev ? c->pf : Pf{}; }
+
+// Keys enter the index without their filter bits in forward ranges that do
+// not use the filter; the filter is rebuilt from the entries before it is
+// used again (a growth's rebuild of the index rebuilds it too).
+template <class T>
+void pf_ensure(swc_ctx* c) {
+  if (c->pf_valid) return;
+  launch_pf_build<T>(c->tab, c->pf, c->B, c->grid, c->st);
+  c->pf_valid = true;
+}
+void pf_ensure_any(swc_ctx* c) {
+  dispatch(c, [&](auto* tp) -> int {
+    pf_ensure<std::remove_pointer_t<decltype(tp)>>(c);
+    return SWC_OK;
+  });
+}
+
 int fwd_grid(const swc_ctx* c) {
   if (hi_occ(c)) return split_members(c) ? c->grid_fsh1 : c->grid_fsh;
   return split_members(c) ? c->grid_fs1 : c->grid_fs;
@@ -428,10 +469,11 @@ uint64_t table_size_for(const swc_ctx* c, uint64_t need, uint64_t Hmin) {
 int reindex_to(swc_ctx* c, uint64_t Hn) {
   set_table(c, Hn);
   dispatch(c, [&](auto* tp) -> int {
-    launch_reindex<std::remove_pointer_t<decltype(tp)>>(c->tab, c->cnt, c->B, c->grid, c->st);
+    launch_reindex<std::remove_pointer_t<decltype(tp)>>(c->tab, c->cnt, c->B, c->grid, c->st, c->pf);
     return SWC_OK;
   });
   SWC_HIP(hipGetLastError());
+  c->pf_valid = true;  // every entry's key re-entered the index and the filter
   ++c->rehashes;
   return SWC_OK;
 }
@@ -448,7 +490,7 @@ int grow_table(swc_ctx* c, uint64_t need) {
 // Reset every batch member to |Psi_0> with an index sized for it.
 int reset_state(swc_ctx* c) {
   set_table(c, table_size_for(c, c->h_init_d.size(), c->table_min));
-  launch_fill(c->tab, c->B, c->st);
+  launch_fill(c->tab, c->B, c->st, c->pf);
   for (int b = 0; b < c->B; ++b) {
     Counters z{};
     z.S = c->S0;
@@ -462,11 +504,12 @@ int reset_state(swc_ctx* c) {
   const int64_t n = static_cast<int64_t>(c->h_init_d.size());
   int r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
-    launch_insert_list<T>(c->tab, c->cnt, c->init_d, c->init_a, n, 0, n, c->B, c->st);
+    launch_insert_list<T>(c->tab, c->cnt, c->init_d, c->init_a, n, 0, n, c->B, c->st, c->pf);
     return SWC_OK;
   });
   if (r) return r;
   SWC_HIP(hipGetLastError());
+  c->pf_valid = true;
   c->fresh = true;
   return SWC_OK;
 }
@@ -482,16 +525,17 @@ int compact_state(swc_ctx* c, uint64_t live) {
   });
   if (r) return r;
   set_table(c, table_size_for(c, live, c->table_min));
-  launch_fill(c->tab, c->B, c->st);
+  launch_fill(c->tab, c->B, c->st, c->pf);
   launch_counters_live_reset(c->cnt, c->B, c->st);
   r = dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
     launch_insert_list<T>(c->tab, c->cnt, c->cp.key, c->cp.amp, -1, c->cp.cs, static_cast<int64_t>(live), c->B,
-                          c->st);
+                          c->st, c->pf);
     return SWC_OK;
   });
   if (r) return r;
   SWC_HIP(hipGetLastError());
+  c->pf_valid = true;
   return SWC_OK;
 }
 
@@ -581,7 +625,8 @@ int64_t fwd_plan(const swc_ctx* c, int64_t k0, int64_t k1, double thr, uint64_t 
       *builds |= wide2(c, c->res_f2w) ? SWC_BUILD_FWD2_PRE : SWC_BUILD_FWD2;
       k += 2;
     } else {
-      *builds |= c->entropy ? SWC_BUILD_FWD_ENT : hi_occ(c) ? SWC_BUILD_FWD_HO : SWC_BUILD_FWD;
+      *builds |= c->entropy ? SWC_BUILD_FWD_ENT
+                            : (hi_occ(c) ? SWC_BUILD_FWD_HO : SWC_BUILD_FWD) | (c->pf_fwd ? SWC_BUILD_FWD_PF : 0);
       n += step_launches(c) - 1;
       k += 1;
     }
@@ -597,7 +642,7 @@ int64_t rev_plan(const swc_ctx* c, int64_t hi, int64_t lo, bool fuse, int64_t* b
       *builds |= wide2(c, c->res_r2w) ? SWC_BUILD_REV2_PRE : SWC_BUILD_REV2;
       k -= 2;
     } else {
-      *builds |= SWC_BUILD_REV;
+      *builds |= SWC_BUILD_REV | (c->pf_rev ? SWC_BUILD_REV_PF : 0);
       n += step_launches(c) - 1;
       k -= 1;
     }
@@ -614,7 +659,7 @@ void issue_fwd(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint6
       k += 2;
     } else {
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, fwd_grid(c), split_members(c), hi_occ(c), st);
+                    log_on, lim, c->B, fwd_grid(c), split_members(c), hi_occ(c), fwd_pf(c), st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid, st);
       k += 1;
@@ -634,7 +679,7 @@ int64_t issue_rev(swc_ctx* c, int64_t hi, int64_t lo, bool fuse, hipStream_t st)
       k -= 2;
     } else {
       launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, rev_grid(c),
-                    split_members(c), st);
+                    split_members(c), rev_pf(c), st);
       k -= 1;
     }
   }
@@ -648,9 +693,14 @@ int64_t issue_rev(swc_ctx* c, int64_t hi, int64_t lo, bool fuse, hipStream_t st)
 int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, uint64_t lim, bool graph_ok) {
   return dispatch(c, [&](auto* tp) -> int {
     using T = std::remove_pointer_t<decltype(tp)>;
+    c->pf_fwd = c->pf_now && (c->tab.H >= PF_FWD_H || c->pf_override == 2);
+    if (c->pf_fwd)
+      pf_ensure<T>(c);
+    else
+      c->pf_valid = false;  // this range's new keys do not enter the filter
     if (c->use_graph && !c->ktiming && graph_ok) {
       const GraphKey key{0, k0, k1, thr, log_on, c->tab.H, lim, c->entropy ? 1 : 0, c->tk_max, c->tk_cut,
-                         c->live ? 1 : 0};
+                         c->live ? 1 : 0, c->pf_fwd ? 1 : 0};
       hipGraphExec_t ex = nullptr;
       const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { issue_fwd<T>(c, k0, k1, thr, log_on, lim, cs); });
       if (rr) return rr;
@@ -663,11 +713,12 @@ int run_fwd_steps(swc_ctx* c, int64_t k0, int64_t k1, double thr, int log_on, ui
       c->fwd_launches += fwd_plan(c, k0, k1, thr, lim, &c->builds);
       return SWC_OK;
     }
-    c->builds |= c->entropy ? SWC_BUILD_FWD_ENT : hi_occ(c) ? SWC_BUILD_FWD_HO : SWC_BUILD_FWD;
+    c->builds |= c->entropy ? SWC_BUILD_FWD_ENT
+                            : (hi_occ(c) ? SWC_BUILD_FWD_HO : SWC_BUILD_FWD) | (c->pf_fwd ? SWC_BUILD_FWD_PF : 0);
     for (int64_t k = k0; k <= k1; ++k) {  // every launch timed: one step per launch
       (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
       launch_fwd<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, c->lg, static_cast<int>(k), thr, k == 1,
-                    log_on, lim, c->B, fwd_grid(c), split_members(c), hi_occ(c), c->st);
+                    log_on, lim, c->B, fwd_grid(c), split_members(c), hi_occ(c), fwd_pf(c), c->st);
       (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
       if (c->tk_max)
         launch_topk<T>(c->tab, c->sa, c->cnt, c->tk, static_cast<int>(k), c->tk_max, c->tk_cut, c->B, c->grid,
@@ -750,6 +801,11 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
   c->rehashes = 0;
   c->compactions = 0;
   c->builds = 0;
+  // the presence filter for this call's sweeps: not with persistent sweeps,
+  // entropy tracking or two-factor launches (threshold 0), whose kernels
+  // neither read nor keep it
+  c->pf_now = !c->persistent && !c->entropy && !(thr == 0.0 && c->fuse) &&
+              (c->pf_override >= 0 ? c->pf_override > 0 : c->pf_auto);
   c->sa.ea = c->entropy ? c->ent_ea : nullptr;
   c->sa.eb = c->entropy ? c->ent_eb : nullptr;
   c->ent_M = -1;
@@ -771,6 +827,8 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
       ++c->compactions;
     }
   }
+  // steps that do not use the filter do not keep it either
+  if (M > 0 && !c->pf_now) c->pf_valid = false;
   dispatch(c, [&](auto* tp) -> int {
     launch_sweep_begin<std::remove_pointer_t<decltype(tp)>>(c->tab, c->sa, c->cnt, M, c->B, c->grid, c->st);
     return SWC_OK;
@@ -874,6 +932,9 @@ int forward_sweep(swc_ctx* c, int64_t M, double thr, int log_on) {
 // maxn[k]: largest number of truncation-log records of step k over the batch.
 int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>& maxn) {
   c->rev_launches = 0;
+  // the reverse creates no keys: a filter made current once serves it all
+  c->pf_rev = c->pf_now && M > 0;
+  if (c->pf_rev) pf_ensure_any(c);
   c->rev_fused = c->fuse && thr == 0.0 && !c->persistent && !c->ktiming && c->log_records == 0;
   // Each step scans only the entries that existed after it in the forward
   // sweep, so the scans shrink as the sweep goes back without any rebuild;
@@ -902,18 +963,18 @@ int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>
           issue_rev<T>(c, hi, lo, fz, c->st);
           return SWC_OK;
         }
-        const GraphKey key{1, lo, hi, fz ? 0.0 : 1.0, 0, c->tab.H, 0};
+        const GraphKey key{1, lo, hi, fz ? 0.0 : 1.0, 0, c->tab.H, 0, 0, 0, 0, 0, c->pf_rev ? 1 : 0};
         hipGraphExec_t ex = nullptr;
         const int rr = cached_graph(c, key, &ex, [&](hipStream_t cs) { issue_rev<T>(c, hi, lo, fz, cs); });
         if (rr) return rr;
         SWC_HIP(hipGraphLaunch(ex, c->st));
         return SWC_OK;
       }
-      c->builds |= SWC_BUILD_REV;
+      c->builds |= SWC_BUILD_REV | (c->pf_rev ? SWC_BUILD_REV_PF : 0);
       for (int64_t k = hi; k >= lo; --k) {
         if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1)], c->st);
         launch_rev<T>(c->tab, c->fac, c->trig, c->Mmax + 1, c->sa, c->cnt, static_cast<int>(k), c->B, rev_grid(c),
-                      split_members(c), c->st);
+                      split_members(c), rev_pf(c), c->st);
         if (c->ktiming) (void)hipEventRecord(c->kev[2 * (k - 1) + 1], c->st);
         if (maxn[k]) launch_log_restore<T>(c->tab, c->lg, c->sa, static_cast<int>(k), c->B, maxn[k], c->st);
       }
@@ -937,6 +998,14 @@ int reverse_sweep(swc_ctx* c, int64_t M, double thr, const std::vector<uint32_t>
 }
 
 int sweep_status(swc_ctx* c) {
+  {
+    uint64_t pairs = 0, hits = 0;
+    for (int b = 0; b < c->B; ++b) {
+      pairs += counter_total(c->hcnt[b], C_PAIRS);
+      hits += counter_total(c->hcnt[b], C_HITS);
+    }
+    if (pairs > 0) c->pf_auto = hits <= pairs / 4;
+  }
   for (int b = 0; b < c->B; ++b) {
     const Counters& k = c->hcnt[b];
     if (k.flags & F_TABLE_FULL) return fail(SWC_ECAPACITY, "hash table full");
@@ -1154,6 +1223,8 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   const uint64_t A = arena_size(c->H);
   c->tab = Tab{w + l.ent, w + l.aux, reinterpret_cast<Idx*>(w + l.idx), reinterpret_cast<uint32_t*>(w + l.ac), c->H,
                c->H, A};
+  c->pf.w = reinterpret_cast<uint64_t*>(w + l.pf);
+  c->pf.stride = c->H / 8;
   c->lg = LogArr{reinterpret_cast<uint64_t*>(w + l.lkey), reinterpret_cast<uint32_t*>(w + l.lmeta),
                  reinterpret_cast<uint32_t*>(w + l.lborn), w + l.lamp, c->L};
   c->sa = StepArr{reinterpret_cast<double*>(w + l.scale),   reinterpret_cast<Fx3*>(w + l.pw),
@@ -1181,6 +1252,8 @@ int swc_create(swc_ctx** out, int n_qubits, int n_alpha, int n_beta, uint64_t ca
   if (const char* e = std::getenv("SWC_GRID")) c->grid_override = std::max(0, std::atoi(e));  // tuning override
   if (const char* e = std::getenv("SWC_SPLIT")) c->split_override = std::atoi(e) != 0 ? 1 : 0;  // testing, tuning
   if (const char* e = std::getenv("SWC_HIOCC")) c->hiocc_override = std::atoi(e) != 0 ? 1 : 0;  // testing, tuning
+  // SWC_PFILTER (testing, tuning): 0 never, 1 always, 2 always and forward steps at every index size
+  if (const char* e = std::getenv("SWC_PFILTER")) c->pf_override = std::max(0, std::min(2, std::atoi(e)));
   if (const char* e = std::getenv("SWC_TABLE_MIN")) {  // smallest table after a reset (testing and tuning)
     const long long v = std::atoll(e);
     if (v >= 64 && pow2(static_cast<uint64_t>(v))) c->table_min = static_cast<uint64_t>(v);

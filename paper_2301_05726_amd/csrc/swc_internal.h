@@ -168,6 +168,16 @@ struct Tab {
   uint64_t A;    // entries per arena (<= 2^ID_POS_BITS)
 };
 
+// Presence filter of an index (a blocked Bloom filter over the keys it
+// holds): member b's words at w + b * stride, n = H/8 of them in use (one
+// 64-bit word per 8 index slots).  w = nullptr: none.  Kept apart from Tab so
+// that the step kernels without it take exactly the arguments they need.
+struct Pf {
+  uint64_t* w = nullptr;
+  uint64_t n = 0;
+  uint64_t stride = 0;
+};
+
 // truncation log: states of dead entries overwritten by a revival during the
 // forward sweep; member b at offset b*cap
 struct LogArr {
@@ -262,12 +272,13 @@ struct Compact {
 // that scan the entries take a grid of NA * r blocks (r blocks per arena).
 // ---------------------------------------------------------------------------
 // an empty state: index cleared (t.H slots), arenas empty
-void launch_fill(const Tab& t, int B, hipStream_t st);
+// pf: the index's presence filter, cleared with it (none by default)
+void launch_fill(const Tab& t, int B, hipStream_t st, const Pf& pf = Pf{});
 // insert n determinants (member b's at b * stride; n_fixed < 0: member b's
 // count is cnt[b].ncompact) into an empty state; nmax bounds the counts
 template <class T>
 void launch_insert_list(const Tab& t, Counters* cnt, const uint64_t* keys, const double* amps, int64_t n_fixed,
-                        uint64_t stride, int64_t nmax, int B, hipStream_t st);
+                        uint64_t stride, int64_t nmax, int B, hipStream_t st, const Pf& pf = Pf{});
 // record `msg` as the calling thread's last error (swc_last_error); returns code
 int report_error(int code, const char* msg);
 
@@ -304,14 +315,15 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
 // NO_LIMIT for an index at full capacity.  split: one launch per batch
 // member (grid blocks each, one after the other) instead of one launch with
 // grid.y = B.  hiocc: the forward build for more resident waves (large
-// states; the entropy build has none)
+// states; the entropy build has none).  pf.w set: the builds whose probes
+// consult the index's presence filter first and keep it (not with entropy)
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
-                int split, int hiocc, hipStream_t st);
+                int split, int hiocc, const Pf& pf, hipStream_t st);
 template <class T>
 void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                int k, int B, int grid, int split, hipStream_t st);
+                int k, int B, int grid, int split, const Pf& pf, hipStream_t st);
 // steps k and k+1 in one launch (threshold 0, factors with different XOR
 // masks; the index cannot grow during it), and their reverse (no truncation
 // log) (wide: several index slots from every home loaded up front; for
@@ -355,7 +367,10 @@ void launch_counters_live_reset(Counters* cnt, int B, hipStream_t st);
 void launch_scan_totals(const StepArr& sa, Counters* cnt, int64_t M, int B, hipStream_t st);
 // rebuild the index (t.H slots) from the entries; the growth stop is lifted
 template <class T>
-void launch_reindex(const Tab& t, Counters* cnt, int B, int grid, hipStream_t st);
+void launch_reindex(const Tab& t, Counters* cnt, int B, int grid, hipStream_t st, const Pf& pf = Pf{});
+// the presence filter rebuilt from every member's entries
+template <class T>
+void launch_pf_build(const Tab& t, const Pf& pf, int B, int grid, hipStream_t st);
 void launch_grad_final(const StepArr& sa, const Counters* cnt, double* grad, int64_t M, int B, hipStream_t st);
 // checkpoints: write the live entries after step k into `sn` (count must be
 // zero), and write a snapshot's amplitudes back over the entries of the same keys

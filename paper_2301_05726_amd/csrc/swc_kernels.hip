@@ -363,6 +363,30 @@ __device__ __forceinline__ bool index_insert(Idx* ix, uint64_t H, uint64_t key, 
   return false;
 }
 
+// Presence filter of the index (a blocked Bloom filter): one 64-bit word per
+// 8 index slots, three bits of one word per key.  While the filter is valid
+// every key the index holds (alive or dead entry alike) has its bits set, so
+// a key with any of its bits clear is not in the index and its probe needs no
+// index read.  The word comes from bits 32 and up of the key's hash (the
+// index home from the low bits), the bits from a second multiplicative hash
+// of it.  It is cleared with the index and filled by every kernel that
+// inserts keys while it is kept (the host tracks whether it is: steps without
+// it leave it stale until it is rebuilt from the entries).
+struct PfPos {
+  uint64_t w, bits;
+};
+__device__ __forceinline__ PfPos pf_pos(uint64_t key, uint64_t nw) {
+  const uint64_t m = mix64(key);
+  const uint64_t q = m * 0x9e3779b97f4a7c15ull;
+  return PfPos{(m >> 32) & (nw - 1), (1ull << (q >> 58)) | (1ull << ((q >> 52) & 63)) | (1ull << ((q >> 46) & 63))};
+}
+// the key's bits into member b's filter, if there is one (after the key entered the index)
+__device__ __forceinline__ void pf_add(const Pf& pf, int b, uint64_t key) {
+  if (!pf.w) return;
+  const PfPos p = pf_pos(key, pf.n);
+  atomicOr(reinterpret_cast<unsigned long long*>(pf.w + b * pf.stride + p.w), static_cast<unsigned long long>(p.bits));
+}
+
 // Entries of every arena of member b when the forward launch that runs step
 // k began (lane a holds arena a): the counts of the launch before it plus its
 // appends.  That launch began at step k-1, or at k-2 when it applied steps
@@ -501,12 +525,13 @@ __device__ __forceinline__ double wave_scale(const StepArr& sa, int b, int k) {
 // ---------------------------------------------------------------------------
 
 // An empty state: every index slot free, every arena empty.
-__global__ void k_fill(Tab t) {
+__global__ void k_fill(Tab t, Pf pf) {
   const int b = blockIdx.y;
   Idx* ix = t.idx + b * t.Hcap;
   for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
     ix[s].key = EMPTY_KEY;
     ix[s].id = NO_ID;
+    if (pf.w && s < pf.n) pf.w[b * pf.stride + s] = 0ull;
   }
   if (blockIdx.x == 0 && threadIdx.x < NA) t.ac[b * NA + threadIdx.x] = 0u;
 }
@@ -517,7 +542,7 @@ __global__ void k_fill(Tab t) {
 // (the compact copies of its live entries).
 template <class T>
 __global__ void k_insert_list(Tab t, Counters* cnt, const uint64_t* __restrict__ keys,
-                              const double* __restrict__ amps, int64_t n_fixed, uint64_t stride) {
+                              const double* __restrict__ amps, int64_t n_fixed, uint64_t stride, Pf pf) {
   const int b = blockIdx.y;
   const View<T> v = view<T>(t, b);
   const int64_t n = n_fixed >= 0 ? n_fixed : static_cast<int64_t>(cnt[b].ncompact);
@@ -540,6 +565,7 @@ __global__ void k_insert_list(Tab t, Counters* cnt, const uint64_t* __restrict__
       atomicOr(&cnt[b].flags, F_TABLE_FULL);
       continue;
     }
+    pf_add(pf, b, key);
     ++ok;
   }
   if (blockIdx.x == 0 && threadIdx.x < NA) {
@@ -745,13 +771,16 @@ __device__ __forceinline__ int claim_positions(const StepArr& sa, int b, int k, 
   return a;
 }
 
-template <class T, bool ENT>
+// PF: partners are looked up in the presence filter first, and in the index
+// only when the filter may hold them.
+template <class T, bool ENT, bool PF = false>
 __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict__ fac,
                                          const Trig* __restrict__ trig, int64_t ld, const StepArr& sa, Counters* cnt,
                                          const LogArr& lg, int k, double thr, int prune_all, int log_on,
-                                         uint64_t occ_lim, int b0, int nmem) {
+                                         uint64_t occ_lim, int b0, int nmem, const Pf& pf = Pf{}) {
   const int b = blockIdx.y + b0;  // b0: the member of a launch for one member (nmem members in all)
   const View<T> v = view<T>(t, b);
+  const uint64_t* pfm = PF ? pf.w + b * pf.stride : nullptr;  // the member's filter words
   // the factor first: its loads then overlap everything the step loads next
   const FacMask f = fac[k - 1];
   const Trig tr = trig[b * ld + k - 1];
@@ -856,9 +885,12 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     for (int u = 0; u < SCAN_U; ++u) mes[u] = nxt[u];
     if (jw + pass < ns) load_pass<T>(v, ebase, ns, j0 + pass, stride, nxt);
     // the home index slots of this pass's partners are then loaded together
+    // (with the filter: their filter words, then the index groups of the
+    // partners the filter may hold)
     uint64_t home[SCAN_U];
     Idx hv[SCAN_U][4];
-    bool act[SCAN_U];
+    bool act[SCAN_U], look[SCAN_U];
+    uint64_t pfw[SCAN_U], pfb[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
       const Slot<T>& me = mes[u];
@@ -885,8 +917,32 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       }
       act[u] = true;
       home[u] = home_slot(me.key ^ pm, v.H);
+      if (PF) {
+        const PfPos p = pf_pos(me.key ^ pm, pf.n);
+        pfw[u] = pfm[p.w];
+        pfb[u] = p.bits;
+      } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) hv[u][i] = v.ix[(home[u] + i) & (v.H - 1)];
+        for (int i = 0; i < 4; ++i) hv[u][i] = v.ix[(home[u] + i) & (v.H - 1)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      look[u] = act[u];
+      if (PF) {
+        look[u] = act[u] && (pfw[u] & pfb[u]) == pfb[u];
+        if (act[u] && !look[u]) {
+          // the partner is absent, so the pair creates it when its new value
+          // (the rotation of this member's amplitude alone) is kept: that
+          // needs a free index slot, so its index group is loaded as well
+          const T ss = (__popcll(mes[u].key & f.sgn) & 1) ? -sn : sn;
+          look[u] = fabs(S * static_cast<double>(static_cast<T>(ss * mes[u].amp))) >= thr;
+        }
+        if (look[u]) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) hv[u][i] = v.ix[(home[u] + i) & (v.H - 1)];
+        }
+      }
     }
     // resolve the probes, then load the partners' entries together
     uint64_t free_start[SCAN_U], pe[SCAN_U];
@@ -896,7 +952,7 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     for (int u = 0; u < SCAN_U; ++u) {
       found[u] = false;
       free_start[u] = v.H;
-      if (!act[u]) continue;
+      if (!look[u]) continue;
       Idx iv;
       found[u] = find_slot_pre<4>(v.ix, v.H, mes[u].key ^ pm, home[u], hv[u], &free_start[u], &iv) >= 0;
       if (found[u]) {
@@ -987,7 +1043,9 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
     // arena, so the two returning atomics overlap; then the entries, and the
     // entry ids into the index slots.  Until its id is written a claimed slot
     // is seen by no probe of this step but its own: a created key is the
-    // partner of one scanned entry only.
+    // partner of one scanned entry only.  (With the filter every creating
+    // lane has probed its index group; the insert from the home covers a lane
+    // that did not.)
     bool slot_ok[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
@@ -1019,11 +1077,13 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
       // (a slot another new key took first: the probe goes on past it)
       if (slot_ok[u]) {
         v.ix[wfree[u]].id = entry_id(a, pos[u]);
-      } else if (!index_insert(v.ix, v.H, wkey[u], wfree[u] < v.H ? (wfree[u] + 1) & (v.H - 1) : v.H,
+      } else if (!index_insert(v.ix, v.H, wkey[u],
+                               PF && !look[u] ? home[u] : wfree[u] < v.H ? (wfree[u] + 1) & (v.H - 1) : v.H,
                                entry_id(a, pos[u]))) {
         flags |= F_TABLE_FULL;
         continue;
       }
+      if (PF) pf_add(pf, b, wkey[u]);
       r.c[3] += 1;
       r.c[5] += 1;
     }
@@ -1068,12 +1128,13 @@ __device__ __forceinline__ void fwd_step(const Tab& t, const FacMask* __restrict
 // Members born in step k are removed; entries that died in step k are
 // revived.  Only the entries that existed after step k are scanned (those
 // created by later steps lie beyond the counts of the next forward launch).
-template <class T>
+template <class T, bool PF = false>
 __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict__ fac,
                                          const Trig* __restrict__ trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                                         int k, int b0) {
+                                         int k, int b0, const Pf& pf = Pf{}) {
   const int b = blockIdx.y + b0;  // b0: the member of a launch for one member
   const View<T> v = view<T>(t, b);
+  const uint64_t* pfm = PF ? pf.w + b * pf.stride : nullptr;  // the member's filter words
   const int s = scan_arena();
   const uint64_t ns = static_cast<uint32_t>(__shfl(static_cast<int>(counts_reverse(sa, b, k, v.A)), s, 64));
 
@@ -1103,7 +1164,8 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
     uint64_t home[SCAN_U];
     Idx hv[SCAN_U][4];
     T lms[SCAN_U];
-    bool act[SCAN_U];
+    bool act[SCAN_U], look[SCAN_U];
+    uint64_t pfw[SCAN_U], pfb[SCAN_U];
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
       const Slot<T>& me = mes[u];
@@ -1128,8 +1190,25 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
       // loaded only by the pair's owner once the partner is found
       lms[u] = v.lam_pre(e);
       home[u] = home_slot(me.key ^ pm, v.H);
+      if (PF) {
+        const PfPos p = pf_pos(me.key ^ pm, pf.n);
+        pfw[u] = pfm[p.w];
+        pfb[u] = p.bits;
+      } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) hv[u][i] = v.ix[(home[u] + i) & (v.H - 1)];
+        for (int i = 0; i < 4; ++i) hv[u][i] = v.ix[(home[u] + i) & (v.H - 1)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      look[u] = act[u];
+      if (PF) {
+        look[u] = act[u] && (pfw[u] & pfb[u]) == pfb[u];
+        if (look[u]) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) hv[u][i] = v.ix[(home[u] + i) & (v.H - 1)];
+        }
+      }
     }
     // resolve the probes, then load the partners' entries together
     bool found[SCAN_U];
@@ -1138,7 +1217,7 @@ __device__ __forceinline__ void rev_step(const Tab& t, const FacMask* __restrict
 #pragma unroll
     for (int u = 0; u < SCAN_U; ++u) {
       found[u] = false;
-      if (!act[u]) continue;
+      if (!look[u]) continue;
       uint64_t ff = v.H;
       Idx iv;
       found[u] = find_slot_pre<4>(v.ix, v.H, mes[u].key ^ pm, home[u], hv[u], &ff, &iv) >= 0;
@@ -1277,6 +1356,21 @@ __global__ __launch_bounds__(BLK) void k_rev(Tab t, const FacMask* __restrict__ 
   rev_step<T>(t, fac, trig, ld, sa, cnt, k, b0);
 }
 
+// The step kernels with the presence-filter probes (large states whose
+// partners are nearly always absent; see pf_pos).
+template <class T>
+__global__ __launch_bounds__(BLK) void k_fwd_pf(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
+                                                int64_t ld, StepArr sa, Counters* cnt, LogArr lg, int k, double thr,
+                                                int prune_all, int log_on, uint64_t occ_lim, int b0, int nmem, Pf pf) {
+  fwd_step<T, false, true>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on, occ_lim, b0, nmem, pf);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_rev_pf(Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig,
+                                                int64_t ld, StepArr sa, Counters* cnt, int k, int b0, Pf pf) {
+  rev_step<T, true>(t, fac, trig, ld, sa, cnt, k, b0, pf);
+}
+
 // The forward step built for three resident waves per SIMD instead of two
 // (fewer registers, a few spilled), so that more loads are in flight on each
 // compute unit.  It pays once the state spans many passes of the grid; small
@@ -1288,6 +1382,13 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(3))) void k
     Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig, int64_t ld, StepArr sa, Counters* cnt,
     LogArr lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int b0, int nmem) {
   fwd_step<T, false>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on, occ_lim, b0, nmem);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(3))) void k_fwd_ho_pf(
+    Tab t, const FacMask* __restrict__ fac, const Trig* __restrict__ trig, int64_t ld, StepArr sa, Counters* cnt,
+    LogArr lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int b0, int nmem, Pf pf) {
+  fwd_step<T, false, true>(t, fac, trig, ld, sa, cnt, lg, k, thr, prune_all, log_on, occ_lim, b0, nmem, pf);
 }
 
 
@@ -2465,25 +2566,29 @@ __global__ __launch_bounds__(BLK) void k_energy_reduce(Compact cp, Counters* cnt
 // ---------------------------------------------------------------------------
 // index growth: a larger index, rebuilt from the entries (which do not move)
 // ---------------------------------------------------------------------------
-__global__ void k_idx_clear(Tab t) {
+__global__ void k_idx_clear(Tab t, Pf pf) {
   Idx* ix = t.idx + blockIdx.y * t.Hcap;
   for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < t.H; s += gridDim.x * blockDim.x) {
     ix[s].key = EMPTY_KEY;
     ix[s].id = NO_ID;
+    if (pf.w && s < pf.n) pf.w[blockIdx.y * pf.stride + s] = 0ull;
   }
 }
 
 // Every entry, alive or dead, is indexed (keys are unique, so every insert
 // claims its own slot); the growth check stopped no step any more.
 template <class T>
-__global__ void k_reindex(Tab t, Counters* cnt) {
+__global__ void k_reindex(Tab t, Counters* cnt, Pf pf) {
   const int b = blockIdx.y;
   const View<T> v = view<T>(t, b);
   const int a = scan_arena();
   const uint64_t n = t.ac[b * NA + a];
   for (uint64_t j = scan_rank() * BLK + threadIdx.x; j < n; j += scan_blocks() * BLK) {
     const uint64_t key = v.sl[a * v.A + j].key;
-    if (!index_insert(v.ix, v.H, key, home_slot(key, v.H), entry_id(a, j))) atomicOr(&cnt[b].flags, F_TABLE_FULL);
+    if (!index_insert(v.ix, v.H, key, home_slot(key, v.H), entry_id(a, j)))
+      atomicOr(&cnt[b].flags, F_TABLE_FULL);
+    else
+      pf_add(pf, b, key);
   }
   if (b == 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[0].stop = ~0u;
 }
@@ -2609,8 +2714,8 @@ int grid_for(uint64_t work, int block, int cap) {
   return static_cast<int>(g);
 }
 
-void launch_fill(const Tab& t, int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t);
+void launch_fill(const Tab& t, int B, hipStream_t st, const Pf& pf) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t, pf);
 }
 
 // Checks a list that k_insert_list put into member 0: every key a
@@ -2642,9 +2747,9 @@ void launch_check_list(const Tab& t, Counters* cnt, const uint64_t* keys, const 
 
 template <class T>
 void launch_insert_list(const Tab& t, Counters* cnt, const uint64_t* keys, const double* amps, int64_t n_fixed,
-                        uint64_t stride, int64_t nmax, int B, hipStream_t st) {
+                        uint64_t stride, int64_t nmax, int B, hipStream_t st, const Pf& pf) {
   hipLaunchKernelGGL(k_insert_list<T>, dim3(grid_for(nmax > 0 ? nmax : 1, BLK, 4096), B), dim3(BLK), 0, st, t, cnt,
-                     keys, amps, n_fixed, stride);
+                     keys, amps, n_fixed, stride, pf);
 }
 
 void launch_trig(const double* theta, Trig* trig, int64_t M, int64_t ld, int B, Counters* cnt, hipStream_t st) {
@@ -2723,15 +2828,21 @@ hipError_t launch_rev_sweep(const Tab& t, const FacMask* fac, const Trig* trig, 
 template <class T>
 void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
                 const LogArr& lg, int k, double thr, int prune_all, int log_on, uint64_t occ_lim, int B, int grid,
-                int split, int hiocc, hipStream_t st) {
+                int split, int hiocc, const Pf& pf, hipStream_t st) {
   const int nl = split ? B : 1, gy = split ? 1 : B;
   for (int b0 = 0; b0 < nl; ++b0) {
     if (sa.ea)
       hipLaunchKernelGGL((k_fwd<T, true>), dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
                          prune_all, log_on, occ_lim, b0, B);
+    else if (hiocc && pf.w)
+      hipLaunchKernelGGL(k_fwd_ho_pf<T>, dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
+                         prune_all, log_on, occ_lim, b0, B, pf);
     else if (hiocc)
       hipLaunchKernelGGL(k_fwd_ho<T>, dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
                          prune_all, log_on, occ_lim, b0, B);
+    else if (pf.w)
+      hipLaunchKernelGGL(k_fwd_pf<T>, dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
+                         prune_all, log_on, occ_lim, b0, B, pf);
     else
       hipLaunchKernelGGL((k_fwd<T, false>), dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, lg, k, thr,
                          prune_all, log_on, occ_lim, b0, B);
@@ -2740,12 +2851,14 @@ void launch_fwd(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, 
 
 template <class T>
 void launch_rev(const Tab& t, const FacMask* fac, const Trig* trig, int64_t ld, const StepArr& sa, Counters* cnt,
-                int k, int B, int grid, int split, hipStream_t st) {
-  if (split)
-    for (int b0 = 0; b0 < B; ++b0)
-      hipLaunchKernelGGL(k_rev<T>, dim3(grid, 1), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k, b0);
-  else
-    hipLaunchKernelGGL(k_rev<T>, dim3(grid, B), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k, 0);
+                int k, int B, int grid, int split, const Pf& pf, hipStream_t st) {
+  const int nl = split ? B : 1, gy = split ? 1 : B;
+  for (int b0 = 0; b0 < nl; ++b0) {
+    if (pf.w)
+      hipLaunchKernelGGL(k_rev_pf<T>, dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k, b0, pf);
+    else
+      hipLaunchKernelGGL(k_rev<T>, dim3(grid, gy), dim3(BLK), 0, st, t, fac, trig, ld, sa, cnt, k, b0);
+  }
 }
 
 template <class T>
@@ -2846,9 +2959,31 @@ void launch_energy_begin(Counters* cnt, int B, hipStream_t st) {
 }
 
 template <class T>
-void launch_reindex(const Tab& t, Counters* cnt, int B, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_idx_clear, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t);
-  hipLaunchKernelGGL(k_reindex<T>, dim3(grid, B), dim3(BLK), 0, st, t, cnt);
+void launch_reindex(const Tab& t, Counters* cnt, int B, int grid, hipStream_t st, const Pf& pf) {
+  hipLaunchKernelGGL(k_idx_clear, dim3(grid_for(t.H, BLK, 8192), B), dim3(BLK), 0, st, t, pf);
+  hipLaunchKernelGGL(k_reindex<T>, dim3(grid, B), dim3(BLK), 0, st, t, cnt, pf);
+}
+
+// The filter rebuilt from every entry of every member (after steps that did
+// not keep it): cleared, then every key's bits set.
+__global__ void k_pf_clear(Pf pf) {
+  for (uint64_t s = blockIdx.x * blockDim.x + threadIdx.x; s < pf.n; s += gridDim.x * blockDim.x)
+    pf.w[blockIdx.y * pf.stride + s] = 0ull;
+}
+
+template <class T>
+__global__ void k_pf_fill(Tab t, Pf pf) {
+  const int b = blockIdx.y;
+  const View<T> v = view<T>(t, b);
+  const int a = scan_arena();
+  const uint64_t n = t.ac[b * NA + a];
+  for (uint64_t j = scan_rank() * BLK + threadIdx.x; j < n; j += scan_blocks() * BLK) pf_add(pf, b, v.sl[a * v.A + j].key);
+}
+
+template <class T>
+void launch_pf_build(const Tab& t, const Pf& pf, int B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_pf_clear, dim3(grid_for(pf.n, BLK, 8192), B), dim3(BLK), 0, st, pf);
+  hipLaunchKernelGGL(k_pf_fill<T>, dim3(grid, B), dim3(BLK), 0, st, t, pf);
 }
 
 void launch_energy_final(Counters* cnt, double* E, int B, hipStream_t st) {
@@ -3195,12 +3330,14 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
 
 #define SWC_INST(T)                                                                                                \
   template void launch_insert_list<T>(const Tab&, Counters*, const uint64_t*, const double*, int64_t, uint64_t,   \
-                                      int64_t, int, hipStream_t);                                                  \
+                                      int64_t, int, hipStream_t, const Pf&);                                       \
   template void launch_sweep_begin<T>(const Tab&, const StepArr&, Counters*, int64_t, int, int, hipStream_t);     \
   template void launch_fwd<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*,        \
-                              const LogArr&, int, double, int, int, uint64_t, int, int, int, int, hipStream_t);    \
+                              const LogArr&, int, double, int, int, uint64_t, int, int, int, int, const Pf&,      \
+                              hipStream_t);                                                                        \
   template void launch_rev<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,   \
-                              int, int, int, hipStream_t);                                                         \
+                              int, int, int, const Pf&, hipStream_t);                                              \
+  template void launch_pf_build<T>(const Tab&, const Pf&, int, int, hipStream_t);                                 \
   template void launch_log_restore<T>(const Tab&, const LogArr&, const StepArr&, int, int, uint32_t,              \
                                       hipStream_t);                                                                \
   template void launch_compact<T>(const Tab&, const Compact&, Counters*, int, int, hipStream_t);                  \
@@ -3213,7 +3350,7 @@ void launch_fx3_zero(Fx3* a, uint64_t n, hipStream_t st) {
                                           hipStream_t);                                                            \
   template hipError_t launch_rev_sweep<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&,       \
                                           Counters*, const LogArr&, int, int, Sync*, int, int, hipStream_t);      \
-  template void launch_reindex<T>(const Tab&, Counters*, int, int, hipStream_t);                                 \
+  template void launch_reindex<T>(const Tab&, Counters*, int, int, hipStream_t, const Pf&);                      \
   template void launch_fwd2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \
                                int, int, int, hipStream_t);                                                        \
   template void launch_rev2<T>(const Tab&, const FacMask*, const Trig*, int64_t, const StepArr&, Counters*, int,  \

@@ -62,7 +62,7 @@ class Stats(ctypes.Structure):
 # sweep kernel builds (Stats.kernel_builds bits)
 BUILD_FWD, BUILD_FWD_ENT, BUILD_FWD2, BUILD_FWD2_PRE = 1, 4, 8, 16
 BUILD_REV, BUILD_REV2, BUILD_REV2_PRE, BUILD_PERSISTENT = 32, 64, 128, 256
-BUILD_FWD_HO = 512
+BUILD_FWD_HO, BUILD_FWD_PF, BUILD_REV_PF = 512, 1024, 2048
 
 
 _lib = None

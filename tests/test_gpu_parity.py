@@ -155,6 +155,86 @@ def test_forward_high_occupancy_build(swc, orc, monkeypatch, prec, batch):
         assert np.max(np.abs(g1[b] - g_ref)) <= tol["g"]
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("shape", ["b1", "b2_apart", "b1_hiocc"])
+def test_presence_filter_probes(swc, orc, monkeypatch, prec, shape):
+    """Steps whose probes consult the index's presence filter first
+    (SWC_PFILTER=2: forward and reverse at every index size; by themselves
+    the library's forward steps use it from 2^22 index slots on, its reverse
+    steps at every size) give the bits of the plain probes and the oracle's
+    values: the forward sweep creates entries, grows the index (the filter is
+    rebuilt with it) and is undone by the adjoint sweep; a second call reuses
+    the state's filter after the reset."""
+    say(f"[case] presence filter q16 {shape} prec={prec}")
+    batch = 2 if shape == "b2_apart" else 1
+    h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 191, batch=batch)
+    M, thr = exc.shape[0], 1e-4
+    monkeypatch.setenv("SWC_TABLE_MIN", "64")
+    monkeypatch.setenv("SWC_SPLIT", "1" if batch > 1 else "0")
+    monkeypatch.setenv("SWC_HIOCC", "1" if shape == "b1_hiocc" else "0")
+    res = {}
+    for pf in ("0", "1", "2"):
+        monkeypatch.setenv("SWC_PFILTER", pf)
+        s = swc.Solver(16, 4, 4, capacity_for(8, 4), prec=prec, batch=batch, max_factors=M)
+        s.build_state()
+        out = []
+        for rep in range(2):
+            E, g = s.energy_and_grad(theta, exc, thr, h1, h2)
+            st = s.stats()
+            out.append((E.cpu().numpy(), g.cpu().numpy(), st["kernel_builds"], st["rehashes"]))
+        s.apply_ucc(theta, exc, thr)
+        states = [s.get_state(b) for b in range(batch)]
+        res[pf] = (out, states)
+        s.close()
+    o0, st0 = res["0"]
+    for pf, fwd_pf in (("1", False), ("2", True)):  # "1": an index this small keeps forward steps plain
+        o1, st1 = res[pf]
+        for (E0, g0, b0, h0), (E1, g1, b1, h1_) in zip(o0, o1):
+            say(f"  SWC_PFILTER={pf}: builds {b0:#x} -> {b1:#x}, growths {h0}")
+            assert h0 == h1_
+            assert not b0 & (swc.BUILD_FWD_PF | swc.BUILD_REV_PF)
+            assert bool(b1 & swc.BUILD_FWD_PF) == fwd_pf and b1 & swc.BUILD_REV_PF
+            assert E1.tobytes() == E0.tobytes() and g1.tobytes() == g0.tobytes()
+        for (d0, a0), (d1, a1) in zip(st0, st1):
+            assert np.array_equal(d0, d1) and a0.tobytes() == a1.tobytes()
+    assert o0[0][3] > 0  # the first call grew the index
+    o1 = res["2"][0]
+    tol = TOL[prec]
+    E1, g1 = o1[0][0], o1[0][1]
+    for b in range(batch):
+        E_ref, g_ref, _ = orc.energy_and_grad(16, [hf], [1.0], exc, theta[b], thr, h1, h2)
+        assert abs(E1[b] - E_ref) <= tol["E"]
+        assert np.max(np.abs(g1[b] - g_ref)) <= tol["g"]
+
+
+@pytest.mark.parametrize("seed,thr", [(191, 1e-4), (192, 0.0)], ids=["thr1e-4", "thr0"])
+def test_presence_filter_chosen_from_last_sweep(swc, orc, monkeypatch, seed, thr):
+    """With SWC_PFILTER unset a call's reverse steps probe through the
+    filter (rebuilt from the entries, since forward steps on an index this
+    small do without it) unless the last completed forward sweep found the
+    partner of more than 1 rotated pair in 4 (threshold 0, one factor per
+    launch: most partners exist); the results match the oracle."""
+    say(f"[case] presence filter policy q16 seed={seed} thr={thr}")
+    h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, seed)
+    monkeypatch.delenv("SWC_PFILTER", raising=False)
+    monkeypatch.setenv("SWC_FUSE", "0")
+    s = swc.Solver(16, 4, 4, capacity_for(8, 4), prec=0, batch=1, max_factors=exc.shape[0])
+    s.build_state()
+    s.apply_ucc(theta, exc, thr)
+    st = s.stats()
+    # (an index this small: forward steps without the filter)
+    assert not st["kernel_builds"] & swc.BUILD_FWD_PF
+    expect = st["partner_hits"] <= st["pair_updates"] // 4
+    say(f"  pairs {st['pair_updates']} hits {st['partner_hits']} -> filter {expect}")
+    E, g = s.energy_and_grad(theta, exc, thr, h1, h2)
+    got = s.stats()["kernel_builds"]
+    assert not got & swc.BUILD_FWD_PF and bool(got & swc.BUILD_REV_PF) == expect
+    E_ref, g_ref, _ = orc.energy_and_grad(16, [hf], [1.0], exc, theta[0], thr, h1, h2)
+    assert abs(E.cpu().numpy()[0] - E_ref) <= TOL[0]["E"]
+    assert np.max(np.abs(g.cpu().numpy()[0] - g_ref)) <= TOL[0]["g"]
+    s.close()
+
+
 def test_bitwise_reproducible(swc):
     say("[case] determinism q16 thr")
     h1, h2, exc, theta, hf = small_problem(8, 4, 0.1, 121)
