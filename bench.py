@@ -342,8 +342,7 @@ def main() -> int:
         prate = ppl / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         lines[name] = {"kernel": name, "what": what, "bound": "hbm", "achieved": round(ach, 2),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
-                       "traffic": traffic.get("k_fwd_step" if name == "k_fwd" and "k_fwd_step" in traffic
-                                              else name), "bytes_per_launch": round(bpl, 1),
+                       "traffic": traffic.get(name + "_step", traffic.get(name)), "bytes_per_launch": round(bpl, 1),
                        "avg_launch_us": round(ms * 1e3, 3),
                        # (a two-factor launch probes for up to three partners per
                        # member: its probes are not these)

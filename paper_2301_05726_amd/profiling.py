@@ -240,15 +240,19 @@ def traffic(a) -> None:
         t = fv * ff + wv * fw
         rows.append((k, t))
         print(f"{k:28s} {n:10d} {fv:12.1f} {wv:12.1f} {t:12.1f}")
-    # the one-factor forward step over both its builds (k_fwd, and k_fwd_ho
-    # on large indexes), weighted by dispatches: what bench.py's k_fwd line
-    # averages over
-    parts = [k for k in ("k_fwd", "k_fwd_ho") if k in fetch and k in write]
-    if len(parts) == 2:
+    # the one-factor steps over all their builds (the plain ones, the forward's
+    # high-occupancy build on large indexes, those probing through the
+    # presence filter), weighted by dispatches: what bench.py's k_fwd and
+    # k_rev lines average over
+    for step, builds in (("k_fwd_step", ("k_fwd", "k_fwd_ho", "k_fwd_pf", "k_fwd_ho_pf")),
+                         ("k_rev_step", ("k_rev", "k_rev_pf"))):
+        parts = [k for k in builds if k in fetch and k in write]
+        if not parts:
+            continue
         n = sum(fetch[k][1] for k in parts)
         t = sum((fetch[k][0] * ff + write[k][0] * fw) * fetch[k][1] for k in parts) / n
-        rows.append(("k_fwd_step", t))
-        print(f"{'k_fwd_step (both builds)':28s} {n:10d} {'':12s} {'':12s} {t:12.1f}")
+        rows.append((step, t))
+        print(f"{step + ' (all builds)':28s} {n:10d} {'':12s} {'':12s} {t:12.1f}")
     print("# per dispatch, calibrated (read by bench.py while the sources are unchanged):")
     for k, t in rows:
         print(f"traffic_kib {k} {t:.1f}")

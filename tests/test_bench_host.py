@@ -26,7 +26,7 @@ def test_help_lists_the_contract_options():
 
 def test_traffic_summary_weights_the_forward_builds(tmp_path):
     """profiling traffic: per-dispatch bytes scaled by the copy calibration,
-    and the forward step over both its builds weighted by dispatches."""
+    and the forward step over all its builds weighted by dispatches."""
     def reduced(path, rows):
         with open(path, "w") as f:
             f.write("Kernel_Name,Counter_Name,Counter_Sum,Dispatches\n")
@@ -48,3 +48,4 @@ def test_traffic_summary_weights_the_forward_builds(tmp_path):
     assert vals["k_fwd"] == 2 * 100.0 + 10.0        # per dispatch: fetch x 2 + write x 1
     assert vals["k_fwd_ho"] == 2 * 300.0 + 10.0
     assert vals["k_fwd_step"] == (2 * 210.0 + 6 * 610.0) / 8
+    assert "k_rev_step" not in vals
