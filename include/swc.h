@@ -62,7 +62,13 @@
  * (never) gives batch members one-factor step launches of their own, which
  * by default they get once their indexes reach 2^22 slots; SWC_HIOCC=1 (0)
  * always (never) runs the one-factor forward steps on their build for three
- * resident waves per SIMD, which by default they use from 2^22 index slots.
+ * resident waves per SIMD, which by default they use from 2^22 index slots;
+ * SWC_PFILTER=0 never probes through the index's presence filter, 1 always
+ * where the library would (reverse steps at every index size, forward steps
+ * from 2^22 slots), 2 always, forward steps at every size; by default a call
+ * uses it unless the last forward sweep found the partner of more than one
+ * rotated pair in four (never with entropy tracking, persistent sweeps or
+ * the two-factor launches of threshold 0).
  */
 #ifndef SWC_H
 #define SWC_H
@@ -171,6 +177,9 @@ enum {
  * per-factor scans read the entries only.  The index maps a determinant to its entry; it starts small
  * after every reset to |Psi_0> and is rebuilt larger (x2 or more) during a
  * forward sweep when the entries near a growth limit (22.5% of its slots).
+ * Beside the index lies its presence filter (one byte per index slot of
+ * capacity): a partner lookup whose key the filter rules out reads no index
+ * slot, which at the usual thresholds is nearly every lookup.
  * Returns 0 for invalid arguments.
  */
 size_t swc_workspace_bytes(int n_qubits, uint64_t capacity, int prec, int batch, int64_t max_factors,
